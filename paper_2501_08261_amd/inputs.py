@@ -1,0 +1,96 @@
+"""Seeded synthetic workloads shaped like the paper's injections (Tab. I).
+
+This module only draws and lays out input numbers (parameter vectors, grids,
+random series).  It holds none of the likelihood arithmetic, so both the HIP
+path and the CPU oracle can consume what it produces.
+
+Parameter vector (one FP64 row of 16 per template):
+  0 m1 [Msun, detector frame]   1 m2 [Msun]
+  2-4 chi1 (x, y, z)            5-7 chi2 (x, y, z)   (L0 frame at f_ref)
+  8 D_L [Mpc]  9 iota  10 phi_ref  11 t_c [s, SSB time of the (2,2) peak]
+  12 lambda  13 beta  14 psi  15 unused
+"""
+import math
+import numpy as np
+
+N_PARAMS = 16
+DEG = math.pi / 180.0
+
+
+def _spin_cart(a, tilt, phi):
+    return [a * math.sin(tilt) * math.cos(phi), a * math.sin(tilt) * math.sin(phi), a * math.cos(tilt)]
+
+
+def grid(n, dt=5.0, t0=0.0):
+    return {"t0": float(t0), "dt": float(dt), "n": int(n)}
+
+
+def peak_time(g, before_end):
+    """SSB time that puts the (2,2) peak `before_end` seconds before the last sample."""
+    return g["t0"] + (g["n"] - 1) * g["dt"] - before_end
+
+
+def tab1_injection(precessing, g, before_end=2000.0):
+    """Tab. I injection: m1 = 1e6, m2 = 7e5 Msun, D = 20 Gpc, SNR ~ 2800."""
+    p = np.zeros(N_PARAMS)
+    p[0], p[1] = 1.0e6, 7.0e5
+    if precessing:
+        p[2:5] = _spin_cart(0.7, 40.1 * DEG, 40.1 * DEG)
+        p[5:8] = _spin_cart(0.4, 22.9 * DEG, 22.9 * DEG)
+    else:
+        p[4], p[7] = 0.7, 0.4
+    p[8] = 2.0e4
+    p[9], p[10] = 149.0 * DEG, 229.2 * DEG
+    p[11] = peak_time(g, before_end)
+    p[12], p[13], p[14] = 34.4 * DEG, -34.4 * DEG, 22.9 * DEG
+    return p
+
+
+def single_template_case():
+    """One-day (2,2) case: M = 1e6 Msun, q = 2, chi = (0.5, 0.3), 17,280 samples at 5 s.
+
+    Returns (grid, injection, template offset by 1e-3 in chirp mass at fixed q)."""
+    g = grid(17280, 5.0)
+    inj = tab1_injection(False, g, before_end=1000.0)
+    inj[0], inj[1] = 1.0e6 * 2.0 / 3.0, 1.0e6 / 3.0
+    inj[4], inj[7] = 0.5, 0.3
+    tmpl = inj.copy()
+    tmpl[0] *= 1.001
+    tmpl[1] *= 1.001
+    return g, inj, tmpl
+
+
+def draw_templates(seed, batch, g, precessing, before_end=2000.0):
+    """Random templates: log10 M ~ U[5, 7], q ~ U[1, 10], isotropic sky / orientation.
+
+    Aligned: chi_z ~ U[-0.99, 0.99].  Precessing: |chi| ~ U[0, 0.99] with
+    isotropic directions.  D = 20 Gpc; (2,2) peak `before_end` s before the end.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = np.zeros((batch, N_PARAMS))
+    M = 10.0 ** rng.uniform(5.0, 7.0, batch)
+    q = rng.uniform(1.0, 10.0, batch)
+    p[:, 0], p[:, 1] = M * q / (1.0 + q), M / (1.0 + q)
+    if precessing:
+        for j, col in ((0, 2), (1, 5)):
+            a = rng.uniform(0.0, 0.99, batch)
+            ct = rng.uniform(-1.0, 1.0, batch)
+            ph = rng.uniform(0.0, 2.0 * math.pi, batch)
+            st = np.sqrt(1.0 - ct * ct)
+            p[:, col], p[:, col + 1], p[:, col + 2] = a * st * np.cos(ph), a * st * np.sin(ph), a * ct
+    else:
+        p[:, 4] = rng.uniform(-0.99, 0.99, batch)
+        p[:, 7] = rng.uniform(-0.99, 0.99, batch)
+    p[:, 8] = 2.0e4
+    p[:, 9] = np.arccos(rng.uniform(-1.0, 1.0, batch))
+    p[:, 10] = rng.uniform(0.0, 2.0 * math.pi, batch)
+    p[:, 11] = peak_time(g, before_end)
+    p[:, 12] = rng.uniform(0.0, 2.0 * math.pi, batch)
+    p[:, 13] = np.arcsin(rng.uniform(-1.0, 1.0, batch))
+    p[:, 14] = rng.uniform(0.0, math.pi, batch)
+    return p
+
+
+def random_series(seed, shape, scale=1.0):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return scale * rng.standard_normal(shape)
