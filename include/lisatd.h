@@ -1,0 +1,159 @@
+/*
+ * liblisatd -- MI355X (gfx950) time-domain LISA likelihood.
+ *
+ * C ABI of the hot path of arXiv:2501.08261 ("GPU-accelerated LISA parameter
+ * estimation with full time domain response"): per template, IMRPhenomT-form
+ * modes (Sec. II.A) twisted up through Euler angles and quaternions
+ * (Eqs. 2.4-2.6), projected on the six LISA links (Eq. 2.8), combined into
+ * TDI 1.5 / 2.0 X, Y, Z (Eqs. 2.9-2.10) and A, E, T (Eq. 2.11), Fourier
+ * transformed and reduced to the PSD-weighted log-likelihood
+ * (Eqs. 2.12-2.13, with the PSD of Eqs. 2.14-2.15).
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns lt_status (0 on success, < 0 on error) and never
+ *    throws or aborts.  lt_last_error() returns a thread-local message for
+ *    the last failing call.
+ *  - "device" pointers are HIP device memory owned by the caller; the library
+ *    never frees caller memory.  Calls are asynchronous and ordered on the
+ *    given stream (0 = the null stream); outputs are valid once the stream
+ *    has been synchronised.  A context may be used by one host thread at a
+ *    time.
+ *  - Layouts are row-major.  params is FP64 [batch][16]:
+ *      0 m1, 1 m2 [solar masses, detector frame]
+ *      2-4 chi1 (x, y, z), 5-7 chi2 (x, y, z)  [dimensionless, L0 frame at f_ref]
+ *      8 D_L [Mpc], 9 iota, 10 phi_ref, 11 t_c [SSB time of the (2,2) peak, s],
+ *      12 lambda (ecliptic longitude), 13 beta (ecliptic latitude), 14 psi, 15 unused
+ *    (angles in radians).  Aligned-spin models use chi1z, chi2z only.
+ *  - Time series are [batch][3][n]; spectra [rows][n/2+1] complex interleaved.
+ *  - Host-checkable faults (null pointers, bad sizes, unsupported options)
+ *    return an error synchronously and launch nothing.  Domain faults of a
+ *    template (unphysical parameters) are reported per template in `status`
+ *    (1 = unphysical, 2 = non-finite result) and give logL = -inf.
+ */
+#ifndef LISATD_H
+#define LISATD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LT_OK = 0,
+  LT_ERR_NULL = -1,        /* a required pointer is null */
+  LT_ERR_SHAPE = -2,       /* batch / n / sizes out of range */
+  LT_ERR_CONFIG = -3,      /* inconsistent option values */
+  LT_ERR_UNSUPPORTED = -4, /* option outside what the library implements */
+  LT_ERR_DEVICE = -5,      /* HIP runtime or launch failure */
+  LT_ERR_WORKSPACE = -6    /* caller workspace too small */
+} lt_status;
+
+typedef struct lt_ctx lt_ctx;   /* opaque: FFT plans, twiddles, orbit tables, scratch */
+
+enum { LT_FP64 = 0, LT_MIXED = 1 };                         /* lt_wf_cfg.precision */
+enum { LT_ORBIT_STATIC_EQUAL = 0, LT_ORBIT_KEPLER = 1 };    /* lt_orbit.kind */
+enum { LT_CH_A = 1, LT_CH_E = 2, LT_CH_T = 4 };             /* lt_tdi_cfg.channels */
+enum { LT_MODE_22 = 1, LT_MODE_21 = 2, LT_MODE_33 = 4, LT_MODE_32 = 8, LT_MODE_44 = 16 };
+
+/* Uniform SSB time grid t_k = t0 + k dt, k = 0..n-1 (Sec. II.C: dt = 5 s). */
+typedef struct { double t0, dt; int64_t n; } lt_grid;
+
+/* Waveform options (Sec. II.A).  mode_mask: OR of LT_MODE_* (co-precessing
+ * modes with m > 0; m < 0 follow by symmetry).  precessing: 0 = aligned spins
+ * (IMRPhenomT / THM form), 1 = twisted-up precessing (TP / TPHM form).
+ * f_low: hard start of the (2,2) mode [Hz]; f_ref: reference frequency of the
+ * orbital phase and spins [Hz].  precision: LT_FP64 or LT_MIXED (phase and
+ * time FP64; stored polarisations, response, FFT FP32; reductions FP64). */
+typedef struct { int mode_mask; int precessing; double f_low, f_ref; int precision; } lt_wf_cfg;
+
+/* Spacecraft orbits (Sec. II.B).  STATIC_EQUAL: rigid equilateral triangle of
+ * side arm_m centred at (au_m, 0, 0), plane inclined 60 deg; KEPLER: three
+ * exact Keplerian ellipses (semi-major axis au_m, eccentricity
+ * arm_m / (2 sqrt(3) au_m), inclination sqrt(3) times that), mean anomalies
+ * offset by 2 pi/3, guiding centre at longitude phase0 at time t_ref. */
+typedef struct { int kind; double arm_m, au_m, phase0, t_ref; } lt_orbit;
+
+/* TDI options (Sec. II.B): generation 15 (Eq. 2.9) or 20 (Eq. 2.10);
+ * channels: OR of LT_CH_* used by the likelihood; taps: even Lagrange
+ * interpolation order K in {2, 4, 6, 8, 12, 16, 24, 32} (K = 2 is the paper's
+ * linear interpolation); out_xyz: 1 makes lt_lisa_tdi_response write X, Y, Z
+ * instead of A, E, T. */
+typedef struct { int generation; int channels; int taps; int out_xyz; } lt_tdi_cfg;
+
+/* One-sided PSD per channel (A, E, T), device FP64 [n/2+1] each, and the
+ * likelihood band [f_lo, f_hi] (Sec. II.C: 3e-4 .. 0.02 Hz). */
+typedef struct { const double* S[3]; double f_lo, f_hi; } lt_psd;
+
+/* Data (the zero-noise injection of Sec. II.C): device time series [3][n] of
+ * A, E, T in the precision's real type (double for LT_FP64, float for
+ * LT_MIXED), and dd = sum_c (d_c|d_c) in FP64 (see lt_noise_inner). */
+typedef struct { const void* aet; double dd; } lt_data;
+
+const char* lt_last_error(void);
+lt_status lt_ctx_create(int hip_device, lt_ctx** out);
+lt_status lt_ctx_destroy(lt_ctx* ctx);
+
+/* Co-precessing modes h_lm(t_k) for the modes in cfg->mode_mask (ascending bit
+ * order: 22, 21, 33, 32, 44), m > 0, zero before the f_low start (Sec. II.A).
+ * modes: device complex FP64 [batch][n_modes][n] interleaved (re, im).
+ * cfg->precision is ignored (always FP64). */
+lt_status lt_phenomt_modes(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                           const lt_grid* grid, double* modes, void* stream);
+
+/* Polarisations h+, hx on the grid via the single-sum twist-up of Eq. (2.4)
+ * with the composite quaternion of Eqs. (2.5)-(2.6), times exp(2 i psi).
+ * hpc: device FP64 [batch][2][n] (h+, then hx). */
+lt_status lt_phenomt_polarizations(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                                   const lt_grid* grid, double* hpc, void* stream);
+
+/* TDI response (Eqs. 2.7-2.11): link responses at the six links with delays
+ * along the orbit, K-tap Lagrange interpolation at delayed times, TDI X, Y, Z
+ * and A, E, T.  out: device [batch][3][n], double (LT_FP64) or float
+ * (LT_MIXED).  status: nullable device int32 [batch]. */
+lt_status lt_lisa_tdi_response(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                               const lt_grid* grid, const lt_orbit* orbit, const lt_tdi_cfg* tdi,
+                               void* out, int32_t* status, void* stream);
+
+/* Log-likelihood (Eq. 2.12 read with the sign of its footnote):
+ *   logl[b]      = sum_c [(d_c|h_c) - (h_c|h_c)/2]
+ *   logl_full[b] = -1/2 sum_c (h_c - d_c | h_c - d_c) = logl[b] - dd/2
+ * with (a|b) = 4 df Re sum_{band} a~ conj(b~) / S (Eq. 2.13), a~ = dt * DFT.
+ * Computed as -(r|r)/2 + dd/2 with the residual r = h - d formed in the time
+ * domain.  logl, logl_full (nullable): device FP64 [batch]; status (nullable):
+ * device int32 [batch].  Scratch memory is owned by the context. */
+lt_status lt_tdi_loglike(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                         const lt_grid* grid, const lt_orbit* orbit, const lt_tdi_cfg* tdi,
+                         const lt_psd* psd, const lt_data* data, double* logl, double* logl_full,
+                         int32_t* status, void* stream);
+
+/* sum over the enabled channels of (x_c|x_c) (Eq. 2.13) for time series x
+ * [batch][3][n] (double if precision == LT_FP64, else float); out: device FP64
+ * [batch].  With x = the injection this is (d|d) = SNR^2. */
+lt_status lt_noise_inner(lt_ctx* ctx, const void* x, int64_t batch, const lt_grid* grid, const lt_psd* psd,
+                         int channels, int precision, double* out, void* stream);
+
+/* Real-to-complex FFT times dt of rows [rows][n] (double or float by
+ * precision) into spectra [rows][n/2+1] complex (same real type).  n must be
+ * even with n/2 = n1 * n2, n1, n2 <= 1024 built from the radices 2, 3, 4, 5, 8. */
+lt_status lt_rfft(lt_ctx* ctx, const void* x, int64_t rows, int64_t n, double dt, int precision, void* spec,
+                  void* stream);
+
+/* Analytic PSD of Eqs. (2.14)-(2.15) (readings: x = 2 pi f L / c,
+ * acceleration noise 2.4e-15 m s^-2 / sqrt(Hz), TDI 2.0 factor 4 sin^2(2x)) on
+ * the rfft grid of `grid`; bin 0 is set to +inf.  S: device FP64 [3][n/2+1]. */
+lt_status lt_psd_sangria(const lt_grid* grid, int generation, double arm_m, double* S, void* stream);
+
+/* Per-kernel timing for benchmarks: when enabled, the library records HIP
+ * events around each launch on the launch stream.  lt_profile_read returns,
+ * for kernel class k (0 waveform/setup, 1 response, 2 fft pass 1,
+ * 3 fft pass 2 + band reduction, 4 finalize), the summed milliseconds and
+ * launch counts since the last reset (it synchronises the recorded events). */
+lt_status lt_profile_enable(lt_ctx* ctx, int on);
+lt_status lt_profile_read(lt_ctx* ctx, double* ms, int64_t* launches, int n_classes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

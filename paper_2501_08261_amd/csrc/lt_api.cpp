@@ -1,0 +1,661 @@
+// liblisatd host side: context, validation, FFT plans, orbit node tables, TDI
+// term tables and the extern "C" entry points declared in include/lisatd.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lisatd.h"
+#include "lt_kernels.hpp"
+
+using namespace lt;
+
+static thread_local std::string g_err;
+
+static lt_status fail(lt_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define LT_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(LT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------ buffers
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      bytes = 0;
+    }
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+};
+
+struct Plan {
+  FftPlanDev dev{};
+  DevBuf tw1d, tw1f, tw2d, tw2f, wlod, wlof, whid, whif;
+};
+
+struct OrbitTab {
+  DevBuf tab;
+  OrbitDev dev{};
+};
+
+struct lt_ctx {
+  int device = 0;
+  std::map<int64_t, std::unique_ptr<Plan>> plans;
+  std::map<std::tuple<int, double, double, double, double, double, double, int64_t>, std::unique_ptr<OrbitTab>> orbits;
+  DevBuf tpl, work, partial, wperm, status;
+  bool profiling = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  double prof_ms[8] = {0};
+  int64_t prof_n[8] = {0};
+};
+
+// Events bracket a launch on its stream when profiling is on.
+struct Prof {
+  lt_ctx* c;
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  Prof(lt_ctx* c_, int cls_, hipStream_t s_) : c(c_), cls(cls_), s(s_) {
+    if (c->profiling) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, s);
+    }
+  }
+  ~Prof() {
+    if (c->profiling) {
+      (void)hipEventRecord(b, s);
+      c->recs.push_back({cls, a, b});
+    }
+  }
+};
+
+static void drain_profile(lt_ctx* c) {
+  for (auto& r : c->recs) {
+    (void)hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof_ms[r.cls] += ms;
+      c->prof_n[r.cls] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  c->recs.clear();
+}
+
+// ------------------------------------------------------------------ FFT plan
+static bool radices(int L, int* rad, int* nr) {
+  int k = 0;
+  while (L % 5 == 0) { rad[k++] = 5; L /= 5; }
+  while (L % 3 == 0) { rad[k++] = 3; L /= 3; }
+  int a = 0;
+  while (L % 2 == 0) { ++a; L /= 2; }
+  if (L != 1) return false;
+  int p = a / 3, r = a % 3;
+  if (r == 1 && p >= 1) { p -= 1; rad[k++] = 4; rad[k++] = 4; }
+  else if (r == 1) rad[k++] = 2;
+  else if (r == 2) rad[k++] = 4;
+  for (int i = 0; i < p; ++i) rad[k++] = 8;
+  if (k > 12) return false;
+  *nr = k;
+  return true;
+}
+
+static void host_tw(std::vector<double>& d, int64_t count, int64_t stride, int64_t N) {
+  d.resize(2 * count);
+  for (int64_t k = 0; k < count; ++k) {
+    int64_t m = (k * stride) % N;
+    double ang = -2.0 * M_PI * (double)m / (double)N;
+    d[2 * k] = std::cos(ang);
+    d[2 * k + 1] = std::sin(ang);
+  }
+}
+
+static hipError_t upload(DevBuf& dd, DevBuf& df, const std::vector<double>& h) {
+  hipError_t e = dd.ensure(h.size() * sizeof(double));
+  if (e != hipSuccess) return e;
+  e = df.ensure(h.size() * sizeof(float));
+  if (e != hipSuccess) return e;
+  std::vector<float> f(h.begin(), h.end());
+  e = hipMemcpy(dd.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(df.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
+}
+
+static lt_status get_plan(lt_ctx* c, int64_t N, Plan** out) {
+  auto it = c->plans.find(N);
+  if (it != c->plans.end()) {
+    *out = it->second.get();
+    return LT_OK;
+  }
+  if (N < 8 || N % 2 != 0) return fail(LT_ERR_SHAPE, "FFT length must be even and >= 8");
+  int64_t n = N / 2;
+  int best1 = -1, best2 = -1;
+  double bestscore = 1e300;
+  for (int64_t d = 2; d <= 1024; d += 2) {
+    if (n % d) continue;
+    int64_t e = n / d;
+    if (e > 1024 || e < 1) continue;
+    int r[12], nr;
+    if (!radices((int)d, r, &nr) || !radices((int)e, r, &nr)) continue;
+    double score = std::fabs(std::log((double)d) - std::log((double)e)) + (e < d ? 1e-3 : 0.0);
+    if (score < bestscore) { bestscore = score; best1 = (int)d; best2 = (int)e; }
+  }
+  if (best1 < 0)
+    return fail(LT_ERR_UNSUPPORTED, "N/2 must factor as n1*n2 (n1 even, both <= 1024) over radices 2,3,5");
+  auto p = std::make_unique<Plan>();
+  FftPlanDev& d = p->dev;
+  d.N = N;
+  d.n = n;
+  d.n1 = best1;
+  d.n2 = best2;
+  radices(d.n1, d.rad1, &d.nr1);
+  radices(d.n2, d.rad2, &d.nr2);
+  std::vector<double> h;
+  host_tw(h, d.n1, 1, d.n1);
+  LT_HIP(upload(p->tw1d, p->tw1f, h));
+  host_tw(h, d.n2, 1, d.n2);
+  LT_HIP(upload(p->tw2d, p->tw2f, h));
+  host_tw(h, 1024, 1, N);
+  LT_HIP(upload(p->wlod, p->wlof, h));
+  host_tw(h, N / 1024 + 2, 1024, N);
+  LT_HIP(upload(p->whid, p->whif, h));
+  d.tw1d = (const double*)p->tw1d.p; d.tw1f = (const float*)p->tw1f.p;
+  d.tw2d = (const double*)p->tw2d.p; d.tw2f = (const float*)p->tw2f.p;
+  d.wlod = (const double*)p->wlod.p; d.wlof = (const float*)p->wlof.p;
+  d.whid = (const double*)p->whid.p; d.whif = (const float*)p->whif.p;
+  *out = p.get();
+  c->plans[N] = std::move(p);
+  return LT_OK;
+}
+
+// ------------------------------------------------------------------ orbits
+static const int kLinkLabel[6] = {1, 2, 3, -1, -2, -3};
+
+static void link_ends(int l, int* s, int* r) {
+  int k = l > 0 ? l : -l;
+  int a = (k + 1) % 3 + 1, b = k % 3 + 1;
+  if (l > 0) { *s = a; *r = b; } else { *s = b; *r = a; }
+}
+
+static void sc_position(const lt_orbit& o, int k, double t, double* r) {
+  const double sig = 2.0 * M_PI * (k - 1) / 3.0;
+  if (o.kind == LT_ORBIT_STATIC_EQUAL) {
+    const double rho = o.arm_m / std::sqrt(3.0);
+    const double cs = std::cos(sig), sn = std::sin(sig);
+    r[0] = o.au_m + rho * cs * 0.5;
+    r[1] = rho * sn;
+    r[2] = rho * cs * (std::sqrt(3.0) / 2.0);
+    return;
+  }
+  const double e = o.arm_m / (2.0 * std::sqrt(3.0) * o.au_m);
+  const double inc = std::sqrt(3.0) * e;
+  const double Om = 2.0 * M_PI / kYear;
+  const double M = Om * (t - o.t_ref) + o.phase0 - sig;
+  double E = M;
+  for (int i = 0; i < 50; ++i) {
+    double dE = (E - e * std::sin(E) - M) / (1.0 - e * std::cos(E));
+    E -= dE;
+    if (std::fabs(dE) < 1e-17) break;
+  }
+  const double xo = o.au_m * (std::cos(E) - e);
+  const double yo = o.au_m * std::sqrt(1.0 - e * e) * std::sin(E);
+  const double x1 = xo * std::cos(inc), z1 = xo * std::sin(inc);
+  const double cs = std::cos(sig), sn = std::sin(sig);
+  r[0] = cs * x1 - sn * yo;
+  r[1] = sn * x1 + cs * yo;
+  r[2] = z1;
+}
+
+static double light_time(const lt_orbit& o, int l, double t, double* rr, double* rs) {
+  int s, r;
+  link_ends(l, &s, &r);
+  sc_position(o, r, t, rr);
+  if (o.kind == LT_ORBIT_STATIC_EQUAL) {
+    sc_position(o, s, t, rs);
+    return o.arm_m / kC;
+  }
+  sc_position(o, s, t, rs);
+  double L = std::sqrt((rr[0] - rs[0]) * (rr[0] - rs[0]) + (rr[1] - rs[1]) * (rr[1] - rs[1]) +
+                       (rr[2] - rs[2]) * (rr[2] - rs[2])) / kC;
+  for (int i = 0; i < 20; ++i) {
+    sc_position(o, s, t - L, rs);
+    double Ln = std::sqrt((rr[0] - rs[0]) * (rr[0] - rs[0]) + (rr[1] - rs[1]) * (rr[1] - rs[1]) +
+                          (rr[2] - rs[2]) * (rr[2] - rs[2])) / kC;
+    bool done = std::fabs(Ln - L) < 1e-15;
+    L = Ln;
+    if (done) break;
+  }
+  sc_position(o, s, t - L, rs);
+  return L;
+}
+
+static constexpr int kNodeSpacing = 256;
+static constexpr int kNodeJ0 = 2;
+
+static lt_status get_orbit(lt_ctx* c, const lt_orbit* o, const lt_grid* g, OrbitDev* out) {
+  auto key = std::make_tuple(o->kind, o->arm_m, o->au_m, o->phase0, o->t_ref, g->t0, g->dt, (int64_t)g->n);
+  auto it = c->orbits.find(key);
+  if (it != c->orbits.end()) {
+    *out = it->second->dev;
+    return LT_OK;
+  }
+  const int64_t ntile = (g->n + tdi_tile() - 1) / tdi_tile();
+  const int64_t last = ntile * tdi_tile() - 1;
+  const int n_nodes = (int)(last / kNodeSpacing + 3 + kNodeJ0 + 2);
+  std::vector<double> tab((size_t)n_nodes * kNodeStride);
+  double maxL = 0.0;
+  for (int j = 0; j < n_nodes; ++j) {
+    double t = g->t0 + (double)((int64_t)(j - kNodeJ0) * kNodeSpacing) * g->dt;
+    for (int li = 0; li < 6; ++li) {
+      double rr[3], rs[3];
+      double L = light_time(*o, kLinkLabel[li], t, rr, rs);
+      double d[3] = {rr[0] - rs[0], rr[1] - rs[1], rr[2] - rs[2]};
+      double nn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double* e = tab.data() + (size_t)j * kNodeStride + li * kNodeLink;
+      e[0] = L;
+      for (int q = 0; q < 3; ++q) {
+        e[1 + q] = rr[q] / kC;
+        e[4 + q] = rs[q] / kC;
+        e[7 + q] = d[q] / nn;
+      }
+      maxL = std::fmax(maxL, L);
+    }
+  }
+  auto ot = std::make_unique<OrbitTab>();
+  LT_HIP(ot->tab.ensure(tab.size() * sizeof(double)));
+  LT_HIP(hipMemcpy(ot->tab.p, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
+  ot->dev.tab = (const double*)ot->tab.p;
+  ot->dev.n_nodes = n_nodes;
+  ot->dev.j0 = kNodeJ0;
+  ot->dev.spacing = kNodeSpacing;
+  ot->dev.max_light_time = maxL;
+  *out = ot->dev;
+  c->orbits[key] = std::move(ot);
+  return LT_OK;
+}
+
+// ------------------------------------------------------------ TDI term tables
+struct HostTerm { int sign, link; std::vector<int> delays; };
+
+// Michelson X: Eq. (2.9) (generation 1.5) and Eq. (2.10) (generation 2.0, with
+// the eleventh delay read as 2L-2 + L2 + 2L3 + 2L-3).
+static std::vector<HostTerm> x_terms(int gen) {
+  std::vector<HostTerm> v = {{+1, -3, {3, 2, -2}}, {-1, -3, {3}}};
+  if (gen == 20) {
+    v.push_back({+1, -3, {-2, 2, 3, 3, -3}});
+    v.push_back({-1, -3, {3, 3, -3, -2, -2, 2, 2}});
+  }
+  v.push_back({+1, 3, {2, -2}});
+  v.push_back({-1, 3, {}});
+  if (gen == 20) {
+    v.push_back({+1, 3, {-2, 2, 3, -3}});
+    v.push_back({-1, 3, {3, -3, -2, -2, 2, 2}});
+  }
+  v.push_back({+1, 2, {-2}});
+  v.push_back({-1, 2, {-2, -3, 3}});
+  if (gen == 20) {
+    v.push_back({+1, 2, {-2, -2, 2, 3, 3, -3, -3}});
+    v.push_back({-1, 2, {3, -3, -2, -2, 2}});
+  }
+  v.push_back({+1, -2, {}});
+  v.push_back({-1, -2, {-3, 3}});
+  if (gen == 20) {
+    v.push_back({+1, -2, {-2, 2, 3, 3, -3, -3}});
+    v.push_back({-1, -2, {3, -3, -2, 2}});
+  }
+  return v;
+}
+
+static int rot_label(int l, int times) {
+  int s = l > 0 ? 1 : -1, k = l > 0 ? l : -l;
+  for (int i = 0; i < times; ++i) k = k % 3 + 1;
+  return s * k;
+}
+
+static int link_index(int l) {
+  for (int i = 0; i < 6; ++i)
+    if (kLinkLabel[i] == l) return i;
+  return -1;
+}
+
+static TermTable make_terms(int gen) {
+  TermTable T;
+  std::memset(&T, 0, sizeof(T));
+  auto xs = x_terms(gen);
+  for (int ch = 0; ch < 3; ++ch) {
+    T.n_terms[ch] = (int)xs.size();
+    for (size_t i = 0; i < xs.size(); ++i) {
+      Term& t = T.t[ch][i];
+      t.sign = xs[i].sign;
+      t.link = link_index(rot_label(xs[i].link, ch));
+      for (int d : xs[i].delays) t.cnt[link_index(rot_label(d, ch))] += 1;
+    }
+  }
+  return T;
+}
+
+// ------------------------------------------------------------------ checks
+static lt_status check_common(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g) {
+  if (!c) return fail(LT_ERR_NULL, "null context");
+  if (!params) return fail(LT_ERR_NULL, "null params");
+  if (!cfg || !g) return fail(LT_ERR_NULL, "null config or grid");
+  if (batch < 1 || batch > 65535) return fail(LT_ERR_SHAPE, "batch must be in [1, 65535]");
+  if (g->n < 8 || g->n > ((int64_t)1 << 26)) return fail(LT_ERR_SHAPE, "grid n must be in [8, 2^26]");
+  if (!(g->dt > 0.0) || !std::isfinite(g->t0)) return fail(LT_ERR_SHAPE, "bad grid t0 / dt");
+  if (cfg->mode_mask <= 0 || cfg->mode_mask > 31) return fail(LT_ERR_CONFIG, "mode_mask must be a nonzero subset of 31");
+  if (cfg->precessing != 0 && cfg->precessing != 1) return fail(LT_ERR_CONFIG, "precessing must be 0 or 1");
+  if (cfg->precision != LT_FP64 && cfg->precision != LT_MIXED) return fail(LT_ERR_CONFIG, "bad precision");
+  if (!(cfg->f_low > 0.0) || !(cfg->f_ref > 0.0)) return fail(LT_ERR_CONFIG, "f_low and f_ref must be positive");
+  LT_HIP(hipSetDevice(c->device));
+  return LT_OK;
+}
+
+static lt_status check_tdi(const lt_orbit* o, const lt_tdi_cfg* t, const lt_grid* g) {
+  if (!o || !t) return fail(LT_ERR_NULL, "null orbit or tdi config");
+  if (o->kind != LT_ORBIT_STATIC_EQUAL && o->kind != LT_ORBIT_KEPLER) return fail(LT_ERR_UNSUPPORTED, "orbit kind");
+  if (!(o->arm_m > 0.0) || !(o->au_m > 0.0) || o->arm_m > 0.1 * o->au_m) return fail(LT_ERR_CONFIG, "bad arm / au");
+  if (t->generation != 15 && t->generation != 20) return fail(LT_ERR_CONFIG, "generation must be 15 or 20");
+  int K = t->taps;
+  if (!(K == 2 || K == 4 || K == 6 || K == 8 || K == 12 || K == 16 || K == 24 || K == 32))
+    return fail(LT_ERR_UNSUPPORTED, "taps must be one of 2,4,6,8,12,16,24,32");
+  if (t->channels <= 0 || t->channels > 7) return fail(LT_ERR_CONFIG, "channels must be a nonzero subset of A|E|T");
+  double HY = 7.0 * (o->arm_m * 1.01 / kC) / g->dt + K / 2 + 3;
+  if (HY > kNodeSpacing - 8) return fail(LT_ERR_UNSUPPORTED, "dt too small for the TDI halo");
+  return LT_OK;
+}
+
+static GridDev gdev(const lt_grid* g) { return GridDev{g->t0, g->dt, 1.0 / g->dt, g->n}; }
+
+static lt_status do_setup(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                          int32_t* status, hipStream_t s) {
+  LT_HIP(c->tpl.ensure((size_t)batch * sizeof(TplConst)));
+  Prof pr(c, 0, s);
+  LT_HIP(launch_setup(params, batch, cfg->f_low, cfg->f_ref, gdev(g), (TplConst*)c->tpl.p, status, s));
+  return LT_OK;
+}
+
+// ------------------------------------------------------------------ API
+extern "C" {
+
+const char* lt_last_error(void) { return g_err.c_str(); }
+
+lt_status lt_ctx_create(int hip_device, lt_ctx** out) {
+  if (!out) return fail(LT_ERR_NULL, "null output pointer");
+  int n = 0;
+  LT_HIP(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n) return fail(LT_ERR_CONFIG, "no such HIP device");
+  LT_HIP(hipSetDevice(hip_device));
+  lt_ctx* c = new lt_ctx();
+  c->device = hip_device;
+  *out = c;
+  return LT_OK;
+}
+
+lt_status lt_ctx_destroy(lt_ctx* c) {
+  if (!c) return fail(LT_ERR_NULL, "null context");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  drain_profile(c);
+  delete c;
+  return LT_OK;
+}
+
+lt_status lt_phenomt_modes(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                           double* modes, void* stream) {
+  lt_status st = check_common(c, params, batch, cfg, g);
+  if (st) return st;
+  if (!modes) return fail(LT_ERR_NULL, "null modes");
+  hipStream_t s = (hipStream_t)stream;
+  st = do_setup(c, params, batch, cfg, g, nullptr, s);
+  if (st) return st;
+  Prof pr(c, 0, s);
+  LT_HIP(launch_modes((TplConst*)c->tpl.p, batch, cfg->mode_mask, gdev(g), modes, s));
+  return LT_OK;
+}
+
+lt_status lt_phenomt_polarizations(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                                   const lt_grid* g, double* hpc, void* stream) {
+  lt_status st = check_common(c, params, batch, cfg, g);
+  if (st) return st;
+  if (!hpc) return fail(LT_ERR_NULL, "null output");
+  hipStream_t s = (hipStream_t)stream;
+  st = do_setup(c, params, batch, cfg, g, nullptr, s);
+  if (st) return st;
+  Prof pr(c, 0, s);
+  LT_HIP(launch_polarizations((TplConst*)c->tpl.p, batch, cfg->mode_mask, cfg->precessing, gdev(g), hpc, s));
+  return LT_OK;
+}
+
+static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                         const lt_orbit* o, const lt_tdi_cfg* t, int out_mode, const void* data, void* out,
+                         int32_t* status, hipStream_t s) {
+  OrbitDev od;
+  lt_status st = get_orbit(c, o, g, &od);
+  if (st) return st;
+  st = do_setup(c, params, batch, cfg, g, status, s);
+  if (st) return st;
+  TdiLaunch L;
+  L.tc = (const TplConst*)c->tpl.p;
+  L.batch = batch;
+  L.mode_mask = cfg->mode_mask;
+  L.precessing = cfg->precessing;
+  L.taps = t->taps;
+  L.precision = cfg->precision;
+  L.out_mode = out_mode;
+  L.g = gdev(g);
+  L.orb = od;
+  L.terms = make_terms(t->generation);
+  L.data = data;
+  L.out = out;
+  L.status = status;
+  Prof pr(c, 1, s);
+  LT_HIP(launch_tdi(L, s));
+  return LT_OK;
+}
+
+lt_status lt_lisa_tdi_response(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                               const lt_orbit* o, const lt_tdi_cfg* t, void* out, int32_t* status, void* stream) {
+  lt_status st = check_common(c, params, batch, cfg, g);
+  if (st) return st;
+  st = check_tdi(o, t, g);
+  if (st) return st;
+  if (!out) return fail(LT_ERR_NULL, "null output");
+  return run_tdi(c, params, batch, cfg, g, o, t, t->out_xyz ? 1 : 0, nullptr, out, status, (hipStream_t)stream);
+}
+
+static lt_status band_bins(const lt_grid* g, const lt_psd* psd, int* k_lo, int* k_hi) {
+  const double T = (double)g->n * g->dt;
+  const double slack = 1e-12;
+  int64_t lo = (int64_t)std::ceil(psd->f_lo * T * (1.0 - slack));
+  int64_t hi = (int64_t)std::floor(psd->f_hi * T * (1.0 + slack));
+  if (lo < 0) lo = 0;
+  if (hi > g->n / 2) hi = g->n / 2;
+  if (!(psd->f_hi > psd->f_lo) || hi < lo) return fail(LT_ERR_CONFIG, "empty likelihood band");
+  *k_lo = (int)lo;
+  *k_hi = (int)hi;
+  return LT_OK;
+}
+
+// FFT both passes over rows of [rows][n] (in place), band power into partials
+static lt_status band_power(lt_ctx* c, Plan* p, void* series, int64_t rows, int precision, const lt_psd* psd,
+                            const lt_grid* g, int channels, hipStream_t s) {
+  int k_lo, k_hi;
+  lt_status st = band_bins(g, psd, &k_lo, &k_hi);
+  if (st) return st;
+  const int64_t n = p->dev.n;
+  LT_HIP(c->wperm.ensure((size_t)3 * (n + 1) * sizeof(double)));
+  LT_HIP(c->partial.ensure((size_t)rows * (p->dev.n1 / 2 + 1) * sizeof(double)));
+  {
+    Prof pr(c, 3, s);
+    LT_HIP(launch_weights(p->dev, psd->S, k_lo, k_hi, channels, (double*)c->wperm.p, s));
+  }
+  {
+    Prof pr(c, 2, s);
+    LT_HIP(launch_fft_pass1(p->dev, series, rows, precision, s));
+  }
+  {
+    Prof pr(c, 3, s);
+    LT_HIP(launch_fft_pass2(p->dev, series, rows, precision, 1, g->dt, nullptr, (const double*)c->wperm.p, 3,
+                            (double*)c->partial.p, s));
+  }
+  return LT_OK;
+}
+
+lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                         const lt_orbit* o, const lt_tdi_cfg* t, const lt_psd* psd, const lt_data* data, double* logl,
+                         double* logl_full, int32_t* status, void* stream) {
+  lt_status st = check_common(c, params, batch, cfg, g);
+  if (st) return st;
+  st = check_tdi(o, t, g);
+  if (st) return st;
+  if (!psd || !psd->S[0] || !psd->S[1] || !psd->S[2]) return fail(LT_ERR_NULL, "null PSD");
+  if (!data || !data->aet) return fail(LT_ERR_NULL, "null data");
+  if (!logl && !logl_full) return fail(LT_ERR_NULL, "no output requested");
+  hipStream_t s = (hipStream_t)stream;
+  Plan* p;
+  st = get_plan(c, g->n, &p);
+  if (st) return st;
+  const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
+  LT_HIP(c->work.ensure((size_t)batch * 3 * g->n * rsz));
+  int32_t* stat = status;
+  if (!stat) {
+    LT_HIP(c->status.ensure((size_t)batch * sizeof(int32_t)));
+    stat = (int32_t*)c->status.p;
+  }
+  st = run_tdi(c, params, batch, cfg, g, o, t, 2, data->aet, c->work.p, stat, s);
+  if (st) return st;
+  st = band_power(c, p, c->work.p, batch * 3, cfg->precision, psd, g, t->channels, s);
+  if (st) return st;
+  Prof pr(c, 4, s);
+  LT_HIP(launch_finalize((const double*)c->partial.p, batch, p->dev.n1 / 2 + 1, 4.0 * g->dt / (double)g->n, data->dd,
+                         stat, logl, logl_full, nullptr, s));
+  return LT_OK;
+}
+
+lt_status lt_noise_inner(lt_ctx* c, const void* x, int64_t batch, const lt_grid* g, const lt_psd* psd, int channels,
+                         int precision, double* out, void* stream) {
+  if (!c) return fail(LT_ERR_NULL, "null context");
+  if (!x || !g || !psd || !out || !psd->S[0] || !psd->S[1] || !psd->S[2]) return fail(LT_ERR_NULL, "null argument");
+  if (batch < 1 || batch > 65535) return fail(LT_ERR_SHAPE, "batch must be in [1, 65535]");
+  if (precision != LT_FP64 && precision != LT_MIXED) return fail(LT_ERR_CONFIG, "bad precision");
+  if (channels <= 0 || channels > 7) return fail(LT_ERR_CONFIG, "bad channels");
+  LT_HIP(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  Plan* p;
+  lt_status st = get_plan(c, g->n, &p);
+  if (st) return st;
+  const size_t rsz = precision == LT_FP64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = (size_t)batch * 3 * g->n * rsz;
+  LT_HIP(c->work.ensure(bytes));
+  LT_HIP(hipMemcpyAsync(c->work.p, x, bytes, hipMemcpyDeviceToDevice, s));
+  st = band_power(c, p, c->work.p, batch * 3, precision, psd, g, channels, s);
+  if (st) return st;
+  Prof pr(c, 4, s);
+  LT_HIP(launch_finalize((const double*)c->partial.p, batch, p->dev.n1 / 2 + 1, 4.0 * g->dt / (double)g->n, 0.0,
+                         nullptr, nullptr, nullptr, out, s));
+  return LT_OK;
+}
+
+lt_status lt_rfft(lt_ctx* c, const void* x, int64_t rows, int64_t n, double dt, int precision, void* spec,
+                  void* stream) {
+  if (!c) return fail(LT_ERR_NULL, "null context");
+  if (!x || !spec) return fail(LT_ERR_NULL, "null argument");
+  if (rows < 1 || rows > 65535) return fail(LT_ERR_SHAPE, "rows must be in [1, 65535]");
+  if (precision != LT_FP64 && precision != LT_MIXED) return fail(LT_ERR_CONFIG, "bad precision");
+  LT_HIP(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  Plan* p;
+  lt_status st = get_plan(c, n, &p);
+  if (st) return st;
+  const size_t rsz = precision == LT_FP64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = (size_t)rows * n * rsz;
+  LT_HIP(c->work.ensure(bytes));
+  LT_HIP(hipMemcpyAsync(c->work.p, x, bytes, hipMemcpyDeviceToDevice, s));
+  {
+    Prof pr(c, 2, s);
+    LT_HIP(launch_fft_pass1(p->dev, c->work.p, rows, precision, s));
+  }
+  Prof pr(c, 3, s);
+  LT_HIP(launch_fft_pass2(p->dev, c->work.p, rows, precision, 0, dt, spec, nullptr, 3, nullptr, s));
+  return LT_OK;
+}
+
+lt_status lt_psd_sangria(const lt_grid* g, int generation, double arm_m, double* S, void* stream) {
+  if (!g || !S) return fail(LT_ERR_NULL, "null argument");
+  if (g->n < 8 || !(g->dt > 0.0)) return fail(LT_ERR_SHAPE, "bad grid");
+  if (generation != 15 && generation != 20) return fail(LT_ERR_CONFIG, "generation must be 15 or 20");
+  const int64_t nb = g->n / 2 + 1;
+  std::vector<double> h(3 * nb);
+  for (int64_t k = 0; k < nb; ++k) {
+    if (k == 0) {
+      h[k] = h[nb + k] = h[2 * nb + k] = INFINITY;
+      continue;
+    }
+    double f = (double)k / ((double)g->n * g->dt);
+    double x = 2.0 * M_PI * f * arm_m / kC;
+    double w = 2.0 * M_PI * f / kC;
+    double sacc = 2.4e-15 * 2.4e-15 * (1.0 + std::pow(4e-4 / f, 2)) * (1.0 + std::pow(f / 8e-3, 4)) *
+                  std::pow(2.0 * M_PI * f, -4) * w * w;
+    double sop = 7.9e-12 * 7.9e-12 * (1.0 + std::pow(2e-3 / f, 4)) * w * w;
+    double s2 = std::sin(x) * std::sin(x);
+    double ae = 8.0 * s2 * (2.0 * sacc * (3.0 + 2.0 * std::cos(x) + std::cos(2.0 * x)) + sop * (2.0 + std::cos(x)));
+    double tt = 16.0 * sop * (1.0 - std::cos(x)) * s2 + 128.0 * sacc * s2 * std::pow(std::sin(0.5 * x), 4);
+    if (generation == 20) {
+      double f2 = 4.0 * std::sin(2.0 * x) * std::sin(2.0 * x);
+      ae *= f2;
+      tt *= f2;
+    }
+    h[k] = ae;
+    h[nb + k] = ae;
+    h[2 * nb + k] = tt;
+  }
+  LT_HIP(hipMemcpyAsync(S, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, (hipStream_t)stream));
+  LT_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return LT_OK;
+}
+
+lt_status lt_profile_enable(lt_ctx* c, int on) {
+  if (!c) return fail(LT_ERR_NULL, "null context");
+  c->profiling = on != 0;
+  return LT_OK;
+}
+
+lt_status lt_profile_read(lt_ctx* c, double* ms, int64_t* launches, int n_classes) {
+  if (!c || !ms || !launches) return fail(LT_ERR_NULL, "null argument");
+  drain_profile(c);
+  for (int i = 0; i < n_classes && i < 8; ++i) {
+    ms[i] = c->prof_ms[i];
+    launches[i] = c->prof_n[i];
+    c->prof_ms[i] = 0.0;
+    c->prof_n[i] = 0;
+  }
+  return LT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// Batched real-to-complex FFT (hot-path step a9) and the band-limited inner
+// products / log-likelihood (a10).
+//
+// A real series of length N is read as n = N/2 complex samples
+// z_j = x_{2j} + i x_{2j+1}.  The length-n complex DFT is done in two passes
+// (four-step, n = n1 * n2, j = n2 j1 + j2, k = k1 + n1 k2):
+//   pass 1: for each column j2, a length-n1 DFT over j1, times exp(-2 pi i j2 k1 / n);
+//   pass 2: for each row k1, a length-n2 DFT over j2 -> Z_{k1 + n1 k2}.
+// Sub-DFTs run in LDS as mixed-radix (2, 3, 4, 5, 8) Stockham autosort stages.
+// Pass 2 works on the row pair (k1, n1 - k1), which holds every mirror pair
+// (k, n - k) needed to untangle the real transform:
+//   X_k = (Z_k + conj Z_{n-k})/2 - (i/2) exp(-2 pi i k / N) (Z_k - conj Z_{n-k}),
+// and either writes X_k * dt or accumulates sum_band |X_k|^2 / S_k in FP64.
+#include "lt_kernels.hpp"
+
+namespace lt {
+
+constexpr int kFT = 256;
+
+template <typename R> struct C2 { R x, y; };
+template <typename R> __device__ inline C2<R> operator+(C2<R> a, C2<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R> __device__ inline C2<R> operator-(C2<R> a, C2<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R> __device__ inline C2<R> cm(C2<R> a, C2<R> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename R> __device__ inline C2<R> mi(C2<R> a) { return {a.y, -a.x}; }   // -i a
+template <typename R> __device__ inline C2<R> sc(C2<R> a, R s) { return {a.x * s, a.y * s}; }
+
+template <typename R> __device__ inline const R* tw_ptr(const double* d, const float* f);
+template <> __device__ inline const double* tw_ptr<double>(const double* d, const float*) { return d; }
+template <> __device__ inline const float* tw_ptr<float>(const double*, const float* f) { return f; }
+
+// forward DFT of size RAD in registers
+template <typename R, int RAD> __device__ inline void dft(C2<R>* v);
+template <typename R> __device__ inline void dft2(C2<R>* v) {
+  C2<R> a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+template <typename R, int RAD> __device__ inline void dft(C2<R>* v) {
+  if constexpr (RAD == 2) {
+    dft2(v);
+  } else if constexpr (RAD == 3) {
+    const R s1 = (R)0.86602540378443864676;
+    C2<R> t1 = v[1] + v[2], t2 = v[0] - sc(t1, (R)0.5), t3 = sc(mi(v[1] - v[2]), s1);
+    v[0] = v[0] + t1;
+    v[1] = t2 + t3;
+    v[2] = t2 - t3;
+  } else if constexpr (RAD == 4) {
+    C2<R> a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3], d = mi(v[1] - v[3]);
+    v[0] = a + c;
+    v[2] = a - c;
+    v[1] = b + d;
+    v[3] = b - d;
+  } else if constexpr (RAD == 5) {
+    const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
+    const R s1 = (R)0.95105651629515357212, s2 = (R)0.58778525229247312917;
+    C2<R> a1 = v[1] + v[4], a2 = v[2] + v[3], b1 = v[1] - v[4], b2 = v[2] - v[3];
+    C2<R> x0 = v[0];
+    C2<R> p1 = x0 + sc(a1, c1) + sc(a2, c2), p2 = x0 + sc(a1, c2) + sc(a2, c1);
+    C2<R> q1 = mi(sc(b1, s1) + sc(b2, s2)), q2 = mi(sc(b1, s2) - sc(b2, s1));
+    v[0] = x0 + a1 + a2;
+    v[1] = p1 + q1;
+    v[4] = p1 - q1;
+    v[2] = p2 + q2;
+    v[3] = p2 - q2;
+  } else if constexpr (RAD == 8) {
+    C2<R> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<R, 4>(e);
+    dft<R, 4>(o);
+    const R h = (R)0.70710678118654752440;
+    C2<R> w1 = {h, -h}, w3 = {-h, -h};
+    C2<R> t0 = o[0], t1 = cm(o[1], w1), t2 = mi(o[2]), t3 = cm(o[3], w3);
+    v[0] = e[0] + t0; v[4] = e[0] - t0;
+    v[1] = e[1] + t1; v[5] = e[1] - t1;
+    v[2] = e[2] + t2; v[6] = e[2] - t2;
+    v[3] = e[3] + t3; v[7] = e[3] - t3;
+  }
+}
+
+// One Stockham stage of radix RAD over `nfft` transforms of length L held in
+// src (row-major [nfft][L]); writes dst.  tw: exp(-2 pi i k / L), k < L.
+template <typename R, int RAD>
+__device__ inline void stage(const C2<R>* src, C2<R>* dst, int L, int Ns, int nfft, const C2<R>* tw) {
+  const int m = L / RAD;
+  const int jobs = nfft * m;
+  const int step = L / (Ns * RAD);
+  for (int job = threadIdx.x; job < jobs; job += kFT) {
+    int f = job / m, j = job - f * m;
+    const C2<R>* s = src + f * L;
+    C2<R>* d = dst + f * L;
+    int k = j % Ns;
+    C2<R> v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) {
+      v[r] = s[j + r * m];
+      if (r > 0 && k > 0) v[r] = cm(v[r], tw[r * k * step]);
+    }
+    dft<R, RAD>(v);
+    int base = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) d[base + r * Ns] = v[r];
+  }
+}
+
+// Full mixed-radix Stockham FFT in LDS; returns the buffer holding the result.
+template <typename R>
+__device__ C2<R>* lds_fft(C2<R>* a, C2<R>* b, int L, const int* rad, int nr, int nfft, const C2<R>* tw) {
+  int Ns = 1;
+  for (int s = 0; s < nr; ++s) {
+    switch (rad[s]) {
+      case 2: stage<R, 2>(a, b, L, Ns, nfft, tw); break;
+      case 3: stage<R, 3>(a, b, L, Ns, nfft, tw); break;
+      case 4: stage<R, 4>(a, b, L, Ns, nfft, tw); break;
+      case 5: stage<R, 5>(a, b, L, Ns, nfft, tw); break;
+      default: stage<R, 8>(a, b, L, Ns, nfft, tw); break;
+    }
+    Ns *= rad[s];
+    __syncthreads();
+    C2<R>* t = a; a = b; b = t;
+  }
+  return a;
+}
+
+// exp(-2 pi i k / N) from the two-level table (k < N)
+template <typename R>
+__device__ inline C2<R> wN(const C2<R>* lo, const C2<R>* hi, int64_t k) {
+  return cm(lo[k & 1023], hi[k >> 10]);
+}
+
+constexpr int kCB = 8;   // columns per pass-1 workgroup
+
+template <typename R>
+__global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n1 = p.n1, n2 = p.n2;
+  C2<R>* a = (C2<R>*)smem;
+  C2<R>* b = a + kCB * n1;
+  const int64_t row = blockIdx.y;
+  const int j2_0 = blockIdx.x * kCB;
+  C2<R>* z = data + row * p.n;
+  for (int i = threadIdx.x; i < kCB * n1; i += kFT) {
+    int j1 = i / kCB, jj = i - j1 * kCB;
+    int j2 = j2_0 + jj;
+    a[jj * n1 + j1] = j2 < n2 ? z[(int64_t)j1 * n2 + j2] : C2<R>{(R)0, (R)0};
+  }
+  __syncthreads();
+  const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
+  C2<R>* res = lds_fft<R>(a, b, n1, p.rad1, p.nr1, kCB, tw);
+  const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
+  const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
+  for (int i = threadIdx.x; i < kCB * n1; i += kFT) {
+    int k1 = i / kCB, jj = i - k1 * kCB;
+    int j2 = j2_0 + jj;
+    if (j2 < n2) {
+      C2<R> v = res[jj * n1 + k1];
+      int64_t m = (int64_t)j2 * k1;                     // < n
+      z[(int64_t)k1 * n2 + j2] = cm(v, wN<R>(lo, hi, 2 * m));
+    }
+  }
+}
+
+// pass 2: rows k1 = pair and k1' = (n1 - pair) mod n1
+template <typename R>
+__global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, int mode, double dt,
+                                               C2<R>* spec, const double* wperm, int64_t ch_rows,
+                                               double* partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[kFT / 64];
+  const int n1 = p.n1, n2 = p.n2;
+  const int64_t n = p.n;
+  const int pair = blockIdx.x;
+  const int64_t row = blockIdx.y;
+  const int k1a = pair, k1b = (n1 - pair) % n1;
+  const int nrows = (k1a == k1b) ? 1 : 2;
+  C2<R>* a = (C2<R>*)smem;
+  C2<R>* b = a + 2 * n2;
+  const C2<R>* z = data + row * n;
+  for (int i = threadIdx.x; i < nrows * n2; i += kFT) {
+    int r = i / n2, j2 = i - r * n2;
+    int k1 = r == 0 ? k1a : k1b;
+    a[r * n2 + j2] = z[(int64_t)k1 * n2 + j2];
+  }
+  __syncthreads();
+  const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw2d, p.tw2f);
+  C2<R>* Z = lds_fft<R>(a, b, n2, p.rad2, p.nr2, nrows, tw);
+  const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
+  const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
+  const double* w = wperm;
+  double acc = 0.0;
+  // outputs: every k in the rows of this block, plus the Nyquist bin for pair 0
+  const int nout = nrows * n2 + (pair == 0 ? 1 : 0);
+  for (int i = threadIdx.x; i < nout; i += kFT) {
+    int r, k2;
+    int64_t k;
+    C2<R> Zk, Zm;
+    if (i < nrows * n2) {
+      r = i / n2;
+      k2 = i - r * n2;
+      int k1 = r == 0 ? k1a : k1b;
+      k = k1 + (int64_t)n1 * k2;
+      Zk = Z[r * n2 + k2];
+      if (k1 == 0) {
+        Zm = Z[r * n2 + (n2 - k2) % n2];
+      } else {
+        int rm = (nrows == 1) ? 0 : 1 - r;
+        Zm = Z[rm * n2 + (n2 - 1 - k2)];
+      }
+    } else {
+      k = n;          // Nyquist: Z_n = Z_0
+      Zk = Z[0];
+      Zm = Z[0];
+      r = 0;
+      k2 = 0;
+    }
+    C2<R> zc = {Zm.x, -Zm.y};
+    C2<R> s = sc(Zk + zc, (R)0.5), d = sc(Zk - zc, (R)0.5);
+    C2<R> wk = (k == n) ? C2<R>{(R)-1, (R)0} : wN<R>(lo, hi, k);
+    C2<R> X = s + mi(cm(wk, d));
+    if (mode == 0) {
+      spec[row * (n + 1) + k] = sc(X, (R)dt);
+    } else {
+      // weights are stored in pass-2 order: index k1 * n2 + k2 (Nyquist at n)
+      int64_t ch = (row % 3);
+      int64_t widx = (k == n) ? n : (int64_t)(k % n1) * n2 + k / n1;
+      double wv = w[ch * (n + 1) + widx];
+      double xr = (double)X.x, xi = (double)X.y;
+      acc += wv * (xr * xr + xi * xi);
+    }
+  }
+  if (mode != 0) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < kFT / 64; ++i) t += red[i];
+      partial[row * (n1 / 2 + 1) + pair] = t;
+    }
+  }
+}
+
+template <typename R>
+static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, hipStream_t s) {
+  size_t bytes = 2 * (size_t)kCB * p.n1 * sizeof(C2<R>);
+  hipError_t e = hipFuncSetAttribute((const void*)k_pass1<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)((p.n2 + kCB - 1) / kCB), (unsigned)rows);
+  hipLaunchKernelGGL(k_pass1<R>, grid, dim3(kFT), bytes, s, p, (C2<R>*)data);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int precision, hipStream_t s) {
+  return precision == 0 ? p1<double>(p, data, rows, s) : p1<float>(p, data, rows, s);
+}
+
+template <typename R>
+static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mode, double dt, void* spec,
+                     const double* wperm, int64_t ch_rows, double* partial, hipStream_t s) {
+  size_t bytes = 4 * (size_t)p.n2 * sizeof(C2<R>);
+  hipError_t e = hipFuncSetAttribute((const void*)k_pass2<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)(p.n1 / 2 + 1), (unsigned)rows);
+  hipLaunchKernelGGL(k_pass2<R>, grid, dim3(kFT), bytes, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
+                     ch_rows, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft_pass2(const FftPlanDev& p, const void* data, int64_t rows, int precision, int mode, double dt,
+                            void* spec, const double* wperm, int64_t ch_rows, double* partial, hipStream_t s) {
+  return precision == 0 ? p2<double>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, s)
+                        : p2<float>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, s);
+}
+
+// weights in pass-2 order: w[c][k1 * n2 + k2] = 1/S_c(k) inside the band of an
+// enabled channel, 0 elsewhere; w[c][n] for the Nyquist bin.
+__global__ void k_weights(FftPlanDev p, const double* S0, const double* S1, const double* S2, int k_lo, int k_hi,
+                          int channels, double* w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = blockIdx.y;
+  const int64_t n = p.n;
+  if (i > n) return;
+  int64_t k;
+  if (i == n) k = n;
+  else {
+    int64_t k1 = i / p.n2, k2 = i - k1 * p.n2;
+    k = k1 + (int64_t)p.n1 * k2;
+  }
+  const double* S = c == 0 ? S0 : (c == 1 ? S1 : S2);
+  double v = 0.0;
+  if ((channels >> c) & 1)
+    if (k >= k_lo && k <= k_hi) v = 1.0 / S[k];
+  w[c * (n + 1) + i] = v;
+}
+
+hipError_t launch_weights(const FftPlanDev& p, const double* const* S, int k_lo, int k_hi, int channels, double* w,
+                          hipStream_t s) {
+  dim3 grid((unsigned)((p.n + 1 + 255) / 256), 3);
+  hipLaunchKernelGGL(k_weights, grid, dim3(256), 0, s, p, S[0], S[1], S[2], k_lo, k_hi, channels, w);
+  return hipGetLastError();
+}
+
+// per template: sum over 3 channels x npairs partial sums in a fixed order
+__global__ void k_finalize(const double* partial, int64_t batch, int npairs, double scale, double dd,
+                           const int32_t* status, double* logl, double* logl_full, double* inner) {
+  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  double s = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double* q = partial + (b * 3 + c) * npairs;
+    double cs = 0.0, comp = 0.0;
+    for (int i = 0; i < npairs; ++i) {      // Kahan-compensated
+      double y = q[i] - comp;
+      double t = cs + y;
+      comp = (t - cs) - y;
+      cs = t;
+    }
+    s += cs;
+  }
+  double rr = scale * s;
+  if (inner) inner[b] = rr;
+  bool bad = status && status[b] != 0;
+  double full = bad ? -INFINITY : -0.5 * rr;
+  if (!bad && !isfinite(full)) full = -INFINITY;
+  if (logl_full) logl_full[b] = full;
+  if (logl) logl[b] = full + 0.5 * dd;
+}
+
+hipError_t launch_finalize(const double* partial, int64_t batch, int npairs, double scale, double dd,
+                           const int32_t* status, double* logl, double* logl_full, double* inner, hipStream_t s) {
+  dim3 grid((unsigned)((batch + 63) / 64));
+  hipLaunchKernelGGL(k_finalize, grid, dim3(64), 0, s, partial, batch, npairs, scale, dd, status, logl, logl_full,
+                     inner);
+  return hipGetLastError();
+}
+
+}  // namespace lt

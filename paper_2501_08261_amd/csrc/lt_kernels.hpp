@@ -1,0 +1,71 @@
+// Launch interfaces of the liblisatd kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "lt_common.hpp"
+
+namespace lt {
+
+// One TDI term: sign * y_link(t - sum_l cnt[l] L_l(t)); links indexed
+// 0..5 for the labels 1, 2, 3, -1, -2, -3.
+struct Term { int sign, link, cnt[6]; };
+struct TermTable { int n_terms[3]; Term t[3][16]; };
+
+// Orbit node table on the device: node j sits at grid sample (j - j0) * spacing;
+// per node and link: L [s], r_receiver / c [s] (3), r_sender(emission) / c [s] (3), n (3).
+constexpr int kNodeLink = 10;
+constexpr int kNodeStride = 6 * kNodeLink;
+struct OrbitDev {
+  const double* tab;
+  int n_nodes, j0, spacing;
+  double max_light_time;
+};
+
+struct GridDev { double t0, dt, inv_dt; int64_t n; };
+
+hipError_t launch_setup(const double* params, int64_t batch, double f_low, double f_ref, GridDev g,
+                        TplConst* tc, int32_t* status, hipStream_t s);
+hipError_t launch_modes(const TplConst* tc, int64_t batch, int mode_mask, GridDev g, double* modes,
+                        hipStream_t s);
+hipError_t launch_polarizations(const TplConst* tc, int64_t batch, int mode_mask, int precessing, GridDev g,
+                                double* hpc, hipStream_t s);
+
+// out_mode: 0 write A,E,T; 1 write X,Y,Z; 2 write A,E,T minus data (residual)
+struct TdiLaunch {
+  const TplConst* tc;
+  int64_t batch;
+  int mode_mask, precessing, taps, precision, out_mode;
+  GridDev g;
+  OrbitDev orb;
+  TermTable terms;
+  const void* data;   // [3][n] (residual mode)
+  void* out;          // [batch][3][n]
+  int32_t* status;    // nullable
+};
+hipError_t launch_tdi(const TdiLaunch& L, hipStream_t s);
+int tdi_tile();
+
+// ---------------------------------------------------------------- FFT
+struct FftPlanDev {
+  int64_t N, n;          // real length, complex length n = N/2
+  int n1, n2;            // n = n1 * n2 (pass 1: FFTs of length n1 over columns, pass 2: length n2 rows)
+  int rad1[12], nr1, rad2[12], nr2;
+  const double* tw1d; const float* tw1f;    // exp(-2 pi i k / n1), k < n1 (complex interleaved)
+  const double* tw2d; const float* tw2f;    // exp(-2 pi i k / n2)
+  const double* wlod; const float* wlof;    // exp(-2 pi i k / N), k < 1024
+  const double* whid; const float* whif;    // exp(-2 pi i 1024 k / N), k <= N/1024
+};
+
+hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int precision, hipStream_t s);
+// mode 0: spectrum out[row][k] = R_k * dt (k = 0..n); mode 1: band power partial sums
+hipError_t launch_fft_pass2(const FftPlanDev& p, const void* data, int64_t rows, int precision, int mode,
+                            double dt, void* spec_out, const double* wperm, int64_t ch_stride_rows,
+                            double* partial, hipStream_t s);
+hipError_t launch_weights(const FftPlanDev& p, const double* const* S, int k_lo, int k_hi, int channels,
+                          double* wperm, hipStream_t s);
+// out[b] = scale * sum_{c, pairs} partial; logl variant adds dd/2 and handles status
+hipError_t launch_finalize(const double* partial, int64_t batch, int npairs, double scale, double dd,
+                           const int32_t* status, double* logl, double* logl_full, double* inner,
+                           hipStream_t s);
+
+}  // namespace lt

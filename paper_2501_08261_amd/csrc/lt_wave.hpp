@@ -1,0 +1,345 @@
+// PhenomT-form waveform on the device: per-template setup (hot-path step a1)
+// and per-sample evaluation of the co-precessing modes (a2), the Euler-angle
+// quaternion (a3) and the single-sum twist-up to h+, hx (a4).
+//
+// Model (paper Sec. II.A; the calibrated IMRPhenomT ansatz is not printed, so
+// this is a PhenomT-form model built from public post-Newtonian physics):
+//  * inspiral: TaylorT3 closed form in theta = [eta (t_c - t)/(5M)]^(-1/8),
+//    orbital phase Phi = -theta^-5/eta (1 + a2 theta^2 + a3 theta^3 + a4 theta^4)
+//    and its exact time derivative as the orbital frequency;
+//  * merger-ringdown (t >= t_m): omega22 = w_lo + Delta (1 + tanh(t/w))/2,
+//    C^1-joined at t_m and tending to the (2,2) QNM frequency, phase by its
+//    closed-form integral;
+//  * amplitude: 8 sqrt(pi/5) eta (M/D) x in the inspiral, a quadratic cap with
+//    its maximum at t = 0 on [t_m, 0], a sech ringdown with the QNM damping;
+//  * higher modes: leading-PN amplitude ratios, phases m times the orbital phase.
+// Precession: single-spin simple precession of L about J, closed forms in
+// u = (M omega22 / 2)^(1/3) for alpha, beta, gamma (NNLO-form), constant
+// J -> L0 rotation chosen so that the composite rotation is the identity at
+// f_ref.  Twist-up: Eq. (2.4) with the rotor Q = conj(q_CP->J) conj(q_J->L0)
+// q(phi, iota, 0), quaternions of Eq. (2.5) (normalised), and the
+// division-free form of Eq. (2.6): W^l_m = D^l_{m,2} as a polynomial in Q_a, Q_b.
+#pragma once
+#include "lt_common.hpp"
+
+namespace lt {
+
+// ---------------------------------------------------------------- Wigner W
+__host__ __device__ constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+__host__ __device__ constexpr double binom(int n, int k) {
+  return (k < 0 || k > n) ? 0.0 : fact(n) / (fact(k) * fact(n - k));
+}
+
+// W^L_M(Q) with pa[k] = Qa^k (k <= 8), pb[k] = Qb^k (k <= 6).
+template <int L, int M>
+__device__ inline cplx wig(const cplx* pa, const cplx* pb) {
+  constexpr int rlo = (M - 2) > 0 ? (M - 2) : 0;
+  constexpr int rhi = (L - 2) < (L + M) ? (L - 2) : (L + M);
+  double pref = __builtin_sqrt(fact(L + 2) * fact(L - 2) / (fact(L + M) * fact(L - M)));
+  cplx acc{0.0, 0.0};
+#pragma unroll
+  for (int rho = rlo; rho <= rhi; ++rho) {
+    double coef = ((rho & 1) ? -1.0 : 1.0) * binom(L + M, rho) * binom(L - M, L - 2 - rho);
+    cplx t = cmul(cmul(pa[L + M - rho], cconj(pa[L - 2 - rho])), cmul(pb[2 - M + rho], cconj(pb[rho])));
+    acc = cadd(acc, cscale(t, coef));
+  }
+  return cscale(acc, pref);
+}
+
+__device__ inline cplx qmul_scalar_first(const double* a, const double* b, double* out) {
+  out[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  out[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  out[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  out[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+  return {0.0, 0.0};
+}
+
+__device__ inline void quat_euler(double alpha, double cos_hb, double sin_hb, double gamma, double* q) {
+  double ss, cs, sd, cd;
+  sincos(0.5 * (alpha + gamma), &ss, &cs);
+  sincos(0.5 * (alpha - gamma), &sd, &cd);
+  q[0] = cos_hb * cs;
+  q[1] = -sin_hb * sd;
+  q[2] = sin_hb * cd;
+  q[3] = cos_hb * ss;
+}
+
+// sqrt((2l+1)/4pi) for l = 2, 3, 4
+constexpr double kY2 = 0.63078313050504001;   // sqrt(5/(4 pi))
+constexpr double kY3 = 0.74635266518023080;   // sqrt(7/(4 pi))
+constexpr double kY4 = 0.84628437532163447;   // sqrt(9/(4 pi))
+
+// -------------------------------------------------------------- setup (a1)
+__device__ inline double lncosh(double z) {
+  double a = fabs(z);
+  return a + log1p(exp(-2.0 * a)) - 0.69314718055994531;
+}
+
+struct Pn {
+  double Ms, a2, a3, a4, eta;
+  __device__ double w_orb(double th) const {
+    double t2 = th * th;
+    return th * t2 / (8.0 * Ms) * (1.0 + 0.6 * a2 * t2 + 0.4 * a3 * t2 * th + 0.2 * a4 * t2 * t2);
+  }
+  __device__ double dw_orb(double th) const {
+    double t2 = th * th;
+    return (3.0 * t2 + 3.0 * a2 * t2 * t2 + 2.4 * a3 * t2 * t2 * th + 1.4 * a4 * t2 * t2 * t2) / (8.0 * Ms);
+  }
+  __device__ double Phi(double th) const {
+    double t2 = th * th;
+    double tm5 = 1.0 / (t2 * t2 * th);
+    return -(1.0 / eta) * tm5 * (1.0 + a2 * t2 + a3 * t2 * th + a4 * t2 * t2);
+  }
+  // inspiral theta where the orbital frequency equals w (Newton); <0 if beyond matching
+  __device__ double solve(double w, double th_m) const {
+    if (!(w < w_orb(th_m))) return -1.0;
+    double th = fmin(cbrt(8.0 * Ms * w), 0.9 * th_m);
+    for (int i = 0; i < 100; ++i) {
+      double d = (w_orb(th) - w) / dw_orb(th);
+      th -= d;
+      if (fabs(d) < 1e-16 * th) break;
+    }
+    return th;
+  }
+};
+
+// Fills c from one parameter row p[16]; returns 1 if physical.
+__device__ inline int setup_template(const double* p, double f_low, double f_ref, double t0, double dt,
+                                     TplConst& c) {
+  int valid = 1;
+  double m1 = p[0], m2 = p[1];
+  if (!(m1 > 0.0 && m2 > 0.0)) { valid = 0; m1 = m2 = 1.0; }
+  double M = m1 + m2;
+  double Ms = M * kMTsun;
+  double eta = m1 * m2 / (M * M);
+  double m1f = m1 / M, m2f = m2 / M;
+  double chi1[3] = {p[2], p[3], p[4]}, chi2[3] = {p[5], p[6], p[7]};
+  double n1 = sqrt(chi1[0] * chi1[0] + chi1[1] * chi1[1] + chi1[2] * chi1[2]);
+  double n2 = sqrt(chi2[0] * chi2[0] + chi2[1] * chi2[1] + chi2[2] * chi2[2]);
+  if (!(n1 < 1.0 && n2 < 1.0)) valid = 0;
+  double DL = p[8];
+  if (!(DL > 0.0)) { valid = 0; DL = 1.0; }
+  double iota = p[9], phi_ref = p[10], lam = p[12], bet = p[13], psi = p[14];
+  c.tc = p[11];
+  c.Ms = Ms;
+  c.eta = eta;
+  c.inv_eta = 1.0 / eta;
+  c.delta = (m1 - m2) / M;
+  c.eta_5M = eta / (5.0 * Ms);
+  double chi1l = chi1[2], chi2l = chi2[2];
+  double beta_so = (113.0 / 12.0 * m1f * m1f + 25.0 / 4.0 * eta) * chi1l
+                 + (113.0 / 12.0 * m2f * m2f + 25.0 / 4.0 * eta) * chi2l;
+  Pn pn;
+  pn.Ms = Ms;
+  pn.eta = eta;
+  pn.a2 = 3715.0 / 8064.0 + 55.0 / 96.0 * eta;
+  pn.a3 = -0.75 * kPi + 3.0 / 16.0 * beta_so;
+  pn.a4 = 9275495.0 / 14450688.0 + 284875.0 / 258048.0 * eta + 1855.0 / 2048.0 * eta * eta;
+  c.a2 = pn.a2; c.a3 = pn.a3; c.a4 = pn.a4;
+  const double thm = kThetaMatch;
+  double thm2 = thm * thm, thm4 = thm2 * thm2;
+  double T = 5.0 * Ms / (eta * thm4 * thm4);
+  c.t_m = -T;
+  double w22m = 2.0 * pn.w_orb(thm);
+  double dw22m = 2.0 * pn.dw_orb(thm) * (eta * thm4 * thm4 * thm / (40.0 * Ms));
+  // remnant and (2,2,0) QNM
+  double af = 2.0 * sqrt(3.0) * eta - 3.871 * eta * eta + 4.028 * eta * eta * eta
+            + m1f * m1f * chi1l + m2f * m2f * chi2l;
+  af = fmin(0.99, fmax(-0.99, af));
+  double mf = 1.0 - 0.0484 * (4.0 * eta) * (4.0 * eta);
+  double wq = 1.5251 - 1.1568 * pow(1.0 - af, 0.1292);
+  double qq = 0.7 + 1.4187 * pow(1.0 - af, -0.4990);
+  double w_rd = wq / (mf * Ms);
+  c.tau_rd = 2.0 * qq / w_rd;
+  // tanh step: s (1 - tanh s) = kappa T, larger root, by bisection
+  double target = dw22m / (w_rd - w22m) * T;
+  if (!(w_rd > w22m && target > 0.0 && target < 0.2784)) { valid = 0; target = 0.1; }
+  double lo = 0.6392, hi = 60.0;
+  for (int i = 0; i < 200; ++i) {
+    double mid = 0.5 * (lo + hi);
+    if (mid * (1.0 - tanh(mid)) > target) lo = mid; else hi = mid;
+  }
+  double s = 0.5 * (lo + hi);
+  c.wt = T / s;
+  c.inv_wt = 1.0 / c.wt;
+  double sig_m = 0.5 * (1.0 - tanh(s));
+  c.Delta = (w_rd - w22m) / (1.0 - sig_m);
+  c.w_lo = w_rd - c.Delta;
+  c.lncosh_tm = lncosh(c.t_m * c.inv_wt);
+  double th_ref = pn.solve(kPi * f_ref, thm);
+  double th_st = pn.solve(kPi * f_low, thm);
+  if (th_ref < 0.0 || th_st < 0.0) { valid = 0; th_ref = th_st = 0.5 * thm; }
+  c.Phi_ref = pn.Phi(th_ref);
+  double ts2 = th_st * th_st, ts4 = ts2 * ts2;
+  c.t_start = -5.0 * Ms / (eta * ts4 * ts4);
+  c.phi22_m = 2.0 * (pn.Phi(thm) - c.Phi_ref);
+  // amplitude
+  c.K_amp = 8.0 * sqrt(kPi / 5.0) * eta * Ms * kC / (DL * kMpc);
+  double xm = pow(Ms * w22m / 2.0, 2.0 / 3.0);
+  c.A_m = c.K_amp * xm;
+  double dAm = c.K_amp * (2.0 / 3.0) * xm * dw22m / w22m;
+  c.A_p = c.A_m + 0.5 * dAm * T;
+  double d = c.delta;
+  c.r21 = d / 3.0;                                  // times i
+  c.r33 = -0.75 * sqrt(15.0 / 14.0) * d;            // times i
+  c.r32 = (1.0 / 3.0) * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta);
+  c.r44 = -(8.0 / 9.0) * sqrt(5.0 / 7.0) * (1.0 - 3.0 * eta);
+  // precession constants
+  double S[3];
+  for (int i = 0; i < 3; ++i) S[i] = chi1[i] * m1f * m1f + chi2[i] * m2f * m2f;
+  double Sp = sqrt(S[0] * S[0] + S[1] * S[1]);
+  c.sig = S[2] / eta;
+  c.vsig2 = (Sp / eta) * (Sp / eta);
+  double qs = fmin(m1f, m2f) / fmax(m1f, m2f);
+  c.Cp = 5.0 * (4.0 + 3.0 * qs) / 256.0;
+  double u_ref = cbrt(kPi * Ms * f_ref);
+  double J[3] = {S[0], S[1], eta / u_ref + S[2]};
+  double beta_ref = atan2(sqrt(J[0] * J[0] + J[1] * J[1]), J[2]);
+  double phi_J = atan2(J[1], J[0]);
+  c.kappa = phi_J - kPi;
+  double ur2 = u_ref * u_ref, ur3 = ur2 * u_ref;
+  c.a_ref = -c.Cp * ((2.0 / 3.0) / ur3 + c.sig / ur2);
+  c.g_ref = 2.0 * c.Cp * (1.0 / (3.0 * ur3) + 0.5 * c.sig / ur2 - 0.5 * c.vsig2 / u_ref);
+  // constant rotor Qc = conj(q_J->L0) q(phi_ref, iota, 0), q_J->L0 = q(kappa, -beta_ref, 0)
+  double q0[4], ql[4];
+  quat_euler(c.kappa, cos(-0.5 * beta_ref), sin(-0.5 * beta_ref), 0.0, q0);
+  quat_euler(phi_ref, cos(0.5 * iota), sin(0.5 * iota), 0.0, ql);
+  double q0c[4] = {q0[0], -q0[1], -q0[2], -q0[3]};
+  qmul_scalar_first(q0c, ql, c.Qc);
+  // polarisation rotation and the aligned-spin harmonics times exp(2 i psi)
+  double s2p, c2p;
+  sincos(2.0 * psi, &s2p, &c2p);
+  c.e2ipsi[0] = c2p;
+  c.e2ipsi[1] = s2p;
+  {
+    cplx Qa{ql[0], ql[3]}, Qb{ql[2], ql[1]};
+    cplx pa[9], pb[7];
+    pa[0] = {1.0, 0.0};
+    pb[0] = {1.0, 0.0};
+    for (int k = 1; k < 9; ++k) pa[k] = cmul(pa[k - 1], Qa);
+    for (int k = 1; k < 7; ++k) pb[k] = cmul(pb[k - 1], Qb);
+    cplx e{c2p, s2p};
+    cplx Yp[5] = {cscale(wig<2, 2>(pa, pb), kY2), cscale(wig<2, 1>(pa, pb), kY2), cscale(wig<3, 3>(pa, pb), kY3),
+                  cscale(wig<3, 2>(pa, pb), kY3), cscale(wig<4, 4>(pa, pb), kY4)};
+    cplx Ym[5] = {cscale(wig<2, -2>(pa, pb), kY2), cscale(wig<2, -1>(pa, pb), kY2),
+                  cscale(wig<3, -3>(pa, pb), -kY3), cscale(wig<3, -2>(pa, pb), -kY3),
+                  cscale(wig<4, -4>(pa, pb), kY4)};
+    for (int i = 0; i < 5; ++i) {
+      cplx a = cmul(Yp[i], e), b = cmul(Ym[i], e);
+      c.cp[i][0] = a.re; c.cp[i][1] = a.im;
+      c.cm[i][0] = b.re; c.cm[i][1] = b.im;
+    }
+  }
+  // sky basis, Eq. (2.7)
+  double cl = cos(lam), sl = sin(lam), cb = cos(bet), sb = sin(bet);
+  c.k[0] = -cb * cl; c.k[1] = -cb * sl; c.k[2] = -sb;
+  c.v[0] = -sb * cl; c.v[1] = -sb * sl; c.v[2] = cb;
+  c.u[0] = sl; c.u[1] = -cl; c.u[2] = 0.0;
+  c.valid = valid ? 1.0 : 0.0;
+  c.n_start = ceil((c.tc + c.t_start - t0) / dt);
+  return valid;
+}
+
+// ------------------------------------------------------ per-sample evaluation
+struct Orb {           // orbital-phase pieces at one sample
+  double A, u, x, cphi, sphi;
+};
+
+// Returns false before the f_low start (all modes zero).
+__device__ inline bool orbital_state(const TplConst& c, double t, Orb& o) {
+  double tau = t - c.tc;
+  if (tau < c.t_start) return false;
+  double phi_orb, w_orb;
+  if (tau < c.t_m) {
+    double y = c.eta_5M * (-tau);
+    double th = sqrt(sqrt(1.0 / sqrt(y)));          // y^(-1/8)
+    double t2 = th * th, t3 = t2 * th;
+    phi_orb = -c.inv_eta * y * t3 * (1.0 + c.a2 * t2 + c.a3 * t3 + c.a4 * t2 * t2) - c.Phi_ref;
+    w_orb = t3 / (8.0 * c.Ms) * (1.0 + 0.6 * c.a2 * t2 + 0.4 * c.a3 * t3 + 0.2 * c.a4 * t2 * t2);
+    o.u = cbrt(c.Ms * w_orb);
+    o.x = o.u * o.u;
+    o.A = c.K_amp * o.x;
+  } else {
+    double z = tau * c.inv_wt;
+    double w22 = c.w_lo + 0.5 * c.Delta * (1.0 + tanh(z));
+    double phi22 = c.phi22_m + (c.w_lo + 0.5 * c.Delta) * (tau - c.t_m) + 0.5 * c.Delta * c.wt * (lncosh(z) - c.lncosh_tm);
+    phi_orb = 0.5 * phi22;
+    w_orb = 0.5 * w22;
+    o.u = cbrt(c.Ms * w_orb);
+    o.x = o.u * o.u;
+    if (tau < 0.0) {
+      double r = tau / c.t_m;
+      o.A = c.A_p - (c.A_p - c.A_m) * r * r;
+    } else {
+      o.A = c.A_p / cosh(tau / c.tau_rd);
+    }
+  }
+  sincos(phi_orb, &o.sphi, &o.cphi);
+  return true;
+}
+
+// The co-precessing modes with m > 0 in the order 22, 21, 33, 32, 44 (all five).
+__device__ inline void cp_modes5(const TplConst& c, const Orb& o, cplx* h) {
+  cplx E1{o.cphi, -o.sphi};
+  cplx E2 = cmul(E1, E1), E3 = cmul(E2, E1), E4 = cmul(E2, E2);
+  double a21 = o.A * c.r21 * o.u, a33 = o.A * c.r33 * o.u;
+  h[0] = cscale(E2, o.A);
+  h[1] = {-a21 * E1.im, a21 * E1.re};
+  h[2] = {-a33 * E3.im, a33 * E3.re};
+  h[3] = cscale(E2, o.A * c.r32 * o.x);
+  h[4] = cscale(E4, o.A * c.r44 * o.x);
+}
+
+// h+ - i hx at SSB time t (including exp(2 i psi)); zero before the start.
+template <bool PREC>
+__device__ inline cplx polarization(const TplConst& c, int mode_mask, double t) {
+  Orb o;
+  if (!orbital_state(c, t, o)) return {0.0, 0.0};
+  cplx h[5];
+  cp_modes5(c, o, h);
+  cplx acc{0.0, 0.0};
+  if (!PREC) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      if (mode_mask & (1 << i)) {
+        cplx a{c.cp[i][0], c.cp[i][1]}, b{c.cm[i][0], c.cm[i][1]};
+        acc = cadd(acc, cadd(cmul(h[i], a), cmul(cconj(h[i]), b)));
+      }
+    }
+    return acc;
+  } else {
+    // Euler angles (NNLO-form) from u, quaternion of Eq. (2.5), composite rotor
+    double u = o.u, iu = 1.0 / u, iu2 = iu * iu, iu3 = iu2 * iu;
+    double alpha = -c.Cp * ((2.0 / 3.0) * iu3 + c.sig * iu2) - c.a_ref;
+    double gamma = -c.kappa + 2.0 * c.Cp * ((1.0 / 3.0) * iu3 + 0.5 * c.sig * iu2 - 0.5 * c.vsig2 * iu) - c.g_ref;
+    double a1 = 1.0 + c.sig * u;
+    double cb = a1 / sqrt(a1 * a1 + c.vsig2 * u * u);
+    double chb = sqrt(0.5 * (1.0 + cb)), shb = sqrt(fmax(0.0, 0.5 * (1.0 - cb)));
+    double q1[4];
+    quat_euler(alpha, chb, shb, gamma, q1);
+    q1[1] = -q1[1]; q1[2] = -q1[2]; q1[3] = -q1[3];
+    double Q[4];
+    qmul_scalar_first(q1, c.Qc, Q);
+    cplx Qa{Q[0], Q[3]}, Qb{Q[2], Q[1]};
+    cplx pa[9], pb[7];
+    pa[0] = {1.0, 0.0};
+    pb[0] = {1.0, 0.0};
+#pragma unroll
+    for (int k = 1; k < 9; ++k) pa[k] = cmul(pa[k - 1], Qa);
+#pragma unroll
+    for (int k = 1; k < 7; ++k) pb[k] = cmul(pb[k - 1], Qb);
+    if (mode_mask & 1)
+      acc = cadd(acc, cadd(cmul(h[0], cscale(wig<2, 2>(pa, pb), kY2)), cmul(cconj(h[0]), cscale(wig<2, -2>(pa, pb), kY2))));
+    if (mode_mask & 2)
+      acc = cadd(acc, cadd(cmul(h[1], cscale(wig<2, 1>(pa, pb), kY2)), cmul(cconj(h[1]), cscale(wig<2, -1>(pa, pb), kY2))));
+    if (mode_mask & 4)
+      acc = cadd(acc, cadd(cmul(h[2], cscale(wig<3, 3>(pa, pb), kY3)), cmul(cconj(h[2]), cscale(wig<3, -3>(pa, pb), -kY3))));
+    if (mode_mask & 8)
+      acc = cadd(acc, cadd(cmul(h[3], cscale(wig<3, 2>(pa, pb), kY3)), cmul(cconj(h[3]), cscale(wig<3, -2>(pa, pb), -kY3))));
+    if (mode_mask & 16)
+      acc = cadd(acc, cadd(cmul(h[4], cscale(wig<4, 4>(pa, pb), kY4)), cmul(cconj(h[4]), cscale(wig<4, -4>(pa, pb), kY4))));
+    return cmul(acc, cplx{c.e2ipsi[0], c.e2ipsi[1]});
+  }
+}
+
+}  // namespace lt

@@ -1,0 +1,211 @@
+"""Thin ctypes binding of liblisatd (include/lisatd.h).
+
+Argument marshalling only: every step of the likelihood runs in the HIP
+kernels of liblisatd.so.  Device buffers are torch tensors on a ROCm device;
+the binding passes their data pointers and the current torch stream.  If the
+library has not been built this module raises at import: there is no CPU
+fallback.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblisatd.so")
+
+LT_FP64, LT_MIXED = 0, 1
+LT_ORBIT_STATIC_EQUAL, LT_ORBIT_KEPLER = 0, 1
+LT_CH_A, LT_CH_E, LT_CH_T = 1, 2, 4
+MODE_BITS = {(2, 2): 1, (2, 1): 2, (3, 3): 4, (3, 2): 8, (4, 4): 16}
+MODE_ORDER = ((2, 2), (2, 1), (3, 3), (3, 2), (4, 4))
+ARM_M = 2.5e9
+AU_M = 1.495978707e11
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("liblisatd.so is not built (run `python -m paper_2501_08261_amd.build`)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("t0", ctypes.c_double), ("dt", ctypes.c_double), ("n", ctypes.c_int64)]
+
+
+class WfCfg(ctypes.Structure):
+    _fields_ = [("mode_mask", ctypes.c_int), ("precessing", ctypes.c_int), ("f_low", ctypes.c_double),
+                ("f_ref", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class Orbit(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("arm_m", ctypes.c_double), ("au_m", ctypes.c_double),
+                ("phase0", ctypes.c_double), ("t_ref", ctypes.c_double)]
+
+
+class TdiCfg(ctypes.Structure):
+    _fields_ = [("generation", ctypes.c_int), ("channels", ctypes.c_int), ("taps", ctypes.c_int),
+                ("out_xyz", ctypes.c_int)]
+
+
+class Psd(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_void_p * 3), ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double)]
+
+
+class Data(ctypes.Structure):
+    _fields_ = [("aet", ctypes.c_void_p), ("dd", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_sig = {
+    "lt_last_error": ([], ctypes.c_char_p),
+    "lt_ctx_create": ([ctypes.c_int, ctypes.POINTER(_P)], ctypes.c_int),
+    "lt_ctx_destroy": ([_P], ctypes.c_int),
+    "lt_phenomt_modes": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), _P, _P], ctypes.c_int),
+    "lt_phenomt_polarizations": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), _P, _P], ctypes.c_int),
+    "lt_lisa_tdi_response": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
+                              ctypes.POINTER(TdiCfg), _P, _P, _P], ctypes.c_int),
+    "lt_tdi_loglike": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
+                        ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data), _P, _P, _P, _P],
+                       ctypes.c_int),
+    "lt_noise_inner": ([_P, _P, _I64, ctypes.POINTER(Grid), ctypes.POINTER(Psd), ctypes.c_int, ctypes.c_int, _P, _P],
+                       ctypes.c_int),
+    "lt_rfft": ([_P, _P, _I64, _I64, ctypes.c_double, ctypes.c_int, _P, _P], ctypes.c_int),
+    "lt_psd_sangria": ([ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_double, _P, _P], ctypes.c_int),
+    "lt_profile_enable": ([_P, ctypes.c_int], ctypes.c_int),
+    "lt_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
+                        ctypes.c_int),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_sig)
+
+
+class LisaTDError(RuntimeError):
+    pass
+
+
+def _check(status):
+    if status != 0:
+        raise LisaTDError("liblisatd error %d: %s" % (status, _lib.lt_last_error().decode()))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor required")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def mode_mask(modes):
+    m = 0
+    for lm in modes:
+        m |= MODE_BITS[tuple(lm)]
+    return m
+
+
+def real_dtype(precision):
+    return torch.float64 if precision == LT_FP64 else torch.float32
+
+
+class Context:
+    """Owns one lt_ctx (plans, orbit tables, scratch) on one HIP device."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(_lib.lt_ctx_create(device, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(_lib.lt_ctx_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- configuration helpers --------------------------------------------
+    @staticmethod
+    def grid(g):
+        return Grid(g["t0"], g["dt"], g["n"])
+
+    @staticmethod
+    def wf_cfg(modes=((2, 2),), precessing=False, f_low=1e-4, f_ref=1e-4, precision=LT_FP64):
+        return WfCfg(mode_mask(modes), int(precessing), f_low, f_ref, precision)
+
+    @staticmethod
+    def orbit(kind="static", arm=ARM_M, au=AU_M, phase0=0.0, t_ref=0.0):
+        k = LT_ORBIT_STATIC_EQUAL if kind == "static" else LT_ORBIT_KEPLER
+        return Orbit(k, arm, au, phase0, t_ref)
+
+    @staticmethod
+    def tdi_cfg(generation=15, channels=7, taps=2, out_xyz=False):
+        return TdiCfg(generation, channels, taps, int(out_xyz))
+
+    # -- entry points ---------------------------------------------------------
+    def phenomt_modes(self, params, g, cfg, out, stream=None):
+        _check(_lib.lt_phenomt_modes(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
+                                     ctypes.byref(self.grid(g)), _ptr(out), _stream(stream)))
+        return out
+
+    def phenomt_polarizations(self, params, g, cfg, out, stream=None):
+        _check(_lib.lt_phenomt_polarizations(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
+                                             ctypes.byref(self.grid(g)), _ptr(out), _stream(stream)))
+        return out
+
+    def lisa_tdi_response(self, params, g, cfg, orbit, tdi, out, status=None, stream=None):
+        _check(_lib.lt_lisa_tdi_response(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
+                                         ctypes.byref(self.grid(g)), ctypes.byref(orbit), ctypes.byref(tdi),
+                                         _ptr(out), _ptr(status), _stream(stream)))
+        return out
+
+    def tdi_loglike(self, params, g, cfg, orbit, tdi, psd, data_aet, dd, logl, logl_full=None, status=None,
+                    f_lo=3e-4, f_hi=0.02, stream=None):
+        P = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
+        D = Data(_ptr(data_aet), float(dd))
+        _check(_lib.lt_tdi_loglike(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
+                                   ctypes.byref(self.grid(g)), ctypes.byref(orbit), ctypes.byref(tdi),
+                                   ctypes.byref(P), ctypes.byref(D), _ptr(logl), _ptr(logl_full), _ptr(status),
+                                   _stream(stream)))
+        return logl
+
+    def noise_inner(self, x, g, psd, out, channels=7, precision=LT_FP64, f_lo=3e-4, f_hi=0.02, stream=None):
+        P = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
+        _check(_lib.lt_noise_inner(self.h, _ptr(x), x.shape[0], ctypes.byref(self.grid(g)), ctypes.byref(P),
+                                   channels, precision, _ptr(out), _stream(stream)))
+        return out
+
+    def rfft(self, x, dt, out, precision=LT_FP64, stream=None):
+        _check(_lib.lt_rfft(self.h, _ptr(x), x.shape[0], x.shape[1], dt, precision, _ptr(out), _stream(stream)))
+        return out
+
+    def profile_enable(self, on=True):
+        _check(_lib.lt_profile_enable(self.h, int(on)))
+
+    def profile_read(self, n=5):
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        _check(_lib.lt_profile_read(self.h, ms, cnt, n))
+        return list(ms), list(cnt)
+
+
+def psd_sangria(g, generation, out, arm=ARM_M, stream=None):
+    """Fills out [3][n/2+1] (device FP64) with the PSD of Eqs. (2.14)-(2.15)."""
+    _check(_lib.lt_psd_sangria(ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), generation, arm, _ptr(out),
+                               _stream(stream)))
+    return out
