@@ -65,7 +65,7 @@ struct lt_ctx {
   int device = 0;
   std::map<int64_t, std::unique_ptr<Plan>> plans;
   std::map<std::tuple<int, double, double, double, double, double, double, int64_t>, std::unique_ptr<OrbitTab>> orbits;
-  DevBuf tpl, work, partial, wperm, status;
+  DevBuf tpl, work, partial, wperm, status, wave;
   bool profiling = false;
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
@@ -460,11 +460,17 @@ static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const l
   if (st) return st;
   st = do_setup(c, params, batch, cfg, g, status, s);
   if (st) return st;
+  const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
+  LT_HIP(c->wave.ensure((size_t)batch * 2 * g->n * rsz));
+  {
+    Prof pr(c, 0, s);
+    LT_HIP(launch_wave((const TplConst*)c->tpl.p, batch, cfg->mode_mask, cfg->precessing, cfg->precision, gdev(g),
+                       c->wave.p, s));
+  }
   TdiLaunch L;
   L.tc = (const TplConst*)c->tpl.p;
   L.batch = batch;
-  L.mode_mask = cfg->mode_mask;
-  L.precessing = cfg->precessing;
+  L.h = c->wave.p;
   L.taps = t->taps;
   L.precision = cfg->precision;
   L.out_mode = out_mode;

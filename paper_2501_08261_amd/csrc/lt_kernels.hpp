@@ -29,15 +29,19 @@ hipError_t launch_modes(const TplConst* tc, int64_t batch, int mode_mask, GridDe
                         hipStream_t s);
 hipError_t launch_polarizations(const TplConst* tc, int64_t batch, int mode_mask, int precessing, GridDev g,
                                 double* hpc, hipStream_t s);
+// h: [batch][2][n], double (precision 0) or float (precision 1)
+hipError_t launch_wave(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int precision, GridDev g,
+                       void* h, hipStream_t s);
 
 // out_mode: 0 write A,E,T; 1 write X,Y,Z; 2 write A,E,T minus data (residual)
 struct TdiLaunch {
   const TplConst* tc;
   int64_t batch;
-  int mode_mask, precessing, taps, precision, out_mode;
+  int taps, precision, out_mode;
   GridDev g;
   OrbitDev orb;
   TermTable terms;
+  const void* h;      // waveform buffer [batch][2][n]
   const void* data;   // [3][n] (residual mode)
   void* out;          // [batch][3][n]
   int32_t* status;    // nullable

@@ -35,8 +35,7 @@ __global__ __launch_bounds__(kNT) void k_modes(const TplConst* tc, int mode_mask
   if (n >= g.n) return;
   const TplConst& c = tc[b];
   cplx h[5] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  Orb o;
-  if (c.valid != 0.0 && orbital_state(c, g.t0 + (double)n * g.dt, o)) cp_modes5(c, o, h);
+  if (c.valid != 0.0) cp_modes_fp64(c, g.t0 + (double)n * g.dt, h);
   int nm = __popc(mode_mask);
   int j = 0;
   for (int i = 0; i < 5; ++i) {
@@ -54,26 +53,40 @@ hipError_t launch_modes(const TplConst* tc, int64_t batch, int mode_mask, GridDe
   return hipGetLastError();
 }
 
-template <bool PREC>
-__global__ __launch_bounds__(kNT) void k_pol(const TplConst* tc, int mode_mask, GridDev g, double* hpc) {
+// Polarisations h+, hx on the grid (steps a2-a4), one thread per sample:
+// h[b][0][n] = h+, h[b][1][n] = hx in the storage type R.
+template <typename R, bool PREC>
+__global__ __launch_bounds__(kNT) void k_wave(const TplConst* tc, int mode_mask, GridDev g, R* h) {
   int64_t n = (int64_t)blockIdx.x * kNT + threadIdx.x;
   int b = blockIdx.y;
   if (n >= g.n) return;
   const TplConst& c = tc[b];
-  cplx h{0.0, 0.0};
-  if (c.valid != 0.0) h = polarization<PREC>(c, mode_mask, g.t0 + (double)n * g.dt);
-  hpc[(2 * (int64_t)b) * g.n + n] = h.re;
-  hpc[(2 * (int64_t)b + 1) * g.n + n] = -h.im;
+  cx<R> v{(R)0, (R)0};
+  if (c.valid != 0.0 && (double)n >= c.n_start - 1.0) v = polarization_t<R, PREC>(c, mode_mask, g.t0 + (double)n * g.dt);
+  h[(2 * (int64_t)b) * g.n + n] = v.re;
+  h[(2 * (int64_t)b + 1) * g.n + n] = -v.im;
+}
+
+template <typename R>
+static hipError_t launch_wave_t(const TplConst* tc, int64_t batch, int mode_mask, int precessing, GridDev g, R* h,
+                                hipStream_t s) {
+  dim3 grid((unsigned)((g.n + kNT - 1) / kNT), (unsigned)batch);
+  if (precessing)
+    hipLaunchKernelGGL((k_wave<R, true>), grid, dim3(kNT), 0, s, tc, mode_mask, g, h);
+  else
+    hipLaunchKernelGGL((k_wave<R, false>), grid, dim3(kNT), 0, s, tc, mode_mask, g, h);
+  return hipGetLastError();
 }
 
 hipError_t launch_polarizations(const TplConst* tc, int64_t batch, int mode_mask, int precessing, GridDev g,
                                 double* hpc, hipStream_t s) {
-  dim3 grid((unsigned)((g.n + kNT - 1) / kNT), (unsigned)batch);
-  if (precessing)
-    hipLaunchKernelGGL(k_pol<true>, grid, dim3(kNT), 0, s, tc, mode_mask, g, hpc);
-  else
-    hipLaunchKernelGGL(k_pol<false>, grid, dim3(kNT), 0, s, tc, mode_mask, g, hpc);
-  return hipGetLastError();
+  return launch_wave_t<double>(tc, batch, mode_mask, precessing, g, hpc, s);
+}
+
+hipError_t launch_wave(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int precision, GridDev g,
+                       void* h, hipStream_t s) {
+  if (precision == 0) return launch_wave_t<double>(tc, batch, mode_mask, precessing, g, (double*)h, s);
+  return launch_wave_t<float>(tc, batch, mode_mask, precessing, g, (float*)h, s);
 }
 
 // ------------------------------------------------------- Lagrange weights
@@ -162,15 +175,20 @@ __device__ inline void cubic_w(double x, double* w) {
   w[3] = xp1 * x * xm1 * (1.0 / 6.0);
 }
 
-constexpr int kND = 5;   // per node and link: P+, Px, D_s, D_r, L
+// per node: for each link (P+, Px, D_s, L), then D_r for each spacecraft
+constexpr int kNL = 4;
+constexpr int kNodeVals = 6 * kNL + 3;
+__constant__ int kRecv[6] = {1, 2, 0, 2, 0, 1};     // receiver spacecraft (0-based) of links 1,2,3,-1,-2,-3
+__constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacecraft 1, 2, 3
 
 // ------------------------------------------------------- fused TDI kernel
 // One workgroup = one template x one tile of kTile output samples.
 //  B: per-link geometry at the orbit nodes covering the tile (LDS, FP64)
 //  A: h+, hx on the window of grid samples the six links read (LDS)
-//  C: y_slr for the tile plus the TDI halo, h interpolated with K taps (LDS)
+//  C: y_slr for the tile plus the TDI halos; h is interpolated with K taps at
+//     the three receiver times and the six sender times (LDS)
 //  D: X, Y, Z from y interpolated at the TDI delays, then A, E, T (global)
-template <typename R, int K, bool PREC>
+template <typename R, int K>
 __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long s_w0;
@@ -195,27 +213,31 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   const int NN = (int)(jn_hi - jn_lo + 1);
 
   // B: node geometry
-  for (int i = tid; i < NN * 6; i += kNT) {
-    int nl = i / 6, li = i % 6;
-    const double* e = P.orb.tab + (jn_lo + nl) * kNodeStride + li * kNodeLink;
-    double L = e[0];
-    double un = c.u[0] * e[7] + c.u[1] * e[8] + c.u[2] * e[9];
-    double vn = c.v[0] * e[7] + c.v[1] * e[8] + c.v[2] * e[9];
-    double kn = c.k[0] * e[7] + c.k[1] * e[8] + c.k[2] * e[9];
-    double inv = 1.0 / (1.0 - kn);
-    double* o = nd + (nl * 6 + li) * kND;
-    o[0] = 0.5 * (un * un - vn * vn) * inv;
-    o[1] = un * vn * inv;
-    o[2] = L + (c.k[0] * e[4] + c.k[1] * e[5] + c.k[2] * e[6]);
-    o[3] = c.k[0] * e[1] + c.k[1] * e[2] + c.k[2] * e[3];
-    o[4] = L;
+  for (int i = tid; i < NN * 9; i += kNT) {
+    int nl = i / 9, q = i - nl * 9;
+    double* o = nd + nl * kNodeVals;
+    if (q < 6) {
+      const double* e = P.orb.tab + (jn_lo + nl) * kNodeStride + q * kNodeLink;
+      double un = c.u[0] * e[7] + c.u[1] * e[8] + c.u[2] * e[9];
+      double vn = c.v[0] * e[7] + c.v[1] * e[8] + c.v[2] * e[9];
+      double kn = c.k[0] * e[7] + c.k[1] * e[8] + c.k[2] * e[9];
+      double inv = 1.0 / (1.0 - kn);
+      o[q * kNL + 0] = 0.5 * (un * un - vn * vn) * inv;
+      o[q * kNL + 1] = un * vn * inv;
+      o[q * kNL + 2] = e[0] + (c.k[0] * e[4] + c.k[1] * e[5] + c.k[2] * e[6]);
+      o[q * kNL + 3] = e[0];
+    } else {
+      const double* e = P.orb.tab + (jn_lo + nl) * kNodeStride + kRecvLink[q - 6] * kNodeLink;
+      o[6 * kNL + (q - 6)] = c.k[0] * e[1] + c.k[1] * e[2] + c.k[2] * e[3];
+    }
   }
   __syncthreads();
   if (tid == 0) {
     double dmin = 1e300, dmax = -1e300;
-    for (int i = 0; i < NN * 6; ++i) {
-      dmin = fmin(dmin, fmin(nd[i * kND + 2], nd[i * kND + 3]));
-      dmax = fmax(dmax, fmax(nd[i * kND + 2], nd[i * kND + 3]));
+    for (int i = 0; i < NN; ++i) {
+      const double* o = nd + i * kNodeVals;
+      for (int q = 0; q < 6; ++q) { dmin = fmin(dmin, o[q * kNL + 2]); dmax = fmax(dmax, o[q * kNL + 2]); }
+      for (int q = 0; q < 3; ++q) { dmin = fmin(dmin, o[6 * kNL + q]); dmax = fmax(dmax, o[6 * kNL + q]); }
     }
     long long w0 = (long long)m_lo - (long long)ceil(dmax * inv_dt) - K / 2 - 2;
     long long w1 = (long long)m_hi - (long long)floor(dmin * inv_dt) + K / 2 + 2;
@@ -234,17 +256,13 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   const int skip = s_skip;
 
   if (!skip) {
-    // A: polarisations on the window
+    // A: polarisations of the window from the waveform buffer
+    const R* hg = (const R*)P.h + (2 * (int64_t)b) * N;
     for (int i = tid; i < W; i += kNT) {
       long long j = w0 + i;
-      R hp = (R)0, hx = (R)0;
-      if (j >= 0 && j < N) {
-        cplx h = polarization<PREC>(c, P.mode_mask, P.g.t0 + (double)j * P.g.dt);
-        hp = (R)h.re;
-        hx = (R)(-h.im);
-      }
-      hpb[i] = hp;
-      hxb[i] = hx;
+      bool in = j >= 0 && j < N;
+      hpb[i] = in ? hg[j] : (R)0;
+      hxb[i] = in ? hg[N + j] : (R)0;
     }
     __syncthreads();
     // C: link responses y_slr for m in [m_lo, m_hi]
@@ -259,21 +277,30 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
       int jl = (int)(q + P.orb.j0 - jn_lo);
       double w[4];
       cubic_w((double)(m - q * S) / (double)S, w);
+      const double* o0 = nd + (jl - 1) * kNodeVals;
+      const double mloc = (double)(m - w0);
+      R hpr[3], hxr[3];
+#pragma unroll
+      for (int sc = 0; sc < 3; ++sc) {
+        double Dr = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Dr += w[r] * o0[r * kNodeVals + 6 * kNL + sc];
+        lag2<R, K>(hpb, hxb, W, mloc - Dr * inv_dt, hpr[sc], hxr[sc]);
+      }
 #pragma unroll
       for (int li = 0; li < 6; ++li) {
-        double v[4] = {0, 0, 0, 0};
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const double* o = nd + ((jl - 1 + r) * 6 + li) * kND;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] += w[r] * o[e];
+          const double* o = o0 + r * kNodeVals + li * kNL;
+          v0 += w[r] * o[0];
+          v1 += w[r] * o[1];
+          v2 += w[r] * o[2];
         }
-        double ss = (double)(m - w0) - v[2] * inv_dt;
-        double sr = (double)(m - w0) - v[3] * inv_dt;
-        R hps, hxs, hpr, hxr;
-        lag2<R, K>(hpb, hxb, W, ss, hps, hxs);
-        lag2<R, K>(hpb, hxb, W, sr, hpr, hxr);
-        yb[li * MY + mi] = (R)v[0] * (hps - hpr) + (R)v[1] * (hxs - hxr);
+        R hps, hxs;
+        lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
+        const int rc = kRecv[li];
+        yb[li * MY + mi] = (R)v0 * (hps - hpr[rc]) + (R)v1 * (hxs - hxr[rc]);
       }
     }
     __syncthreads();
@@ -295,7 +322,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
       for (int li = 0; li < 6; ++li) {
         double a = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a += w[r] * nd[((jl - 1 + r) * 6 + li) * kND + 4];
+        for (int r = 0; r < 4; ++r) a += w[r] * nd[(jl - 1 + r) * kNodeVals + li * kNL + 3];
         Lt[li] = a;
       }
       for (int cc = 0; cc < 3; ++cc) {
@@ -333,7 +360,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   }
 }
 
-template <typename R, int K, bool PREC>
+template <typename R, int K>
 static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
   int HY = (int)ceil(7.0 * P.orb.max_light_time * P.g.inv_dt * 1.001) + K / 2 + 2;
   int spread = (int)ceil(2.0 * P.orb.max_light_time * P.g.inv_dt * 1.01) + 8;
@@ -342,35 +369,33 @@ static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
   int NNMAX = MY / P.orb.spacing + 5;
   if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
   size_t bytes = (((size_t)(6 * MY + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) +
-                 (size_t)NNMAX * 6 * kND * sizeof(double);
+                 (size_t)NNMAX * kNodeVals * sizeof(double);
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void*)k_tdi<R, K, PREC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_tdi<R, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((P.g.n + kTile - 1) / kTile), (unsigned)P.batch);
-  hipLaunchKernelGGL((k_tdi<R, K, PREC>), grid, dim3(kNT), bytes, s, P, HY, WMAX, NNMAX);
+  hipLaunchKernelGGL((k_tdi<R, K>), grid, dim3(kNT), bytes, s, P, HY, WMAX, NNMAX);
   return hipGetLastError();
 }
 
-template <typename R, bool PREC>
+template <typename R>
 static hipError_t launch_tdi_k(const TdiLaunch& P, hipStream_t s) {
   switch (P.taps) {
-    case 2: return launch_tdi_t<R, 2, PREC>(P, s);
-    case 4: return launch_tdi_t<R, 4, PREC>(P, s);
-    case 6: return launch_tdi_t<R, 6, PREC>(P, s);
-    case 8: return launch_tdi_t<R, 8, PREC>(P, s);
-    case 12: return launch_tdi_t<R, 12, PREC>(P, s);
-    case 16: return launch_tdi_t<R, 16, PREC>(P, s);
-    case 24: return launch_tdi_t<R, 24, PREC>(P, s);
-    case 32: return launch_tdi_t<R, 32, PREC>(P, s);
+    case 2: return launch_tdi_t<R, 2>(P, s);
+    case 4: return launch_tdi_t<R, 4>(P, s);
+    case 6: return launch_tdi_t<R, 6>(P, s);
+    case 8: return launch_tdi_t<R, 8>(P, s);
+    case 12: return launch_tdi_t<R, 12>(P, s);
+    case 16: return launch_tdi_t<R, 16>(P, s);
+    case 24: return launch_tdi_t<R, 24>(P, s);
+    case 32: return launch_tdi_t<R, 32>(P, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_tdi(const TdiLaunch& P, hipStream_t s) {
-  if (P.precision == 0)
-    return P.precessing ? launch_tdi_k<double, true>(P, s) : launch_tdi_k<double, false>(P, s);
-  return P.precessing ? launch_tdi_k<float, true>(P, s) : launch_tdi_k<float, false>(P, s);
+  return P.precision == 0 ? launch_tdi_k<double>(P, s) : launch_tdi_k<float>(P, s);
 }
 
 }  // namespace lt

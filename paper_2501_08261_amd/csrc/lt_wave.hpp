@@ -54,6 +54,8 @@ __device__ inline cplx qmul_scalar_first(const double* a, const double* b, doubl
   return {0.0, 0.0};
 }
 
+template <typename A> __device__ inline A sb_neg(A shb, A sd) { return -shb * sd; }
+
 __device__ inline void quat_euler(double alpha, double cos_hb, double sin_hb, double gamma, double* q) {
   double ss, cs, sd, cd;
   sincos(0.5 * (alpha + gamma), &ss, &cs);
@@ -241,105 +243,175 @@ __device__ inline int setup_template(const double* p, double f_low, double f_ref
 }
 
 // ------------------------------------------------------ per-sample evaluation
-struct Orb {           // orbital-phase pieces at one sample
-  double A, u, x, cphi, sphi;
-};
-
-// Returns false before the f_low start (all modes zero).
-__device__ inline bool orbital_state(const TplConst& c, double t, Orb& o) {
+// FP64 part (phase, frequency, time): returns false before the f_low start.
+//   phi  : orbital phase (FP64, unreduced)
+//   msw  : M * omega_orb, so that u = (M omega_orb)^(1/3), x = u^2
+//   amp  : A22 when !insp (merger-ringdown); in the inspiral A22 = K_amp x
+__device__ inline bool phase_state(const TplConst& c, double t, double& phi, double& msw, double& amp,
+                                   bool& insp) {
   double tau = t - c.tc;
   if (tau < c.t_start) return false;
-  double phi_orb, w_orb;
   if (tau < c.t_m) {
     double y = c.eta_5M * (-tau);
     double th = sqrt(sqrt(1.0 / sqrt(y)));          // y^(-1/8)
     double t2 = th * th, t3 = t2 * th;
-    phi_orb = -c.inv_eta * y * t3 * (1.0 + c.a2 * t2 + c.a3 * t3 + c.a4 * t2 * t2) - c.Phi_ref;
-    w_orb = t3 / (8.0 * c.Ms) * (1.0 + 0.6 * c.a2 * t2 + 0.4 * c.a3 * t3 + 0.2 * c.a4 * t2 * t2);
-    o.u = cbrt(c.Ms * w_orb);
-    o.x = o.u * o.u;
-    o.A = c.K_amp * o.x;
+    phi = -c.inv_eta * y * t3 * (1.0 + c.a2 * t2 + c.a3 * t3 + c.a4 * t2 * t2) - c.Phi_ref;
+    msw = c.Ms * (t3 / (8.0 * c.Ms)) * (1.0 + 0.6 * c.a2 * t2 + 0.4 * c.a3 * t3 + 0.2 * c.a4 * t2 * t2);
+    insp = true;
+    amp = 0.0;
   } else {
     double z = tau * c.inv_wt;
     double w22 = c.w_lo + 0.5 * c.Delta * (1.0 + tanh(z));
     double phi22 = c.phi22_m + (c.w_lo + 0.5 * c.Delta) * (tau - c.t_m) + 0.5 * c.Delta * c.wt * (lncosh(z) - c.lncosh_tm);
-    phi_orb = 0.5 * phi22;
-    w_orb = 0.5 * w22;
-    o.u = cbrt(c.Ms * w_orb);
-    o.x = o.u * o.u;
+    phi = 0.5 * phi22;
+    msw = c.Ms * 0.5 * w22;
+    insp = false;
     if (tau < 0.0) {
       double r = tau / c.t_m;
-      o.A = c.A_p - (c.A_p - c.A_m) * r * r;
+      amp = c.A_p - (c.A_p - c.A_m) * r * r;
     } else {
-      o.A = c.A_p / cosh(tau / c.tau_rd);
+      amp = c.A_p / cosh(tau / c.tau_rd);
     }
   }
-  sincos(phi_orb, &o.sphi, &o.cphi);
   return true;
 }
 
-// The co-precessing modes with m > 0 in the order 22, 21, 33, 32, 44 (all five).
-__device__ inline void cp_modes5(const TplConst& c, const Orb& o, cplx* h) {
-  cplx E1{o.cphi, -o.sphi};
-  cplx E2 = cmul(E1, E1), E3 = cmul(E2, E1), E4 = cmul(E2, E2);
-  double a21 = o.A * c.r21 * o.u, a33 = o.A * c.r33 * o.u;
-  h[0] = cscale(E2, o.A);
-  h[1] = {-a21 * E1.im, a21 * E1.re};
-  h[2] = {-a33 * E3.im, a33 * E3.re};
-  h[3] = cscale(E2, o.A * c.r32 * o.x);
-  h[4] = cscale(E4, o.A * c.r44 * o.x);
+// phase reduced to [-pi, pi] in FP64 (two-part 2 pi), for FP32 trigonometry
+__device__ inline double reduce2pi(double x) {
+  double k = rint(x * 0.15915494309189533577);
+  double r = fma(-k, 6.283185307179586232, x);
+  return fma(-k, 2.4492935982947064e-16, r);
 }
 
-// h+ - i hx at SSB time t (including exp(2 i psi)); zero before the start.
-template <bool PREC>
-__device__ inline cplx polarization(const TplConst& c, int mode_mask, double t) {
-  Orb o;
-  if (!orbital_state(c, t, o)) return {0.0, 0.0};
-  cplx h[5];
-  cp_modes5(c, o, h);
-  cplx acc{0.0, 0.0};
+template <typename A> struct cx { A re, im; };
+template <typename A> __device__ inline cx<A> xmul(cx<A> a, cx<A> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename A> __device__ inline cx<A> xadd(cx<A> a, cx<A> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename A> __device__ inline cx<A> xsc(cx<A> a, A s) { return {a.re * s, a.im * s}; }
+template <typename A> __device__ inline cx<A> xconj(cx<A> a) { return {a.re, -a.im}; }
+
+// sin / cos of an FP64 phase in arithmetic type A
+__device__ inline void sincos_a(double x, double& s, double& c) { sincos(x, &s, &c); }
+__device__ inline void sincos_a(double x, float& s, float& c) { sincosf((float)reduce2pi(x), &s, &c); }
+__device__ inline double cbrt_a(double x, double) { return cbrt(x); }
+__device__ inline float cbrt_a(double x, float) { return cbrtf((float)x); }
+__device__ inline double rsqrt_a(double x) { return 1.0 / sqrt(x); }
+__device__ inline float rsqrt_a(float x) { return rsqrtf(x); }
+
+// W^L_M in type A with pa[k] = Qa^k (k <= 8), pb[k] = Qb^k (k <= 6)
+template <int L, int M, typename A>
+__device__ inline cx<A> wigA(const cx<A>* pa, const cx<A>* pb) {
+  constexpr int rlo = (M - 2) > 0 ? (M - 2) : 0;
+  constexpr int rhi = (L - 2) < (L + M) ? (L - 2) : (L + M);
+  const A pref = (A)__builtin_sqrt(fact(L + 2) * fact(L - 2) / (fact(L + M) * fact(L - M)));
+  cx<A> acc{(A)0, (A)0};
+#pragma unroll
+  for (int rho = rlo; rho <= rhi; ++rho) {
+    const A coef = (A)(((rho & 1) ? -1.0 : 1.0) * binom(L + M, rho) * binom(L - M, L - 2 - rho));
+    cx<A> t = xmul(xmul(pa[L + M - rho], xconj(pa[L - 2 - rho])), xmul(pb[2 - M + rho], xconj(pb[rho])));
+    acc = xadd(acc, xsc(t, coef));
+  }
+  return xsc(acc, pref);
+}
+
+// h+ - i hx at SSB time t including exp(2 i psi); zero before the start.
+// Phase, frequency and the Euler-angle phases are FP64; amplitudes, the
+// quaternion, the Wigner-D polynomials and the mode sum are in type A.
+template <typename A, bool PREC>
+__device__ inline cx<A> polarization_t(const TplConst& c, int mode_mask, double t) {
+  double phi, msw, ampd;
+  bool insp;
+  if (!phase_state(c, t, phi, msw, ampd, insp)) return {(A)0, (A)0};
+  const A u = cbrt_a(msw, (A)0);
+  const A x = u * u;
+  const A amp = insp ? (A)c.K_amp * x : (A)ampd;
+  A sphi, cphi;
+  sincos_a(phi, sphi, cphi);
+  cx<A> h[5];
+  {
+    cx<A> E1{cphi, -sphi};
+    cx<A> E2 = xmul(E1, E1);
+    A a21 = amp * (A)c.r21 * u, a33 = amp * (A)c.r33 * u;
+    h[0] = xsc(E2, amp);
+    h[1] = {-a21 * E1.im, a21 * E1.re};
+    cx<A> E3 = xmul(E2, E1);
+    h[2] = {-a33 * E3.im, a33 * E3.re};
+    h[3] = xsc(E2, amp * (A)c.r32 * x);
+    h[4] = xsc(xmul(E2, E2), amp * (A)c.r44 * x);
+  }
+  cx<A> acc{(A)0, (A)0};
   if (!PREC) {
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
       if (mode_mask & (1 << i)) {
-        cplx a{c.cp[i][0], c.cp[i][1]}, b{c.cm[i][0], c.cm[i][1]};
-        acc = cadd(acc, cadd(cmul(h[i], a), cmul(cconj(h[i]), b)));
+        cx<A> a{(A)c.cp[i][0], (A)c.cp[i][1]}, b{(A)c.cm[i][0], (A)c.cm[i][1]};
+        acc = xadd(acc, xadd(xmul(h[i], a), xmul(xconj(h[i]), b)));
       }
     }
     return acc;
-  } else {
-    // Euler angles (NNLO-form) from u, quaternion of Eq. (2.5), composite rotor
-    double u = o.u, iu = 1.0 / u, iu2 = iu * iu, iu3 = iu2 * iu;
-    double alpha = -c.Cp * ((2.0 / 3.0) * iu3 + c.sig * iu2) - c.a_ref;
-    double gamma = -c.kappa + 2.0 * c.Cp * ((1.0 / 3.0) * iu3 + 0.5 * c.sig * iu2 - 0.5 * c.vsig2 * iu) - c.g_ref;
-    double a1 = 1.0 + c.sig * u;
-    double cb = a1 / sqrt(a1 * a1 + c.vsig2 * u * u);
-    double chb = sqrt(0.5 * (1.0 + cb)), shb = sqrt(fmax(0.0, 0.5 * (1.0 - cb)));
-    double q1[4];
-    quat_euler(alpha, chb, shb, gamma, q1);
-    q1[1] = -q1[1]; q1[2] = -q1[2]; q1[3] = -q1[3];
-    double Q[4];
-    qmul_scalar_first(q1, c.Qc, Q);
-    cplx Qa{Q[0], Q[3]}, Qb{Q[2], Q[1]};
-    cplx pa[9], pb[7];
-    pa[0] = {1.0, 0.0};
-    pb[0] = {1.0, 0.0};
-#pragma unroll
-    for (int k = 1; k < 9; ++k) pa[k] = cmul(pa[k - 1], Qa);
-#pragma unroll
-    for (int k = 1; k < 7; ++k) pb[k] = cmul(pb[k - 1], Qb);
-    if (mode_mask & 1)
-      acc = cadd(acc, cadd(cmul(h[0], cscale(wig<2, 2>(pa, pb), kY2)), cmul(cconj(h[0]), cscale(wig<2, -2>(pa, pb), kY2))));
-    if (mode_mask & 2)
-      acc = cadd(acc, cadd(cmul(h[1], cscale(wig<2, 1>(pa, pb), kY2)), cmul(cconj(h[1]), cscale(wig<2, -1>(pa, pb), kY2))));
-    if (mode_mask & 4)
-      acc = cadd(acc, cadd(cmul(h[2], cscale(wig<3, 3>(pa, pb), kY3)), cmul(cconj(h[2]), cscale(wig<3, -3>(pa, pb), -kY3))));
-    if (mode_mask & 8)
-      acc = cadd(acc, cadd(cmul(h[3], cscale(wig<3, 2>(pa, pb), kY3)), cmul(cconj(h[3]), cscale(wig<3, -2>(pa, pb), -kY3))));
-    if (mode_mask & 16)
-      acc = cadd(acc, cadd(cmul(h[4], cscale(wig<4, 4>(pa, pb), kY4)), cmul(cconj(h[4]), cscale(wig<4, -4>(pa, pb), kY4))));
-    return cmul(acc, cplx{c.e2ipsi[0], c.e2ipsi[1]});
   }
+  // Euler angles (NNLO-form): u^-3 = 1 / (M omega_orb) exactly in FP64
+  const double iu3 = 1.0 / msw;
+  const double iu = 1.0 / (double)u, iu2 = iu * iu;
+  const double alpha = -c.Cp * ((2.0 / 3.0) * iu3 + c.sig * iu2) - c.a_ref;
+  const double gamma = -c.kappa + 2.0 * c.Cp * ((1.0 / 3.0) * iu3 + 0.5 * c.sig * iu2 - 0.5 * c.vsig2 * iu) - c.g_ref;
+  const A a1 = (A)1 + (A)c.sig * u;
+  const A cb = a1 * rsqrt_a(a1 * a1 + (A)c.vsig2 * x);
+  const A chb = sqrt((A)0.5 * ((A)1 + cb));
+  const A omc = (A)0.5 * ((A)1 - cb);
+  const A shb = sqrt(omc > (A)0 ? omc : (A)0);
+  A ss, cs, sd, cd;
+  sincos_a(0.5 * (alpha + gamma), ss, cs);
+  sincos_a(0.5 * (alpha - gamma), sd, cd);
+  // q1 = q(alpha, beta, gamma) (Eq. 2.5, normalised); Q = conj(q1) Qc
+  const A w1 = chb * cs, x1 = sb_neg(shb, sd), y1 = shb * cd, z1 = chb * ss;
+  const A qw = (A)c.Qc[0], qx = (A)c.Qc[1], qy = (A)c.Qc[2], qz = (A)c.Qc[3];
+  // conj(q1) = (w1, -x1, -y1, -z1)
+  const A Q0 = w1 * qw + x1 * qx + y1 * qy + z1 * qz;
+  const A Q1 = w1 * qx - x1 * qw - y1 * qz + z1 * qy;
+  const A Q2 = w1 * qy + x1 * qz - y1 * qw - z1 * qx;
+  const A Q3 = w1 * qz - x1 * qy + y1 * qx - z1 * qw;
+  const cx<A> Qa{Q0, Q3}, Qb{Q2, Q1};
+  cx<A> pa[9], pb[7];
+  pa[0] = {(A)1, (A)0};
+  pb[0] = {(A)1, (A)0};
+#pragma unroll
+  for (int k = 1; k < 9; ++k) pa[k] = xmul(pa[k - 1], Qa);
+#pragma unroll
+  for (int k = 1; k < 7; ++k) pb[k] = xmul(pb[k - 1], Qb);
+  const A y2 = (A)kY2, y3 = (A)kY3, y4 = (A)kY4;
+  if (mode_mask & 1)
+    acc = xadd(acc, xadd(xmul(h[0], xsc(wigA<2, 2>(pa, pb), y2)), xmul(xconj(h[0]), xsc(wigA<2, -2>(pa, pb), y2))));
+  if (mode_mask & 2)
+    acc = xadd(acc, xadd(xmul(h[1], xsc(wigA<2, 1>(pa, pb), y2)), xmul(xconj(h[1]), xsc(wigA<2, -1>(pa, pb), y2))));
+  if (mode_mask & 4)
+    acc = xadd(acc, xadd(xmul(h[2], xsc(wigA<3, 3>(pa, pb), y3)), xmul(xconj(h[2]), xsc(wigA<3, -3>(pa, pb), -y3))));
+  if (mode_mask & 8)
+    acc = xadd(acc, xadd(xmul(h[3], xsc(wigA<3, 2>(pa, pb), y3)), xmul(xconj(h[3]), xsc(wigA<3, -2>(pa, pb), -y3))));
+  if (mode_mask & 16)
+    acc = xadd(acc, xadd(xmul(h[4], xsc(wigA<4, 4>(pa, pb), y4)), xmul(xconj(h[4]), xsc(wigA<4, -4>(pa, pb), y4))));
+  return xmul(acc, cx<A>{(A)c.e2ipsi[0], (A)c.e2ipsi[1]});
+}
+
+// co-precessing modes (m > 0, order 22, 21, 33, 32, 44) in FP64
+__device__ inline bool cp_modes_fp64(const TplConst& c, double t, cplx* h) {
+  double phi, msw, ampd;
+  bool insp;
+  if (!phase_state(c, t, phi, msw, ampd, insp)) return false;
+  double u = cbrt(msw), x = u * u;
+  double amp = insp ? c.K_amp * x : ampd;
+  double sphi, cphi;
+  sincos(phi, &sphi, &cphi);
+  cplx E1{cphi, -sphi};
+  cplx E2 = cmul(E1, E1), E3 = cmul(E2, E1), E4 = cmul(E2, E2);
+  double a21 = amp * c.r21 * u, a33 = amp * c.r33 * u;
+  h[0] = cscale(E2, amp);
+  h[1] = {-a21 * E1.im, a21 * E1.re};
+  h[2] = {-a33 * E3.im, a33 * E3.re};
+  h[3] = cscale(E2, amp * c.r32 * x);
+  h[4] = cscale(E4, amp * c.r44 * x);
+  return true;
 }
 
 }  // namespace lt
