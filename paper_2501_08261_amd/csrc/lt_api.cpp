@@ -354,7 +354,15 @@ static TermTable make_terms(int gen) {
       Term& t = T.t[ch][i];
       t.sign = xs[i].sign;
       t.link = link_index(rot_label(xs[i].link, ch));
-      for (int d : xs[i].delays) t.cnt[link_index(rot_label(d, ch))] += 1;
+      int cnt[6] = {0, 0, 0, 0, 0, 0};
+      for (int d : xs[i].delays) cnt[link_index(rot_label(d, ch))] += 1;
+      t.nd = 0;
+      for (int li = 0; li < 6; ++li)
+        if (cnt[li]) {
+          t.dlink[t.nd] = li;
+          t.dcnt[t.nd] = cnt[li];
+          ++t.nd;
+        }
     }
   }
   return T;

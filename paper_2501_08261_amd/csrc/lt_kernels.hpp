@@ -6,9 +6,9 @@
 
 namespace lt {
 
-// One TDI term: sign * y_link(t - sum_l cnt[l] L_l(t)); links indexed
-// 0..5 for the labels 1, 2, 3, -1, -2, -3.
-struct Term { int sign, link, cnt[6]; };
+// One TDI term: sign * y_link(t - sum_k dcnt[k] L_{dlink[k]}(t)); links
+// indexed 0..5 for the labels 1, 2, 3, -1, -2, -3.
+struct Term { int sign, link, nd, dlink[4], dcnt[4]; };
 struct TermTable { int n_terms[3]; Term t[3][16]; };
 
 // Orbit node table on the device: node j sits at grid sample (j - j0) * spacing;

@@ -126,36 +126,50 @@ __device__ inline void lag_weights(R f, R* w) {
   }
 }
 
-// Interpolate array a[0..len) (zero outside) at fractional index s.
-template <typename R, int K>
-__device__ inline R lag1(const R* a, int len, double s) {
-  double fl = floor(s);
-  int j0 = (int)fl;
-  R w[K];
-  lag_weights<R, K>((R)(s - fl), w);
-  R acc = (R)0;
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    int idx = j0 - K / 2 + 1 + i;
-    idx = idx < 0 ? 0 : (idx >= len ? len - 1 : idx);   // memory safety only: windows are sized to contain every stencil
-    acc += w[i] * a[idx];
-  }
-  return acc;
+// Stencil start for fractional index s: the K taps are a[j0 - K/2 + 1 .. j0 + K/2].
+// Windows are sized so that every stencil lies inside; the clamp only keeps
+// memory accesses in bounds and never triggers for valid inputs.
+template <int K>
+__device__ inline int stencil_start(double fl, int len) {
+  int j = (int)fl - K / 2 + 1;
+  j = j < 0 ? 0 : j;
+  return j > len - K ? len - K : j;
 }
 
+// One series at fractional index s, in the product form
+//   sum_i c_i y_i prod_{j != i} d_j,  d_j = f - o_j,  c_i = 1 / prod_{j != i}(o_i - o_j),
+// accumulated left to right: S_i = S_{i-1} d_i + c_i y_i P_{i-1}, P_i = P_{i-1} d_i.
+template <typename R, int K>
+__device__ inline R lag1(const R* a, int len, double s) {
+  constexpr LagDen<K> den;
+  double fl = floor(s);
+  const R f = (R)(s - fl);
+  const R* p = a + stencil_start<K>(fl, len);
+  R P = f - (R)(-K / 2 + 1);
+  R S = (R)den.inv[0] * p[0];
+#pragma unroll
+  for (int i = 1; i < K; ++i) {
+    const R d = f - (R)(i - K / 2 + 1);
+    S = S * d + (R)den.inv[i] * p[i] * P;
+    P *= d;
+  }
+  return S;
+}
+
+// Two series sharing one set of weights (h+ and hx at the same time).
 template <typename R, int K>
 __device__ inline void lag2(const R* a, const R* b, int len, double s, R& ra, R& rb) {
   double fl = floor(s);
-  int j0 = (int)fl;
   R w[K];
   lag_weights<R, K>((R)(s - fl), w);
+  const int j = stencil_start<K>(fl, len);
+  const R* pa = a + j;
+  const R* pb = b + j;
   R acc_a = (R)0, acc_b = (R)0;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    int idx = j0 - K / 2 + 1 + i;
-    idx = idx < 0 ? 0 : (idx >= len ? len - 1 : idx);
-    acc_a += w[i] * a[idx];
-    acc_b += w[i] * b[idx];
+    acc_a += w[i] * pa[i];
+    acc_b += w[i] * pb[i];
   }
   ra = acc_a;
   rb = acc_b;
@@ -330,8 +344,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
         for (int t = 0; t < P.terms.n_terms[cc]; ++t) {
           const Term& tm = P.terms.t[cc][t];
           double D = 0.0;
-#pragma unroll
-          for (int li = 0; li < 6; ++li) D += (double)tm.cnt[li] * Lt[li];
+          for (int k = 0; k < tm.nd; ++k) D += (double)tm.dcnt[k] * Lt[tm.dlink[k]];
           double s = (double)(n - m_lo) - D * inv_dt;
           R yv = lag1<R, K>(yb + tm.link * MY, MY, s);
           acc += tm.sign > 0 ? yv : -yv;

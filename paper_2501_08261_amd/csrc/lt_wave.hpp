@@ -244,19 +244,29 @@ __device__ inline int setup_template(const double* p, double f_low, double f_ref
 
 // ------------------------------------------------------ per-sample evaluation
 // FP64 part (phase, frequency, time): returns false before the f_low start.
-//   phi  : orbital phase (FP64, unreduced)
-//   msw  : M * omega_orb, so that u = (M omega_orb)^(1/3), x = u^2
-//   amp  : A22 when !insp (merger-ringdown); in the inspiral A22 = K_amp x
-__device__ inline bool phase_state(const TplConst& c, double t, double& phi, double& msw, double& amp,
+//   phi : orbital phase (FP64, unreduced)
+//   msw : M omega_orb;  v = msw^(-1/3) = 1/u,  u = (M omega_orb)^(1/3), x = u^2
+//   amp : A22 in the merger-ringdown (inspiral: A22 = K_amp x)
+// theta = y^(-1/8) and v are seeded in FP32 and refined by NEWTON steps of
+// the multiplication-only iterations th <- th (9 - y th^8)/8 and
+// v <- v (4 - msw v^3)/3 (each squares the relative error).
+template <int NEWTON>
+__device__ inline bool phase_state(const TplConst& c, double t, double& phi, double& msw, double& v, double& amp,
                                    bool& insp) {
   double tau = t - c.tc;
   if (tau < c.t_start) return false;
   if (tau < c.t_m) {
     double y = c.eta_5M * (-tau);
-    double th = sqrt(sqrt(1.0 / sqrt(y)));          // y^(-1/8)
+    float yf = (float)y;
+    double th = (double)__builtin_amdgcn_sqrtf(__builtin_amdgcn_sqrtf(__builtin_amdgcn_rsqf(yf)));
+#pragma unroll
+    for (int k = 0; k < NEWTON; ++k) {
+      double t2 = th * th, t4 = t2 * t2;
+      th = th * (9.0 - y * (t4 * t4)) * 0.125;
+    }
     double t2 = th * th, t3 = t2 * th;
     phi = -c.inv_eta * y * t3 * (1.0 + c.a2 * t2 + c.a3 * t3 + c.a4 * t2 * t2) - c.Phi_ref;
-    msw = c.Ms * (t3 / (8.0 * c.Ms)) * (1.0 + 0.6 * c.a2 * t2 + 0.4 * c.a3 * t3 + 0.2 * c.a4 * t2 * t2);
+    msw = 0.125 * t3 * (1.0 + 0.6 * c.a2 * t2 + 0.4 * c.a3 * t3 + 0.2 * c.a4 * t2 * t2);
     insp = true;
     amp = 0.0;
   } else {
@@ -273,6 +283,10 @@ __device__ inline bool phase_state(const TplConst& c, double t, double& phi, dou
       amp = c.A_p / cosh(tau / c.tau_rd);
     }
   }
+  double vv = (double)__builtin_amdgcn_exp2f(-0.33333333f * __builtin_amdgcn_logf((float)msw));
+#pragma unroll
+  for (int k = 0; k < NEWTON; ++k) vv = vv * (4.0 - msw * (vv * vv * vv)) * (1.0 / 3.0);
+  v = vv;
   return true;
 }
 
@@ -290,40 +304,36 @@ template <typename A> __device__ inline cx<A> xmul(cx<A> a, cx<A> b) {
 template <typename A> __device__ inline cx<A> xadd(cx<A> a, cx<A> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename A> __device__ inline cx<A> xsc(cx<A> a, A s) { return {a.re * s, a.im * s}; }
 template <typename A> __device__ inline cx<A> xconj(cx<A> a) { return {a.re, -a.im}; }
+// a * b + conj(a) * c
+template <typename A> __device__ inline cx<A> pair_sum(cx<A> a, cx<A> b, cx<A> c) {
+  return {a.re * (b.re + c.re) - a.im * (b.im - c.im), a.re * (b.im + c.im) + a.im * (b.re - c.re)};
+}
 
 // sin / cos of an FP64 phase in arithmetic type A
 __device__ inline void sincos_a(double x, double& s, double& c) { sincos(x, &s, &c); }
 __device__ inline void sincos_a(double x, float& s, float& c) { sincosf((float)reduce2pi(x), &s, &c); }
-__device__ inline double cbrt_a(double x, double) { return cbrt(x); }
-__device__ inline float cbrt_a(double x, float) { return cbrtf((float)x); }
 __device__ inline double rsqrt_a(double x) { return 1.0 / sqrt(x); }
-__device__ inline float rsqrt_a(float x) { return rsqrtf(x); }
+__device__ inline float rsqrt_a(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// W^L_M in type A with pa[k] = Qa^k (k <= 8), pb[k] = Qb^k (k <= 6)
-template <int L, int M, typename A>
-__device__ inline cx<A> wigA(const cx<A>* pa, const cx<A>* pb) {
-  constexpr int rlo = (M - 2) > 0 ? (M - 2) : 0;
-  constexpr int rhi = (L - 2) < (L + M) ? (L - 2) : (L + M);
-  const A pref = (A)__builtin_sqrt(fact(L + 2) * fact(L - 2) / (fact(L + M) * fact(L - M)));
-  cx<A> acc{(A)0, (A)0};
-#pragma unroll
-  for (int rho = rlo; rho <= rhi; ++rho) {
-    const A coef = (A)(((rho & 1) ? -1.0 : 1.0) * binom(L + M, rho) * binom(L - M, L - 2 - rho));
-    cx<A> t = xmul(xmul(pa[L + M - rho], xconj(pa[L - 2 - rho])), xmul(pb[2 - M + rho], xconj(pb[rho])));
-    acc = xadd(acc, xsc(t, coef));
-  }
-  return xsc(acc, pref);
-}
+template <typename A> struct NewtonSteps;
+template <> struct NewtonSteps<double> { static constexpr int n = 2; };
+template <> struct NewtonSteps<float> { static constexpr int n = 1; };
 
 // h+ - i hx at SSB time t including exp(2 i psi); zero before the start.
 // Phase, frequency and the Euler-angle phases are FP64; amplitudes, the
 // quaternion, the Wigner-D polynomials and the mode sum are in type A.
+// The Wigner-D polynomials of Eq. (2.6) (division-free reading) reduce, with
+// a = Q_a, b = Q_b, |a|^2 = A2, |b|^2 = B2, to
+//   W2,2 = a^4, W2,1 = 2 a^3 b, W2,-1 = 2 a b^3, W2,-2 = b^4,
+//   W3,3 = -sqrt6 a^5 conj(b), W3,2 = a^4 (A2 - 5 B2), W3,-2 = b^4 (5 A2 - B2),
+//   W3,-3 = sqrt6 conj(a) b^5, W4,4 = 2 sqrt7 a^6 conj(b)^2, W4,-4 = 2 sqrt7 conj(a)^2 b^6.
 template <typename A, bool PREC>
 __device__ inline cx<A> polarization_t(const TplConst& c, int mode_mask, double t) {
-  double phi, msw, ampd;
+  double phi, msw, vd, ampd;
   bool insp;
-  if (!phase_state(c, t, phi, msw, ampd, insp)) return {(A)0, (A)0};
-  const A u = cbrt_a(msw, (A)0);
+  if (!phase_state<NewtonSteps<A>::n>(c, t, phi, msw, vd, ampd, insp)) return {(A)0, (A)0};
+  const double ud = msw * vd * vd;          // (M omega_orb)^(1/3)
+  const A u = (A)ud;
   const A x = u * u;
   const A amp = insp ? (A)c.K_amp * x : (A)ampd;
   A sphi, cphi;
@@ -351,11 +361,10 @@ __device__ inline cx<A> polarization_t(const TplConst& c, int mode_mask, double 
     }
     return acc;
   }
-  // Euler angles (NNLO-form): u^-3 = 1 / (M omega_orb) exactly in FP64
-  const double iu3 = 1.0 / msw;
-  const double iu = 1.0 / (double)u, iu2 = iu * iu;
+  // Euler angles (NNLO-form) with v = 1/u
+  const double iu2 = vd * vd, iu3 = iu2 * vd;
   const double alpha = -c.Cp * ((2.0 / 3.0) * iu3 + c.sig * iu2) - c.a_ref;
-  const double gamma = -c.kappa + 2.0 * c.Cp * ((1.0 / 3.0) * iu3 + 0.5 * c.sig * iu2 - 0.5 * c.vsig2 * iu) - c.g_ref;
+  const double gamma = -c.kappa + 2.0 * c.Cp * ((1.0 / 3.0) * iu3 + 0.5 * c.sig * iu2 - 0.5 * c.vsig2 * vd) - c.g_ref;
   const A a1 = (A)1 + (A)c.sig * u;
   const A cb = a1 * rsqrt_a(a1 * a1 + (A)c.vsig2 * x);
   const A chb = sqrt((A)0.5 * ((A)1 + cb));
@@ -365,41 +374,46 @@ __device__ inline cx<A> polarization_t(const TplConst& c, int mode_mask, double 
   sincos_a(0.5 * (alpha + gamma), ss, cs);
   sincos_a(0.5 * (alpha - gamma), sd, cd);
   // q1 = q(alpha, beta, gamma) (Eq. 2.5, normalised); Q = conj(q1) Qc
-  const A w1 = chb * cs, x1 = sb_neg(shb, sd), y1 = shb * cd, z1 = chb * ss;
+  const A w1 = chb * cs, x1 = -shb * sd, y1 = shb * cd, z1 = chb * ss;
   const A qw = (A)c.Qc[0], qx = (A)c.Qc[1], qy = (A)c.Qc[2], qz = (A)c.Qc[3];
-  // conj(q1) = (w1, -x1, -y1, -z1)
   const A Q0 = w1 * qw + x1 * qx + y1 * qy + z1 * qz;
   const A Q1 = w1 * qx - x1 * qw - y1 * qz + z1 * qy;
   const A Q2 = w1 * qy + x1 * qz - y1 * qw - z1 * qx;
   const A Q3 = w1 * qz - x1 * qy + y1 * qx - z1 * qw;
-  const cx<A> Qa{Q0, Q3}, Qb{Q2, Q1};
-  cx<A> pa[9], pb[7];
-  pa[0] = {(A)1, (A)0};
-  pb[0] = {(A)1, (A)0};
-#pragma unroll
-  for (int k = 1; k < 9; ++k) pa[k] = xmul(pa[k - 1], Qa);
-#pragma unroll
-  for (int k = 1; k < 7; ++k) pb[k] = xmul(pb[k - 1], Qb);
+  const cx<A> a{Q0, Q3}, b{Q2, Q1};
+  const A A2 = Q0 * Q0 + Q3 * Q3, B2 = Q2 * Q2 + Q1 * Q1;
+  const cx<A> a2 = xmul(a, a), b2 = xmul(b, b);
+  const cx<A> a4 = xmul(a2, a2), b4 = xmul(b2, b2);
   const A y2 = (A)kY2, y3 = (A)kY3, y4 = (A)kY4;
-  if (mode_mask & 1)
-    acc = xadd(acc, xadd(xmul(h[0], xsc(wigA<2, 2>(pa, pb), y2)), xmul(xconj(h[0]), xsc(wigA<2, -2>(pa, pb), y2))));
-  if (mode_mask & 2)
-    acc = xadd(acc, xadd(xmul(h[1], xsc(wigA<2, 1>(pa, pb), y2)), xmul(xconj(h[1]), xsc(wigA<2, -1>(pa, pb), y2))));
-  if (mode_mask & 4)
-    acc = xadd(acc, xadd(xmul(h[2], xsc(wigA<3, 3>(pa, pb), y3)), xmul(xconj(h[2]), xsc(wigA<3, -3>(pa, pb), -y3))));
-  if (mode_mask & 8)
-    acc = xadd(acc, xadd(xmul(h[3], xsc(wigA<3, 2>(pa, pb), y3)), xmul(xconj(h[3]), xsc(wigA<3, -2>(pa, pb), -y3))));
-  if (mode_mask & 16)
-    acc = xadd(acc, xadd(xmul(h[4], xsc(wigA<4, 4>(pa, pb), y4)), xmul(xconj(h[4]), xsc(wigA<4, -4>(pa, pb), y4))));
+  if (mode_mask & 1)   // (2, +-2)
+    acc = xadd(acc, xsc(pair_sum(h[0], a4, b4), y2));
+  if (mode_mask & 2) { // (2, +-1)
+    cx<A> ab = xmul(a, b);
+    acc = xadd(acc, xsc(pair_sum(h[1], xmul(a2, ab), xmul(b2, ab)), (A)2 * y2));
+  }
+  if (mode_mask & 4) { // (3, +-3): h33 W3,3 + (-1) conj(h33) W3,-3
+    const A s6 = (A)2.44948974278317809820 * y3;
+    cx<A> p = xmul(xmul(a4, a), xconj(b)), q = xmul(xmul(b4, b), xconj(a));
+    acc = xadd(acc, xsc(pair_sum(h[2], p, q), -s6));
+  }
+  if (mode_mask & 8) { // (3, +-2)
+    cx<A> p = xsc(a4, A2 - (A)5 * B2), q = xsc(b4, -((A)5 * A2 - B2));
+    acc = xadd(acc, xsc(pair_sum(h[3], p, q), y3));
+  }
+  if (mode_mask & 16) { // (4, +-4)
+    const A s7 = (A)5.29150262212918118100 * y4;
+    cx<A> p = xmul(xmul(a4, a2), xconj(b2)), q = xmul(xmul(b4, b2), xconj(a2));
+    acc = xadd(acc, xsc(pair_sum(h[4], p, q), s7));
+  }
   return xmul(acc, cx<A>{(A)c.e2ipsi[0], (A)c.e2ipsi[1]});
 }
 
 // co-precessing modes (m > 0, order 22, 21, 33, 32, 44) in FP64
 __device__ inline bool cp_modes_fp64(const TplConst& c, double t, cplx* h) {
-  double phi, msw, ampd;
+  double phi, msw, vd, ampd;
   bool insp;
-  if (!phase_state(c, t, phi, msw, ampd, insp)) return false;
-  double u = cbrt(msw), x = u * u;
+  if (!phase_state<2>(c, t, phi, msw, vd, ampd, insp)) return false;
+  double u = msw * vd * vd, x = u * u;
   double amp = insp ? c.K_amp * x : ampd;
   double sphi, cphi;
   sincos(phi, &sphi, &cphi);
