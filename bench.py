@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (known traffic) to calibrate HBM counters")
     return ap.parse_args()
 
 
@@ -157,6 +159,14 @@ def main():
         "kernels_ms": kern,
         "roofline": roof,
     }
+    if a.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4, "launches": 3}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, P, TAPS)
     ctx.close()

@@ -153,6 +153,64 @@ lt_status lt_psd_sangria(const lt_grid* grid, int generation, double arm_m, doub
 lt_status lt_profile_enable(lt_ctx* ctx, int on);
 lt_status lt_profile_read(lt_ctx* ctx, double* ms, int64_t* launches, int n_classes);
 
+
+/* ------------------------------------------------------------------------
+ * On-device parallel-tempered ensemble sampler (Sec. II.C: the paper runs
+ * ptemcee with Fisher-initialised walkers; here every step -- stretch-move
+ * proposals, prior, batched logL, Metropolis-Hastings acceptance and the
+ * adjacent-temperature swaps -- runs on the GPU and is replayed as one HIP
+ * graph).  Random numbers: Philox4x32-10 keyed by the seed, counter
+ * (step, purpose, slot, lane); one step needs no host interaction.
+ *
+ * Sampling coordinates (param_kind):
+ *   LT_PARAMS_ALIGNED10:     m1, m2, chi1z, chi2z, D_L[Mpc], iota, phi_ref, beta, lambda, psi
+ *   LT_PARAMS_PRECESSING14:  m1, m2, a1, theta1, phi1, a2, theta2, phi2, D_L[Mpc], iota, phi_ref,
+ *                            beta, lambda, psi   (spins in polar form, Tab. I)
+ *   LT_PARAMS_RAW:           the coordinates themselves (analytic test targets)
+ * Priors are uniform boxes [lo, hi] (Tab. I; beta in [-pi/2, pi/2]).
+ * Targets: LT_TARGET_TDI (lt_tdi_loglike with the stored configuration and
+ * data), LT_TARGET_GAUSS (n_gauss Gaussians sharing one inverse covariance,
+ * equal weights; for tests of the sampler itself). */
+enum { LT_PARAMS_ALIGNED10 = 0, LT_PARAMS_PRECESSING14 = 1, LT_PARAMS_RAW = 2 };
+enum { LT_TARGET_TDI = 0, LT_TARGET_GAUSS = 1 };
+
+typedef struct lt_sampler lt_sampler;
+typedef struct {
+  int n_walkers;      /* per temperature; even, >= 4 */
+  int n_temps;        /* >= 1; geometric ladder beta_i = t_max^(-i/(n_temps-1)) */
+  int dim;            /* coordinates per walker (<= 32) */
+  int param_kind;     /* LT_PARAMS_* */
+  int target;         /* LT_TARGET_* */
+  double stretch_a;   /* stretch-move scale a > 1 (2.0) */
+  double t_max;       /* hottest temperature (>= 1) */
+  uint64_t seed;
+  double t_c;         /* fixed SSB peak time for the TDI target [s] */
+  const double* lo;   /* host [dim] */
+  const double* hi;   /* host [dim] */
+  int n_gauss;        /* LT_TARGET_GAUSS: 1 or 2 */
+  const double* gauss_mean;  /* host [n_gauss][dim] */
+  const double* gauss_icov;  /* host [dim][dim] */
+} lt_sampler_cfg;
+
+/* Creates a sampler with its own context (so that the captured graph owns its
+ * scratch).  For LT_TARGET_TDI the likelihood configuration is copied; the
+ * device arrays psd->S[] and data->aet must stay valid for the sampler's life. */
+lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_wf_cfg* wf, const lt_grid* grid,
+                            const lt_orbit* orbit, const lt_tdi_cfg* tdi, const lt_psd* psd, const lt_data* data,
+                            lt_sampler** out);
+lt_status lt_sampler_destroy(lt_sampler* s);
+/* Sets every walker (host [n_temps][n_walkers][dim], temperature-major) and
+ * evaluates its log-prior and logL; resets the step counter and statistics. */
+lt_status lt_sampler_set_state(lt_sampler* s, const double* pos);
+/* Runs n_steps sampler steps (each: two half-ensemble stretch updates, then
+ * the tempering swaps) on `stream` by replaying the captured graph. */
+lt_status lt_sampler_step(lt_sampler* s, int n_steps, void* stream);
+/* Copies the state to host memory (synchronises): pos [T][W][dim], logl and
+ * logp [T][W] (nullable), step (nullable); counters (nullable, int64 [4]):
+ * accepted moves, proposed moves, accepted swaps, proposed swaps. */
+lt_status lt_sampler_get_state(lt_sampler* s, double* pos, double* logl, double* logp, uint64_t* step,
+                               int64_t* counters);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,181 @@
+"""Parallel-tempered ensemble MCMC in numpy (paper Sec. II.C).  Test infrastructure only.
+
+The paper drives its likelihood with ptemcee (parallel-tempered affine-
+invariant ensemble sampler) from Fisher-initialised walkers; its settings are
+not printed.  This oracle fixes one reading and is the step-by-step reference
+of the GPU sampler:
+
+* Goodman-Weare stretch move on the two halves of each temperature's
+  ensemble: for walker k of half h, partner j uniform in the other half,
+  z = ((a - 1) u + 1)^2 / a (density ~ 1/sqrt(z) on [1/a, a]),
+  Y = X_j + z (X_k - X_j), accepted when
+  ln u' < (d - 1) ln z + beta (logL_Y - logL_X) + (logP_Y - logP_X);
+* uniform-box prior (Tab. I ranges);
+* after both halves, adjacent-temperature swaps from the hottest pair down:
+  walker k at beta_i against walker (k + r) mod W at beta_{i+1}, accepted with
+  min(1, exp((beta_i - beta_{i+1}) (logL_{i+1} - logL_i)));
+* geometric ladder beta_i = t_max^(-i / (T - 1));
+* random numbers from Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011) keyed
+  by the seed, counter (step, purpose, slot, 0), uniforms (u + 1/2) 2^-32.
+"""
+import math
+
+import numpy as np
+
+M0, M1 = 0xD2511F53, 0xCD9E8D57
+W0, W1 = 0x9E3779B9, 0xBB67AE85
+MASK = 0xFFFFFFFF
+TAG_MOVE, TAG_SHIFT, TAG_SWAP = 0x100, 0x200, 0x300
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32 with 10 rounds on arrays of counters [..., 4] and a key (k0, k1)."""
+    c = [np.asarray(ctr[..., i], dtype=np.uint64) for i in range(4)]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    m0, m1 = np.uint64(M0), np.uint64(M1)
+    mask = np.uint64(MASK)
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + np.uint64(W0)) & mask
+            k1 = (k1 + np.uint64(W1)) & mask
+        p0 = m0 * c[0]
+        p1 = m1 * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+    return np.stack(c, axis=-1).astype(np.uint64)
+
+
+def u01(u):
+    return (np.asarray(u, dtype=np.float64) + 0.5) * 2.0 ** -32
+
+
+def _ctr(step, tag, slots, lane=0):
+    slots = np.asarray(slots, dtype=np.uint64)
+    out = np.zeros(slots.shape + (4,), dtype=np.uint64)
+    out[..., 0] = step & MASK
+    out[..., 1] = tag
+    out[..., 2] = slots
+    out[..., 3] = lane
+    return out
+
+
+def to_params(x, kind, t_c):
+    """Sampling coordinates -> 16-entry parameter rows (see include/lisatd.h)."""
+    x = np.atleast_2d(x)
+    p = np.zeros((x.shape[0], 16))
+    p[:, 0], p[:, 1] = x[:, 0], x[:, 1]
+    if kind == "precessing14":
+        for a, th, ph, col in ((2, 3, 4, 2), (5, 6, 7, 5)):
+            p[:, col] = x[:, a] * np.sin(x[:, th]) * np.cos(x[:, ph])
+            p[:, col + 1] = x[:, a] * np.sin(x[:, th]) * np.sin(x[:, ph])
+            p[:, col + 2] = x[:, a] * np.cos(x[:, th])
+        p[:, 8], p[:, 9], p[:, 10], p[:, 13], p[:, 12], p[:, 14] = x[:, 8], x[:, 9], x[:, 10], x[:, 11], x[:, 12], x[:, 13]
+    elif kind == "aligned10":
+        p[:, 4], p[:, 7] = x[:, 2], x[:, 3]
+        p[:, 8], p[:, 9], p[:, 10], p[:, 13], p[:, 12], p[:, 14] = x[:, 4], x[:, 5], x[:, 6], x[:, 7], x[:, 8], x[:, 9]
+    else:
+        raise ValueError(kind)
+    p[:, 11] = t_c
+    return p
+
+
+class PTSampler:
+    """State X [T][W][d]; logl_fn maps coordinates [n][d] to logL [n]."""
+
+    def __init__(self, logl_fn, lo, hi, n_walkers, n_temps, dim, seed, a=2.0, t_max=10.0):
+        self.logl_fn = logl_fn
+        self.lo, self.hi = np.asarray(lo, float), np.asarray(hi, float)
+        self.W, self.T, self.d, self.a = n_walkers, n_temps, dim, a
+        self.key = (seed & MASK, (seed >> 32) & MASK)
+        self.beta = np.array([t_max ** (-i / (n_temps - 1)) if n_temps > 1 else 1.0 for i in range(n_temps)])
+        self.step_count = 0
+        self.acc = self.prop = self.sacc = self.sprop = 0
+
+    def log_prior(self, x):
+        inside = np.all((x >= self.lo) & (x <= self.hi), axis=-1)
+        return np.where(inside, 0.0, -np.inf)
+
+    def set_state(self, X):
+        self.X = np.array(X, dtype=np.float64).reshape(self.T, self.W, self.d)
+        flat = self.X.reshape(-1, self.d)
+        self.logp = self.log_prior(flat).reshape(self.T, self.W)
+        self.logl = np.asarray(self.logl_fn(flat), dtype=np.float64).reshape(self.T, self.W)
+        self.step_count = 0
+        self.acc = self.prop = self.sacc = self.sprop = 0
+
+    def step(self):
+        T, W, d, half = self.T, self.W, self.d, self.W // 2
+        s = self.step_count
+        for h in (0, 1):
+            t = np.repeat(np.arange(T), half)
+            k = h * half + np.tile(np.arange(half), T)
+            r = philox4x32_10(_ctr(s, TAG_MOVE + h, t * W + k), self.key)
+            jj = np.minimum((u01(r[:, 0]) * half).astype(np.int64), half - 1)
+            j = (1 - h) * half + jj
+            z = ((self.a - 1.0) * u01(r[:, 1]) + 1.0) ** 2 / self.a
+            xk, xj = self.X[t, k], self.X[t, j]
+            Y = xj + z[:, None] * (xk - xj)
+            lpy = self.log_prior(Y)
+            lly = np.asarray(self.logl_fn(Y), dtype=np.float64)
+            la = (d - 1) * np.log(z) + self.beta[t] * (lly - self.logl[t, k]) + (lpy - self.logp[t, k])
+            with np.errstate(invalid="ignore"):
+                ok = (lpy > -np.inf) & ~np.isnan(lly) & (lly > -np.inf) & (np.log(u01(r[:, 2])) < la)
+            self.X[t[ok], k[ok]] = Y[ok]
+            self.logl[t[ok], k[ok]] = lly[ok]
+            self.logp[t[ok], k[ok]] = lpy[ok]
+            self.acc += int(ok.sum())
+            self.prop += ok.size
+        for i in range(T - 2, -1, -1):
+            rr = philox4x32_10(_ctr(s, TAG_SHIFT + i, np.array([0])), self.key)
+            shift = int(rr[0, 0] % np.uint64(W))
+            k = np.arange(W)
+            k2 = (k + shift) % W
+            ru = philox4x32_10(_ctr(s, TAG_SWAP + i, k), self.key)
+            with np.errstate(invalid="ignore"):
+                la = (self.beta[i] - self.beta[i + 1]) * (self.logl[i + 1, k2] - self.logl[i, k])
+                ok = np.log(u01(ru[:, 0])) < la
+            a_idx, b_idx = k[ok], k2[ok]
+            for arr in (self.X, self.logl, self.logp):
+                tmp = arr[i, a_idx].copy()
+                arr[i, a_idx] = arr[i + 1, b_idx]
+                arr[i + 1, b_idx] = tmp
+            self.sacc += int(ok.sum())
+            self.sprop += W
+        self.step_count += 1
+
+
+def gaussian_logl(mean, icov):
+    """Equal-weight mixture of Gaussians sharing one inverse covariance."""
+    means = np.atleast_2d(mean)
+
+    def f(x):
+        x = np.atleast_2d(x)
+        q = np.stack([-0.5 * np.einsum("ni,ij,nj->n", x - m, icov, x - m) for m in means])
+        best = q.max(axis=0)
+        return best + np.log(np.exp(q - best).sum(axis=0) / len(means))
+    return f
+
+
+def integrated_time(chain, c=5.0):
+    """Integrated autocorrelation time per coordinate of chain [steps][walkers][d]
+    (autocorrelation averaged over walkers, Sokal's window: smallest M with
+    M >= c tau(M))."""
+    chain = np.asarray(chain, dtype=np.float64)
+    n = chain.shape[0]
+    taus = []
+    for q in range(chain.shape[2]):
+        acf = np.zeros(n)
+        for w in range(chain.shape[1]):
+            x = chain[:, w, q] - chain[:, w, q].mean()
+            f = np.fft.rfft(x, 2 * n)
+            r = np.fft.irfft(f * np.conj(f))[:n]
+            if r[0] > 0:
+                acf += r / r[0]
+        acf /= chain.shape[1]
+        tau = 2.0 * np.cumsum(acf) - 1.0
+        m = np.arange(n)
+        ok = m >= c * tau
+        M = int(np.argmax(ok)) if np.any(ok) else n - 1
+        taus.append(tau[M])
+    return np.array(taus)

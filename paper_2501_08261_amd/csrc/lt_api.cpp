@@ -18,6 +18,10 @@ using namespace lt;
 
 static thread_local std::string g_err;
 
+namespace lt {
+void set_error(const std::string& msg) { g_err = msg; }
+}  // namespace lt
+
 static lt_status fail(lt_status s, const std::string& msg) {
   g_err = msg;
   return s;

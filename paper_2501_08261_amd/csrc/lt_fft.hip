@@ -238,8 +238,173 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compile-time plans for the hot size N = 2^20 (n = 2^19 = 512 x 1024).
+// Each stage reads all its butterfly inputs into registers, synchronises,
+// writes the outputs in Stockham order into the same LDS buffer, synchronises.
+template <typename R, int L, int NFFT, int RAD, int NS>
+__device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
+  constexpr int M = L / RAD;
+  constexpr int JOBS = NFFT * M;
+  constexpr int PER = (JOBS + kFT - 1) / kFT;
+  constexpr int STEP = L / (NS * RAD);
+  C2<R> v[PER][RAD];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int job = threadIdx.x + p * kFT;
+    if (JOBS % kFT == 0 || job < JOBS) {
+      const int f = job / M, j = job % M, k = j % NS;
+      const C2<R>* src = buf + f * L + j;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        v[p][r] = src[r * M];
+        if (NS > 1 && r > 0) v[p][r] = cm(v[p][r], tw[r * k * STEP]);
+      }
+      dft<R, RAD>(v[p]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int job = threadIdx.x + p * kFT;
+    if (JOBS % kFT == 0 || job < JOBS) {
+      const int f = job / M, j = job % M, k = j % NS;
+      C2<R>* dst = buf + f * L + (j / NS) * NS * RAD + k;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) dst[r * NS] = v[p][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename R, int L, int NFFT, int NS, int RAD, int... REST>
+__device__ inline void ct_fft(C2<R>* buf, const C2<R>* tw) {
+  ct_stage<R, L, NFFT, RAD, NS>(buf, tw);
+  if constexpr (sizeof...(REST) > 0) ct_fft<R, L, NFFT, NS * RAD, REST...>(buf, tw);
+}
+
+// pass 1 for n1 = 512: CB columns (128 bytes of each row) per workgroup
+template <typename R>
+__global__ __launch_bounds__(kFT) void k_pass1_512(FftPlanDev p, C2<R>* data) {
+  constexpr int N1 = 512, N2 = 1024, CB = 128 / (int)sizeof(C2<R>);
+  __shared__ C2<R> buf[CB * N1];
+  const int64_t row = blockIdx.y;
+  const int j2_0 = blockIdx.x * CB;
+  C2<R>* z = data + row * ((int64_t)N1 * N2);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < CB * N1; i += kFT) {
+    const int j1 = i / CB, jj = i % CB;
+    buf[jj * N1 + j1] = z[(int64_t)j1 * N2 + j2_0 + jj];
+  }
+  __syncthreads();
+  const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
+  ct_fft<R, N1, CB, 1, 8, 8, 8>(buf, tw);
+  const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
+  const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < CB * N1; i += kFT) {
+    const int k1 = i / CB, jj = i % CB;
+    const int j2 = j2_0 + jj;
+    const int64_t m = (int64_t)j2 * k1;
+    z[(int64_t)k1 * N2 + j2] = cm(buf[jj * N1 + k1], wN<R>(lo, hi, 2 * m));
+  }
+}
+
+// pass 2 for n2 = 1024: two row pairs (up to four rows) per workgroup
+template <typename R>
+__global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* data, int mode, double dt,
+                                                    C2<R>* spec, const double* wperm, double* partial) {
+  constexpr int N1 = 512, N2 = 1024, NR = 4;
+  constexpr int64_t n = (int64_t)N1 * N2;
+  __shared__ C2<R> buf[NR * N2];
+  __shared__ int rowk1[NR];
+  __shared__ double red[kFT / 64];
+  const int64_t row = blockIdx.y;
+  const int pa = 2 * blockIdx.x;       // pairs pa, pa + 1 (pair index <= N1/2)
+  const C2<R>* z = data + row * n;
+  // row slots: 0: pa, 1: N1 - pa, 2: pa + 1, 3: N1 - pa - 1 (-1 where absent / duplicate)
+  if (threadIdx.x == 0) {
+    int r0 = pa, r1 = (N1 - pa) % N1, r2 = pa + 1, r3 = N1 - pa - 1;
+    rowk1[0] = r0;
+    rowk1[1] = (r1 != r0) ? r1 : -1;
+    rowk1[2] = (r2 <= N1 / 2) ? r2 : -1;
+    rowk1[3] = (r2 <= N1 / 2 && r3 != r2) ? r3 : -1;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int i = threadIdx.x; i < NR * N2; i += kFT) {
+    const int r = i / N2, j2 = i % N2;
+    const int k1 = rowk1[r];
+    buf[i] = k1 >= 0 ? z[(int64_t)k1 * N2 + j2] : C2<R>{(R)0, (R)0};
+  }
+  __syncthreads();
+  const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw2d, p.tw2f);
+  ct_fft<R, N2, NR, 1, 4, 4, 8, 8>(buf, tw);
+  const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
+  const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
+  double acc = 0.0;
+  const int64_t ch = row % 3;
+  for (int i = threadIdx.x; i < NR * N2 + 1; i += kFT) {
+    int64_t k;
+    C2<R> Zk, Zm;
+    int k1, k2;
+    if (i < NR * N2) {
+      const int r = i / N2;
+      k2 = i % N2;
+      k1 = rowk1[r];
+      if (k1 < 0) continue;
+      k = k1 + (int64_t)N1 * k2;
+      Zk = buf[i];
+      if (k1 == 0) {
+        Zm = buf[r * N2 + (N2 - k2) % N2];
+      } else {
+        const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
+        Zm = buf[rm * N2 + (N2 - 1 - k2)];
+      }
+    } else {
+      if (pa != 0) continue;
+      k = n;            // Nyquist: Z_n = Z_0
+      k1 = 0;
+      k2 = 0;
+      Zk = buf[0];
+      Zm = buf[0];
+    }
+    C2<R> zc = {Zm.x, -Zm.y};
+    C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
+    C2<R> wk = (k == n) ? C2<R>{(R)-1, (R)0} : wN<R>(lo, hi, k);
+    C2<R> X = sm + mi(cm(wk, df));
+    if (mode == 0) {
+      spec[row * (n + 1) + k] = sc(X, (R)dt);
+    } else {
+      const int64_t widx = (k == n) ? n : (int64_t)k1 * N2 + k2;
+      const double wv = wperm[ch * (n + 1) + widx];
+      const double xr = (double)X.x, xi = (double)X.y;
+      acc += wv * (xr * xr + xi * xi);
+    }
+  }
+  if (mode != 0) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int i = 0; i < kFT / 64; ++i) t += red[i];
+      partial[row * (N1 / 2 + 1) + pa] = t;
+      if (pa + 1 <= N1 / 2) partial[row * (N1 / 2 + 1) + pa + 1] = 0.0;
+    }
+  }
+}
+
+static bool hot_plan(const FftPlanDev& p) { return p.n1 == 512 && p.n2 == 1024; }
+
 template <typename R>
 static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, hipStream_t s) {
+  if (hot_plan(p)) {
+    constexpr int CB = 128 / (int)sizeof(C2<R>);
+    dim3 grid((unsigned)(p.n2 / CB), (unsigned)rows);
+    hipLaunchKernelGGL(k_pass1_512<R>, grid, dim3(kFT), 0, s, p, (C2<R>*)data);
+    return hipGetLastError();
+  }
   size_t bytes = 2 * (size_t)kCB * p.n1 * sizeof(C2<R>);
   hipError_t e = hipFuncSetAttribute((const void*)k_pass1<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
@@ -255,6 +420,12 @@ hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int p
 template <typename R>
 static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mode, double dt, void* spec,
                      const double* wperm, int64_t ch_rows, double* partial, hipStream_t s) {
+  if (hot_plan(p)) {
+    dim3 grid((unsigned)((p.n1 / 2 + 2) / 2), (unsigned)rows);
+    hipLaunchKernelGGL(k_pass2_1024<R>, grid, dim3(kFT), 0, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
+                       partial);
+    return hipGetLastError();
+  }
   size_t bytes = 4 * (size_t)p.n2 * sizeof(C2<R>);
   hipError_t e = hipFuncSetAttribute((const void*)k_pass2<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
@@ -299,25 +470,29 @@ hipError_t launch_weights(const FftPlanDev& p, const double* const* S, int k_lo,
 }
 
 // per template: sum over 3 channels x npairs partial sums in a fixed order
-__global__ void k_finalize(const double* partial, int64_t batch, int npairs, double scale, double dd,
-                           const int32_t* status, double* logl, double* logl_full, double* inner) {
-  int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  double s = 0.0;
-  for (int c = 0; c < 3; ++c) {
-    const double* q = partial + (b * 3 + c) * npairs;
-    double cs = 0.0, comp = 0.0;
-    for (int i = 0; i < npairs; ++i) {      // Kahan-compensated
-      double y = q[i] - comp;
-      double t = cs + y;
-      comp = (t - cs) - y;
-      cs = t;
-    }
-    s += cs;
+// (per-thread compensated strided sums, then a pairwise wavefront / block tree)
+__global__ __launch_bounds__(256) void k_finalize(const double* partial, int npairs, double scale, double dd,
+                                                  const int32_t* status, double* logl, double* logl_full,
+                                                  double* inner) {
+  __shared__ double red[4];
+  const int64_t b = blockIdx.x;
+  const double* q = partial + b * 3 * npairs;
+  const int total = 3 * npairs;
+  double cs = 0.0, comp = 0.0;
+  for (int i = threadIdx.x; i < total; i += 256) {
+    double y = q[i] - comp;
+    double t = cs + y;
+    comp = (t - cs) - y;
+    cs = t;
   }
-  double rr = scale * s;
+  for (int off = 32; off > 0; off >>= 1) cs += __shfl_down(cs, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cs;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double s = (red[0] + red[1]) + (red[2] + red[3]);
+  const double rr = scale * s;
   if (inner) inner[b] = rr;
-  bool bad = status && status[b] != 0;
+  const bool bad = status && status[b] != 0;
   double full = bad ? -INFINITY : -0.5 * rr;
   if (!bad && !isfinite(full)) full = -INFINITY;
   if (logl_full) logl_full[b] = full;
@@ -326,9 +501,8 @@ __global__ void k_finalize(const double* partial, int64_t batch, int npairs, dou
 
 hipError_t launch_finalize(const double* partial, int64_t batch, int npairs, double scale, double dd,
                            const int32_t* status, double* logl, double* logl_full, double* inner, hipStream_t s) {
-  dim3 grid((unsigned)((batch + 63) / 64));
-  hipLaunchKernelGGL(k_finalize, grid, dim3(64), 0, s, partial, batch, npairs, scale, dd, status, logl, logl_full,
-                     inner);
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)batch), dim3(256), 0, s, partial, npairs, scale, dd, status, logl,
+                     logl_full, inner);
   return hipGetLastError();
 }
 

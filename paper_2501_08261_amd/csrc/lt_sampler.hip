@@ -1,0 +1,412 @@
+// On-device parallel-tempered ensemble sampler (hot-path step a11).
+//
+// Per step: for each half of every temperature's ensemble, a Goodman-Weare
+// stretch proposal Y = X_j + z (X_k - X_j) against a random walker j of the
+// other half, z ~ g(z) on [1/a, a] with g ~ 1/sqrt(z); uniform-box prior;
+// batched logL of all proposals; Metropolis-Hastings with
+// log alpha = (d - 1) ln z + beta_T (logL_Y - logL_X) + (logP_Y - logP_X);
+// then adjacent-temperature swaps (hottest pair first) between walker k at
+// beta_i and walker (k + r) mod W at beta_{i+1}, accepted with
+// min(1, exp((beta_i - beta_{i+1}) (logL_{i+1} - logL_i))).
+// Random numbers: Philox4x32-10 (Salmon et al. 2011), key = seed, counter =
+// (step, purpose, slot, 0), uniforms (u + 1/2) 2^-32.  One step is captured
+// once as a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lisatd.h"
+
+namespace lt_s {
+
+__host__ __device__ inline void philox4x32_10(uint32_t* c, uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+
+__device__ inline double u01(uint32_t u) { return ((double)u + 0.5) * 2.3283064365386963e-10; }
+
+constexpr uint32_t kTagMove = 0x100, kTagShift = 0x200, kTagSwap = 0x300;
+constexpr int kMaxDim = 32;
+
+struct Dev {
+  int T, W, d, kind, target, n_gauss;
+  double a, t_c;
+  uint32_t k0, k1;
+  double *X, *logl, *logp, *beta;
+  double *Y, *ylogl, *ylogp, *ylogz, *yu;
+  double* params;           // [T*W][16] (set_state) / [T*W/2][16] (proposals)
+  double *lo, *hi, *gmean, *gicov;
+  uint64_t* step;
+  int64_t *acc, *prop, *sacc, *sprop;
+};
+
+__device__ inline void to_params(const Dev& D, const double* x, double* p) {
+  for (int i = 0; i < 16; ++i) p[i] = 0.0;
+  p[0] = x[0];
+  p[1] = x[1];
+  if (D.kind == LT_PARAMS_PRECESSING14) {
+    double s1, c1, s2, c2;
+    sincos(x[3], &s1, &c1);
+    sincos(x[4], &s2, &c2);
+    p[2] = x[2] * s1 * c2; p[3] = x[2] * s1 * s2; p[4] = x[2] * c1;
+    sincos(x[6], &s1, &c1);
+    sincos(x[7], &s2, &c2);
+    p[5] = x[5] * s1 * c2; p[6] = x[5] * s1 * s2; p[7] = x[5] * c1;
+    p[8] = x[8]; p[9] = x[9]; p[10] = x[10]; p[13] = x[11]; p[12] = x[12]; p[14] = x[13];
+  } else {
+    p[4] = x[2]; p[7] = x[3];
+    p[8] = x[4]; p[9] = x[5]; p[10] = x[6]; p[13] = x[7]; p[12] = x[8]; p[14] = x[9];
+  }
+  p[11] = D.t_c;
+}
+
+__device__ inline double log_prior(const Dev& D, const double* x) {
+  for (int i = 0; i < D.d; ++i)
+    if (!(x[i] >= D.lo[i] && x[i] <= D.hi[i])) return -INFINITY;
+  return 0.0;
+}
+
+// proposals for half h: one thread per (temperature, walker of the half)
+__global__ void k_propose(Dev D, int h) {
+  const int half = D.W / 2;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= D.T * half) return;
+  const int t = idx / half, kk = idx - t * half;
+  const int k = h * half + kk;
+  uint32_t c[4] = {(uint32_t)*D.step, kTagMove + (uint32_t)h, (uint32_t)(t * D.W + k), 0u};
+  philox4x32_10(c, D.k0, D.k1);
+  int jj = (int)(u01(c[0]) * half);
+  jj = jj < half ? jj : half - 1;
+  const int j = (1 - h) * half + jj;
+  const double zr = (D.a - 1.0) * u01(c[1]) + 1.0;
+  const double z = zr * zr / D.a;
+  const double* xk = D.X + ((int64_t)t * D.W + k) * D.d;
+  const double* xj = D.X + ((int64_t)t * D.W + j) * D.d;
+  double* y = D.Y + (int64_t)idx * D.d;
+  for (int i = 0; i < D.d; ++i) y[i] = xj[i] + z * (xk[i] - xj[i]);
+  D.ylogz[idx] = log(z);
+  D.yu[idx] = u01(c[2]);
+  D.ylogp[idx] = log_prior(D, y);
+  if (D.target == LT_TARGET_TDI) to_params(D, y, D.params + (int64_t)idx * 16);
+}
+
+// all walkers (set_state): prior and parameter rows
+__global__ void k_prepare_all(Dev D) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= D.T * D.W) return;
+  const double* x = D.X + (int64_t)idx * D.d;
+  D.logp[idx] = log_prior(D, x);
+  if (D.target == LT_TARGET_TDI) to_params(D, x, D.params + (int64_t)idx * 16);
+}
+
+// analytic test target: log of an equal-weight mixture of Gaussians
+__global__ void k_gauss(Dev D, const double* xs, int64_t count, double* out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= count) return;
+  const double* x = xs + idx * D.d;
+  double best = -INFINITY, q[2];
+  for (int m = 0; m < D.n_gauss; ++m) {
+    double dx[kMaxDim];
+    for (int i = 0; i < D.d; ++i) dx[i] = x[i] - D.gmean[m * D.d + i];
+    double s = 0.0;
+    for (int i = 0; i < D.d; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < D.d; ++j) r += D.gicov[i * D.d + j] * dx[j];
+      s += dx[i] * r;
+    }
+    q[m] = -0.5 * s;
+    best = fmax(best, q[m]);
+  }
+  double acc = 0.0;
+  for (int m = 0; m < D.n_gauss; ++m) acc += exp(q[m] - best);
+  out[idx] = best + log(acc / D.n_gauss);
+}
+
+__global__ void k_accept(Dev D, int h) {
+  const int half = D.W / 2;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= D.T * half) return;
+  const int t = idx / half, kk = idx - t * half;
+  const int64_t w = (int64_t)t * D.W + h * half + kk;
+  const double lly = D.ylogl[idx], lpy = D.ylogp[idx];
+  const double la = (D.d - 1) * D.ylogz[idx] + D.beta[t] * (lly - D.logl[w]) + (lpy - D.logp[w]);
+  const bool ok = lpy > -INFINITY && !isnan(lly) && lly > -INFINITY && log(D.yu[idx]) < la;
+  if (ok) {
+    const double* y = D.Y + (int64_t)idx * D.d;
+    double* x = D.X + w * D.d;
+    for (int i = 0; i < D.d; ++i) x[i] = y[i];
+    D.logl[w] = lly;
+    D.logp[w] = lpy;
+  }
+  D.acc[w] += ok ? 1 : 0;
+  D.prop[w] += 1;
+}
+
+// tempering swaps, hottest adjacent pair first; one workgroup, then the step counter advances
+__global__ void k_swap(Dev D) {
+  const uint64_t step = *D.step;
+  for (int i = D.T - 2; i >= 0; --i) {
+    uint32_t c[4] = {(uint32_t)step, kTagShift + (uint32_t)i, 0u, 0u};
+    philox4x32_10(c, D.k0, D.k1);
+    const int r = (int)(c[0] % (uint32_t)D.W);
+    const double db = D.beta[i] - D.beta[i + 1];
+    for (int k = threadIdx.x; k < D.W; k += blockDim.x) {
+      const int k2 = (k + r) % D.W;
+      const int64_t a = (int64_t)i * D.W + k, b = (int64_t)(i + 1) * D.W + k2;
+      uint32_t e[4] = {(uint32_t)step, kTagSwap + (uint32_t)i, (uint32_t)k, 0u};
+      philox4x32_10(e, D.k0, D.k1);
+      const double la = db * (D.logl[b] - D.logl[a]);
+      const bool ok = log(u01(e[0])) < la;
+      if (ok) {
+        for (int q = 0; q < D.d; ++q) {
+          double tmp = D.X[a * D.d + q];
+          D.X[a * D.d + q] = D.X[b * D.d + q];
+          D.X[b * D.d + q] = tmp;
+        }
+        double tl = D.logl[a]; D.logl[a] = D.logl[b]; D.logl[b] = tl;
+        double tp = D.logp[a]; D.logp[a] = D.logp[b]; D.logp[b] = tp;
+      }
+      D.sacc[a] += ok ? 1 : 0;
+      D.sprop[a] += 1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *D.step = step + 1;
+}
+
+}  // namespace lt_s
+
+using namespace lt_s;
+
+namespace lt {
+void set_error(const std::string& msg);   // thread-local message returned by lt_last_error()
+}
+
+struct lt_sampler {
+  int device = 0;
+  lt_sampler_cfg cfg{};
+  lt_wf_cfg wf{};
+  lt_grid grid{};
+  lt_orbit orbit{};
+  lt_tdi_cfg tdi{};
+  lt_psd psd{};
+  lt_data data{};
+  lt_ctx* ctx = nullptr;
+  Dev D{};
+  std::vector<void*> allocs;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+#define S_HIP(call)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      lt::set_error(std::string(#call) + ": " + hipGetErrorString(e_));             \
+      return LT_ERR_DEVICE;                                                          \
+    }                                                                                \
+  } while (0)
+
+template <typename T>
+static lt_status salloc(lt_sampler* s, T** p, size_t count) {
+  void* q = nullptr;
+  S_HIP(hipMalloc(&q, count * sizeof(T) + 64));
+  s->allocs.push_back(q);
+  *p = (T*)q;
+  return LT_OK;
+}
+
+static lt_status sfail(lt_status st, const char* msg) {
+  lt::set_error(msg);
+  return st;
+}
+
+// logL of `count` parameter rows / coordinates on the capture or default stream
+static lt_status eval_logl(lt_sampler* s, const double* xs, int64_t count, double* out, hipStream_t st) {
+  if (s->cfg.target == LT_TARGET_GAUSS) {
+    hipLaunchKernelGGL(k_gauss, dim3((unsigned)((count + 127) / 128)), dim3(128), 0, st, s->D, xs, count, out);
+    S_HIP(hipGetLastError());
+    return LT_OK;
+  }
+  lt_status r = lt_tdi_loglike(s->ctx, s->D.params, count, &s->wf, &s->grid, &s->orbit, &s->tdi, &s->psd, &s->data,
+                               out, nullptr, nullptr, st);
+  if (r != LT_OK) lt::set_error(std::string("logL: ") + lt_last_error());
+  return r;
+}
+
+static lt_status record_step(lt_sampler* s, hipStream_t st) {
+  const int half = s->cfg.n_walkers / 2;
+  const int n = s->cfg.n_temps * half;
+  for (int h = 0; h < 2; ++h) {
+    hipLaunchKernelGGL(k_propose, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h);
+    S_HIP(hipGetLastError());
+    lt_status r = eval_logl(s, s->D.Y, n, s->D.ylogl, st);
+    if (r != LT_OK) return r;
+    hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h);
+    S_HIP(hipGetLastError());
+  }
+  const int nt = s->cfg.n_walkers < 1024 ? s->cfg.n_walkers : 1024;
+  hipLaunchKernelGGL(k_swap, dim3(1), dim3((unsigned)((nt + 63) / 64 * 64)), 0, st, s->D);
+  S_HIP(hipGetLastError());
+  return LT_OK;
+}
+
+extern "C" {
+
+lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_wf_cfg* wf, const lt_grid* grid,
+                            const lt_orbit* orbit, const lt_tdi_cfg* tdi, const lt_psd* psd, const lt_data* data,
+                            lt_sampler** out) {
+  if (!cfg || !out || !cfg->lo || !cfg->hi) return sfail(LT_ERR_NULL, "null sampler argument");
+  if (cfg->n_walkers < 4 || cfg->n_walkers % 2 || cfg->n_walkers > 65536) return sfail(LT_ERR_SHAPE, "n_walkers");
+  if (cfg->n_temps < 1 || cfg->n_temps > 64) return sfail(LT_ERR_SHAPE, "n_temps");
+  if (cfg->dim < 1 || cfg->dim > kMaxDim) return sfail(LT_ERR_SHAPE, "dim");
+  if (!(cfg->stretch_a > 1.0) || !(cfg->t_max >= 1.0)) return sfail(LT_ERR_CONFIG, "stretch_a > 1, t_max >= 1");
+  if (cfg->target == LT_TARGET_TDI) {
+    if (!wf || !grid || !orbit || !tdi || !psd || !data) return sfail(LT_ERR_NULL, "TDI target needs the likelihood");
+    int need = cfg->param_kind == LT_PARAMS_PRECESSING14 ? 14 : (cfg->param_kind == LT_PARAMS_ALIGNED10 ? 10 : -1);
+    if (need != cfg->dim) return sfail(LT_ERR_CONFIG, "param_kind does not match dim");
+    if ((int64_t)cfg->n_temps * cfg->n_walkers > 65535) return sfail(LT_ERR_SHAPE, "too many walkers for one batch");
+  } else if (cfg->target == LT_TARGET_GAUSS) {
+    if (!cfg->gauss_mean || !cfg->gauss_icov || cfg->n_gauss < 1 || cfg->n_gauss > 2)
+      return sfail(LT_ERR_CONFIG, "Gaussian target needs 1 or 2 means and an inverse covariance");
+  } else {
+    return sfail(LT_ERR_CONFIG, "target");
+  }
+  S_HIP(hipSetDevice(hip_device));
+  lt_sampler* s = new lt_sampler();
+  s->device = hip_device;
+  s->cfg = *cfg;
+  if (cfg->target == LT_TARGET_TDI) {
+    s->wf = *wf; s->grid = *grid; s->orbit = *orbit; s->tdi = *tdi; s->psd = *psd; s->data = *data;
+    if (lt_ctx_create(hip_device, &s->ctx) != LT_OK) {
+      delete s;
+      return sfail(LT_ERR_DEVICE, "context");
+    }
+  }
+  const int T = cfg->n_temps, W = cfg->n_walkers, d = cfg->dim;
+  Dev& D = s->D;
+  D.T = T; D.W = W; D.d = d; D.kind = cfg->param_kind; D.target = cfg->target; D.n_gauss = cfg->n_gauss;
+  D.a = cfg->stretch_a; D.t_c = cfg->t_c;
+  D.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
+  D.k1 = (uint32_t)(cfg->seed >> 32);
+  lt_status r = LT_OK;
+  const size_t TW = (size_t)T * W;
+  if ((r = salloc(s, &D.X, TW * d)) || (r = salloc(s, &D.logl, TW)) || (r = salloc(s, &D.logp, TW)) ||
+      (r = salloc(s, &D.beta, T)) || (r = salloc(s, &D.Y, TW / 2 * d)) || (r = salloc(s, &D.ylogl, TW / 2)) ||
+      (r = salloc(s, &D.ylogp, TW / 2)) || (r = salloc(s, &D.ylogz, TW / 2)) || (r = salloc(s, &D.yu, TW / 2)) ||
+      (r = salloc(s, &D.params, TW * 16)) || (r = salloc(s, &D.lo, d)) || (r = salloc(s, &D.hi, d)) ||
+      (r = salloc(s, &D.gmean, 2 * d)) || (r = salloc(s, &D.gicov, (size_t)d * d)) || (r = salloc(s, &D.step, 1)) ||
+      (r = salloc(s, &D.acc, TW)) || (r = salloc(s, &D.prop, TW)) || (r = salloc(s, &D.sacc, TW)) ||
+      (r = salloc(s, &D.sprop, TW))) {
+    lt_sampler_destroy(s);
+    return r;
+  }
+  std::vector<double> beta(T);
+  for (int i = 0; i < T; ++i) beta[i] = T > 1 ? std::pow(cfg->t_max, -(double)i / (double)(T - 1)) : 1.0;
+  S_HIP(hipMemcpy(D.beta, beta.data(), T * sizeof(double), hipMemcpyHostToDevice));
+  S_HIP(hipMemcpy(D.lo, cfg->lo, d * sizeof(double), hipMemcpyHostToDevice));
+  S_HIP(hipMemcpy(D.hi, cfg->hi, d * sizeof(double), hipMemcpyHostToDevice));
+  if (cfg->target == LT_TARGET_GAUSS) {
+    S_HIP(hipMemcpy(D.gmean, cfg->gauss_mean, (size_t)cfg->n_gauss * d * sizeof(double), hipMemcpyHostToDevice));
+    S_HIP(hipMemcpy(D.gicov, cfg->gauss_icov, (size_t)d * d * sizeof(double), hipMemcpyHostToDevice));
+  }
+  S_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+  s->cfg.lo = s->cfg.hi = s->cfg.gauss_mean = s->cfg.gauss_icov = nullptr;
+  *out = s;
+  return LT_OK;
+}
+
+lt_status lt_sampler_destroy(lt_sampler* s) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  (void)hipSetDevice(s->device);
+  (void)hipDeviceSynchronize();
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->cap) (void)hipStreamDestroy(s->cap);
+  for (void* p : s->allocs) (void)hipFree(p);
+  if (s->ctx) lt_ctx_destroy(s->ctx);
+  delete s;
+  return LT_OK;
+}
+
+lt_status lt_sampler_set_state(lt_sampler* s, const double* pos) {
+  if (!s || !pos) return sfail(LT_ERR_NULL, "null argument");
+  S_HIP(hipSetDevice(s->device));
+  const int64_t TW = (int64_t)s->cfg.n_temps * s->cfg.n_walkers;
+  S_HIP(hipMemcpy(s->D.X, pos, TW * s->cfg.dim * sizeof(double), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_prepare_all, dim3((unsigned)((TW + 127) / 128)), dim3(128), 0, s->cap, s->D);
+  S_HIP(hipGetLastError());
+  lt_status r = eval_logl(s, s->D.X, TW, s->D.logl, s->cap);
+  if (r != LT_OK) return r;
+  std::vector<int64_t> z(TW, 0);
+  uint64_t zero = 0;
+  S_HIP(hipMemcpyAsync(s->D.step, &zero, sizeof(uint64_t), hipMemcpyHostToDevice, s->cap));
+  for (int64_t* p : {s->D.acc, s->D.prop, s->D.sacc, s->D.sprop})
+    S_HIP(hipMemcpyAsync(p, z.data(), TW * sizeof(int64_t), hipMemcpyHostToDevice, s->cap));
+  S_HIP(hipStreamSynchronize(s->cap));
+  return LT_OK;
+}
+
+lt_status lt_sampler_step(lt_sampler* s, int n_steps, void* stream) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  if (n_steps < 0) return sfail(LT_ERR_SHAPE, "n_steps");
+  S_HIP(hipSetDevice(s->device));
+  if (!s->exec) {
+    S_HIP(hipStreamSynchronize(s->cap));
+    S_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+    lt_status r = record_step(s, s->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->cap, &g);
+    if (r != LT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    S_HIP(e);
+    s->graph = g;
+    S_HIP(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+  }
+  for (int i = 0; i < n_steps; ++i) S_HIP(hipGraphLaunch(s->exec, (hipStream_t)stream));
+  return LT_OK;
+}
+
+lt_status lt_sampler_get_state(lt_sampler* s, double* pos, double* logl, double* logp, uint64_t* step,
+                               int64_t* counters) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  const int64_t TW = (int64_t)s->cfg.n_temps * s->cfg.n_walkers;
+  if (pos) S_HIP(hipMemcpy(pos, s->D.X, TW * s->cfg.dim * sizeof(double), hipMemcpyDeviceToHost));
+  if (logl) S_HIP(hipMemcpy(logl, s->D.logl, TW * sizeof(double), hipMemcpyDeviceToHost));
+  if (logp) S_HIP(hipMemcpy(logp, s->D.logp, TW * sizeof(double), hipMemcpyDeviceToHost));
+  if (step) S_HIP(hipMemcpy(step, s->D.step, sizeof(uint64_t), hipMemcpyDeviceToHost));
+  if (counters) {
+    std::vector<int64_t> v(TW);
+    int64_t* src[4] = {s->D.acc, s->D.prop, s->D.sacc, s->D.sprop};
+    for (int q = 0; q < 4; ++q) {
+      S_HIP(hipMemcpy(v.data(), src[q], TW * sizeof(int64_t), hipMemcpyDeviceToHost));
+      int64_t t = 0;
+      for (int64_t x : v) t += x;
+      counters[q] = t;
+    }
+  }
+  return LT_OK;
+}
+
+}  // extern "C"

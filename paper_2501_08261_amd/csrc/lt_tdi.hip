@@ -202,7 +202,13 @@ __constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacec
 //  C: y_slr for the tile plus the TDI halos; h is interpolated with K taps at
 //     the three receiver times and the six sender times (LDS)
 //  D: X, Y, Z from y interpolated at the TDI delays, then A, E, T (global)
-template <typename R, int K>
+// Per (TDI term, node interval) reference: the stencil start and fraction at
+// the interval midpoint; the fraction of output n is f0 - delta(n) with
+// delta(n) = (D(t_n) - D(t_ref)) / dt, cubic in the node values dn.
+constexpr int kTerms = 48;          // 3 channels x at most 16 terms
+constexpr int kNV = kTile / 256;    // node intervals per tile (node spacing 256)
+
+template <typename R, int K, bool TAY>
 __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long s_w0;
@@ -219,6 +225,11 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   R* hpb = yb + 6 * MY;
   R* hxb = hpb + WMAX;
   double* nd = (double*)(smem + (((size_t)(6 * MY + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15));
+  double* tf0 = nd + NNMAX * kNodeVals;                    // [kTerms * kNV] reference fraction
+  int* tjr = (int*)(tf0 + kTerms * kNV);                   // [kTerms * kNV] reference stencil index
+  int* tflag = tjr + kTerms * kNV;                         // 0 Taylor, 1 direct, 2 zero delay
+  R* tdn = (R*)(tflag + kTerms * kNV);                     // [kTerms * kNV][4] node offsets in samples
+  R* tco = tdn + kTerms * kNV * 4;                         // [kTerms * kNV][2][K] weights and derivatives
   const double inv_dt = P.g.inv_dt;
   const int64_t m_lo = n0 - HY, m_hi = m_lo + MY - 1;
   const int S = P.orb.spacing;
@@ -319,54 +330,160 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     }
     __syncthreads();
   }
-  // D: TDI and A, E, T
+  // E: per (term, interval) references for the TDI delays
+  const int S2 = S / 2;
+  for (int e = tid; e < kTerms * kNV; e += kNT) {
+    const int tg = e / kNV, v = e - tg * kNV;
+    const int cc = tg >> 4, t = tg & 15;
+    if (t >= P.terms.n_terms[cc]) continue;
+    const Term& tm = P.terms.t[cc][t];
+    const int64_t nv0 = n0 + (int64_t)v * S;
+    const int jlv = (int)(floordiv(nv0, S) + P.orb.j0 - jn_lo);
+    double D[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double a = 0.0;
+      for (int k = 0; k < tm.nd; ++k) a += (double)tm.dcnt[k] * nd[(jlv - 1 + r) * kNodeVals + tm.dlink[k] * kNL + 3];
+      D[r] = a;
+    }
+    // cubic interpolant at the interval midpoint (weights -1/16, 9/16, 9/16, -1/16)
+    const double Dref = (-D[0] + 9.0 * D[1] + 9.0 * D[2] - D[3]) * 0.0625;
+    const double sref = (double)(nv0 + S2 - m_lo) - Dref * inv_dt;
+    const double fl = floor(sref);
+    const double f0 = sref - fl;
+    double db = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double dn = (D[r] - Dref) * inv_dt;
+      tdn[e * 4 + r] = (R)dn;
+      db = fmax(db, fabs(dn));
+    }
+    db *= 1.25;   // bound of the cubic interpolant over the interval
+    // first-order weights are exact to 1.6 K delta^2 relative: keep that below 2e-8
+    const double thr = TAY ? sqrt(2e-8 / (1.6 * K)) : -1.0;
+    int flag;
+    if (tm.nd == 0) flag = 2;
+    else if (db <= thr && f0 - db >= 0.0 && f0 + db < 1.0) flag = 0;
+    else flag = 1;
+    tf0[e] = f0;
+    tjr[e] = (int)fl;
+    tflag[e] = flag;
+  }
+  __syncthreads();
+  if (TAY) {
+    constexpr LagDen<K> den;
+    for (int it = tid; it < kTerms * kNV * K; it += kNT) {
+      const int e = it / K, i = it - e * K;
+      const int tg = e / kNV;
+      if ((tg & 15) >= P.terms.n_terms[tg >> 4] || tflag[e] != 0) continue;
+      const double f0 = tf0[e];
+      double c0 = den.inv[i], c1 = 0.0;   // truncated product of (f0 + x - o_j), j != i
+      for (int j = 0; j < K; ++j) {
+        if (j == i) continue;
+        const double aj = f0 - (double)(j - K / 2 + 1);
+        c1 = c1 * aj + c0;
+        c0 = c0 * aj;
+      }
+      tco[(e * 2) * K + i] = (R)c0;
+      tco[(e * 2 + 1) * K + i] = (R)c1;
+    }
+  }
+  __syncthreads();
+
+  // D: TDI and A, E, T; each thread owns four consecutive output samples
   const R* data = (const R*)P.data;
   R* out = (R*)P.out;
-  for (int ni = tid; ni < kTile; ni += kNT) {
-    int64_t n = n0 + ni;
-    if (n >= N) break;
-    R ch[3] = {(R)0, (R)0, (R)0};
-    if (!skip) {
-      int64_t q = floordiv(n, S);
-      int jl = (int)(q + P.orb.j0 - jn_lo);
+  const int nl0 = 4 * tid;
+  const int64_t nb = n0 + nl0;
+  if (nb >= N) return;
+  R ch[3][4];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ch[cc][k] = (R)0;
+  if (!skip) {
+    const int v = nl0 / S;
+    const int64_t nref = n0 + (int64_t)v * S + S2;
+    R cw[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
       double w[4];
-      cubic_w((double)(n - q * S) / (double)S, w);
-      double Lt[6];
+      cubic_w((double)(nl0 - v * S + k) / (double)S, w);
 #pragma unroll
-      for (int li = 0; li < 6; ++li) {
-        double a = 0.0;
+      for (int r = 0; r < 4; ++r) cw[k][r] = (R)w[r];
+    }
+    for (int cc = 0; cc < 3; ++cc) {
+      for (int t = 0; t < P.terms.n_terms[cc]; ++t) {
+        const Term& tm = P.terms.t[cc][t];
+        const int e = (cc * 16 + t) * kNV + v;
+        const R* yl = yb + tm.link * MY;
+        const int flag = tflag[e];
+        R val[4];
+        if (flag == 2) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a += w[r] * nd[(jl - 1 + r) * kNodeVals + li * kNL + 3];
-        Lt[li] = a;
-      }
-      for (int cc = 0; cc < 3; ++cc) {
-        R acc = (R)0;
-        for (int t = 0; t < P.terms.n_terms[cc]; ++t) {
-          const Term& tm = P.terms.t[cc][t];
-          double D = 0.0;
-          for (int k = 0; k < tm.nd; ++k) D += (double)tm.dcnt[k] * Lt[tm.dlink[k]];
-          double s = (double)(n - m_lo) - D * inv_dt;
-          R yv = lag1<R, K>(yb + tm.link * MY, MY, s);
-          acc += tm.sign > 0 ? yv : -yv;
+          for (int k = 0; k < 4; ++k) val[k] = yl[nb + k - m_lo];
+        } else {
+          R dl[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            dl[k] = cw[k][0] * tdn[e * 4] + cw[k][1] * tdn[e * 4 + 1] + cw[k][2] * tdn[e * 4 + 2] +
+                    cw[k][3] * tdn[e * 4 + 3];
+          const int jb = tjr[e] + (int)(nb - nref);
+          if (TAY && flag == 0) {
+            int s0 = jb - K / 2 + 1;
+            s0 = s0 < 0 ? 0 : (s0 > MY - K - 3 ? MY - K - 3 : s0);   // memory safety only
+            R yv[K + 3];
+#pragma unroll
+            for (int j = 0; j < K + 3; ++j) yv[j] = yl[s0 + j];
+            const R* c0 = tco + (e * 2) * K;
+            const R* c1 = c0 + K;
+            R a0[4] = {(R)0, (R)0, (R)0, (R)0}, a1[4] = {(R)0, (R)0, (R)0, (R)0};
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+              const R w0 = c0[i], w1 = c1[i];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                a0[k] += w0 * yv[k + i];
+                a1[k] += w1 * yv[k + i];
+              }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) val[k] = a0[k] - dl[k] * a1[k];
+          } else {
+            const double f0 = tf0[e];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) val[k] = lag1<R, K>(yl, MY, (double)(jb + k) + (f0 - (double)dl[k]));
+          }
         }
-        ch[cc] = acc;
+        if (tm.sign > 0) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ch[cc][k] += val[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ch[cc][k] -= val[k];
+        }
       }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t n = nb + k;
+    if (n >= N) break;
     R o0, o1, o2;
     if (P.out_mode == 1) {
-      o0 = ch[0]; o1 = ch[1]; o2 = ch[2];
+      o0 = ch[0][k]; o1 = ch[1][k]; o2 = ch[2][k];
     } else {
       const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
-      o0 = (ch[2] - ch[0]) * r2;
-      o1 = (ch[0] - (R)2 * ch[1] + ch[2]) * r6;
-      o2 = (ch[0] + ch[1] + ch[2]) * r3;
+      o0 = (ch[2][k] - ch[0][k]) * r2;
+      o1 = (ch[0][k] - (R)2 * ch[1][k] + ch[2][k]) * r6;
+      o2 = (ch[0][k] + ch[1][k] + ch[2][k]) * r3;
       if (P.out_mode == 2) {
         o0 -= data[n];
         o1 -= data[N + n];
         o2 -= data[2 * N + n];
       }
     }
-    int64_t base = (int64_t)b * 3 * N + n;
+    const int64_t base = (int64_t)b * 3 * N + n;
     out[base] = o0;
     out[base + N] = o1;
     out[base + 2 * N] = o2;
@@ -375,20 +492,24 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
 
 template <typename R, int K>
 static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
+  // first-order Taylor weights in FP32 for K <= 16; direct weights otherwise
+  constexpr bool TAY = sizeof(R) == 4 && K <= 16;
   int HY = (int)ceil(7.0 * P.orb.max_light_time * P.g.inv_dt * 1.001) + K / 2 + 2;
   int spread = (int)ceil(2.0 * P.orb.max_light_time * P.g.inv_dt * 1.01) + 8;
   const int MY = kTile + HY + K / 2 + 1;
   int WMAX = MY + spread + K + 8;
   int NNMAX = MY / P.orb.spacing + 5;
   if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
+  if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
   size_t bytes = (((size_t)(6 * MY + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) +
-                 (size_t)NNMAX * kNodeVals * sizeof(double);
+                 (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kTerms * kNV * (sizeof(double) + 2 * sizeof(int)) +
+                 (size_t)kTerms * kNV * (4 + (TAY ? 2 * K : 0)) * sizeof(R);
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void*)k_tdi<R, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((P.g.n + kTile - 1) / kTile), (unsigned)P.batch);
-  hipLaunchKernelGGL((k_tdi<R, K>), grid, dim3(kNT), bytes, s, P, HY, WMAX, NNMAX);
+  hipLaunchKernelGGL((k_tdi<R, K, TAY>), grid, dim3(kNT), bytes, s, P, HY, WMAX, NNMAX);
   return hipGetLastError();
 }
 

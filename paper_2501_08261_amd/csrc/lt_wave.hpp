@@ -157,7 +157,7 @@ __device__ inline int setup_template(const double* p, double f_low, double f_ref
   double target = dw22m / (w_rd - w22m) * T;
   if (!(w_rd > w22m && target > 0.0 && target < 0.2784)) { valid = 0; target = 0.1; }
   double lo = 0.6392, hi = 60.0;
-  for (int i = 0; i < 200; ++i) {
+  for (int i = 0; i < 64; ++i) {    // (hi - lo) / 2^64 is below one ulp of the root
     double mid = 0.5 * (lo + hi);
     if (mid * (1.0 - tanh(mid)) > target) lo = mid; else hi = mid;
   }

@@ -55,6 +55,17 @@ class Data(ctypes.Structure):
     _fields_ = [("aet", ctypes.c_void_p), ("dd", ctypes.c_double)]
 
 
+class SamplerCfg(ctypes.Structure):
+    _fields_ = [("n_walkers", ctypes.c_int), ("n_temps", ctypes.c_int), ("dim", ctypes.c_int),
+                ("param_kind", ctypes.c_int), ("target", ctypes.c_int), ("stretch_a", ctypes.c_double),
+                ("t_max", ctypes.c_double), ("seed", ctypes.c_uint64), ("t_c", ctypes.c_double),
+                ("lo", ctypes.c_void_p), ("hi", ctypes.c_void_p), ("n_gauss", ctypes.c_int),
+                ("gauss_mean", ctypes.c_void_p), ("gauss_icov", ctypes.c_void_p)]
+
+
+LT_PARAMS_ALIGNED10, LT_PARAMS_PRECESSING14, LT_PARAMS_RAW = 0, 1, 2
+LT_TARGET_TDI, LT_TARGET_GAUSS = 0, 1
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _sig = {
@@ -72,6 +83,13 @@ _sig = {
                        ctypes.c_int),
     "lt_rfft": ([_P, _P, _I64, _I64, ctypes.c_double, ctypes.c_int, _P, _P], ctypes.c_int),
     "lt_psd_sangria": ([ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_double, _P, _P], ctypes.c_int),
+    "lt_sampler_create": ([ctypes.c_int, ctypes.POINTER(SamplerCfg), ctypes.POINTER(WfCfg), ctypes.POINTER(Grid),
+                           ctypes.POINTER(Orbit), ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data),
+                           ctypes.POINTER(_P)], ctypes.c_int),
+    "lt_sampler_destroy": ([_P], ctypes.c_int),
+    "lt_sampler_set_state": ([_P, _P], ctypes.c_int),
+    "lt_sampler_step": ([_P, ctypes.c_int, _P], ctypes.c_int),
+    "lt_sampler_get_state": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "lt_profile_enable": ([_P, ctypes.c_int], ctypes.c_int),
     "lt_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
                         ctypes.c_int),
@@ -209,3 +227,72 @@ def psd_sangria(g, generation, out, arm=ARM_M, stream=None):
     _check(_lib.lt_psd_sangria(ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), generation, arm, _ptr(out),
                                _stream(stream)))
     return out
+
+
+def _host(a, dtype=None):
+    import numpy as np
+    arr = np.ascontiguousarray(a, dtype=dtype or np.float64)
+    return arr, ctypes.c_void_p(arr.ctypes.data)
+
+
+class Sampler:
+    """On-device parallel-tempered ensemble sampler (lt_sampler_*).
+
+    target "tdi": likelihood = lt_tdi_loglike with (g, cfg, orbit, tdi, psd,
+    data_aet, dd); target "gauss": means [n][dim], icov [dim][dim]."""
+
+    def __init__(self, n_walkers, n_temps, dim, lo, hi, seed, target="tdi", param_kind="aligned10",
+                 stretch_a=2.0, t_max=10.0, t_c=0.0, means=None, icov=None, g=None, cfg=None, orbit=None,
+                 tdi=None, psd=None, data_aet=None, dd=0.0, f_lo=3e-4, f_hi=0.02, device=0):
+        import numpy as np
+        self.T, self.W, self.d = n_temps, n_walkers, dim
+        kinds = {"aligned10": LT_PARAMS_ALIGNED10, "precessing14": LT_PARAMS_PRECESSING14, "raw": LT_PARAMS_RAW}
+        self._lo, plo = _host(lo)
+        self._hi, phi = _host(hi)
+        c = SamplerCfg(n_walkers, n_temps, dim, kinds[param_kind],
+                       LT_TARGET_TDI if target == "tdi" else LT_TARGET_GAUSS, stretch_a, t_max, seed, t_c, plo, phi,
+                       0, None, None)
+        args = [None] * 6
+        if target == "gauss":
+            self._m, pm = _host(np.atleast_2d(means))
+            self._ic, pic = _host(icov)
+            c.n_gauss, c.gauss_mean, c.gauss_icov = self._m.shape[0], pm, pic
+        else:
+            self._psd = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
+            self._data = Data(_ptr(data_aet), float(dd))
+            self._keep = (psd, data_aet)
+            args = [ctypes.byref(cfg), ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), ctypes.byref(orbit),
+                    ctypes.byref(tdi), ctypes.byref(self._psd), ctypes.byref(self._data)]
+        h = ctypes.c_void_p()
+        _check(_lib.lt_sampler_create(device, ctypes.byref(c), *args, ctypes.byref(h)))
+        self.h = h
+
+    def set_state(self, pos):
+        import numpy as np
+        arr, p = _host(np.reshape(pos, (self.T, self.W, self.d)))
+        _check(_lib.lt_sampler_set_state(self.h, p))
+
+    def step(self, n=1, stream=None):
+        _check(_lib.lt_sampler_step(self.h, int(n), _stream(stream)))
+
+    def state(self):
+        import numpy as np
+        pos = np.zeros((self.T, self.W, self.d))
+        logl = np.zeros((self.T, self.W))
+        logp = np.zeros((self.T, self.W))
+        step = np.zeros(1, dtype=np.uint64)
+        cnt = np.zeros(4, dtype=np.int64)
+        _check(_lib.lt_sampler_get_state(self.h, pos.ctypes.data, logl.ctypes.data, logp.ctypes.data,
+                                         step.ctypes.data, cnt.ctypes.data))
+        return pos, logl, logp, int(step[0]), cnt
+
+    def close(self):
+        if self.h:
+            _check(_lib.lt_sampler_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -256,3 +256,21 @@ def test_host_errors(lt):
     with pytest.raises(lib.LisaTDError):
         ctx.rfft(torch.zeros((1, 14), dtype=torch.float64, device=DEV), 5.0,
                  torch.zeros((1, 8, 2), dtype=torch.float64, device=DEV))
+
+
+@pytest.mark.parametrize("n", [17280, 2 ** 20])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_band_inner_parity(lt, n, precision):
+    """sum_c (x_c|x_c) over the band: FFT passes plus the fused weighted reduction."""
+    lib, ctx = lt
+    g = inputs.grid(n, 5.0)
+    x = inputs.random_series(n + precision, (2, 3, n), 1e-20)
+    S = _psd_dev(lib, g, 20)
+    out = torch.zeros(2, dtype=torch.float64, device=DEV)
+    ctx.noise_inner(_dev(x, lib.real_dtype(precision)), g, S, out, precision=precision)
+    torch.cuda.synchronize()
+    Snp = olk.channel_psds(n, g["dt"], 20)
+    xs = x.astype(np.float32).astype(np.float64) if precision else x
+    for b in range(2):
+        want = olk.noise_inner(xs[b], Snp, g["dt"])
+        assert abs(out[b].item() - want) < (1e-12 if precision == 0 else 1e-5) * want

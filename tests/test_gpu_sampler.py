@@ -1,0 +1,145 @@
+"""GPU sampler (lt_sampler_*) against the oracle sampler, step by step."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import likelihood as olk
+from oracle.orbits import Orbit as OOrbit
+from oracle.response import Response
+from oracle.sampler import PTSampler, gaussian_logl, to_params
+from oracle.waveform import Template
+from paper_2501_08261_amd import inputs
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2501_08261_amd import lib as L
+    return L
+
+
+def _gauss_case(d=5, seed=0, two=False):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(d, d))
+    C = A @ A.T + d * np.eye(d)
+    mu = rng.normal(size=d)
+    means = np.stack([mu, mu + 6.0]) if two else mu[None]
+    return means, np.linalg.inv(C), C
+
+
+@pytest.mark.parametrize("T,two", [(1, False), (3, True)])
+def test_chain_parity_gaussian(lib, T, two):
+    """P26: GPU and CPU chains agree step by step under the same Philox stream."""
+    d, W, seed = 5, 16, 12345
+    means, icov, _ = _gauss_case(d, 1, two)
+    lo, hi = -30 * np.ones(d), 30 * np.ones(d)
+    start = means[0] + np.random.default_rng(2).normal(size=(T, W, d))
+    g = lib.Sampler(W, T, d, lo, hi, seed, target="gauss", param_kind="raw", t_max=20.0, means=means, icov=icov)
+    g.set_state(start)
+    o = PTSampler(gaussian_logl(means, icov), lo, hi, W, T, d, seed, t_max=20.0)
+    o.set_state(start)
+    for s in range(25):
+        g.step(1)
+        o.step()
+        pos, logl, _, step, cnt = g.state()
+        assert step == s + 1
+        assert np.max(np.abs(pos - o.X)) < 1e-12 * (1 + np.max(np.abs(o.X))), s
+        assert np.max(np.abs(logl - o.logl)) < 1e-9 * (1 + np.max(np.abs(o.logl))), s
+        assert cnt[0] == o.acc and cnt[2] == o.sacc
+    g.close()
+
+
+def test_graph_replay_is_deterministic(lib):
+    d, W, T = 4, 32, 2
+    means, icov, _ = _gauss_case(d, 3)
+    lo, hi = -30 * np.ones(d), 30 * np.ones(d)
+    start = means[0] + np.random.default_rng(4).normal(size=(T, W, d))
+    a = lib.Sampler(W, T, d, lo, hi, 99, target="gauss", param_kind="raw", means=means, icov=icov)
+    b = lib.Sampler(W, T, d, lo, hi, 99, target="gauss", param_kind="raw", means=means, icov=icov)
+    a.set_state(start)
+    b.set_state(start)
+    a.step(40)
+    for _ in range(40):
+        b.step(1)
+    pa, pb = a.state()[0], b.state()[0]
+    assert np.array_equal(pa, pb)
+    a.close()
+    b.close()
+
+
+def test_gpu_gaussian_moments(lib):
+    d, W = 4, 256
+    means, icov, C = _gauss_case(d, 5)
+    lo, hi = -60 * np.ones(d), 60 * np.ones(d)
+    s = lib.Sampler(W, 1, d, lo, hi, 5, target="gauss", param_kind="raw", means=means, icov=icov)
+    s.set_state(means[0] + np.random.default_rng(6).normal(size=(1, W, d)))
+    s.step(300)
+    chain = []
+    for _ in range(400):
+        s.step(1)
+        chain.append(s.state()[0][0])
+    flat = np.array(chain).reshape(-1, d)
+    assert np.allclose(flat.mean(0), means[0], atol=0.15 * np.sqrt(np.diag(C)).max())
+    assert np.allclose(np.cov(flat.T), C, rtol=0.15, atol=0.1 * np.max(np.abs(C)))
+    s.close()
+
+
+def test_chain_parity_tdi(lib):
+    """Two sampler steps on the real likelihood (aligned, static arms, TDI 1.5,
+    K = 2, FP64, 4096 samples) agree with the oracle sampler using the oracle logL."""
+    from paper_2501_08261_amd.lib import Context
+    n = 4096
+    gr = inputs.grid(n, 5.0)
+    inj = inputs.tab1_injection(False, gr, before_end=1000.0)
+    ctx = Context(0)
+    cfg, orb, tdi = ctx.wf_cfg(((2, 2), (3, 3))), ctx.orbit("static"), ctx.tdi_cfg(15, 7, 2)
+    S = torch.zeros((3, n // 2 + 1), dtype=torch.float64, device=DEV)
+    lib.psd_sangria(gr, 15, S)
+    d_aet = torch.zeros((1, 3, n), dtype=torch.float64, device=DEV)
+    ctx.lisa_tdi_response(torch.tensor(inj[None], device=DEV), gr, cfg, orb, tdi, d_aet)
+    dd = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ctx.noise_inner(d_aet, gr, S, dd)
+    torch.cuda.synchronize()
+    x0 = np.array([inj[0], inj[1], inj[4], inj[7], inj[8], inj[9], inj[10], inj[13], inj[12], inj[14]])
+    lo = np.array([0.99e6, 0.69e6, -1, -1, 1.9e4, 0, 0, -math.pi / 2, 0, -math.pi])
+    hi = np.array([1.01e6, 0.71e6, 1, 1, 2.1e4, math.pi, 2 * math.pi, math.pi / 2, 2 * math.pi, math.pi])
+    T, W = 2, 8
+    rng = np.random.default_rng(8)
+    start = x0 + 1e-4 * (hi - lo) * rng.normal(size=(T, W, 10))
+    smp = lib.Sampler(W, T, 10, lo, hi, 2024, target="tdi", param_kind="aligned10", t_c=inj[11], g=gr, cfg=cfg,
+                      orbit=orb, tdi=tdi, psd=S, data_aet=d_aet[0], dd=dd.item())
+    smp.set_state(start)
+    Snp = olk.channel_psds(n, gr["dt"], 15)
+
+    def oaet(p):
+        r = Response(Template(p), gr["t0"], gr["dt"], n, OOrbit("static"), taps=2, modes=((2, 2), (3, 3)))
+        r.cache_full_grid()
+        return np.array(r.aet(np.arange(n)))
+    od = oaet(inj)
+
+    def ologl(xs):
+        P = to_params(xs, "aligned10", inj[11])
+        out = []
+        for p in P:
+            tpl = Template(p)
+            out.append(olk.loglike(od, oaet(p), Snp, gr["dt"])[0] if tpl.valid else -np.inf)
+        return np.array(out)
+    o = PTSampler(ologl, lo, hi, W, T, 10, 2024)
+    o.set_state(start)
+    _, gl, _, _, _ = smp.state()
+    tol = 1e-6 + 1e-11 * dd.item()
+    assert np.max(np.abs(gl - o.logl)) < tol
+    for _ in range(2):
+        smp.step(1)
+        o.step()
+        pos, gl, _, _, cnt = smp.state()
+        assert np.max(np.abs(pos - o.X) / (hi - lo)) < 1e-12
+        assert np.max(np.abs(gl - o.logl)) < tol
+        assert cnt[0] == o.acc
+    smp.close()
+    ctx.close()

@@ -1,0 +1,76 @@
+"""Pins of the oracle sampler: Philox known answers, Gaussian moments, tempering, ESS."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle.sampler import PTSampler, philox4x32_10, gaussian_logl, integrated_time
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+
+
+def test_philox_known_answers():
+    for line in open(GOLD):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(x, 16) for x in line.split()]
+        got = philox4x32_10(np.array([v[:4]], dtype=np.uint64), (v[4], v[5]))[0]
+        assert [int(x) for x in got] == v[6:]
+
+
+def test_gaussian_moments():
+    """P26: the T = 1 chain reproduces the mean and covariance of a Gaussian."""
+    rng = np.random.default_rng(0)
+    d = 3
+    A = rng.normal(size=(d, d))
+    C = A @ A.T + d * np.eye(d)
+    mu = np.array([1.0, -2.0, 0.5])
+    s = PTSampler(gaussian_logl(mu, np.linalg.inv(C)), [-50] * d, [50] * d, 32, 1, d, seed=7)
+    s.set_state(mu + rng.normal(size=(1, 32, d)))
+    chain = []
+    for i in range(3000):
+        s.step()
+        if i >= 500:
+            chain.append(s.X[0].copy())
+    chain = np.array(chain)
+    flat = chain.reshape(-1, d)
+    tau = integrated_time(chain).max()
+    n_eff = flat.shape[0] / tau
+    err = np.sqrt(np.diag(C) / n_eff)
+    assert np.all(np.abs(flat.mean(0) - mu) < 5 * err)
+    assert np.allclose(np.cov(flat.T), C, rtol=0.2, atol=0.2 * np.sqrt(np.outer(np.diag(C), np.diag(C))).max())
+    assert 0.2 < s.acc / s.prop < 0.9
+
+
+def test_tempering_reaches_both_modes():
+    """P26: a separated bimodal target needs the tempering swaps."""
+    d = 2
+    means = np.array([[-4.0, 0.0], [4.0, 0.0]])
+    f = gaussian_logl(means, np.eye(d) * 4.0)
+    start = np.tile(means[0], (6, 16, 1)) + 0.1 * np.random.default_rng(1).normal(size=(6, 16, d))
+    s = PTSampler(f, [-20, -20], [20, 20], 16, 6, d, seed=3, t_max=200.0)
+    s.set_state(start)
+    frac = []
+    for i in range(1500):
+        s.step()
+        if i > 300:
+            frac.append(np.mean(s.X[0, :, 0] > 0))
+    assert 0.3 < np.mean(frac) < 0.7
+    assert s.sacc > 0
+    cold = PTSampler(f, [-20, -20], [20, 20], 16, 1, d, seed=3)
+    cold.set_state(start[:1])
+    for _ in range(300):
+        cold.step()
+    assert np.mean(cold.X[0, :, 0] > 0) < 0.2
+
+
+def test_integrated_time_ar1():
+    """P26: the ESS estimator recovers tau = (1 + rho) / (1 - rho) for AR(1)."""
+    rng = np.random.default_rng(5)
+    rho, n, w = 0.9, 20000, 8
+    x = np.zeros((n, w, 1))
+    e = rng.normal(size=(n, w))
+    for t in range(1, n):
+        x[t, :, 0] = rho * x[t - 1, :, 0] + e[t]
+    tau = integrated_time(x)[0]
+    assert abs(tau / ((1 + rho) / (1 - rho)) - 1) < 0.1
