@@ -211,6 +211,25 @@ lt_status lt_sampler_step(lt_sampler* s, int n_steps, void* stream);
 lt_status lt_sampler_get_state(lt_sampler* s, double* pos, double* logl, double* logp, uint64_t* step,
                                int64_t* counters);
 
+/* Fisher matrix for the initialisation of the sampler (Sec. II.C: starting
+ * points drawn from N(theta_inj, Gamma^-1), Gamma from finite differences of
+ * the likelihood).  In zero noise at the injection Gamma_ij = (d_i h | d_j h)
+ * (Eq. 2.13 summed over the enabled channels), computed here with central
+ * differences of the TDI response in the sampling coordinates of param_kind
+ * (steps: host [dim] half-widths).  x0: host [dim]; gamma: host [dim][dim].
+ * Synchronous; FP64 throughout. */
+lt_status lt_fisher(lt_ctx* ctx, const double* x0, int param_kind, double t_c, const double* steps,
+                    const lt_wf_cfg* cfg, const lt_grid* grid, const lt_orbit* orbit, const lt_tdi_cfg* tdi,
+                    const lt_psd* psd, double* gamma);
+
+/* Draws count starting points from N(x0, Gamma^-1) (host FP64): Gamma is
+ * symmetrised and its eigenvalues floored at reg * max eigenvalue (near-
+ * degenerate directions of 22-only models), normal deviates from Philox4x32-10
+ * (Box-Muller); draws outside [lo, hi] are redrawn (up to 64 times, then
+ * clipped).  out: host [count][dim]. */
+lt_status lt_fisher_draw(const double* x0, const double* gamma, int dim, const double* lo, const double* hi,
+                         int64_t count, uint64_t seed, double reg, double* out);
+
 #ifdef __cplusplus
 }
 #endif
