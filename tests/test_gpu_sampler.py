@@ -143,3 +143,31 @@ def test_chain_parity_tdi(lib):
         assert cnt[0] == o.acc
     smp.close()
     ctx.close()
+
+
+def test_fisher_parity(lib):
+    """lt_fisher (GPU finite differences + band inner products) against the oracle Fisher."""
+    import ctypes
+    from oracle.fisher import fisher as ofisher
+    from paper_2501_08261_amd.lib import Context, _lib, Grid, Psd, _check
+    g = inputs.grid(2048, 5.0)
+    inj = inputs.tab1_injection(False, g, before_end=1000.0)
+    x0 = np.array([inj[0], inj[1], inj[4], inj[7], inj[8], inj[9], inj[10], inj[13], inj[12], inj[14]])
+    steps = np.array([1.0, 1.0, 1e-4, 1e-4, 1.0, 1e-5, 1e-5, 1e-5, 1e-5, 1e-5])
+    ctx = Context(0)
+    cfg, orb, tdi = ctx.wf_cfg(((2, 2), (3, 3))), ctx.orbit("static"), ctx.tdi_cfg(15, 7, 2)
+    S = torch.zeros((3, g["n"] // 2 + 1), dtype=torch.float64, device=DEV)
+    lib.psd_sangria(g, 15, S)
+    P = Psd((ctypes.c_void_p * 3)(*[S[i].data_ptr() for i in range(3)]), 3e-4, 0.02)
+    G = np.zeros((10, 10))
+    f = _lib.lt_fisher
+    f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p] + \
+        [ctypes.c_void_p] * 6
+    f.restype = ctypes.c_int
+    _check(f(ctx.h, x0.ctypes.data, 0, inj[11], steps.ctypes.data, ctypes.byref(cfg),
+             ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), ctypes.byref(orb), ctypes.byref(tdi), ctypes.byref(P),
+             G.ctypes.data))
+    W = ofisher(x0, "aligned10", inj[11], steps, g, "static", 2, ((2, 2), (3, 3)), False, 15)
+    scale = np.sqrt(np.outer(np.diag(W), np.diag(W)))
+    assert np.max(np.abs(G - W) / scale) < 1e-5
+    ctx.close()
