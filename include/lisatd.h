@@ -230,6 +230,67 @@ lt_status lt_fisher(lt_ctx* ctx, const double* x0, int param_kind, double t_c, c
 lt_status lt_fisher_draw(const double* x0, const double* gamma, int dim, const double* lo, const double* hi,
                          int64_t count, uint64_t seed, double reg, double* out);
 
+/* ---------------------------------------------------------------------------
+ * Learned proposal (Sec. II.A names machine-learning proposals as a reason to
+ * keep the whole pipeline on the accelerator; the flow itself is this
+ * library's design).  A RealNVP-style normalising flow over the sampling
+ * coordinates:
+ *   u = (x - mu) / sigma; for layer l = 0..L-1 the conditioning set A_l is the
+ *   first floor(d/2) coordinates (even l) or the last floor(d/2) (odd l), B_l
+ *   the rest; h1 = relu(W1 u_A + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3,
+ *   s = 3 tanh(o[0:|B|] / 3), t = o[|B|:2|B|], u_B <- u_B exp(s) + t;
+ *   log q(x) = -|z|^2/2 - (d/2) log 2pi + sum_l sum s_l - sum log sigma.
+ * Parameters: FP32 host vector, per layer W1[H][|A|], b1[H], W2[H][H], b2[H],
+ * W3[2|B|][H], b3[2|B|] (row-major), layers in order.  The GEMMs run on the
+ * matrix cores with BF16 operands and FP32 accumulation; the coupling update,
+ * log-determinants and log q are FP64 (a flow with W3 = b3 = 0 is the exact
+ * identity).  Training: Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the mean
+ * negative log q.  A flow object may be used by one host thread at a time;
+ * its buffers are shared by all its calls, so calls on different streams
+ * must not overlap. */
+typedef struct lt_flow lt_flow;
+
+/* 2 <= dim <= 64, 1 <= n_layers <= 32, hidden in [8, 4096] and a multiple of
+ * 8, 1 <= max_batch <= 2^20 rows per call.  Parameters start at zero (the
+ * identity flow, mu = 0, sigma = 1).  Device memory: about
+ * n_layers * max_batch * (12 hidden + 26 dim) bytes of activations. */
+lt_status lt_flow_create(int hip_device, int dim, int n_layers, int hidden, int max_batch, lt_flow** out);
+lt_status lt_flow_destroy(lt_flow* f);
+/* Number of FP32 parameters (-1 for a null flow). */
+int64_t lt_flow_num_params(const lt_flow* f);
+/* Host params [num_params], mu and sigma [dim] (sigma > 0); resets Adam's
+ * moments and step count.  Synchronous. */
+lt_status lt_flow_set_params(lt_flow* f, const float* params, const double* mu, const double* sigma);
+/* Copies the FP32 master parameters to host memory.  Synchronous. */
+lt_status lt_flow_get_params(lt_flow* f, float* params);
+/* log q of n rows of x (device FP64 [n][dim]) into logq (device FP64 [n]). */
+lt_status lt_flow_log_prob(lt_flow* f, const double* x, int64_t n, double* logq, void* stream);
+/* Inverse pass: base samples z (device FP64 [n][dim], standard normal) ->
+ * x (device FP64 [n][dim]) and log q(x) (device FP64 [n]). */
+lt_status lt_flow_sample(lt_flow* f, const double* z, int64_t n, double* x, double* logq, void* stream);
+/* Mean negative log q of the n rows of x (device) and its gradient with
+ * respect to the parameters; logq (host FP64 [n], nullable) and grad (host
+ * FP32 [num_params], nullable).  Synchronous; does not update the weights. */
+lt_status lt_flow_loss_grad(lt_flow* f, const double* x, int64_t n, double* logq, float* grad);
+/* `steps` Adam steps on minibatches of `batch` rows of x (device FP64
+ * [n][dim]); step i uses rows (i batch + r) mod n, r < batch (shuffle x to
+ * randomise).  batch <= max_batch. */
+lt_status lt_flow_train(lt_flow* f, const double* x, int64_t n, int steps, int batch, double lr, void* stream);
+
+/* Attaches a flow (nullable: detach) to a sampler.  With a flow attached each
+ * sampler step adds, after the two stretch half-steps and before the swaps,
+ * an independence Metropolis-Hastings move for every walker of the coldest
+ * rung: y from the flow (base normals from Philox counter
+ * (step, 0x400, walker, q), two Box-Muller pairs per counter), accepted with
+ * log u < beta_0 (logL_y - logL_x) + (logP_y - logP_x) + log q(x) - log q(y),
+ * u from counter (step, 0x500, walker, 0).  The flow's dim must equal the
+ * sampler's and its max_batch be >= n_walkers; the flow must outlive the
+ * sampler or be detached first.  Retraining the attached flow between
+ * lt_sampler_step calls changes the proposal in place. */
+lt_status lt_sampler_set_flow(lt_sampler* s, lt_flow* flow);
+/* Flow moves accepted and proposed since lt_sampler_set_state (host int64 [2]). */
+lt_status lt_sampler_flow_counts(lt_sampler* s, int64_t* counts);
+
 #ifdef __cplusplus
 }
 #endif

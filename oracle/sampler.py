@@ -15,6 +15,12 @@ of the GPU sampler:
   walker k at beta_i against walker (k + r) mod W at beta_{i+1}, accepted with
   min(1, exp((beta_i - beta_{i+1}) (logL_{i+1} - logL_i)));
 * geometric ladder beta_i = t_max^(-i / (T - 1));
+* optional learned-proposal move (a normalising flow q, see oracle.flow):
+  after both halves and before the swaps, every walker of the coldest rung
+  proposes y = flow inverse of z, z standard normal from Box-Muller pairs
+  (Philox counter (step, 0x400, walker, q) -> coordinates 4q..4q+3), accepted
+  when ln u < beta_0 (logL_y - logL_x) + (logP_y - logP_x) + ln q(x) - ln q(y)
+  (independence Metropolis-Hastings), u from counter (step, 0x500, walker, 0);
 * random numbers from Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011) keyed
   by the seed, counter (step, purpose, slot, 0), uniforms (u + 1/2) 2^-32.
 """
@@ -22,10 +28,12 @@ import math
 
 import numpy as np
 
+from . import flow as _flow
+
 M0, M1 = 0xD2511F53, 0xCD9E8D57
 W0, W1 = 0x9E3779B9, 0xBB67AE85
 MASK = 0xFFFFFFFF
-TAG_MOVE, TAG_SHIFT, TAG_SWAP = 0x100, 0x200, 0x300
+TAG_MOVE, TAG_SHIFT, TAG_SWAP, TAG_FLOWZ, TAG_FLOWU = 0x100, 0x200, 0x300, 0x400, 0x500
 
 
 def philox4x32_10(ctr, key):
@@ -91,6 +99,47 @@ class PTSampler:
         self.beta = np.array([t_max ** (-i / (n_temps - 1)) if n_temps > 1 else 1.0 for i in range(n_temps)])
         self.step_count = 0
         self.acc = self.prop = self.sacc = self.sprop = 0
+        self.flow = None
+        self.facc = self.fprop = 0
+
+    def set_flow(self, P, mu, sigma):
+        """Attach a flow (oracle.flow parameters; None detaches)."""
+        self.flow = None if P is None else (P, np.asarray(mu, float), np.asarray(sigma, float))
+
+    def flow_normals(self, s):
+        """Base samples z [W][d] of step s."""
+        W, d = self.W, self.d
+        z = np.zeros((W, d))
+        k = np.arange(W)
+        for q in range((d + 3) // 4):
+            r = philox4x32_10(_ctr(s, TAG_FLOWZ, k, q), self.key)
+            for p in (0, 1):
+                rad = np.sqrt(-2.0 * np.log(u01(r[:, 2 * p])))
+                ph = 2.0 * math.pi * u01(r[:, 2 * p + 1])
+                i0 = 4 * q + 2 * p
+                if i0 < d:
+                    z[:, i0] = rad * np.cos(ph)
+                if i0 + 1 < d:
+                    z[:, i0 + 1] = rad * np.sin(ph)
+        return z
+
+    def flow_move(self, s):
+        P, mu, sigma = self.flow
+        W = self.W
+        y, lqy = _flow.inverse(P, self.flow_normals(s), mu, sigma)
+        _, lqx = _flow.forward(P, self.X[0], mu, sigma)
+        lpy = self.log_prior(y)
+        lly = np.asarray(self.logl_fn(y), dtype=np.float64)
+        ru = philox4x32_10(_ctr(s, TAG_FLOWU, np.arange(W)), self.key)
+        with np.errstate(invalid="ignore"):
+            la = self.beta[0] * (lly - self.logl[0]) + (lpy - self.logp[0]) + (lqx - lqy)
+            ok = (lpy > -np.inf) & ~np.isnan(lly) & (lly > -np.inf) & ~np.isnan(la) & (np.log(u01(ru[:, 0])) < la)
+        self.X[0, ok] = y[ok]
+        self.logl[0, ok] = lly[ok]
+        self.logp[0, ok] = lpy[ok]
+        self.facc += int(ok.sum())
+        self.fprop += W
+        return ok
 
     def log_prior(self, x):
         inside = np.all((x >= self.lo) & (x <= self.hi), axis=-1)
@@ -103,6 +152,7 @@ class PTSampler:
         self.logl = np.asarray(self.logl_fn(flat), dtype=np.float64).reshape(self.T, self.W)
         self.step_count = 0
         self.acc = self.prop = self.sacc = self.sprop = 0
+        self.facc = self.fprop = 0
 
     def step(self):
         T, W, d, half = self.T, self.W, self.d, self.W // 2
@@ -126,6 +176,8 @@ class PTSampler:
             self.logp[t[ok], k[ok]] = lpy[ok]
             self.acc += int(ok.sum())
             self.prop += ok.size
+        if self.flow is not None:
+            self.flow_move(s)
         for i in range(T - 2, -1, -1):
             rr = philox4x32_10(_ctr(s, TAG_SHIFT + i, np.array([0])), self.key)
             shift = int(rr[0, 0] % np.uint64(W))

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblisatd.so")
-SOURCES = ["lt_tdi.hip", "lt_fft.hip", "lt_sampler.hip", "lt_fisher.cpp", "lt_api.cpp"]
+SOURCES = ["lt_tdi.hip", "lt_fft.hip", "lt_sampler.hip", "lt_flow.hip", "lt_fisher.cpp", "lt_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/lisatd.h"
+#include "lt_rng.hpp"
 
 namespace lt {
 void set_error(const std::string& msg);
@@ -99,14 +100,6 @@ void jacobi(std::vector<double>& a, int n, std::vector<double>& w, std::vector<d
   for (int i = 0; i < n; ++i) w[i] = a[i * n + i];
 }
 
-void philox10(uint32_t* c, uint32_t k0, uint32_t k1) {
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
-    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-    c[1] = (uint32_t)p1; c[3] = (uint32_t)p0; c[0] = n0; c[2] = n2;
-  }
-}
 
 }  // namespace
 
@@ -210,7 +203,7 @@ lt_status lt_fisher_draw(const double* x0, const double* gamma, int dim, const d
     for (int attempt = 0; attempt < 64 && !inside; ++attempt) {
       for (int i = 0; i < dim; i += 2) {
         uint32_t c[4] = {(uint32_t)s, (uint32_t)attempt, (uint32_t)i, 0x51u};
-        philox10(c, k0, k1);
+        lt_rng::philox4x32_10(c, k0, k1);
         double u1 = ((double)c[0] + 0.5) * 2.3283064365386963e-10, u2 = ((double)c[1] + 0.5) * 2.3283064365386963e-10;
         double r = std::sqrt(-2.0 * std::log(u1));
         z[i] = r * std::cos(2.0 * M_PI * u2);

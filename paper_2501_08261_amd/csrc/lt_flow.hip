@@ -1,0 +1,604 @@
+// Learned proposal: a RealNVP-style affine-coupling flow whose conditioner
+// networks run on the matrix cores (BF16 operands, FP32 accumulation), with
+// FP32 master weights, Adam, and FP64 coupling arithmetic.
+//
+// Flow definition: coordinates standardised, u = (x - mu) / sigma; layer l
+// conditions on A_l (even l: the first floor(d/2) coordinates, odd l: the last
+// floor(d/2)) and transforms B_l (the rest); conditioner h1 = relu(W1 u_A + b1),
+// h2 = relu(W2 h1 + b2), o = W3 h2 + b3, s = 3 tanh(o_s / 3), t = o_t;
+// y_B = u_B exp(s) + t; log q(x) = -|z|^2/2 - d/2 log 2pi + sum_l sum s_l
+// - sum log sigma.  Training minimises the mean negative log q of samples.
+//
+// Precision split: the GEMM operands (u_A, h1, h2, weights, back-propagated
+// activations) are BF16, accumulation FP32; u, the coupling update, log-dets
+// and log q are FP64, so that a flow whose output layer is zero is the exact
+// identity and its log q the exact standardised normal density.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/lisatd.h"
+#include "lt_rng.hpp"
+
+namespace lt {
+void set_error(const std::string& msg);
+}
+
+namespace lt_f {
+
+typedef unsigned short bf16;
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+
+constexpr double kSMax = 3.0;
+constexpr double kLog2Pi = 1.8378770664093454836;
+
+__device__ __host__ inline bf16 to_bf16(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (inputs are finite)
+  return (bf16)(u >> 16);
+}
+
+// C[m][n] = act(sum_k A(m,k) B(k,n) + bias[n]) with A(m,k) = A[m*sAm + k*sAk],
+// B(k,n) = B[k*sBk + n*sBn] (BF16), C FP32 (row stride ldc) and optional BF16
+// copy Cb.  A workgroup of four wavefronts covers a 64x64 block, one 32x32
+// tile per wavefront, v_mfma_f32_32x32x8bf16_1k over k in steps of 8.  Operand
+// layout of the instruction (wave64): lane l supplies A[l % 32][4 (l / 32) + j]
+// and B[4 (l / 32) + j][l % 32], j = 0..3, and receives
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32], r = 0..15.
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A, int64_t sAm,
+                                              int64_t sAk, const bf16* __restrict__ B, int64_t sBk, int64_t sBn,
+                                              float* __restrict__ C, int64_t ldc, bf16* __restrict__ Cb,
+                                              const float* __restrict__ bias, int relu) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  if (m0 >= M || n0 >= N) return;   // whole wavefront leaves together
+  const int lm = lane & 31, lk = (lane >> 5) * 4;
+  const int m = m0 + lm, n = n0 + lm;
+  float16v acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    short4v a, b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + lk + j;
+      a[j] = (k < K && m < M) ? (short)A[(int64_t)m * sAm + (int64_t)k * sAk] : (short)0;
+      b[j] = (k < K && n < N) ? (short)B[(int64_t)k * sBk + (int64_t)n * sBn] : (short)0;
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3);
+    const int col = n0 + lm;
+    if (row < M && col < N) {
+      float v = acc[r];
+      if (bias) v += bias[col];
+      if (relu) v = v > 0.0f ? v : 0.0f;
+      C[(int64_t)row * ldc + col] = v;
+      if (Cb) Cb[(int64_t)row * ldc + col] = to_bf16(v);
+    }
+  }
+}
+
+// u (FP64 [n][d]) columns [c0, c0+w) -> BF16 [n][w]
+__global__ void k_gather(const double* u, int n, int d, int c0, int w, bf16* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * w) return;
+  const int r = i / w, c = i - r * w;
+  out[i] = to_bf16((float)u[(int64_t)r * d + c0 + c]);
+}
+
+// coupling: s = S tanh(o_s / S); forward u_B <- u_B e^s + t, inverse
+// u_B <- (u_B - t) e^-s; logdet += sum s (the forward log-det in both cases)
+__global__ void k_couple(double* u, int n, int d, int b0, int nb, const float* o, double* s_out, double* ub_in,
+                         double* logdet, int inverse) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double ld = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    const double s = kSMax * tanh((double)o[(int64_t)r * 2 * nb + j] / kSMax);
+    const double t = (double)o[(int64_t)r * 2 * nb + nb + j];
+    double& x = u[(int64_t)r * d + b0 + j];
+    if (ub_in) ub_in[(int64_t)r * nb + j] = x;
+    if (s_out) s_out[(int64_t)r * nb + j] = s;
+    x = inverse ? (x - t) * exp(-s) : x * exp(s) + t;
+    ld += s;
+  }
+  logdet[r] += ld;
+}
+
+// coupling backward: gu holds dL/dy on entry and dL/du_B on exit; writes g_o (FP32 + BF16)
+__global__ void k_couple_bwd(double* gu, int n, int d, int b0, int nb, const float* o, const double* s,
+                             const double* ub_in, double inv_n, float* go, bf16* gob) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int j = 0; j < nb; ++j) {
+    const double sj = s[(int64_t)r * nb + j], es = exp(sj);
+    const double gy = gu[(int64_t)r * d + b0 + j];
+    const double th = tanh((double)o[(int64_t)r * 2 * nb + j] / kSMax);
+    const double gs = gy * ub_in[(int64_t)r * nb + j] * es - inv_n;   // y_B and -log|det|
+    const float graw = (float)(gs * (1.0 - th * th));
+    const float gt = (float)gy;
+    go[(int64_t)r * 2 * nb + j] = graw;
+    go[(int64_t)r * 2 * nb + nb + j] = gt;
+    gob[(int64_t)r * 2 * nb + j] = to_bf16(graw);
+    gob[(int64_t)r * 2 * nb + nb + j] = to_bf16(gt);
+    gu[(int64_t)r * d + b0 + j] = gy * es;
+  }
+}
+
+// g (FP32 [count]) *= (h > 0), BF16 copy
+__global__ void k_relu_bwd(float* g, const float* h, int64_t count, bf16* gb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float v = h[i] > 0.0f ? g[i] : 0.0f;
+  g[i] = v;
+  gb[i] = to_bf16(v);
+}
+
+// out[c] = sum_r g[r][c]; one 64-lane wavefront per column, fixed order
+__global__ __launch_bounds__(64) void k_colsum(const float* g, int n, int w, float* out) {
+  const int c = blockIdx.x;
+  float acc = 0.0f;
+  for (int r = threadIdx.x; r < n; r += 64) acc += g[(int64_t)r * w + c];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (threadIdx.x == 0) out[c] = acc;
+}
+
+// gu[r][c0 + c] += g[r][c]
+__global__ void k_scatter_add(double* gu, int n, int d, int c0, int w, const float* g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * w) return;
+  const int r = i / w, c = i - r * w;
+  gu[(int64_t)r * d + c0 + c] += (double)g[i];
+}
+
+// u = (x[src] - mu) / sigma with src = (start + r) mod n_src; logdet = 0
+__global__ void k_standardise(const double* x, int64_t n_src, int64_t start, int n, int d, const double* mu,
+                              const double* sig, double* u, double* logdet) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * d) return;
+  const int r = i / d, c = i - r * d;
+  const int64_t src = (start + r) % n_src;
+  u[i] = (x[src * d + c] - mu[c]) / sig[c];
+  if (c == 0) logdet[r] = 0.0;
+}
+
+// log q = -|u|^2/2 - d/2 log 2pi + logdet - lsig; optionally dL/dz = u / n for the mean NLL
+__global__ void k_logq(const double* u, int n, int d, const double* logdet, double lsig, double* logq, double* gu,
+                       double inv_n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double q = 0.0;
+  for (int c = 0; c < d; ++c) {
+    const double v = u[(int64_t)r * d + c];
+    q += v * v;
+    if (gu) gu[(int64_t)r * d + c] = v * inv_n;
+  }
+  logq[r] = -0.5 * q - 0.5 * d * kLog2Pi + logdet[r] - lsig;
+}
+
+// logq += logdet - lsig (inverse pass: base density computed before it)
+__global__ void k_logq_add(int n, const double* logdet, double lsig, double* logq) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  logq[r] = logq[r] + logdet[r] - lsig;
+}
+
+// x = u sigma + mu, rounded as two operations (no fused multiply-add)
+__global__ void k_destandardise(const double* u, int n, int d, const double* mu, const double* sig, double* x) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * d) return;
+  const int c = i % d;
+  const double p = u[i] * sig[c];
+  x[i] = p + mu[c];
+}
+
+// u = z (the base sample)
+__global__ void k_load(const double* z, int64_t count, double* u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) u[i] = z[i];
+}
+
+__global__ void k_zero(double* p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.0;
+}
+
+__global__ void k_copy(const double* src, int64_t count, double* dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i];
+}
+
+// standard normal base samples for the proposal of walker k: Philox counter
+// (step, kTagFlowZ, k, q) gives two Box-Muller pairs for coordinates 4q..4q+3
+__global__ void k_base_normal(const uint64_t* step, uint32_t k0, uint32_t k1, int n, int d, double* u) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t st = (uint32_t)*step;
+  for (int q = 0; 4 * q < d; ++q) {
+    uint32_t c[4] = {st, lt_rng::kTagFlowZ, (uint32_t)k, (uint32_t)q};
+    lt_rng::philox4x32_10(c, k0, k1);
+    for (int p = 0; p < 2; ++p) {
+      const double r = sqrt(-2.0 * log(lt_rng::u01(c[2 * p])));
+      const double ph = 2.0 * M_PI * lt_rng::u01(c[2 * p + 1]);
+      const int i0 = 4 * q + 2 * p;
+      if (i0 < d) u[(int64_t)k * d + i0] = r * cos(ph);
+      if (i0 + 1 < d) u[(int64_t)k * d + i0 + 1] = r * sin(ph);
+    }
+  }
+}
+
+__global__ void k_adam(float* w, bf16* wb, const float* g, float* m, float* v, int64_t count, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  wb[i] = to_bf16(wi);
+}
+
+__global__ void k_to_bf16(const float* w, bf16* wb, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) wb[i] = to_bf16(w[i]);
+}
+
+}  // namespace lt_f
+
+using namespace lt_f;
+
+namespace {
+struct LayerOff {
+  int64_t W1, b1, W2, b2, W3, b3;
+  int a0, na, b0, nb;
+};
+}  // namespace
+
+struct lt_flow {
+  int device = 0, d = 0, L = 0, H = 0, maxB = 0;
+  int64_t nparam = 0;
+  std::vector<LayerOff> lay;
+  float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+  bf16* wb = nullptr;
+  double *mu = nullptr, *sig = nullptr;
+  double lsig = 0.0;
+  int64_t t = 0;
+  // per-row state (maxB rows) and per-layer activations kept for the backward pass
+  double *u = nullptr, *gu = nullptr, *logdet = nullptr, *logq = nullptr, *s = nullptr, *ub = nullptr;
+  float *a1 = nullptr, *a2 = nullptr, *o = nullptr, *tmpH = nullptr, *go = nullptr, *tmpA = nullptr;
+  bf16 *uA = nullptr, *h1 = nullptr, *h2 = nullptr, *gob = nullptr, *gH = nullptr;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+lt_status ffail(lt_status s, const std::string& m) {
+  lt::set_error(m);
+  return s;
+}
+
+#define FL_HIP(call)                                                                                      \
+  do {                                                                                                    \
+    hipError_t e_ = (call);                                                                               \
+    if (e_ != hipSuccess) return ffail(LT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+hipError_t falloc(lt_flow* f, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T) + 256);
+  if (e == hipSuccess) {
+    f->allocs.push_back(q);
+    *p = (T*)q;
+  }
+  return e;
+}
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+void gemm(hipStream_t st, int M, int N, int K, const bf16* A, int64_t sAm, int64_t sAk, const bf16* B, int64_t sBk,
+          int64_t sBn, float* C, int64_t ldc, bf16* Cb, const float* bias, int relu) {
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb, bias, relu);
+}
+
+struct Slots {
+  bf16 *uA, *h1, *h2;
+  float *a1, *a2, *o;
+  double *s, *ub;
+};
+
+Slots slots(const lt_flow* f, int l, int n) {
+  const int64_t H = f->H, d = f->d;
+  Slots S;
+  S.uA = f->uA + l * n * d;
+  S.h1 = f->h1 + l * n * H;
+  S.h2 = f->h2 + l * n * H;
+  S.a1 = f->a1 + l * n * H;
+  S.a2 = f->a2 + l * n * H;
+  S.o = f->o + l * n * 2 * d;
+  S.s = f->s + l * n * d;
+  S.ub = f->ub + l * n * d;
+  return S;
+}
+
+// forward (inverse = 0) or inverse pass over the n rows of f->u; logdet accumulates sum s
+void pass(lt_flow* f, int n, int inverse, hipStream_t st) {
+  const int d = f->d, H = f->H;
+  for (int q = 0; q < f->L; ++q) {
+    const int l = inverse ? f->L - 1 - q : q;
+    const LayerOff& Lo = f->lay[l];
+    Slots S = slots(f, l, n);
+    hipLaunchKernelGGL(k_gather, dim3(blocks((int64_t)n * Lo.na)), dim3(256), 0, st, f->u, n, d, Lo.a0, Lo.na, S.uA);
+    gemm(st, n, H, Lo.na, S.uA, Lo.na, 1, f->wb + Lo.W1, 1, Lo.na, S.a1, H, S.h1, f->w + Lo.b1, 1);
+    gemm(st, n, H, H, S.h1, H, 1, f->wb + Lo.W2, 1, H, S.a2, H, S.h2, f->w + Lo.b2, 1);
+    gemm(st, n, 2 * Lo.nb, H, S.h2, H, 1, f->wb + Lo.W3, 1, H, S.o, 2 * Lo.nb, nullptr, f->w + Lo.b3, 0);
+    hipLaunchKernelGGL(k_couple, dim3(blocks(n)), dim3(256), 0, st, f->u, n, d, Lo.b0, Lo.nb, S.o, S.s, S.ub,
+                       f->logdet, inverse);
+  }
+}
+
+// log q of n rows x[(start + r) mod n_src] into f->logq (and dL/dz into f->gu when grad)
+void logq_rows(lt_flow* f, const double* x, int64_t n_src, int64_t start, int n, bool grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_standardise, dim3(blocks((int64_t)n * f->d)), dim3(256), 0, st, x, n_src, start, n, f->d,
+                     f->mu, f->sig, f->u, f->logdet);
+  pass(f, n, 0, st);
+  hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, f->d, f->logdet, f->lsig, f->logq,
+                     grad ? f->gu : (double*)nullptr, 1.0 / n);
+}
+
+// inverse pass from base samples already in f->u: x (FP64 [n][d]) and log q(x)
+void sample_rows(lt_flow* f, int n, double* x, double* logq, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(blocks(n)), dim3(256), 0, st, f->logdet, (int64_t)n);
+  hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, f->d, f->logdet, 0.0, logq,
+                     (double*)nullptr, 0.0);
+  pass(f, n, 1, st);
+  hipLaunchKernelGGL(k_logq_add, dim3(blocks(n)), dim3(256), 0, st, n, f->logdet, f->lsig, logq);
+  hipLaunchKernelGGL(k_destandardise, dim3(blocks((int64_t)n * f->d)), dim3(256), 0, st, f->u, n, f->d, f->mu,
+                     f->sig, x);
+}
+
+// backward pass of the mean NLL after logq_rows(grad = true); gradients into f->g
+void backward(lt_flow* f, int n, hipStream_t s) {
+  const int d = f->d, H = f->H;
+  for (int l = f->L - 1; l >= 0; --l) {
+    const LayerOff& Lo = f->lay[l];
+    Slots S = slots(f, l, n);
+    const int no = 2 * Lo.nb;
+    hipLaunchKernelGGL(k_couple_bwd, dim3(blocks(n)), dim3(256), 0, s, f->gu, n, d, Lo.b0, Lo.nb, S.o, S.s, S.ub,
+                       1.0 / n, f->go, f->gob);
+    // dW3 = g_o^T h2, db3 = column sums of g_o
+    gemm(s, no, H, n, f->gob, 1, no, S.h2, H, 1, f->g + Lo.W3, H, nullptr, nullptr, 0);
+    hipLaunchKernelGGL(k_colsum, dim3(no), dim3(64), 0, s, f->go, n, no, f->g + Lo.b3);
+    // g_a2 = (g_o W3) * (h2 > 0); dW2 = g_a2^T h1
+    gemm(s, n, H, no, f->gob, no, 1, f->wb + Lo.W3, H, 1, f->tmpH, H, nullptr, nullptr, 0);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks((int64_t)n * H)), dim3(256), 0, s, f->tmpH, S.a2, (int64_t)n * H,
+                       f->gH);
+    gemm(s, H, H, n, f->gH, 1, H, S.h1, H, 1, f->g + Lo.W2, H, nullptr, nullptr, 0);
+    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(64), 0, s, f->tmpH, n, H, f->g + Lo.b2);
+    // g_a1 = (g_a2 W2) * (h1 > 0); dW1 = g_a1^T u_A
+    gemm(s, n, H, H, f->gH, H, 1, f->wb + Lo.W2, H, 1, f->tmpH, H, nullptr, nullptr, 0);
+    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks((int64_t)n * H)), dim3(256), 0, s, f->tmpH, S.a1, (int64_t)n * H,
+                       f->gH);
+    gemm(s, H, Lo.na, n, f->gH, 1, H, S.uA, Lo.na, 1, f->g + Lo.W1, Lo.na, nullptr, nullptr, 0);
+    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(64), 0, s, f->tmpH, n, H, f->g + Lo.b1);
+    // dL/du_A += g_a1 W1
+    gemm(s, n, Lo.na, H, f->gH, H, 1, f->wb + Lo.W1, Lo.na, 1, f->tmpA, Lo.na, nullptr, nullptr, 0);
+    hipLaunchKernelGGL(k_scatter_add, dim3(blocks((int64_t)n * Lo.na)), dim3(256), 0, s, f->gu, n, d, Lo.a0, Lo.na,
+                       f->tmpA);
+  }
+}
+
+void adam(lt_flow* f, float lr, hipStream_t s) {
+  f->t += 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)f->t)), c2 = (float)(1.0 - std::pow(0.999, (double)f->t));
+  hipLaunchKernelGGL(k_adam, dim3(blocks(f->nparam)), dim3(256), 0, s, f->w, f->wb, f->g, f->m, f->v, f->nparam, lr,
+                     0.9f, 0.999f, 1e-8f, c1, c2);
+}
+
+lt_status check_batch(const lt_flow* f, int64_t n) {
+  if (n < 1 || n > f->maxB) return ffail(LT_ERR_SHAPE, "flow batch must be in [1, max_batch]");
+  return LT_OK;
+}
+
+}  // namespace
+
+// Used by the sampler's flow move (same library, not exported).
+namespace lt {
+int flow_dim(const lt_flow* f) { return f->d; }
+int flow_max_batch(const lt_flow* f) { return f->maxB; }
+int flow_device(const lt_flow* f) { return f->device; }
+// proposals y ~ q for n walkers from Philox base samples keyed by (k0, k1) at the device step counter
+hipError_t flow_propose(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y, double* logq_y,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_base_normal, dim3(blocks(n, 64)), dim3(64), 0, st, step, k0, k1, n, f->d, f->u);
+  sample_rows(f, n, y, logq_y, st);
+  return hipGetLastError();
+}
+// log q of the n rows of x (FP64 [n][d]) into logq
+hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st) {
+  logq_rows(f, x, n, 0, n, false, st);
+  hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, st, f->logq, (int64_t)n, logq);
+  return hipGetLastError();
+}
+}  // namespace lt
+
+extern "C" {
+
+lt_status lt_flow_create(int hip_device, int dim, int n_layers, int hidden, int max_batch, lt_flow** out) {
+  if (!out) return ffail(LT_ERR_NULL, "null output");
+  if (dim < 2 || dim > 64 || n_layers < 1 || n_layers > 32 || hidden < 8 || hidden > 4096 || hidden % 8 ||
+      max_batch < 1 || max_batch > (1 << 20))
+    return ffail(LT_ERR_SHAPE, "flow dimensions: 2 <= dim <= 64, 1 <= layers <= 32, hidden in [8, 4096] and a "
+                               "multiple of 8, 1 <= max_batch <= 2^20");
+  FL_HIP(hipSetDevice(hip_device));
+  lt_flow* f = new lt_flow();
+  f->device = hip_device;
+  f->d = dim;
+  f->L = n_layers;
+  f->H = hidden;
+  f->maxB = max_batch;
+  int64_t off = 0;
+  const int da = dim / 2;
+  for (int l = 0; l < n_layers; ++l) {
+    LayerOff Lo;
+    Lo.na = da;
+    Lo.nb = dim - da;
+    Lo.a0 = (l % 2 == 0) ? 0 : dim - da;
+    Lo.b0 = (l % 2 == 0) ? da : 0;
+    Lo.W1 = off; off += (int64_t)hidden * Lo.na;
+    Lo.b1 = off; off += hidden;
+    Lo.W2 = off; off += (int64_t)hidden * hidden;
+    Lo.b2 = off; off += hidden;
+    Lo.W3 = off; off += (int64_t)2 * Lo.nb * hidden;
+    Lo.b3 = off; off += 2 * Lo.nb;
+    f->lay.push_back(Lo);
+  }
+  f->nparam = off;
+  const int64_t B = max_batch, H = hidden, L = n_layers;
+  hipError_t e = hipSuccess;
+#define FA(ptr, cnt) \
+  if (e == hipSuccess) e = falloc(f, &f->ptr, (size_t)(cnt))
+  FA(w, off); FA(g, off); FA(m, off); FA(v, off); FA(wb, off);
+  FA(mu, dim); FA(sig, dim);
+  FA(u, B * dim); FA(gu, B * dim); FA(logdet, B); FA(logq, B);
+  FA(a1, L * B * H); FA(a2, L * B * H); FA(o, L * B * 2 * dim); FA(s, L * B * dim); FA(ub, L * B * dim);
+  FA(uA, L * B * dim); FA(h1, L * B * H); FA(h2, L * B * H);
+  FA(tmpH, B * H); FA(go, B * 2 * dim); FA(gob, B * 2 * dim); FA(gH, B * H); FA(tmpA, B * dim);
+#undef FA
+  if (e != hipSuccess) {
+    lt_flow_destroy(f);
+    return ffail(LT_ERR_DEVICE, std::string("flow allocation: ") + hipGetErrorString(e));
+  }
+  std::vector<double> one(dim, 1.0), zero(dim, 0.0);
+  std::vector<float> zf(off, 0.0f);
+  if (hipMemcpy(f->mu, zero.data(), dim * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f->sig, one.data(), dim * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f->w, zf.data(), off * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f->m, zf.data(), off * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f->v, zf.data(), off * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    lt_flow_destroy(f);
+    return ffail(LT_ERR_DEVICE, "flow initialisation copies");
+  }
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks(off)), dim3(256), 0, 0, f->w, f->wb, off);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    lt_flow_destroy(f);
+    return ffail(LT_ERR_DEVICE, "flow initialisation");
+  }
+  *out = f;
+  return LT_OK;
+}
+
+lt_status lt_flow_destroy(lt_flow* f) {
+  if (!f) return ffail(LT_ERR_NULL, "null flow");
+  (void)hipSetDevice(f->device);
+  (void)hipDeviceSynchronize();
+  for (void* p : f->allocs) (void)hipFree(p);
+  delete f;
+  return LT_OK;
+}
+
+int64_t lt_flow_num_params(const lt_flow* f) { return f ? f->nparam : -1; }
+
+lt_status lt_flow_set_params(lt_flow* f, const float* params, const double* mu, const double* sigma) {
+  if (!f || !params || !mu || !sigma) return ffail(LT_ERR_NULL, "null argument");
+  double lsig = 0.0;
+  for (int i = 0; i < f->d; ++i) {
+    if (!(sigma[i] > 0.0) || !std::isfinite(sigma[i]) || !std::isfinite(mu[i]))
+      return ffail(LT_ERR_CONFIG, "mu must be finite and sigma positive");
+    lsig += std::log(sigma[i]);
+  }
+  for (int64_t i = 0; i < f->nparam; ++i)
+    if (!std::isfinite(params[i])) return ffail(LT_ERR_CONFIG, "non-finite flow parameter");
+  FL_HIP(hipSetDevice(f->device));
+  FL_HIP(hipDeviceSynchronize());
+  FL_HIP(hipMemcpy(f->w, params, f->nparam * sizeof(float), hipMemcpyHostToDevice));
+  FL_HIP(hipMemcpy(f->mu, mu, f->d * sizeof(double), hipMemcpyHostToDevice));
+  FL_HIP(hipMemcpy(f->sig, sigma, f->d * sizeof(double), hipMemcpyHostToDevice));
+  f->lsig = lsig;
+  std::vector<float> zf(f->nparam, 0.0f);
+  FL_HIP(hipMemcpy(f->m, zf.data(), f->nparam * sizeof(float), hipMemcpyHostToDevice));
+  FL_HIP(hipMemcpy(f->v, zf.data(), f->nparam * sizeof(float), hipMemcpyHostToDevice));
+  f->t = 0;
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks(f->nparam)), dim3(256), 0, 0, f->w, f->wb, f->nparam);
+  FL_HIP(hipDeviceSynchronize());
+  return LT_OK;
+}
+
+lt_status lt_flow_get_params(lt_flow* f, float* params) {
+  if (!f || !params) return ffail(LT_ERR_NULL, "null argument");
+  FL_HIP(hipSetDevice(f->device));
+  FL_HIP(hipDeviceSynchronize());
+  FL_HIP(hipMemcpy(params, f->w, f->nparam * sizeof(float), hipMemcpyDeviceToHost));
+  return LT_OK;
+}
+
+lt_status lt_flow_log_prob(lt_flow* f, const double* x, int64_t n, double* logq, void* stream) {
+  if (!f || !x || !logq) return ffail(LT_ERR_NULL, "null argument");
+  lt_status st = check_batch(f, n);
+  if (st) return st;
+  FL_HIP(hipSetDevice(f->device));
+  hipStream_t s = (hipStream_t)stream;
+  logq_rows(f, x, n, 0, (int)n, false, s);
+  hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, s, f->logq, n, logq);
+  FL_HIP(hipGetLastError());
+  return LT_OK;
+}
+
+lt_status lt_flow_sample(lt_flow* f, const double* z, int64_t n, double* x, double* logq, void* stream) {
+  if (!f || !z || !x || !logq) return ffail(LT_ERR_NULL, "null argument");
+  lt_status st = check_batch(f, n);
+  if (st) return st;
+  FL_HIP(hipSetDevice(f->device));
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_load, dim3(blocks(n * f->d)), dim3(256), 0, s, z, n * f->d, f->u);
+  sample_rows(f, (int)n, x, logq, s);
+  FL_HIP(hipGetLastError());
+  return LT_OK;
+}
+
+lt_status lt_flow_loss_grad(lt_flow* f, const double* x, int64_t n, double* logq, float* grad) {
+  if (!f || !x) return ffail(LT_ERR_NULL, "null argument");
+  lt_status st = check_batch(f, n);
+  if (st) return st;
+  FL_HIP(hipSetDevice(f->device));
+  logq_rows(f, x, n, 0, (int)n, true, 0);
+  backward(f, (int)n, 0);
+  FL_HIP(hipGetLastError());
+  FL_HIP(hipDeviceSynchronize());
+  if (logq) FL_HIP(hipMemcpy(logq, f->logq, n * sizeof(double), hipMemcpyDeviceToHost));
+  if (grad) FL_HIP(hipMemcpy(grad, f->g, f->nparam * sizeof(float), hipMemcpyDeviceToHost));
+  return LT_OK;
+}
+
+lt_status lt_flow_train(lt_flow* f, const double* x, int64_t n, int steps, int batch, double lr, void* stream) {
+  if (!f || !x) return ffail(LT_ERR_NULL, "null argument");
+  if (n < 1 || steps < 0) return ffail(LT_ERR_SHAPE, "training sizes");
+  lt_status st = check_batch(f, batch);
+  if (st) return st;
+  if (!(lr > 0.0) || !std::isfinite(lr)) return ffail(LT_ERR_CONFIG, "lr must be positive");
+  FL_HIP(hipSetDevice(f->device));
+  hipStream_t s = (hipStream_t)stream;
+  for (int it = 0; it < steps; ++it) {
+    const int64_t start = ((int64_t)it * batch) % n;
+    logq_rows(f, x, n, start, batch, true, s);
+    backward(f, batch, s);
+    adam(f, (float)lr, s);
+  }
+  FL_HIP(hipGetLastError());
+  return LT_OK;
+}
+
+}  // extern "C"

@@ -19,29 +19,12 @@
 #include <vector>
 
 #include "../../include/lisatd.h"
+#include "lt_rng.hpp"
 
 namespace lt_s {
 
-__host__ __device__ inline void philox4x32_10(uint32_t* c, uint32_t k0, uint32_t k1) {
-  for (int r = 0; r < 10; ++r) {
-    if (r > 0) {
-      k0 += 0x9E3779B9u;
-      k1 += 0xBB67AE85u;
-    }
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-    c[1] = (uint32_t)p1;
-    c[3] = (uint32_t)p0;
-    c[0] = n0;
-    c[2] = n2;
-  }
-}
+using namespace lt_rng;
 
-__device__ inline double u01(uint32_t u) { return ((double)u + 0.5) * 2.3283064365386963e-10; }
-
-constexpr uint32_t kTagMove = 0x100, kTagShift = 0x200, kTagSwap = 0x300;
 constexpr int kMaxDim = 32;
 
 struct Dev {
@@ -54,6 +37,9 @@ struct Dev {
   double *lo, *hi, *gmean, *gicov;
   uint64_t* step;
   int64_t *acc, *prop, *sacc, *sprop;
+  // flow move on the cold rung (beta_0 = 1)
+  double *fy, *fqy, *fqx, *fylogl, *fylogp;
+  int64_t *facc, *fprop;
 };
 
 __device__ inline void to_params(const Dev& D, const double* x, double* p) {
@@ -158,6 +144,36 @@ __global__ void k_accept(Dev D, int h) {
   D.prop[w] += 1;
 }
 
+// flow proposals y (one per cold walker): prior and parameter rows
+__global__ void k_flow_prep(Dev D) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.W) return;
+  const double* y = D.fy + (int64_t)k * D.d;
+  D.fylogp[k] = log_prior(D, y);
+  if (D.target == LT_TARGET_TDI) to_params(D, y, D.params + (int64_t)k * 16);
+}
+
+// independence Metropolis-Hastings with the flow density q:
+// log alpha = beta_0 (logL_y - logL_x) + (logP_y - logP_x) + log q(x) - log q(y)
+__global__ void k_flow_accept(Dev D) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.W) return;
+  uint32_t c[4] = {(uint32_t)*D.step, kTagFlowU, (uint32_t)k, 0u};
+  philox4x32_10(c, D.k0, D.k1);
+  const double lly = D.fylogl[k], lpy = D.fylogp[k];
+  const double la = D.beta[0] * (lly - D.logl[k]) + (lpy - D.logp[k]) + (D.fqx[k] - D.fqy[k]);
+  const bool ok = lpy > -INFINITY && !isnan(lly) && lly > -INFINITY && !isnan(la) && log(u01(c[0])) < la;
+  if (ok) {
+    const double* y = D.fy + (int64_t)k * D.d;
+    double* x = D.X + (int64_t)k * D.d;
+    for (int i = 0; i < D.d; ++i) x[i] = y[i];
+    D.logl[k] = lly;
+    D.logp[k] = lpy;
+  }
+  D.facc[k] += ok ? 1 : 0;
+  D.fprop[k] += 1;
+}
+
 // tempering swaps, hottest adjacent pair first; one workgroup, then the step counter advances
 __global__ void k_swap(Dev D) {
   const uint64_t step = *D.step;
@@ -196,6 +212,12 @@ using namespace lt_s;
 
 namespace lt {
 void set_error(const std::string& msg);   // thread-local message returned by lt_last_error()
+int flow_dim(const lt_flow* f);
+int flow_max_batch(const lt_flow* f);
+int flow_device(const lt_flow* f);
+hipError_t flow_propose(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y, double* logq_y,
+                        hipStream_t st);
+hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st);
 }
 
 struct lt_sampler {
@@ -213,6 +235,7 @@ struct lt_sampler {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  lt_flow* flow = nullptr;
 };
 
 #define S_HIP(call)                                                                  \
@@ -260,6 +283,17 @@ static lt_status record_step(lt_sampler* s, hipStream_t st) {
     lt_status r = eval_logl(s, s->D.Y, n, s->D.ylogl, st);
     if (r != LT_OK) return r;
     hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h);
+    S_HIP(hipGetLastError());
+  }
+  if (s->flow) {
+    const int W = s->cfg.n_walkers;
+    S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st));
+    S_HIP(lt::flow_logq(s->flow, s->D.X, W, s->D.fqx, st));
+    hipLaunchKernelGGL(k_flow_prep, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
+    S_HIP(hipGetLastError());
+    lt_status r = eval_logl(s, s->D.fy, W, s->D.fylogl, st);
+    if (r != LT_OK) return r;
+    hipLaunchKernelGGL(k_flow_accept, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());
   }
   const int nt = s->cfg.n_walkers < 1024 ? s->cfg.n_walkers : 1024;
@@ -314,7 +348,9 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
       (r = salloc(s, &D.params, TW * 16)) || (r = salloc(s, &D.lo, d)) || (r = salloc(s, &D.hi, d)) ||
       (r = salloc(s, &D.gmean, 2 * d)) || (r = salloc(s, &D.gicov, (size_t)d * d)) || (r = salloc(s, &D.step, 1)) ||
       (r = salloc(s, &D.acc, TW)) || (r = salloc(s, &D.prop, TW)) || (r = salloc(s, &D.sacc, TW)) ||
-      (r = salloc(s, &D.sprop, TW))) {
+      (r = salloc(s, &D.sprop, TW)) || (r = salloc(s, &D.fy, (size_t)W * d)) || (r = salloc(s, &D.fqy, W)) ||
+      (r = salloc(s, &D.fqx, W)) || (r = salloc(s, &D.fylogl, W)) || (r = salloc(s, &D.fylogp, W)) ||
+      (r = salloc(s, &D.facc, W)) || (r = salloc(s, &D.fprop, W))) {
     lt_sampler_destroy(s);
     return r;
   }
@@ -360,6 +396,8 @@ lt_status lt_sampler_set_state(lt_sampler* s, const double* pos) {
   S_HIP(hipMemcpyAsync(s->D.step, &zero, sizeof(uint64_t), hipMemcpyHostToDevice, s->cap));
   for (int64_t* p : {s->D.acc, s->D.prop, s->D.sacc, s->D.sprop})
     S_HIP(hipMemcpyAsync(p, z.data(), TW * sizeof(int64_t), hipMemcpyHostToDevice, s->cap));
+  for (int64_t* p : {s->D.facc, s->D.fprop})
+    S_HIP(hipMemcpyAsync(p, z.data(), s->cfg.n_walkers * sizeof(int64_t), hipMemcpyHostToDevice, s->cap));
   S_HIP(hipStreamSynchronize(s->cap));
   return LT_OK;
 }
@@ -405,6 +443,39 @@ lt_status lt_sampler_get_state(lt_sampler* s, double* pos, double* logl, double*
       for (int64_t x : v) t += x;
       counters[q] = t;
     }
+  }
+  return LT_OK;
+}
+
+lt_status lt_sampler_set_flow(lt_sampler* s, lt_flow* flow) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  if (flow) {
+    if (lt::flow_dim(flow) != s->cfg.dim) return sfail(LT_ERR_CONFIG, "flow dimension differs from the sampler's");
+    if (lt::flow_max_batch(flow) < s->cfg.n_walkers) return sfail(LT_ERR_SHAPE, "flow max_batch < n_walkers");
+    if (lt::flow_device(flow) != s->device) return sfail(LT_ERR_CONFIG, "flow lives on another device");
+  }
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->exec = nullptr;
+  s->graph = nullptr;
+  s->flow = flow;
+  return LT_OK;
+}
+
+lt_status lt_sampler_flow_counts(lt_sampler* s, int64_t* counts) {
+  if (!s || !counts) return sfail(LT_ERR_NULL, "null argument");
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  const int W = s->cfg.n_walkers;
+  std::vector<int64_t> v(W);
+  int64_t* src[2] = {s->D.facc, s->D.fprop};
+  for (int q = 0; q < 2; ++q) {
+    S_HIP(hipMemcpy(v.data(), src[q], W * sizeof(int64_t), hipMemcpyDeviceToHost));
+    int64_t t = 0;
+    for (int64_t x : v) t += x;
+    counts[q] = t;
   }
   return LT_OK;
 }

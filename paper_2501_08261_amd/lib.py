@@ -90,6 +90,21 @@ _sig = {
     "lt_sampler_set_state": ([_P, _P], ctypes.c_int),
     "lt_sampler_step": ([_P, ctypes.c_int, _P], ctypes.c_int),
     "lt_sampler_get_state": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "lt_sampler_set_flow": ([_P, _P], ctypes.c_int),
+    "lt_sampler_flow_counts": ([_P, _P], ctypes.c_int),
+    "lt_fisher": ([_P, _P, ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid),
+                   ctypes.POINTER(Orbit), ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), _P], ctypes.c_int),
+    "lt_fisher_draw": ([_P, _P, ctypes.c_int, _P, _P, _I64, ctypes.c_uint64, ctypes.c_double, _P], ctypes.c_int),
+    "lt_flow_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)],
+                       ctypes.c_int),
+    "lt_flow_destroy": ([_P], ctypes.c_int),
+    "lt_flow_num_params": ([_P], _I64),
+    "lt_flow_set_params": ([_P, _P, _P, _P], ctypes.c_int),
+    "lt_flow_get_params": ([_P, _P], ctypes.c_int),
+    "lt_flow_log_prob": ([_P, _P, _I64, _P, _P], ctypes.c_int),
+    "lt_flow_sample": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int),
+    "lt_flow_loss_grad": ([_P, _P, _I64, _P, _P], ctypes.c_int),
+    "lt_flow_train": ([_P, _P, _I64, ctypes.c_int, ctypes.c_int, ctypes.c_double, _P], ctypes.c_int),
     "lt_profile_enable": ([_P, ctypes.c_int], ctypes.c_int),
     "lt_profile_read": ([_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int],
                         ctypes.c_int),
@@ -286,6 +301,17 @@ class Sampler:
                                          step.ctypes.data, cnt.ctypes.data))
         return pos, logl, logp, int(step[0]), cnt
 
+    def set_flow(self, flow):
+        """Attach a Flow (None: detach) for independence moves on the cold rung."""
+        _check(_lib.lt_sampler_set_flow(self.h, flow.h if flow is not None else None))
+        self._flow = flow
+
+    def flow_counts(self):
+        import numpy as np
+        c = np.zeros(2, dtype=np.int64)
+        _check(_lib.lt_sampler_flow_counts(self.h, c.ctypes.data))
+        return int(c[0]), int(c[1])
+
     def close(self):
         if self.h:
             _check(_lib.lt_sampler_destroy(self.h))
@@ -296,3 +322,119 @@ class Sampler:
             self.close()
         except Exception:
             pass
+
+
+def fisher(ctx, x0, param_kind, t_c, steps, g, cfg, orbit, tdi, psd, f_lo=3e-4, f_hi=0.02):
+    """Fisher matrix in the sampling coordinates (lt_fisher); psd: device [3][n/2+1]."""
+    import numpy as np
+    kinds = {"aligned10": LT_PARAMS_ALIGNED10, "precessing14": LT_PARAMS_PRECESSING14}
+    x, px = _host(x0)
+    st, ps = _host(steps)
+    d = x.size
+    G = np.zeros((d, d))
+    P = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
+    _check(_lib.lt_fisher(ctx.h, px, kinds[param_kind], float(t_c), ps, ctypes.byref(cfg),
+                          ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), ctypes.byref(orbit), ctypes.byref(tdi),
+                          ctypes.byref(P), G.ctypes.data))
+    return G
+
+
+def fisher_draw(x0, gamma, lo, hi, count, seed, reg=1e-10):
+    """count draws from N(x0, gamma^-1) inside [lo, hi] (lt_fisher_draw), host [count][d]."""
+    import numpy as np
+    x, px = _host(x0)
+    G, pg = _host(gamma)
+    l, pl = _host(lo)
+    h, ph = _host(hi)
+    out = np.zeros((int(count), x.size))
+    _check(_lib.lt_fisher_draw(px, pg, x.size, pl, ph, int(count), int(seed), float(reg), out.ctypes.data))
+    return out
+
+
+class Flow:
+    """RealNVP-style flow proposal (lt_flow_*); parameter vector layout as in include/lisatd.h."""
+
+    def __init__(self, dim, n_layers=8, hidden=256, max_batch=4096, device=0):
+        h = ctypes.c_void_p()
+        _check(_lib.lt_flow_create(device, dim, n_layers, hidden, max_batch, ctypes.byref(h)))
+        self.h, self.d, self.L, self.H, self.max_batch = h, dim, n_layers, hidden, max_batch
+
+    @property
+    def num_params(self):
+        return int(_lib.lt_flow_num_params(self.h))
+
+    def set_params(self, params, mu, sigma):
+        import numpy as np
+        w, pw = _host(params, np.float32)
+        if w.size != self.num_params:
+            raise ValueError("expected %d parameters" % self.num_params)
+        m, pm = _host(mu)
+        s, ps = _host(sigma)
+        _check(_lib.lt_flow_set_params(self.h, pw, pm, ps))
+
+    def get_params(self):
+        import numpy as np
+        w = np.zeros(self.num_params, dtype=np.float32)
+        _check(_lib.lt_flow_get_params(self.h, w.ctypes.data))
+        return w
+
+    def log_prob(self, x, out=None, stream=None):
+        out = out if out is not None else torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        _check(_lib.lt_flow_log_prob(self.h, _ptr(x), x.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def sample(self, z, stream=None):
+        x = torch.empty_like(z)
+        logq = torch.empty(z.shape[0], dtype=torch.float64, device=z.device)
+        _check(_lib.lt_flow_sample(self.h, _ptr(z), z.shape[0], _ptr(x), _ptr(logq), _stream(stream)))
+        return x, logq
+
+    def loss_grad(self, x):
+        import numpy as np
+        logq = np.zeros(x.shape[0])
+        g = np.zeros(self.num_params, dtype=np.float32)
+        _check(_lib.lt_flow_loss_grad(self.h, _ptr(x), x.shape[0], logq.ctypes.data, g.ctypes.data))
+        return logq, g
+
+    def train(self, x, steps, batch, lr, stream=None):
+        _check(_lib.lt_flow_train(self.h, _ptr(x), x.shape[0], int(steps), int(batch), float(lr), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _check(_lib.lt_flow_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def flow_pack(P):
+    """Oracle-style parameter list (dicts W1, b1, W2, b2, W3, b3 per layer) -> FP32 vector."""
+    import numpy as np
+    parts = []
+    for p in P:
+        for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            parts.append(np.asarray(p[k], dtype=np.float32).ravel())
+    return np.concatenate(parts)
+
+
+def flow_unpack(w, d, n_layers, hidden):
+    """FP32 vector -> list of per-layer dicts (float64 arrays)."""
+    import numpy as np
+    da, db = d // 2, d - d // 2
+    shapes = (("W1", (hidden, da)), ("b1", (hidden,)), ("W2", (hidden, hidden)), ("b2", (hidden,)),
+              ("W3", (2 * db, hidden)), ("b3", (2 * db,)))
+    out, off = [], 0
+    for _ in range(n_layers):
+        p = {}
+        for k, shp in shapes:
+            n = int(np.prod(shp))
+            p[k] = np.asarray(w[off:off + n], dtype=np.float64).reshape(shp)
+            off += n
+        out.append(p)
+    if off != len(w):
+        raise ValueError("parameter vector length does not match the flow shape")
+    return out

@@ -1,0 +1,236 @@
+"""GPU flow proposal (lt_flow_*) and the sampler's flow move against the oracle.
+
+Tolerances.  The identity flow (zero output layer) is exact in the library's
+FP64 coupling path, so it is compared to 1e-12.  A non-trivial flow runs its
+conditioner GEMMs on BF16 operands (unit roundoff 2^-9 ~ 2e-3) with FP32
+accumulation: with output-layer weights of scale 0.3 / sqrt(H) and O(1)
+activations each s and t carries an error of about 2e-3 x 0.3, and log q sums
+L |B| such terms (8 x 7 = 56 at d = 14) that add like a random walk, about
+5e-3; the tests allow 0.05 on log q, 0.02 on z, and 5 % relative (Frobenius)
+on each gradient block.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import flow as fl
+from oracle.sampler import PTSampler, gaussian_logl, integrated_time
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2501_08261_amd import lib as L
+    return L
+
+
+def _rand_params(d, L, H, seed):
+    P = fl.init_params(d, L, H, seed)
+    rng = np.random.default_rng(seed + 1)
+    for p in P:
+        p["W3"] = rng.normal(size=p["W3"].shape) * 0.3 / np.sqrt(p["W3"].shape[1])
+        p["b3"] = rng.normal(size=p["b3"].shape) * 0.1
+        p["b1"] = rng.normal(size=p["b1"].shape) * 0.1
+    return P
+
+
+def _f32(P):
+    """The oracle evaluated with the FP32 master weights the library holds."""
+    return [{k: np.asarray(v, np.float32).astype(np.float64) for k, v in p.items()} for p in P]
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def test_pack_layout(lib):
+    d, L, H = 7, 3, 16
+    P = _rand_params(d, L, H, 0)
+    f = lib.Flow(d, L, H, 8)
+    w = lib.flow_pack(P)
+    assert f.num_params == w.size
+    f.set_params(w, np.zeros(d), np.ones(d))
+    assert np.array_equal(f.get_params(), w)
+    Q = lib.flow_unpack(w, d, L, H)
+    assert all(np.array_equal(Q[l][k], np.float32(P[l][k])) for l in range(L) for k in P[l])
+    f.close()
+
+
+@pytest.mark.parametrize("n", [1, 37, 300])
+def test_identity_flow_is_exact(lib, n):
+    d, L, H = 14, 8, 256
+    rng = np.random.default_rng(n)
+    P = fl.init_params(d, L, H, 3)
+    mu, sig = rng.normal(size=d), rng.uniform(0.5, 3.0, size=d)
+    f = lib.Flow(d, L, H, 512)
+    f.set_params(lib.flow_pack(P), mu, sig)
+    x = mu + sig * rng.normal(size=(n, d))
+    lq = f.log_prob(_dev(x)).cpu().numpy()
+    _, lq_o = fl.forward(P, x, mu, sig)
+    assert np.max(np.abs(lq - lq_o)) < 1e-12 * (1 + np.max(np.abs(lq_o)))
+    z = rng.normal(size=(n, d))
+    xs, lqs = f.sample(_dev(z))
+    xo, lqo = fl.inverse(P, z, mu, sig)
+    assert np.array_equal(xs.cpu().numpy(), xo)
+    assert np.max(np.abs(lqs.cpu().numpy() - lqo)) < 1e-12 * (1 + np.max(np.abs(lqo)))
+    f.close()
+
+
+@pytest.mark.parametrize("d,n", [(14, 300), (11, 1000), (2, 65)])
+def test_flow_parity_bf16(lib, d, n):
+    L, H = 8, 256
+    rng = np.random.default_rng(d)
+    P = _f32(_rand_params(d, L, H, d))
+    mu, sig = rng.normal(size=d), rng.uniform(0.5, 3.0, size=d)
+    f = lib.Flow(d, L, H, 1024)
+    f.set_params(lib.flow_pack(P), mu, sig)
+    x = mu + sig * rng.normal(size=(n, d))
+    lq = f.log_prob(_dev(x)).cpu().numpy()
+    z_o, lq_o = fl.forward(P, x, mu, sig)
+    assert np.max(np.abs(lq - lq_o)) < 0.05
+    zz = rng.normal(size=(n, d))
+    xs, lqs = f.sample(_dev(zz))
+    xs, lqs = xs.cpu().numpy(), lqs.cpu().numpy()
+    xo, lqo = fl.inverse(P, zz, mu, sig)
+    assert np.max(np.abs((xs - xo) / sig)) < 0.02
+    assert np.max(np.abs(lqs - lqo)) < 0.05
+    # the library's own inverse and forward agree far below the BF16 level
+    lq_back = f.log_prob(_dev(xs)).cpu().numpy()
+    assert np.median(np.abs(lq_back - lqs)) < 1e-9 and np.max(np.abs(lq_back - lqs)) < 0.05
+    f.close()
+
+
+@pytest.mark.parametrize("d,n", [(14, 512), (5, 200)])
+def test_gradient_parity(lib, d, n):
+    L, H = 8, 256
+    rng = np.random.default_rng(100 + d)
+    P = _f32(_rand_params(d, L, H, 7 + d))
+    mu, sig = rng.normal(size=d), rng.uniform(0.5, 2.0, size=d)
+    f = lib.Flow(d, L, H, 1024)
+    f.set_params(lib.flow_pack(P), mu, sig)
+    x = mu + sig * rng.normal(size=(n, d)) * 1.3
+    lq, g = f.loss_grad(_dev(x))
+    loss_o, G = fl.nll_and_grad(P, x, mu, sig)
+    assert abs(-lq.mean() - loss_o) < 0.01
+    Gg = lib.flow_unpack(g, d, L, H)
+    for l in range(L):
+        for k in G[l]:
+            ref = G[l][k]
+            err = np.linalg.norm(Gg[l][k] - ref) / max(np.linalg.norm(ref), 1e-3)
+            assert err < 0.05, (l, k, err)
+    f.close()
+
+
+def test_adam_step_parity(lib):
+    d, L, H, n = 6, 4, 64, 256
+    rng = np.random.default_rng(9)
+    P = _f32(_rand_params(d, L, H, 4))
+    mu, sig = np.zeros(d), np.ones(d)
+    f = lib.Flow(d, L, H, n)
+    w0 = lib.flow_pack(P)
+    f.set_params(w0, mu, sig)
+    x = rng.normal(size=(n, d))
+    f.train(_dev(x), steps=1, batch=n, lr=1e-3)
+    w1 = f.get_params()
+    _, G = fl.nll_and_grad(P, x, mu, sig)
+    opt = fl.Adam(P, lr=1e-3)
+    opt.step(P, G)
+    wo = lib.flow_pack(P)
+    # first Adam step: each parameter moves by lr * g / (|g| + eps), i.e. by about +-lr
+    dg, do = w1.astype(np.float64) - w0, wo.astype(np.float64) - w0
+    close = np.abs(dg - do) < 2e-5
+    assert close.mean() > 0.97
+    f.close()
+
+
+def test_trained_flow_matches_gaussian(lib):
+    d, L, H = 4, 6, 128
+    rng = np.random.default_rng(21)
+    A = rng.normal(size=(d, d))
+    C = A @ A.T + 0.5 * np.eye(d)
+    m = np.array([1.0, -2.0, 3.0, 0.0])
+    x = rng.multivariate_normal(m, C, size=20000)
+    f = lib.Flow(d, L, H, 1024)
+    f.set_params(lib.flow_pack(fl.init_params(d, L, H, 2)), x.mean(0), x.std(0))
+    f.train(_dev(x), steps=1500, batch=1024, lr=2e-3)
+    xs, _ = f.sample(_dev(rng.normal(size=(1024, d))))
+    xs = xs.cpu().numpy()
+    assert np.allclose(xs.mean(0), m, atol=0.2 * np.sqrt(np.diag(C)).max())
+    assert np.allclose(np.cov(xs.T), C, atol=0.2 * np.abs(C).max())
+    exact = -0.5 * np.einsum("ni,ij,nj->n", x - m, np.linalg.inv(C), x - m) - 0.5 * np.log(np.linalg.det(2 * np.pi * C))
+    lq = f.log_prob(_dev(x[:1024])).cpu().numpy()
+    assert abs(lq.mean() - exact[:1024].mean()) < 0.1
+    f.close()
+
+
+@pytest.mark.parametrize("T", [1, 2])
+def test_sampler_flow_move_parity(lib, T):
+    """P28: GPU chain with an (exact, identity) flow move against the oracle chain, step by step."""
+    d, W, seed = 5, 16, 777
+    rng = np.random.default_rng(T)
+    A = rng.normal(size=(d, d))
+    icov = np.linalg.inv(A @ A.T + d * np.eye(d))
+    means = rng.normal(size=(1, d))
+    lo, hi = -30 * np.ones(d), 30 * np.ones(d)
+    P = fl.init_params(d, 4, 32, 1)
+    mu, sig = means[0] + 0.5, np.linspace(1.0, 3.0, d)
+    start = means[0] + rng.normal(size=(T, W, d))
+    fg = lib.Flow(d, 4, 32, W)
+    fg.set_params(lib.flow_pack(P), mu, sig)
+    g = lib.Sampler(W, T, d, lo, hi, seed, target="gauss", param_kind="raw", t_max=5.0, means=means, icov=icov)
+    g.set_flow(fg)
+    g.set_state(start)
+    o = PTSampler(gaussian_logl(means, icov), lo, hi, W, T, d, seed, t_max=5.0)
+    o.set_flow(P, mu, sig)
+    o.set_state(start)
+    for s in range(25):
+        g.step(1)
+        o.step()
+        pos, logl, _, step, cnt = g.state()
+        assert np.max(np.abs(pos - o.X)) < 1e-12 * (1 + np.max(np.abs(o.X))), s
+        assert cnt[0] == o.acc and cnt[2] == o.sacc
+        assert g.flow_counts() == (o.facc, o.fprop), s
+    assert 0 < o.facc < o.fprop
+    g.close()
+    fg.close()
+
+
+def test_learned_proposal_raises_ess(lib):
+    """A flow trained on burn-in samples lowers the cold chain's integrated autocorrelation time."""
+    d, W = 4, 64
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(d, d))
+    C = A @ A.T + 0.05 * np.eye(d)          # strongly correlated
+    means = np.zeros((1, d))
+    icov = np.linalg.inv(C)
+    lo, hi = -60 * np.ones(d), 60 * np.ones(d)
+    start = rng.multivariate_normal(means[0], C, size=(1, W))
+
+    def run(flow, steps):
+        s = lib.Sampler(W, 1, d, lo, hi, 99, target="gauss", param_kind="raw", means=means, icov=icov)
+        if flow is not None:
+            s.set_flow(flow)
+        s.set_state(start)
+        chain = []
+        for _ in range(steps):
+            s.step(1)
+            chain.append(s.state()[0][0])
+        s.close()
+        return np.array(chain)
+
+    plain = run(None, 1200)
+    burn = plain[200:].reshape(-1, d)
+    f = lib.Flow(d, 6, 128, 1024)
+    f.set_params(lib.flow_pack(fl.init_params(d, 6, 128, 0)), burn.mean(0), burn.std(0))
+    xs = burn[rng.permutation(len(burn))]
+    f.train(_dev(xs), steps=1000, batch=1024, lr=2e-3)
+    learned = run(f, 1200)
+    tau_plain = integrated_time(plain[200:]).max()
+    tau_flow = integrated_time(learned[200:]).max()
+    assert tau_flow < 0.5 * tau_plain, (tau_flow, tau_plain)
+    flat = learned[200:].reshape(-1, d)
+    assert np.allclose(np.cov(flat.T), C, atol=0.15 * np.abs(C).max())
+    f.close()

@@ -74,3 +74,75 @@ def test_integrated_time_ar1():
         x[t, :, 0] = rho * x[t - 1, :, 0] + e[t]
     tau = integrated_time(x)[0]
     assert abs(tau / ((1 + rho) / (1 - rho)) - 1) < 0.1
+
+
+def _identity_flow(d, L=2, H=8):
+    from oracle import flow as fl
+    return fl.init_params(d, L, H, 0)           # zero output layer: the identity map
+
+
+def test_flow_normals_are_standard():
+    """P28: the Box-Muller base samples of the flow move are standard normal and uncorrelated."""
+    s = PTSampler(lambda x: np.zeros(len(x)), [-1] * 6, [1] * 6, 64, 1, 6, seed=11)
+    z = np.concatenate([s.flow_normals(k) for k in range(200)])
+    assert np.all(np.abs(z.mean(0)) < 4 / np.sqrt(len(z)))
+    assert np.allclose(np.cov(z.T), np.eye(6), atol=0.03)
+    assert np.allclose((z ** 4).mean(0), 3.0, atol=0.15)
+
+
+def test_flow_move_exact_proposal_always_accepted():
+    """P28: when q equals the target, the independence move accepts every proposal."""
+    d = 4
+    m = np.array([1.0, -2.0, 0.5, 3.0])
+    sd = np.array([0.5, 2.0, 1.0, 0.1])
+    s = PTSampler(gaussian_logl(m, np.diag(1 / sd ** 2)), m - 100, m + 100, 16, 1, d, seed=5)
+    s.set_state(m + sd * np.random.default_rng(0).normal(size=(1, 16, d)))
+    s.set_flow(_identity_flow(d), m, sd)
+    for _ in range(20):
+        s.step()
+    assert s.fprop == 20 * 16 and s.facc == s.fprop
+
+
+def test_flow_move_keeps_the_target():
+    """P28: with a mismatched flow the chain still samples the target (the q(x)/q(y) correction)."""
+    rng = np.random.default_rng(3)
+    d = 2
+    C = np.array([[1.0, 0.6], [0.6, 2.0]])
+    m = np.array([0.5, -1.0])
+    s = PTSampler(gaussian_logl(m, np.linalg.inv(C)), [-40] * d, [40] * d, 32, 1, d, seed=9)
+    s.set_state(m + rng.multivariate_normal(np.zeros(d), C, size=(1, 32)))
+    s.set_flow(_identity_flow(d), m + np.array([1.0, -1.0]), np.array([2.0, 2.5]))
+    chain = []
+    for i in range(2500):
+        s.step()
+        if i >= 200:
+            chain.append(s.X[0].copy())
+    chain = np.array(chain)
+    flat = chain.reshape(-1, d)
+    tau = integrated_time(chain).max()
+    err = np.sqrt(np.diag(C) / (flat.shape[0] / tau))
+    assert np.all(np.abs(flat.mean(0) - m) < 5 * err)
+    assert np.allclose(np.cov(flat.T), C, atol=0.15)
+    assert 0.1 < s.facc / s.fprop < 0.9
+
+
+def test_flow_move_lowers_autocorrelation():
+    """P28: a proposal close to the target decorrelates the cold chain faster than stretch moves alone."""
+    rng = np.random.default_rng(4)
+    d = 3
+    A = rng.normal(size=(d, d))
+    C = A @ A.T + 0.1 * np.eye(d)
+    m = np.zeros(d)
+    f = gaussian_logl(m, np.linalg.inv(C))
+    taus = []
+    for use_flow in (False, True):
+        s = PTSampler(f, [-60] * d, [60] * d, 16, 1, d, seed=2)
+        s.set_state(rng.multivariate_normal(m, C, size=(1, 16)))
+        if use_flow:
+            s.set_flow(_identity_flow(d), m, np.sqrt(np.diag(C)) * 1.2)
+        chain = []
+        for i in range(1500):
+            s.step()
+            chain.append(s.X[0].copy())
+        taus.append(integrated_time(np.array(chain)).max())
+    assert taus[1] < 0.7 * taus[0]
