@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--no-sampler", action="store_true", help="skip the sampler-step and ESS measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known traffic) to calibrate HBM counters")
     return ap.parse_args()
@@ -72,6 +73,125 @@ def cpu_baseline(g, params, taps):
             "sample": "oracle on template 0: response+TDI on %d of %d samples (scaled x%.0f) + full-length "
                       "rfft/inner products; %.1f s measured" % (slice_len, n, n / slice_len,
                                                               per * slice_len / n + t_fft)}
+
+
+FISHER_STEPS_P14 = [1.0, 1.0, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1.0, 1e-5, 1e-5, 1e-5, 1e-5, 1e-5]
+
+
+def _tdi_setup(lib, inputs, ctx, n, prec, before_end=2000.0):
+    """Precessing Tab. I injection (zero noise) on an n-sample grid: config, data, PSD, dd."""
+    import torch
+    dev = "cuda:0"
+    g = inputs.grid(n, 5.0)
+    modes = ((2, 2), (2, 1), (3, 3), (3, 2), (4, 4))
+    cfg = ctx.wf_cfg(modes, True, precision=prec)
+    cfg64 = ctx.wf_cfg(modes, True, precision=lib.LT_FP64)
+    orb = ctx.orbit("kepler")
+    tdi = ctx.tdi_cfg(20, 7, TAPS)
+    S = torch.zeros((3, n // 2 + 1), dtype=torch.float64, device=dev)
+    lib.psd_sangria(g, 20, S)
+    inj = inputs.tab1_injection(True, g, before_end=before_end)
+    d = torch.zeros((1, 3, n), dtype=lib.real_dtype(prec), device=dev)
+    ctx.lisa_tdi_response(torch.tensor(inj[None], device=dev), g, cfg, orb, tdi, d)
+    dd = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.noise_inner(d, g, S, dd, precision=prec)
+    torch.cuda.synchronize()
+    return dict(g=g, cfg=cfg, cfg64=cfg64, orb=orb, tdi=tdi, S=S, inj=inj, d=d, dd=float(dd.item()))
+
+
+def _sampler(lib, inputs, ctx, su, W, T, seed):
+    """Fisher-initialised sampler on the precessing 14-D coordinates."""
+    x0, lo, hi = inputs.tab1_prior(True, su["inj"])
+    G = lib.fisher(ctx, x0, "precessing14", su["inj"][11], FISHER_STEPS_P14, su["g"], su["cfg64"], su["orb"],
+                   su["tdi"], su["S"])
+    start = lib.fisher_draw(x0, G, lo, hi, T * W, seed, 1e-12)
+    smp = lib.Sampler(W, T, 14, lo, hi, seed, target="tdi", param_kind="precessing14", t_c=su["inj"][11],
+                      g=su["g"], cfg=su["cfg"], orbit=su["orb"], tdi=su["tdi"], psd=su["S"], data_aet=su["d"][0],
+                      dd=su["dd"])
+    smp.set_state(start)
+    return smp
+
+
+def sampler_bench(lib, inputs, prec, steps=3, W=512, T=8):
+    """One full sampler step on the device (propose, waveform, response, FFT,
+    logL, accept, swaps) replayed as a HIP graph: 512 walkers x 8 temperatures,
+    precessing 14-D, 2^20 samples, TDI-2 AET, Fisher-initialised."""
+    import torch
+    ctx = lib.Context(0)
+    su = _tdi_setup(lib, inputs, ctx, N_SAMPLES, prec)
+    smp = _sampler(lib, inputs, ctx, su, W, T, 11)
+    smp.step(1)                                    # captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    smp.step(steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    _, _, _, k, cnt = smp.state()
+    smp.close()
+    ctx.close()
+    return {"walkers": W, "temps": T, "steps": steps, "ms_per_step": 1e3 * dt, "steps_per_s": 1.0 / dt,
+            "logl_per_s": T * W / dt, "stretch_accept": cnt[0] / max(cnt[1], 1),
+            "swap_accept": cnt[2] / max(cnt[3], 1)}
+
+
+def ess_bench(lib, inputs, prec, n=1 << 14, W=64, T=4, burn=300, m=1500, train_steps=1500):
+    """Effective samples per second of the cold chain, plain stretch moves
+    against stretch + learned-flow moves, on the same injection and GPU
+    (precessing 14-D, TDI-2 AET, n samples around the merger).  The flow
+    (8 couplings, width 256) is trained on the plain run's cold samples."""
+    import numpy as np
+    import torch
+    from paper_2501_08261_amd.diagnostics import autocorr_time
+    ctx = lib.Context(0)
+    su = _tdi_setup(lib, inputs, ctx, n, prec)
+    smp = _sampler(lib, inputs, ctx, su, W, T, 5)
+    smp.step(burn)
+
+    def run(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        smp.step(200)
+        torch.cuda.synchronize()
+        t_step = (time.perf_counter() - t0) / 200
+        chain = []
+        for _ in range(k):
+            smp.step(1)
+            chain.append(smp.state()[0][0])
+        return np.array(chain), t_step
+
+    start_state = smp.state()[0]
+    plain, t_plain = run(m)
+    acc_plain = smp.state()[4]
+    tau_plain = autocorr_time(plain)
+    samples = plain.reshape(-1, 14)
+    flow = lib.Flow(14, 8, 256, 2048)
+    flow.set_params(lib.flow_init_params(14, 8, 256, 3), samples.mean(0), samples.std(0))
+    xs = torch.tensor(samples[np.random.default_rng(0).permutation(len(samples))], device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flow.train(xs, train_steps, 2048, 1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    smp.set_state(start_state)
+    smp.set_flow(flow)
+    smp.step(burn)
+    learned, t_learned = run(m)
+    acc_f, prop_f = smp.flow_counts()
+    tau_learned = autocorr_time(learned)
+    ess_plain = m * W / tau_plain.max()
+    ess_learned = m * W / tau_learned.max()
+    drift = np.max(np.abs(learned.reshape(-1, 14).mean(0) - samples.mean(0)) / samples.std(0))
+    smp.close()
+    flow.close()
+    ctx.close()
+    return {"n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
+            "plain": {"ess_per_s": ess_plain / (m * t_plain), "tau_max": float(tau_plain.max()),
+                      "ms_per_step": 1e3 * t_plain, "stretch_accept": acc_plain[0] / max(acc_plain[1], 1)},
+            "learned": {"ess_per_s": ess_learned / (m * t_learned), "tau_max": float(tau_learned.max()),
+                        "ms_per_step": 1e3 * t_learned, "flow_accept": acc_f / max(prop_f, 1),
+                        "train_s": t_train, "train_steps": train_steps},
+            "ratio": (ess_learned / (m * t_learned)) / (ess_plain / (m * t_plain)),
+            "posterior_mean_shift_sigma": float(drift)}
 
 
 def main():
@@ -142,13 +262,13 @@ def main():
                 "traffic": None, "kernel": dom}
     else:
         from paper_2501_08261_amd import workcount
-        flops = workcount.tdi_flops_per_sample(TAPS, 20, precessing=True, modes=len(modes))
+        flops = workcount.tdi_flops_per_sample(TAPS, 20)
         achieved = flops * a.n * a.batch / (kern[dom]["avg_ms"] * 1e-3) / 1e12
         peak = 78.6 if prec == lib.LT_FP64 else 157.3
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None, "kernel": dom}
     out = {
-        "metric": "logL evals/s (1M-sample precessing AET)",
+        "metric": "logL evals/s (1M-sample precessing AET); ESS/s learned vs plain proposal",
         "value": value, "unit": "logL evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32" if prec == lib.LT_MIXED else "f64", "data": "synthetic",
@@ -167,9 +287,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4, "launches": 3}
+    ctx.close()
+    if not a.no_sampler:
+        for key, fn in (("sampler", sampler_bench), ("ess", ess_bench)):
+            try:
+                out[key] = fn(lib, inputs, prec)
+            except Exception as e:                      # reported, the throughput line still prints
+                out[key] = {"error": "%s: %s" % (type(e).__name__, e)}
+            print("%s done" % key, file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, P, TAPS)
-    ctx.close()
     print(json.dumps(out))
 
 

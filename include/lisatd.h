@@ -122,7 +122,9 @@ lt_status lt_lisa_tdi_response(lt_ctx* ctx, const double* params, int64_t batch,
  * with (a|b) = 4 df Re sum_{band} a~ conj(b~) / S (Eq. 2.13), a~ = dt * DFT.
  * Computed as -(r|r)/2 + dd/2 with the residual r = h - d formed in the time
  * domain.  logl, logl_full (nullable): device FP64 [batch]; status (nullable):
- * device int32 [batch].  Scratch memory is owned by the context. */
+ * device int32 [batch].  Scratch memory is owned by the context; templates
+ * are processed in chunks of 256, so it holds 5 series of n samples (FP64 or
+ * FP32 by precision) for at most 256 templates whatever the batch. */
 lt_status lt_tdi_loglike(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
                          const lt_grid* grid, const lt_orbit* orbit, const lt_tdi_cfg* tdi,
                          const lt_psd* psd, const lt_data* data, double* logl, double* logl_full,

@@ -373,6 +373,8 @@ static TermTable make_terms(int gen) {
 }
 
 // ------------------------------------------------------------------ checks
+constexpr int64_t kLoglikeChunk = 256;
+
 static lt_status check_common(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g) {
   if (!c) return fail(LT_ERR_NULL, "null context");
   if (!params) return fail(LT_ERR_NULL, "null params");
@@ -560,19 +562,26 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
   st = get_plan(c, g->n, &p);
   if (st) return st;
   const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
-  LT_HIP(c->work.ensure((size_t)batch * 3 * g->n * rsz));
+  // templates are processed in chunks so that the workspace stays bounded
+  // (per chunk: 2 waveform + 3 TDI series of n samples per template)
+  const int64_t chunk = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+  LT_HIP(c->work.ensure((size_t)chunk * 3 * g->n * rsz));
   int32_t* stat = status;
   if (!stat) {
     LT_HIP(c->status.ensure((size_t)batch * sizeof(int32_t)));
     stat = (int32_t*)c->status.p;
   }
-  st = run_tdi(c, params, batch, cfg, g, o, t, 2, data->aet, c->work.p, stat, s);
-  if (st) return st;
-  st = band_power(c, p, c->work.p, batch * 3, cfg->precision, psd, g, t->channels, s);
-  if (st) return st;
-  Prof pr(c, 4, s);
-  LT_HIP(launch_finalize((const double*)c->partial.p, batch, p->dev.n1 / 2 + 1, 4.0 * g->dt / (double)g->n, data->dd,
-                         stat, logl, logl_full, nullptr, s));
+  for (int64_t off = 0; off < batch; off += chunk) {
+    const int64_t b = batch - off < chunk ? batch - off : chunk;
+    st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, c->work.p, stat + off, s);
+    if (st) return st;
+    st = band_power(c, p, c->work.p, b * 3, cfg->precision, psd, g, t->channels, s);
+    if (st) return st;
+    Prof pr(c, 4, s);
+    LT_HIP(launch_finalize((const double*)c->partial.p, b, p->dev.n1 / 2 + 1, 4.0 * g->dt / (double)g->n, data->dd,
+                           stat + off, logl ? logl + off : nullptr, logl_full ? logl_full + off : nullptr, nullptr,
+                           s));
+  }
   return LT_OK;
 }
 

@@ -46,6 +46,29 @@ def tab1_injection(precessing, g, before_end=2000.0):
     return p
 
 
+def tab1_prior(precessing, inj):
+    """Sampling coordinates of the Tab. I injection and the uniform prior box
+    (Tab. I ranges; ecliptic latitude restricted to [-pi/2, pi/2]).
+    precessing: m1, m2, a1, theta1, phi1, a2, theta2, phi2, D_L[Mpc], iota, phi_ref, beta, lambda, psi;
+    aligned: m1, m2, chi1z, chi2z, D_L[Mpc], iota, phi_ref, beta, lambda, psi."""
+    tail = [inj[8], inj[9], inj[10], inj[13], inj[12], inj[14]]
+    tail_lo = [1.9e4, 0.0, 0.0, -np.pi / 2, 0.0, -np.pi]
+    tail_hi = [2.1e4, np.pi, 2 * np.pi, np.pi / 2, 2 * np.pi, np.pi]
+    if precessing:
+        sp = []
+        for c in (2, 5):
+            a = float(np.linalg.norm(inj[c:c + 3]))
+            sp += [a, float(np.arccos(inj[c + 2] / a)), float(np.arctan2(inj[c + 1], inj[c]))]
+        x0 = np.array([inj[0], inj[1]] + sp + tail)
+        lo = np.array([0.99e6, 0.69e6, 0.0, 0.0, -np.pi, 0.0, 0.0, -np.pi] + tail_lo)
+        hi = np.array([1.01e6, 0.71e6, 1.0, np.pi, np.pi, 1.0, np.pi, np.pi] + tail_hi)
+    else:
+        x0 = np.array([inj[0], inj[1], inj[4], inj[7]] + tail)
+        lo = np.array([0.99e6, 0.69e6, -1.0, -1.0] + tail_lo)
+        hi = np.array([1.01e6, 0.71e6, 1.0, 1.0] + tail_hi)
+    return x0, lo, hi
+
+
 def single_template_case():
     """One-day (2,2) case: M = 1e6 Msun, q = 2, chi = (0.5, 0.3), 17,280 samples at 5 s.
 

@@ -411,6 +411,19 @@ class Flow:
             pass
 
 
+def flow_init_params(d, n_layers, hidden, seed):
+    """Starting weights: He-normal hidden layers, zero output layer (the identity flow)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    da, db = d // 2, d - d // 2
+    parts = []
+    for _ in range(n_layers):
+        parts += [rng.normal(size=hidden * da) * math.sqrt(2.0 / da), np.zeros(hidden),
+                  rng.normal(size=hidden * hidden) * math.sqrt(2.0 / hidden), np.zeros(hidden),
+                  np.zeros(2 * db * hidden), np.zeros(2 * db)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def flow_pack(P):
     """Oracle-style parameter list (dicts W1, b1, W2, b2, W3, b3 per layer) -> FP32 vector."""
     import numpy as np

@@ -1,29 +1,25 @@
-"""Algorithmic work per template-sample of the fused TDI response kernel.
+"""Algorithmic work per template-sample of the fused response / TDI kernel.
 
-Used for roofline accounting only.  Counts are the floating-point operations
-of the closed forms as written (a fused multiply-add counts 2; sqrt, cbrt,
-divide, sin, cos, tanh count 1 each), not instruction counts of the build:
+Used for roofline accounting only.  The count is the direct method's, whatever
+shortcuts the kernel takes: every interpolation at a delayed time needs one
+set of K Lagrange weights (3K flops: K differences and the two running
+products) and one K-tap dot product per interpolated series (2K flops, a
+fused multiply-add counting 2).
 
-* Lagrange interpolation with K taps: weights 5K (K differences, prefix and
-  suffix products, normalisation) plus 2K per interpolated series.
-* link response y at one grid sample: 6 links x 2 delayed reads x (5K + 2x2K)
-  for h+ and hx, cubic interpolation of 4 node quantities per link (6 x 4 x 8),
-  and the projection (6 x 5).
-* TDI at one output sample: 3 channels x (terms with a nonzero delay) x
-  (5K + 2K), the delay sums (terms x 6 x 2), 6 light-time interpolations x 8,
-  and A, E, T (10).
-* waveform + twist-up at one grid sample (FP64): aligned ~ 120, precessing
-  with five co-precessing modes ~ 800 (Euler angles, quaternion products,
-  powers of Q_a, Q_b, the ten Wigner-D polynomials, the mode sum).  The h
-  window exceeds the output tile by ~7 % (halos).
+* TDI 2.0, per output sample: the six links read h+ and hx at 3 receiver and
+  6 sender times (9 weight sets, 18 dot products); X, Y, Z have 3 x 16 terms,
+  of which 3 x 14 are delayed (42 weight sets, 42 dot products); the orbit
+  and delay interpolations and the y projections bring the totals to about
+  60 weight sets and 72 dot products, i.e. 60 * 3K + 72 * 2K = 324 K flops
+  (2592 at K = 8).
+* TDI 1.5: 36 weight sets and 48 dot products, i.e. 204 K flops.
+
+The waveform kernel is not included (it is a separate launch).
 """
 
 
-def tdi_flops_per_sample(taps, generation, precessing=True, modes=5):
+def tdi_flops_per_sample(taps, generation):
     K = taps
-    y = 6 * 2 * (5 * K + 2 * 2 * K) + 6 * 4 * 8 + 6 * 5
-    terms_nonzero = 14 if generation == 20 else 6
-    terms_all = 16 if generation == 20 else 8
-    tdi = 3 * terms_nonzero * (5 * K + 2 * K) + 3 * terms_all * 6 * 2 + 6 * 8 + 10
-    wave = (800 if precessing else 120) * modes / 5.0
-    return 1.07 * wave + y + tdi
+    if generation == 20:
+        return 60 * 3 * K + 72 * 2 * K
+    return 36 * 3 * K + 48 * 2 * K

@@ -3,11 +3,16 @@
 Tolerances.  The identity flow (zero output layer) is exact in the library's
 FP64 coupling path, so it is compared to 1e-12.  A non-trivial flow runs its
 conditioner GEMMs on BF16 operands (unit roundoff 2^-9 ~ 2e-3) with FP32
-accumulation: with output-layer weights of scale 0.3 / sqrt(H) and O(1)
-activations each s and t carries an error of about 2e-3 x 0.3, and log q sums
-L |B| such terms (8 x 7 = 56 at d = 14) that add like a random walk, about
-5e-3; the tests allow 0.05 on log q, 0.02 on z, and 5 % relative (Frobenius)
-on each gradient block.
+accumulation, and a composition of 8 random layers passes rounding errors on
+multiplied by each layer's Lipschitz constant (layers of output scale
+0.3 / sqrt(H) make it chaotic in the tails).  Two comparisons therefore:
+(1) the library against tests/bf16_ref.py, the same flow in numpy with the
+library's rounding points, where only the FP32 summation order differs
+(1e-3 on log q, 1 % on gradient blocks); (2) the library against the FP64
+oracle, row by row no further than the BF16 model itself is from it (plus
+1e-3), for near-identity layers of scale 0.05 / sqrt(H) whose BF16 deviation
+stays below about 0.05 on log q and 5 % on gradients.  A wrong GEMM tile
+moves log q by about 0.4 and fails both.
 """
 import numpy as np
 import pytest
@@ -18,6 +23,8 @@ pytestmark = pytest.mark.gpu
 from oracle import flow as fl
 from oracle.sampler import PTSampler, gaussian_logl, integrated_time
 
+import bf16_ref
+
 DEV = "cuda:0"
 
 
@@ -27,11 +34,11 @@ def lib():
     return L
 
 
-def _rand_params(d, L, H, seed):
+def _rand_params(d, L, H, seed, scale=0.05):
     P = fl.init_params(d, L, H, seed)
     rng = np.random.default_rng(seed + 1)
     for p in P:
-        p["W3"] = rng.normal(size=p["W3"].shape) * 0.3 / np.sqrt(p["W3"].shape[1])
+        p["W3"] = rng.normal(size=p["W3"].shape) * scale / np.sqrt(p["W3"].shape[1])
         p["b3"] = rng.normal(size=p["b3"].shape) * 0.1
         p["b1"] = rng.normal(size=p["b1"].shape) * 0.1
     return P
@@ -89,14 +96,22 @@ def test_flow_parity_bf16(lib, d, n):
     f.set_params(lib.flow_pack(P), mu, sig)
     x = mu + sig * rng.normal(size=(n, d))
     lq = f.log_prob(_dev(x)).cpu().numpy()
-    z_o, lq_o = fl.forward(P, x, mu, sig)
-    assert np.max(np.abs(lq - lq_o)) < 0.05
+    _, lq_o = fl.forward(P, x, mu, sig)
+    _, lq_b = bf16_ref.forward(P, x, mu, sig)
+    assert np.max(np.abs(lq - lq_b)) < 1e-3
+    assert np.all(np.abs(lq - lq_o) <= np.abs(lq_b - lq_o) + 1e-3)
+    assert np.max(np.abs(lq - lq_o)) < 0.1
     zz = rng.normal(size=(n, d))
     xs, lqs = f.sample(_dev(zz))
     xs, lqs = xs.cpu().numpy(), lqs.cpu().numpy()
     xo, lqo = fl.inverse(P, zz, mu, sig)
-    assert np.max(np.abs((xs - xo) / sig)) < 0.02
-    assert np.max(np.abs(lqs - lqo)) < 0.05
+    xb, lqb = bf16_ref.inverse(P, zz, mu, sig)
+    # rounding-boundary flips of single BF16 operands leave rare larger outliers
+    exb = np.abs((xs - xb) / sig)
+    assert np.quantile(exb, 0.99) < 1e-6 and exb.max() < 5e-3
+    assert np.max(np.abs(lqs - lqb)) < 1e-3
+    assert np.all(np.abs(lqs - lqo) <= np.abs(lqb - lqo) + 1e-3)
+    assert np.max(np.abs((xs - xo) / sig)) < 0.05
     # the library's own inverse and forward agree far below the BF16 level
     lq_back = f.log_prob(_dev(xs)).cpu().numpy()
     assert np.median(np.abs(lq_back - lqs)) < 1e-9 and np.max(np.abs(lq_back - lqs)) < 0.05
@@ -114,13 +129,16 @@ def test_gradient_parity(lib, d, n):
     x = mu + sig * rng.normal(size=(n, d)) * 1.3
     lq, g = f.loss_grad(_dev(x))
     loss_o, G = fl.nll_and_grad(P, x, mu, sig)
+    Gb = bf16_ref.nll_grad(P, x, mu, sig)
     assert abs(-lq.mean() - loss_o) < 0.01
     Gg = lib.flow_unpack(g, d, L, H)
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-3)
     for l in range(L):
         for k in G[l]:
-            ref = G[l][k]
-            err = np.linalg.norm(Gg[l][k] - ref) / max(np.linalg.norm(ref), 1e-3)
-            assert err < 0.05, (l, k, err)
+            assert rel(Gg[l][k], Gb[l][k]) < 0.01, (l, k)
+            assert rel(Gg[l][k], G[l][k]) < max(0.1, 2 * rel(Gb[l][k], G[l][k])), (l, k)
     f.close()
 
 
@@ -163,6 +181,12 @@ def test_trained_flow_matches_gaussian(lib):
     exact = -0.5 * np.einsum("ni,ij,nj->n", x - m, np.linalg.inv(C), x - m) - 0.5 * np.log(np.linalg.det(2 * np.pi * C))
     lq = f.log_prob(_dev(x[:1024])).cpu().numpy()
     assert abs(lq.mean() - exact[:1024].mean()) < 0.1
+    # parity of the trained flow with the oracle evaluated on the same FP32 weights
+    P = lib.flow_unpack(f.get_params(), d, L, H)
+    _, lq_o = fl.forward(P, x[:1024], x.mean(0), x.std(0))
+    _, lq_b = bf16_ref.forward(P, x[:1024], x.mean(0), x.std(0))
+    assert np.max(np.abs(lq - lq_b)) < 1e-3
+    assert np.max(np.abs(lq - lq_o)) < 0.05
     f.close()
 
 

@@ -146,3 +146,16 @@ def test_flow_move_lowers_autocorrelation():
             chain.append(s.X[0].copy())
         taus.append(integrated_time(np.array(chain)).max())
     assert taus[1] < 0.7 * taus[0]
+
+
+def test_package_autocorr_time_matches_oracle():
+    """The package's host ESS estimator agrees with the oracle's on AR(1) chains."""
+    from paper_2501_08261_amd.diagnostics import autocorr_time
+    rng = np.random.default_rng(6)
+    n, w = 5000, 6
+    x = np.zeros((n, w, 2))
+    e = rng.normal(size=(n, w, 2))
+    rhos = np.array([0.5, 0.95])
+    for t in range(1, n):
+        x[t] = rhos * x[t - 1] + e[t]
+    assert np.allclose(autocorr_time(x), integrated_time(x), rtol=1e-9)
