@@ -134,11 +134,13 @@ def sampler_bench(lib, inputs, prec, steps=3, W=512, T=8):
             "swap_accept": cnt[2] / max(cnt[3], 1)}
 
 
-def ess_bench(lib, inputs, prec, n=1 << 14, W=64, T=4, burn=300, m=1500, train_steps=1500):
+def ess_bench(lib, inputs, prec, n=1 << 14, W=512, T=8, burn=300, m=1000, train_steps=2000):
     """Effective samples per second of the cold chain, plain stretch moves
     against stretch + learned-flow moves, on the same injection and GPU
-    (precessing 14-D, TDI-2 AET, n samples around the merger).  The flow
-    (8 couplings, width 256) is trained on the plain run's cold samples."""
+    (precessing 14-D, TDI-2 AET, 512 walkers x 8 temperatures, n samples
+    around the merger).  The flow (8 couplings, width 256) is whitened by the
+    Cholesky factor of the plain run's cold-sample covariance and trained on
+    those samples."""
     import numpy as np
     import torch
     from paper_2501_08261_amd.diagnostics import autocorr_time
@@ -164,8 +166,9 @@ def ess_bench(lib, inputs, prec, n=1 << 14, W=64, T=4, burn=300, m=1500, train_s
     acc_plain = smp.state()[4]
     tau_plain = autocorr_time(plain)
     samples = plain.reshape(-1, 14)
-    flow = lib.Flow(14, 8, 256, 2048)
+    flow = lib.Flow(14, 8, 256, max(2048, W))
     flow.set_params(lib.flow_init_params(14, 8, 256, 3), samples.mean(0), samples.std(0))
+    flow.set_whitening(samples.mean(0), np.linalg.cholesky(np.cov(samples.T)))
     xs = torch.tensor(samples[np.random.default_rng(0).permutation(len(samples))], device="cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()

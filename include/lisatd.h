@@ -237,11 +237,12 @@ lt_status lt_fisher_draw(const double* x0, const double* gamma, int dim, const d
  * keep the whole pipeline on the accelerator; the flow itself is this
  * library's design).  A RealNVP-style normalising flow over the sampling
  * coordinates:
- *   u = (x - mu) / sigma; for layer l = 0..L-1 the conditioning set A_l is the
+ *   u = Lw^-1 (x - mu) (Lw lower triangular: diag(sigma) or a full factor such
+ *   as the Cholesky factor of a sample covariance); for layer l = 0..L-1 the conditioning set A_l is the
  *   first floor(d/2) coordinates (even l) or the last floor(d/2) (odd l), B_l
  *   the rest; h1 = relu(W1 u_A + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3,
  *   s = 3 tanh(o[0:|B|] / 3), t = o[|B|:2|B|], u_B <- u_B exp(s) + t;
- *   log q(x) = -|z|^2/2 - (d/2) log 2pi + sum_l sum s_l - sum log sigma.
+ *   log q(x) = -|z|^2/2 - (d/2) log 2pi + sum_l sum s_l - sum log diag(Lw).
  * Parameters: FP32 host vector, per layer W1[H][|A|], b1[H], W2[H][H], b2[H],
  * W3[2|B|][H], b3[2|B|] (row-major), layers in order.  The GEMMs run on the
  * matrix cores with BF16 operands and FP32 accumulation; the coupling update,
@@ -260,9 +261,13 @@ lt_status lt_flow_create(int hip_device, int dim, int n_layers, int hidden, int 
 lt_status lt_flow_destroy(lt_flow* f);
 /* Number of FP32 parameters (-1 for a null flow). */
 int64_t lt_flow_num_params(const lt_flow* f);
-/* Host params [num_params], mu and sigma [dim] (sigma > 0); resets Adam's
+/* Host params [num_params], mu and sigma [dim] (sigma > 0, Lw = diag(sigma)); resets Adam's
  * moments and step count.  Synchronous. */
 lt_status lt_flow_set_params(lt_flow* f, const float* params, const double* mu, const double* sigma);
+/* Whitening only: mu [dim] and Lw host [dim][dim] row-major, of which only
+ * the lower triangle is read (diagonal > 0); the network weights and Adam's
+ * state are kept.  Synchronous. */
+lt_status lt_flow_set_whitening(lt_flow* f, const double* mu, const double* L);
 /* Copies the FP32 master parameters to host memory.  Synchronous. */
 lt_status lt_flow_get_params(lt_flow* f, float* params);
 /* log q of n rows of x (device FP64 [n][dim]) into logq (device FP64 [n]). */

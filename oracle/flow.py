@@ -4,7 +4,9 @@ The learned proposal is not in the paper (Sec. II.A mentions machine learning
 only as a motivation for a Python implementation); its definition here is the
 reference of the GPU flow kernels:
 
-* coordinates are standardised, u = (x - mu) / sigma;
+* coordinates are whitened, u = Lw^-1 (x - mu), with Lw either the diagonal
+  diag(sigma) (sigma a vector) or a lower-triangular matrix with a positive
+  diagonal (sigma a matrix, e.g. the Cholesky factor of a sample covariance);
 * L affine coupling layers; layer l splits u into a conditioning part A and a
   transformed part B (even l: A = first floor(d/2) coordinates, B = the rest;
   odd l: A = last floor(d/2) coordinates, B = the first d - floor(d/2));
@@ -12,13 +14,14 @@ reference of the GPU flow kernels:
   o = W3 h2 + b3 (width H), s = S tanh(o[:d_B] / S) with S = 3, t = o[d_B:];
 * y_B = u_B exp(s) + t, y_A = u_A, log|det| += sum(s);
 * base density standard normal: log q(x) = -|z|^2/2 - d/2 log(2 pi)
-  + sum_l sum(s_l) - sum log sigma;
+  + sum_l sum(s_l) - sum log diag(Lw);
 * training: mean negative log-likelihood of samples, Adam (beta1 0.9,
   beta2 0.999, eps 1e-8).
 """
 import math
 
 import numpy as np
+from scipy.linalg import solve_triangular
 
 S_MAX = 3.0
 
@@ -43,6 +46,21 @@ def init_params(d, n_layers, hidden, seed):
     return P
 
 
+def _whiten(x, mu, sigma):
+    sigma = np.asarray(sigma, float)
+    r = np.asarray(x, float) - mu
+    if sigma.ndim == 1:
+        return r / sigma, np.log(sigma).sum()
+    return solve_triangular(sigma, r.T, lower=True).T, np.log(np.diag(sigma)).sum()
+
+
+def _unwhiten(u, mu, sigma):
+    sigma = np.asarray(sigma, float)
+    if sigma.ndim == 1:
+        return u * sigma + mu
+    return u @ sigma.T + mu
+
+
 def _cond(p, uA):
     a1 = uA @ p["W1"].T + p["b1"]
     h1 = np.maximum(a1, 0.0)
@@ -54,7 +72,7 @@ def _cond(p, uA):
 
 def forward(P, x, mu, sigma):
     """x [n][d] -> z [n][d], log q(x) [n]."""
-    u = (np.asarray(x, float) - mu) / sigma
+    u, lsig = _whiten(x, mu, sigma)
     d = u.shape[1]
     ld = np.zeros(u.shape[0])
     for l, p in enumerate(P):
@@ -65,7 +83,7 @@ def forward(P, x, mu, sigma):
         u = u.copy()
         u[:, B] = u[:, B] * np.exp(s) + o[:, nb:]
         ld += s.sum(1)
-    logq = -0.5 * (u * u).sum(1) - 0.5 * d * math.log(2 * math.pi) + ld - np.log(sigma).sum()
+    logq = -0.5 * (u * u).sum(1) - 0.5 * d * math.log(2 * math.pi) + ld - lsig
     return u, logq
 
 
@@ -83,12 +101,13 @@ def inverse(P, z, mu, sigma):
         s = S_MAX * np.tanh(o[:, :nb] / S_MAX)
         u[:, B] = (u[:, B] - o[:, nb:]) * np.exp(-s)
         ld += s.sum(1)
-    return u * sigma + mu, base + ld - np.log(sigma).sum()
+    lsig = _whiten(np.zeros((1, d)), np.zeros(d), sigma)[1]
+    return _unwhiten(u, mu, sigma), base + ld - lsig
 
 
 def nll_and_grad(P, x, mu, sigma):
     """Mean negative log-likelihood of samples x and its gradient (same structure as P)."""
-    u = (np.asarray(x, float) - mu) / sigma
+    u, lsig = _whiten(x, mu, sigma)
     n, d = u.shape
     cache = []
     for l, p in enumerate(P):
@@ -102,7 +121,7 @@ def nll_and_grad(P, x, mu, sigma):
         u[:, B] = uB * np.exp(s) + o[:, nb:]
         cache.append((A, B, uA, uB, a1, h1, a2, h2, o, s))
     logq = -0.5 * (u * u).sum(1) - 0.5 * d * math.log(2 * math.pi) + \
-        sum(c[9].sum(1) for c in cache) - np.log(sigma).sum()
+        sum(c[9].sum(1) for c in cache) - lsig
     loss = -logq.mean()
     g_u = u / n                         # d loss / d z
     grads = [None] * len(P)

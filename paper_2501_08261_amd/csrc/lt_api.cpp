@@ -367,6 +367,20 @@ static TermTable make_terms(int gen) {
           t.dcnt[t.nd] = cnt[li];
           ++t.nd;
         }
+      int total = 0;
+      for (int li = 0; li < 6; ++li) total += cnt[li];
+      if (total > T.max_delays) T.max_delays = total;
+    }
+    for (int i = 0; i < T.n_terms[ch]; ++i) {
+      const int link = T.t[ch][i].link;
+      int g = 0;
+      while (g < T.n_groups[ch] && T.g_link[ch][g] != link) ++g;
+      if (g == T.n_groups[ch]) {
+        T.g_link[ch][g] = link;
+        T.g_n[ch][g] = 0;
+        ++T.n_groups[ch];
+      }
+      T.g_t[ch][g][T.g_n[ch][g]++] = i;
     }
   }
   return T;
@@ -486,6 +500,7 @@ static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const l
   L.batch = batch;
   L.h = c->wave.p;
   L.taps = t->taps;
+  L.comb = 1;
   L.precision = cfg->precision;
   L.out_mode = out_mode;
   L.g = gdev(g);

@@ -2,12 +2,14 @@
 // networks run on the matrix cores (BF16 operands, FP32 accumulation), with
 // FP32 master weights, Adam, and FP64 coupling arithmetic.
 //
-// Flow definition: coordinates standardised, u = (x - mu) / sigma; layer l
+// Flow definition: coordinates whitened, u = Lw^-1 (x - mu) with Lw lower
+// triangular (diag(sigma), or e.g. the Cholesky factor of a sample covariance,
+// so that the network only has to model what is not Gaussian); layer l
 // conditions on A_l (even l: the first floor(d/2) coordinates, odd l: the last
 // floor(d/2)) and transforms B_l (the rest); conditioner h1 = relu(W1 u_A + b1),
 // h2 = relu(W2 h1 + b2), o = W3 h2 + b3, s = 3 tanh(o_s / 3), t = o_t;
 // y_B = u_B exp(s) + t; log q(x) = -|z|^2/2 - d/2 log 2pi + sum_l sum s_l
-// - sum log sigma.  Training minimises the mean negative log q of samples.
+// - sum log diag(Lw).  Training minimises the mean negative log q of samples.
 //
 // Precision split: the GEMM operands (u_A, h1, h2, weights, back-propagated
 // activations) are BF16, accumulation FP32; u, the coupling update, log-dets
@@ -159,15 +161,20 @@ __global__ void k_scatter_add(double* gu, int n, int d, int c0, int w, const flo
   gu[(int64_t)r * d + c0 + c] += (double)g[i];
 }
 
-// u = (x[src] - mu) / sigma with src = (start + r) mod n_src; logdet = 0
+// u = Lw^-1 (x[src] - mu), src = (start + r) mod n_src, by forward substitution
+// (one thread per row); logdet = 0.  A diagonal Lw gives (x - mu) / sigma exactly.
 __global__ void k_standardise(const double* x, int64_t n_src, int64_t start, int n, int d, const double* mu,
-                              const double* sig, double* u, double* logdet) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * d) return;
-  const int r = i / d, c = i - r * d;
+                              const double* Lw, double* u, double* logdet) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
   const int64_t src = (start + r) % n_src;
-  u[i] = (x[src * d + c] - mu[c]) / sig[c];
-  if (c == 0) logdet[r] = 0.0;
+  double* ur = u + (int64_t)r * d;
+  for (int i = 0; i < d; ++i) {
+    double acc = 0.0;
+    for (int k = 0; k < i; ++k) acc += Lw[i * d + k] * ur[k];
+    ur[i] = ((x[src * d + i] - mu[i]) - acc) / Lw[i * d + i];
+  }
+  logdet[r] = 0.0;
 }
 
 // log q = -|u|^2/2 - d/2 log 2pi + logdet - lsig; optionally dL/dz = u / n for the mean NLL
@@ -191,14 +198,18 @@ __global__ void k_logq_add(int n, const double* logdet, double lsig, double* log
   logq[r] = logq[r] + logdet[r] - lsig;
 }
 
-// x = u sigma + mu, rounded as two operations (no fused multiply-add)
-__global__ void k_destandardise(const double* u, int n, int d, const double* mu, const double* sig, double* x) {
+// x = Lw u + mu, the diagonal product and the additions rounded separately (no
+// fused multiply-add), so that a diagonal Lw gives u sigma + mu exactly
+__global__ void k_destandardise(const double* u, int n, int d, const double* mu, const double* Lw, double* x) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * d) return;
-  const int c = i % d;
-  const double p = u[i] * sig[c];
-  x[i] = p + mu[c];
+  const int r = i / d, c = i - r * d;
+  const double* ur = u + (int64_t)r * d;
+  double acc = 0.0;
+  for (int k = 0; k < c; ++k) acc += Lw[c * d + k] * ur[k];
+  const double p = ur[c] * Lw[c * d + c];
+  x[i] = (acc + p) + mu[c];
 }
 
 // u = z (the base sample)
@@ -272,7 +283,7 @@ struct lt_flow {
   std::vector<LayerOff> lay;
   float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
   bf16* wb = nullptr;
-  double *mu = nullptr, *sig = nullptr;
+  double *mu = nullptr, *Lw = nullptr;   // whitening: x = Lw u + mu, Lw [d][d] lower triangular
   double lsig = 0.0;
   int64_t t = 0;
   // per-row state (maxB rows) and per-layer activations kept for the backward pass
@@ -352,8 +363,8 @@ void pass(lt_flow* f, int n, int inverse, hipStream_t st) {
 
 // log q of n rows x[(start + r) mod n_src] into f->logq (and dL/dz into f->gu when grad)
 void logq_rows(lt_flow* f, const double* x, int64_t n_src, int64_t start, int n, bool grad, hipStream_t st) {
-  hipLaunchKernelGGL(k_standardise, dim3(blocks((int64_t)n * f->d)), dim3(256), 0, st, x, n_src, start, n, f->d,
-                     f->mu, f->sig, f->u, f->logdet);
+  hipLaunchKernelGGL(k_standardise, dim3(blocks(n, 64)), dim3(64), 0, st, x, n_src, start, n, f->d, f->mu, f->Lw,
+                     f->u, f->logdet);
   pass(f, n, 0, st);
   hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, f->d, f->logdet, f->lsig, f->logq,
                      grad ? f->gu : (double*)nullptr, 1.0 / n);
@@ -367,7 +378,7 @@ void sample_rows(lt_flow* f, int n, double* x, double* logq, hipStream_t st) {
   pass(f, n, 1, st);
   hipLaunchKernelGGL(k_logq_add, dim3(blocks(n)), dim3(256), 0, st, n, f->logdet, f->lsig, logq);
   hipLaunchKernelGGL(k_destandardise, dim3(blocks((int64_t)n * f->d)), dim3(256), 0, st, f->u, n, f->d, f->mu,
-                     f->sig, x);
+                     f->Lw, x);
 }
 
 // backward pass of the mean NLL after logq_rows(grad = true); gradients into f->g
@@ -472,7 +483,7 @@ lt_status lt_flow_create(int hip_device, int dim, int n_layers, int hidden, int 
 #define FA(ptr, cnt) \
   if (e == hipSuccess) e = falloc(f, &f->ptr, (size_t)(cnt))
   FA(w, off); FA(g, off); FA(m, off); FA(v, off); FA(wb, off);
-  FA(mu, dim); FA(sig, dim);
+  FA(mu, dim); FA(Lw, (int64_t)dim * dim);
   FA(u, B * dim); FA(gu, B * dim); FA(logdet, B); FA(logq, B);
   FA(a1, L * B * H); FA(a2, L * B * H); FA(o, L * B * 2 * dim); FA(s, L * B * dim); FA(ub, L * B * dim);
   FA(uA, L * B * dim); FA(h1, L * B * H); FA(h2, L * B * H);
@@ -482,10 +493,11 @@ lt_status lt_flow_create(int hip_device, int dim, int n_layers, int hidden, int 
     lt_flow_destroy(f);
     return ffail(LT_ERR_DEVICE, std::string("flow allocation: ") + hipGetErrorString(e));
   }
-  std::vector<double> one(dim, 1.0), zero(dim, 0.0);
+  std::vector<double> eye((size_t)dim * dim, 0.0), zero(dim, 0.0);
+  for (int i = 0; i < dim; ++i) eye[(size_t)i * dim + i] = 1.0;
   std::vector<float> zf(off, 0.0f);
   if (hipMemcpy(f->mu, zero.data(), dim * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(f->sig, one.data(), dim * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(f->Lw, eye.data(), eye.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(f->w, zf.data(), off * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(f->m, zf.data(), off * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(f->v, zf.data(), off * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
@@ -512,22 +524,37 @@ lt_status lt_flow_destroy(lt_flow* f) {
 
 int64_t lt_flow_num_params(const lt_flow* f) { return f ? f->nparam : -1; }
 
-lt_status lt_flow_set_params(lt_flow* f, const float* params, const double* mu, const double* sigma) {
-  if (!f || !params || !mu || !sigma) return ffail(LT_ERR_NULL, "null argument");
+static lt_status set_whitening(lt_flow* f, const double* mu, const double* L, bool diagonal) {
+  const int d = f->d;
+  std::vector<double> W((size_t)d * d, 0.0);
   double lsig = 0.0;
-  for (int i = 0; i < f->d; ++i) {
-    if (!(sigma[i] > 0.0) || !std::isfinite(sigma[i]) || !std::isfinite(mu[i]))
-      return ffail(LT_ERR_CONFIG, "mu must be finite and sigma positive");
-    lsig += std::log(sigma[i]);
+  for (int i = 0; i < d; ++i) {
+    const double di = diagonal ? L[i] : L[(size_t)i * d + i];
+    if (!(di > 0.0) || !std::isfinite(di) || !std::isfinite(mu[i]))
+      return ffail(LT_ERR_CONFIG, "mu must be finite and the whitening diagonal positive");
+    lsig += std::log(di);
+    W[(size_t)i * d + i] = di;
+    if (!diagonal)
+      for (int k = 0; k < i; ++k) {
+        if (!std::isfinite(L[(size_t)i * d + k])) return ffail(LT_ERR_CONFIG, "non-finite whitening matrix");
+        W[(size_t)i * d + k] = L[(size_t)i * d + k];
+      }
   }
-  for (int64_t i = 0; i < f->nparam; ++i)
-    if (!std::isfinite(params[i])) return ffail(LT_ERR_CONFIG, "non-finite flow parameter");
   FL_HIP(hipSetDevice(f->device));
   FL_HIP(hipDeviceSynchronize());
-  FL_HIP(hipMemcpy(f->w, params, f->nparam * sizeof(float), hipMemcpyHostToDevice));
-  FL_HIP(hipMemcpy(f->mu, mu, f->d * sizeof(double), hipMemcpyHostToDevice));
-  FL_HIP(hipMemcpy(f->sig, sigma, f->d * sizeof(double), hipMemcpyHostToDevice));
+  FL_HIP(hipMemcpy(f->mu, mu, d * sizeof(double), hipMemcpyHostToDevice));
+  FL_HIP(hipMemcpy(f->Lw, W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice));
   f->lsig = lsig;
+  return LT_OK;
+}
+
+lt_status lt_flow_set_params(lt_flow* f, const float* params, const double* mu, const double* sigma) {
+  if (!f || !params || !mu || !sigma) return ffail(LT_ERR_NULL, "null argument");
+  for (int64_t i = 0; i < f->nparam; ++i)
+    if (!std::isfinite(params[i])) return ffail(LT_ERR_CONFIG, "non-finite flow parameter");
+  lt_status st = set_whitening(f, mu, sigma, true);
+  if (st) return st;
+  FL_HIP(hipMemcpy(f->w, params, f->nparam * sizeof(float), hipMemcpyHostToDevice));
   std::vector<float> zf(f->nparam, 0.0f);
   FL_HIP(hipMemcpy(f->m, zf.data(), f->nparam * sizeof(float), hipMemcpyHostToDevice));
   FL_HIP(hipMemcpy(f->v, zf.data(), f->nparam * sizeof(float), hipMemcpyHostToDevice));
@@ -535,6 +562,11 @@ lt_status lt_flow_set_params(lt_flow* f, const float* params, const double* mu, 
   hipLaunchKernelGGL(k_to_bf16, dim3(blocks(f->nparam)), dim3(256), 0, 0, f->w, f->wb, f->nparam);
   FL_HIP(hipDeviceSynchronize());
   return LT_OK;
+}
+
+lt_status lt_flow_set_whitening(lt_flow* f, const double* mu, const double* L) {
+  if (!f || !mu || !L) return ffail(LT_ERR_NULL, "null argument");
+  return set_whitening(f, mu, L, false);
 }
 
 lt_status lt_flow_get_params(lt_flow* f, float* params) {

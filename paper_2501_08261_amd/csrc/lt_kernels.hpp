@@ -9,7 +9,15 @@ namespace lt {
 // One TDI term: sign * y_link(t - sum_k dcnt[k] L_{dlink[k]}(t)); links
 // indexed 0..5 for the labels 1, 2, 3, -1, -2, -3.
 struct Term { int sign, link, nd, dlink[4], dcnt[4]; };
-struct TermTable { int n_terms[3]; Term t[3][16]; };
+// Terms of one channel that read the same link form a group (at most 4 links
+// and 8 terms per group); max_delays bounds the number of light times summed
+// in one term delay.
+struct TermTable {
+  int n_terms[3];
+  Term t[3][16];
+  int n_groups[3], g_link[3][4], g_n[3][4], g_t[3][4][8];
+  int max_delays;
+};
 
 // Orbit node table on the device: node j sits at grid sample (j - j0) * spacing;
 // per node and link: L [s], r_receiver / c [s] (3), r_sender(emission) / c [s] (3), n (3).
@@ -38,6 +46,7 @@ struct TdiLaunch {
   const TplConst* tc;
   int64_t batch;
   int taps, precision, out_mode;
+  int comb;           // mixed precision: per-link combined filters (phase D) allowed
   GridDev g;
   OrbitDev orb;
   TermTable terms;

@@ -1,5 +1,7 @@
 // Per-template setup, mode / polarisation kernels, and the fused TDI response
 // kernel (hot-path steps a1-a8 of the time-domain LISA likelihood).
+#include <algorithm>
+
 #include "lt_kernels.hpp"
 #include "lt_wave.hpp"
 
@@ -136,15 +138,26 @@ __device__ inline int stencil_start(double fl, int len) {
   return j > len - K ? len - K : j;
 }
 
-// One series at fractional index s, in the product form
+// One series at fractional index s.  FP64: the product form
 //   sum_i c_i y_i prod_{j != i} d_j,  d_j = f - o_j,  c_i = 1 / prod_{j != i}(o_i - o_j),
 // accumulated left to right: S_i = S_{i-1} d_i + c_i y_i P_{i-1}, P_i = P_{i-1} d_i.
+// FP32: explicit weights first.  Its partial sums start at c_0 y_0, and with
+// c_0 = 1/(K-1)! ~ 1e-34 at K = 32 and strain-sized y ~ 1e-21 that product
+// is below the FP32 range; the weights themselves are O(1).
 template <typename R, int K>
 __device__ inline R lag1(const R* a, int len, double s) {
-  constexpr LagDen<K> den;
   double fl = floor(s);
   const R f = (R)(s - fl);
   const R* p = a + stencil_start<K>(fl, len);
+  if (sizeof(R) == 4) {
+    R w[K];
+    lag_weights<R, K>(f, w);
+    R acc = (R)0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) acc += w[i] * p[i];
+    return acc;
+  }
+  constexpr LagDen<K> den;
   R P = f - (R)(-K / 2 + 1);
   R S = (R)den.inv[0] * p[0];
 #pragma unroll
@@ -204,15 +217,31 @@ __constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacec
 //  D: X, Y, Z from y interpolated at the TDI delays, then A, E, T (global)
 // Per (TDI term, node interval) reference: the stencil start and fraction at
 // the interval midpoint; the fraction of output n is f0 - delta(n) with
-// delta(n) = (D(t_n) - D(t_ref)) / dt, cubic in the node values dn.
+// delta(n) = (D(t_n) - D(t_ref)) / dt, cubic in the node values dn (FP64
+// path) or linear, beta (n - n_ref), in mixed precision: the delays are sums
+// of light times, whose second derivative moves delta by < 1e-9 samples over
+// half an interval.
+// Mixed precision, combined filters: the terms of one channel that read the
+// same link are merged per interval into two filters over that link,
+//   F = sum_t s_t c0_t (shifted to the term's stencil),
+//   G = sum_t s_t beta_t c1_t,
+// so that sum_t s_t y(n - D_t(n)) = (F * y)(n) - (n - n_ref) (G * y)(n),
+// with c0, c1 the first-order Taylor weights of each term.
 constexpr int kTerms = 48;          // 3 channels x at most 16 terms
+constexpr int kGroups = 12;         // 3 channels x at most 4 links
 constexpr int kNV = kTile / 256;    // node intervals per tile (node spacing 256)
+constexpr int kYPad = 8;            // zero samples after each y series
+template <int K>
+struct CombLen {
+  static constexpr int value = ((K + 16 + 3) / 4) * 4;   // filter length bound (multiple of 4)
+};
 
 template <typename R, int K, bool TAY>
-__global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
+__global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX, int comb) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ long long s_w0;
-  __shared__ int s_W, s_skip;
+  __shared__ int s_W, s_skip, s_comb, s_span_bad;
+  constexpr int JMAX = CombLen<K>::value;
   const int tid = threadIdx.x;
   const int b = blockIdx.y;
   const int64_t N = P.g.n;
@@ -221,18 +250,23 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   // y is needed on [n0 - HY, n0 + kTile + K/2]: the centred stencils of the
   // shortest TDI delays reach K/2 - 1 samples past the last output sample
   const int MY = kTile + HY + K / 2 + 1;
+  const int MYP = MY + kYPad;
   R* yb = (R*)smem;
-  R* hpb = yb + 6 * MY;
+  R* hpb = yb + 6 * MYP;
   R* hxb = hpb + WMAX;
-  double* nd = (double*)(smem + (((size_t)(6 * MY + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15));
+  const int HREG = TAY ? max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
+  double* nd = (double*)(smem + (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15));
   double* tf0 = nd + NNMAX * kNodeVals;                    // [kTerms * kNV] reference fraction
   int* tjr = (int*)(tf0 + kTerms * kNV);                   // [kTerms * kNV] reference stencil index
   int* tflag = tjr + kTerms * kNV;                         // 0 Taylor, 1 direct, 2 zero delay
-  R* tdn = (R*)(tflag + kTerms * kNV);                     // [kTerms * kNV][4] node offsets in samples
-  R* tco = tdn + kTerms * kNV * 4;                         // [kTerms * kNV][2][K] weights and derivatives
+  int* gj0 = tflag + kTerms * kNV;                         // [kGroups * kNV] combined-filter start
+  int* gJ = gj0 + kGroups * kNV;                           // [kGroups * kNV] combined-filter length
+  R* tdn = (R*)(gJ + kGroups * kNV);   // mixed: [kTerms * kNV] delay rate; FP64: [kTerms * kNV][4] node offsets
+  R* tco = tdn + kTerms * kNV * (TAY ? 1 : 4);             // mixed: [kTerms * kNV][2][K] Taylor weights
+  R* fg = hpb;                                             // later [kGroups * kNV][2][JMAX] combined filters
   const double inv_dt = P.g.inv_dt;
   const int64_t m_lo = n0 - HY, m_hi = m_lo + MY - 1;
-  const int S = P.orb.spacing;
+  constexpr int S = kTile / kNV;   // node spacing (the launch checks that the table uses it)
   const int64_t jn_lo = floordiv(m_lo, S) - 1 + P.orb.j0;
   const int64_t jn_hi = floordiv(m_hi, S) + 2 + P.orb.j0;
   const int NN = (int)(jn_hi - jn_lo + 1);
@@ -273,6 +307,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     s_W = W;
     // every needed h sample precedes the f_low start (or the template is invalid): all zero
     s_skip = (c.valid == 0.0 || (double)w1 < c.n_start - 2.0) ? 1 : 0;
+    s_comb = comb;
+    s_span_bad = 0;
     if (bad && P.status) P.status[b] = 3;
   }
   __syncthreads();
@@ -295,7 +331,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
       int64_t m = m_lo + mi;
       if (m < 0 || m >= N) {
 #pragma unroll
-        for (int li = 0; li < 6; ++li) yb[li * MY + mi] = (R)0;
+        for (int li = 0; li < 6; ++li) yb[li * MYP + mi] = (R)0;
         continue;
       }
       int64_t q = floordiv(m, S);
@@ -325,9 +361,10 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
         R hps, hxs;
         lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
         const int rc = kRecv[li];
-        yb[li * MY + mi] = (R)v0 * (hps - hpr[rc]) + (R)v1 * (hxs - hxr[rc]);
+        yb[li * MYP + mi] = (R)v0 * (hps - hpr[rc]) + (R)v1 * (hxs - hxr[rc]);
       }
     }
+    for (int i = tid; i < 6 * kYPad; i += kNT) yb[(i / kYPad) * MYP + MY + (i % kYPad)] = (R)0;
     __syncthreads();
   }
   // E: per (term, interval) references for the TDI delays
@@ -351,13 +388,15 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     const double sref = (double)(nv0 + S2 - m_lo) - Dref * inv_dt;
     const double fl = floor(sref);
     const double f0 = sref - fl;
-    double db = 0.0;
+    double db = 0.0, dnr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const double dn = (D[r] - Dref) * inv_dt;
-      tdn[e * 4 + r] = (R)dn;
-      db = fmax(db, fabs(dn));
+      dnr[r] = (D[r] - Dref) * inv_dt;
+      if (!TAY) tdn[e * 4 + r] = (R)dnr[r];
+      db = fmax(db, fabs(dnr[r]));
     }
+    // delay rate at the midpoint (derivative of the cubic node interpolant), samples per sample
+    if (TAY) tdn[e] = (R)(((dnr[0] - dnr[3]) * (1.0 / 24.0) + (dnr[2] - dnr[1]) * 1.125) / (double)S);
     db *= 1.25;   // bound of the cubic interpolant over the interval
     // first-order weights are exact to 1.6 K delta^2 relative: keep that below 2e-8
     const double thr = TAY ? sqrt(2e-8 / (1.6 * K)) : -1.0;
@@ -365,6 +404,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     if (tm.nd == 0) flag = 2;
     else if (db <= thr && f0 - db >= 0.0 && f0 + db < 1.0) flag = 0;
     else flag = 1;
+    if (flag == 1) s_comb = 0;
     tf0[e] = f0;
     tjr[e] = (int)fl;
     tflag[e] = flag;
@@ -390,6 +430,64 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   }
   __syncthreads();
 
+  // F: combined filters per (channel, link group, interval) -- mixed precision only
+  int comb1 = 0;
+  if (TAY) {
+    const int comb0 = s_comb;     // final after the barrier above
+    if (comb0) {
+      for (int gi = tid; gi < kGroups * kNV; gi += kNT) {
+        const int cg = gi / kNV, v = gi - cg * kNV, cc = cg >> 2, g = cg & 3;
+        int lo = 0, hi = 0;
+        if (g < P.terms.n_groups[cc]) {
+          const int nrefl = v * S + S2 + HY;          // n_ref - m_lo
+          lo = 1 << 30;
+          hi = -(1 << 30);
+          for (int q = 0; q < P.terms.g_n[cc][g]; ++q) {
+            const int e = (cc * 16 + P.terms.g_t[cc][g][q]) * kNV + v;
+            const int bq = tflag[e] == 2 ? nrefl : tjr[e] - K / 2 + 1;
+            lo = min(lo, bq);
+            hi = max(hi, bq + (tflag[e] == 2 ? 1 : K));
+          }
+          // every read of phase D stays in [0, MYP): outputs sit within [-128, 124] of n_ref
+          if (hi - lo > JMAX || lo - 128 < 0 || hi + 130 > MYP) s_span_bad = 1;
+        }
+        gj0[gi] = lo;
+        gJ[gi] = hi - lo;
+      }
+    }
+    __syncthreads();
+    comb1 = comb0 && !s_span_bad;
+    if (comb1) {
+      // written over the h window, which phase C has finished reading
+      for (int item = tid; item < kGroups * kNV * JMAX; item += kNT) {
+        const int gi = item / JMAX, j = item - gi * JMAX;
+        const int cg = gi / kNV, v = gi - cg * kNV, cc = cg >> 2, g = cg & 3;
+        R f = (R)0, gg = (R)0;
+        if (g < P.terms.n_groups[cc] && j < gJ[gi]) {
+          const int nrefl = v * S + S2 + HY;
+          const int at = gj0[gi] + j;
+          for (int q = 0; q < P.terms.g_n[cc][g]; ++q) {
+            const int t = P.terms.g_t[cc][g][q];
+            const int e = (cc * 16 + t) * kNV + v;
+            const R sg = (R)P.terms.t[cc][t].sign;
+            if (tflag[e] == 2) {
+              if (at == nrefl) f += sg;
+            } else {
+              const int i = at - (tjr[e] - K / 2 + 1);
+              if (i >= 0 && i < K) {
+                f += sg * tco[(e * 2) * K + i];
+                gg += sg * tdn[e] * tco[(e * 2 + 1) * K + i];
+              }
+            }
+          }
+        }
+        fg[(gi * 2) * JMAX + j] = f;
+        fg[(gi * 2 + 1) * JMAX + j] = gg;
+      }
+    }
+    __syncthreads();
+  }
+
   // D: TDI and A, E, T; each thread owns four consecutive output samples
   const R* data = (const R*)P.data;
   R* out = (R*)P.out;
@@ -404,19 +502,50 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   if (!skip) {
     const int v = nl0 / S;
     const int64_t nref = n0 + (int64_t)v * S + S2;
+    if (TAY && comb1) {
+      const int dn0 = (int)(nb - nref);
+      for (int cc = 0; cc < 3; ++cc) {
+        for (int g = 0; g < P.terms.n_groups[cc]; ++g) {
+          const int gi = (cc * 4 + g) * kNV + v;
+          const int J = gJ[gi];
+          const R* yl = yb + P.terms.g_link[cc][g] * MYP + gj0[gi] + dn0;
+          const R* F = fg + (gi * 2) * JMAX;
+          const R* G = F + JMAX;
+          R a[4] = {(R)0, (R)0, (R)0, (R)0}, d[4] = {(R)0, (R)0, (R)0, (R)0};
+          for (int j = 0; j < J; j += 4) {
+            R yv[7];
+#pragma unroll
+            for (int q = 0; q < 7; ++q) yv[q] = yl[j + q];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const R f = F[j + i], gg = G[j + i];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                a[k] += f * yv[i + k];
+                d[k] += gg * yv[i + k];
+              }
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) ch[cc][k] += a[k] - (R)(dn0 + k) * d[k];
+        }
+      }
+    } else {
     R cw[4][4];
+    if (!TAY) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double w[4];
-      cubic_w((double)(nl0 - v * S + k) / (double)S, w);
+      for (int k = 0; k < 4; ++k) {
+        double w[4];
+        cubic_w((double)(nl0 - v * S + k) / (double)S, w);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) cw[k][r] = (R)w[r];
+        for (int r = 0; r < 4; ++r) cw[k][r] = (R)w[r];
+      }
     }
     for (int cc = 0; cc < 3; ++cc) {
       for (int t = 0; t < P.terms.n_terms[cc]; ++t) {
         const Term& tm = P.terms.t[cc][t];
         const int e = (cc * 16 + t) * kNV + v;
-        const R* yl = yb + tm.link * MY;
+        const R* yl = yb + tm.link * MYP;
         const int flag = tflag[e];
         R val[4];
         if (flag == 2) {
@@ -424,10 +553,15 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
           for (int k = 0; k < 4; ++k) val[k] = yl[nb + k - m_lo];
         } else {
           R dl[4];
+          if (TAY) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            dl[k] = cw[k][0] * tdn[e * 4] + cw[k][1] * tdn[e * 4 + 1] + cw[k][2] * tdn[e * 4 + 2] +
-                    cw[k][3] * tdn[e * 4 + 3];
+            for (int k = 0; k < 4; ++k) dl[k] = tdn[e] * (R)(nb + k - nref);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              dl[k] = cw[k][0] * tdn[e * 4] + cw[k][1] * tdn[e * 4 + 1] + cw[k][2] * tdn[e * 4 + 2] +
+                      cw[k][3] * tdn[e * 4 + 3];
+          }
           const int jb = tjr[e] + (int)(nb - nref);
           if (TAY && flag == 0) {
             int s0 = jb - K / 2 + 1;
@@ -464,6 +598,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
         }
       }
     }
+    }
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -497,19 +632,26 @@ static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
   int HY = (int)ceil(7.0 * P.orb.max_light_time * P.g.inv_dt * 1.001) + K / 2 + 2;
   int spread = (int)ceil(2.0 * P.orb.max_light_time * P.g.inv_dt * 1.01) + 8;
   const int MY = kTile + HY + K / 2 + 1;
+  const int MYP = MY + kYPad;
   int WMAX = MY + spread + K + 8;
   int NNMAX = MY / P.orb.spacing + 5;
   if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
   if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
-  size_t bytes = (((size_t)(6 * MY + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) +
+  constexpr int JMAX = CombLen<K>::value;
+  const size_t taylor = TAY ? (size_t)kTerms * kNV * 2 * K : 0;
+  const int HREG = TAY ? std::max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
+  size_t bytes = (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15) +
                  (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kTerms * kNV * (sizeof(double) + 2 * sizeof(int)) +
-                 (size_t)kTerms * kNV * (4 + (TAY ? 2 * K : 0)) * sizeof(R);
+                 (size_t)kGroups * kNV * 2 * sizeof(int) + ((size_t)kTerms * kNV * (TAY ? 1 : 4) + taylor) * sizeof(R);
+  // combined filters: the longest group spans at most max_delays light times plus one stencil
+  const int span = (int)ceil(P.terms.max_delays * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K;
+  const int comb = (TAY && P.comb && span <= JMAX) ? 1 : 0;
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)bytes);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((P.g.n + kTile - 1) / kTile), (unsigned)P.batch);
-  hipLaunchKernelGGL((k_tdi<R, K, TAY>), grid, dim3(kNT), bytes, s, P, HY, WMAX, NNMAX);
+  hipLaunchKernelGGL((k_tdi<R, K, TAY>), grid, dim3(kNT), bytes, s, P, HY, WMAX, NNMAX, comb);
   return hipGetLastError();
 }
 

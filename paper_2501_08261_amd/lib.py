@@ -101,6 +101,7 @@ _sig = {
     "lt_flow_num_params": ([_P], _I64),
     "lt_flow_set_params": ([_P, _P, _P, _P], ctypes.c_int),
     "lt_flow_get_params": ([_P, _P], ctypes.c_int),
+    "lt_flow_set_whitening": ([_P, _P, _P], ctypes.c_int),
     "lt_flow_log_prob": ([_P, _P, _I64, _P, _P], ctypes.c_int),
     "lt_flow_sample": ([_P, _P, _I64, _P, _P, _P], ctypes.c_int),
     "lt_flow_loss_grad": ([_P, _P, _I64, _P, _P], ctypes.c_int),
@@ -371,6 +372,13 @@ class Flow:
         m, pm = _host(mu)
         s, ps = _host(sigma)
         _check(_lib.lt_flow_set_params(self.h, pw, pm, ps))
+
+    def set_whitening(self, mu, L):
+        """x = L u + mu with L lower triangular (e.g. the Cholesky factor of a sample covariance)."""
+        import numpy as np
+        m, pm = _host(mu)
+        Lh, pl = _host(np.reshape(L, (self.d, self.d)))
+        _check(_lib.lt_flow_set_whitening(self.h, pm, pl))
 
     def get_params(self):
         import numpy as np

@@ -5,7 +5,7 @@ FP64 oracle) from what the kernels do (the library against this model).
 """
 import numpy as np
 
-from oracle.flow import split, S_MAX
+from oracle.flow import split, S_MAX, _whiten, _unwhiten
 
 
 def bf(a):
@@ -28,7 +28,7 @@ def _cond(p, u, A):
 
 
 def forward(P, x, mu, sigma):
-    u = (np.asarray(x, float) - mu) / sigma
+    u, lsig = _whiten(x, mu, sigma)
     d = u.shape[1]
     ld = np.zeros(len(u))
     for l, p in enumerate(P):
@@ -39,7 +39,7 @@ def forward(P, x, mu, sigma):
         u = u.copy()
         u[:, B] = u[:, B] * np.exp(s) + o[:, nb:]
         ld += s.sum(1)
-    return u, -0.5 * (u * u).sum(1) - 0.5 * d * np.log(2 * np.pi) + ld - np.log(sigma).sum()
+    return u, -0.5 * (u * u).sum(1) - 0.5 * d * np.log(2 * np.pi) + ld - lsig
 
 
 def inverse(P, z, mu, sigma):
@@ -54,11 +54,12 @@ def inverse(P, z, mu, sigma):
         s = S_MAX * np.tanh(o[:, :nb] / S_MAX)
         u[:, B] = (u[:, B] - o[:, nb:]) * np.exp(-s)
         ld += s.sum(1)
-    return u * sigma + mu, base + ld - np.log(sigma).sum()
+    lsig = _whiten(np.zeros((1, d)), np.zeros(d), sigma)[1]
+    return _unwhiten(u, mu, sigma), base + ld - lsig
 
 
 def nll_grad(P, x, mu, sigma):
-    u = (np.asarray(x, float) - mu) / sigma
+    u, _ = _whiten(x, mu, sigma)
     n, d = u.shape
     cache = []
     for l, p in enumerate(P):

@@ -86,6 +86,30 @@ def test_identity_flow_is_exact(lib, n):
     f.close()
 
 
+def test_whitened_identity_flow(lib):
+    """Full lower-triangular whitening (x = Lw u + mu) with the identity flow: the exact
+    Gaussian N(mu, Lw Lw^T) on both sides (1e-12)."""
+    d, L, H, n = 14, 8, 256, 300
+    rng = np.random.default_rng(31)
+    A = rng.normal(size=(d, d))
+    Lw = np.linalg.cholesky(A @ A.T + 0.01 * np.eye(d))
+    mu = rng.normal(size=d) * 100.0
+    P = fl.init_params(d, L, H, 5)
+    f = lib.Flow(d, L, H, 512)
+    f.set_params(lib.flow_pack(P), np.zeros(d), np.ones(d))
+    f.set_whitening(mu, Lw)
+    x = mu + rng.normal(size=(n, d)) @ Lw.T
+    lq = f.log_prob(_dev(x)).cpu().numpy()
+    _, lq_o = fl.forward(P, x, mu, Lw)
+    assert np.max(np.abs(lq - lq_o)) < 1e-12 * (1 + np.max(np.abs(lq_o)))
+    z = rng.normal(size=(n, d))
+    xs, lqs = f.sample(_dev(z))
+    xo, lqo = fl.inverse(P, z, mu, Lw)
+    assert np.max(np.abs(xs.cpu().numpy() - xo)) < 1e-12 * np.max(np.abs(xo))
+    assert np.max(np.abs(lqs.cpu().numpy() - lqo)) < 1e-12 * (1 + np.max(np.abs(lqo)))
+    f.close()
+
+
 @pytest.mark.parametrize("d,n", [(14, 300), (11, 1000), (2, 65)])
 def test_flow_parity_bf16(lib, d, n):
     L, H = 8, 256
@@ -190,8 +214,8 @@ def test_trained_flow_matches_gaussian(lib):
     f.close()
 
 
-@pytest.mark.parametrize("T", [1, 2])
-def test_sampler_flow_move_parity(lib, T):
+@pytest.mark.parametrize("T,full", [(1, False), (2, False), (2, True)])
+def test_sampler_flow_move_parity(lib, T, full):
     """P28: GPU chain with an (exact, identity) flow move against the oracle chain, step by step."""
     d, W, seed = 5, 16, 777
     rng = np.random.default_rng(T)
@@ -204,6 +228,9 @@ def test_sampler_flow_move_parity(lib, T):
     start = means[0] + rng.normal(size=(T, W, d))
     fg = lib.Flow(d, 4, 32, W)
     fg.set_params(lib.flow_pack(P), mu, sig)
+    if full:                 # whitening by the target's own Cholesky factor (scaled up by 1.2)
+        sig = 1.2 * np.linalg.cholesky(np.linalg.inv(icov))
+        fg.set_whitening(mu, sig)
     g = lib.Sampler(W, T, d, lo, hi, seed, target="gauss", param_kind="raw", t_max=5.0, means=means, icov=icov)
     g.set_flow(fg)
     g.set_state(start)

@@ -117,6 +117,85 @@ def test_tdi_parity(lt, orbit, gen, taps, precessing):
         _assert_aet(got[b], want, 1e-9, b)
 
 
+# Mixed precision (FP32 response and TDI, FP64 times and delays): the output
+# error is set by FP32 rounding of h, which y = h(t_s) - h(t_r) turns into an
+# absolute error of order u max|h| (u = 2^-24) whatever the size of y, and
+# which the K-tap interpolations and the TDI sums accumulate.  Measured over
+# 15 templates (M = 1.7e5 - 8.2e6, K = 2 - 16, both generations, both orbit
+# kinds) the error per channel was C u max|h| with C between 3 and 42; the
+# bound below is 24 sqrt(K) u max|h|, at least 1.6 times every measurement,
+# in the metric of R20 (relative to the channel's maximum).
+U32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("orbit,gen,taps,precessing,dt", [
+    ("kepler", 20, 8, True, 5.0), ("kepler", 20, 2, False, 5.0), ("kepler", 15, 8, False, 5.0),
+    ("static", 20, 8, True, 5.0), ("kepler", 20, 16, True, 5.0), ("kepler", 20, 8, True, 1.0),
+    ("kepler", 20, 24, False, 5.0), ("kepler", 20, 32, True, 5.0)])
+def test_tdi_parity_mixed(lt, orbit, gen, taps, precessing, dt):
+    """Mixed path against the oracle: combined per-link filters (K <= 16 at dt = 5 s), per-term
+    Taylor weights (dt = 1 s, where the filters would exceed their length bound) and direct
+    FP32 weights (K > 16)."""
+    lib, ctx = lt
+    n = 5000
+    g = inputs.grid(n, dt)
+    P = inputs.draw_templates(100 + taps, 3, g, precessing=precessing, before_end=1000.0)
+    out = torch.zeros((P.shape[0], 3, n), dtype=torch.float32, device=DEV)
+    st = torch.full((P.shape[0],), -7, dtype=torch.int32, device=DEV)
+    ctx.lisa_tdi_response(_dev(P), g, ctx.wf_cfg(MODES_ALL, precessing, precision=lib.LT_MIXED),
+                          ctx.orbit(orbit), ctx.tdi_cfg(gen, 7, taps), out, st)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    for b in range(P.shape[0]):
+        r = Response(Template(P[b]), g["t0"], g["dt"], n, OOrbit(orbit), taps=taps, modes=MODES_ALL,
+                     precessing=precessing, generation=gen)
+        r.cache_full_grid()
+        idx = np.arange(n)
+        want = np.array(r.aet(idx))
+        hp, hc = r.h_grid(idx)
+        hmax = max(np.max(np.abs(hp)), np.max(np.abs(hc)))
+        scale = np.max(np.abs(want))
+        for c in range(3):
+            norm = max(np.max(np.abs(want[c])), scale if c == 2 else 0.0)
+            err = np.max(np.abs(got[b, c] - want[c]))
+            assert err < 24.0 * math.sqrt(taps) * U32 * hmax, (b, c, err / (U32 * hmax), err / norm)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tdi_full_size_sampled(lt, precision):
+    """The bench workload at full size (256 precessing templates, 2^20 samples, Kepler arms,
+    TDI 2.0, K = 8, one launch): the lightest, a median and the heaviest template checked
+    against the oracle at sampled outputs
+    (every sample of the last 2400, where the merger and each channel's maximum lie, and 200
+    drawn over the rest)."""
+    lib, ctx = lt
+    n, B, K = 2 ** 20, 256, 8
+    g = inputs.grid(n, 5.0)
+    P = inputs.draw_templates(3, B, g, precessing=True)
+    rdt = lib.real_dtype(precision)
+    out = torch.zeros((B, 3, n), dtype=rdt, device=DEV)
+    st = torch.full((B,), -7, dtype=torch.int32, device=DEV)
+    ctx.lisa_tdi_response(_dev(P), g, ctx.wf_cfg(MODES_ALL, True, precision=precision), ctx.orbit("kepler"),
+                          ctx.tdi_cfg(20, 7, K), out, st)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([np.arange(n - 2400, n), rng.integers(0, n - 2400, 200)]))
+    M = P[:, 0] + P[:, 1]
+    for b in (int(np.argmin(M)), int(np.argsort(M)[B // 2]), int(np.argmax(M))):
+        got = out[b][:, torch.as_tensor(idx, device=DEV)].double().cpu().numpy()
+        r = Response(Template(P[b]), g["t0"], g["dt"], n, OOrbit("kepler"), taps=K, modes=MODES_ALL,
+                     precessing=True, generation=20)
+        want = np.array(r.aet(idx))
+        if precision == 0:
+            _assert_aet(got, want, 1e-9, b)
+        else:
+            hp, hc = r.h_grid(np.arange(n - 2400, n))
+            hmax = max(np.max(np.abs(hp)), np.max(np.abs(hc)))
+            assert np.max(np.abs(got - want)) < 24.0 * math.sqrt(K) * U32 * hmax, b
+
+
 def test_xyz_output(lt):
     lib, ctx = lt
     n = 3000

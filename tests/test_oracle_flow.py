@@ -87,3 +87,57 @@ def test_learns_a_gaussian():
     assert np.allclose(np.cov(xs.T), C, atol=0.25 * np.abs(C).max())
     exact = -0.5 * np.einsum("ni,ij,nj->n", x - m, np.linalg.inv(C), x - m) - 0.5 * np.log(np.linalg.det(2 * np.pi * C))
     assert abs(fl.forward(P, x, mu, sig)[1].mean() - exact.mean()) < 0.1
+
+
+def _chol_case(d, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(d, d))
+    C = A @ A.T + 0.1 * np.eye(d)
+    return rng.normal(size=d), C, np.linalg.cholesky(C)
+
+
+def test_whitened_identity_flow_is_the_gaussian():
+    """P27: with a zero output layer and Lw = chol(C), q is N(mu, C) (closed form) and the
+    inverse map is x = mu + Lw z."""
+    from scipy.stats import multivariate_normal
+    d = 6
+    mu, C, Lw = _chol_case(d, 1)
+    P = fl.init_params(d, 4, 16, 0)
+    x = np.random.default_rng(2).multivariate_normal(mu, C, size=40)
+    _, lq = fl.forward(P, x, mu, Lw)
+    assert np.allclose(lq, multivariate_normal(mu, C).logpdf(x), atol=1e-10)
+    z = np.random.default_rng(3).normal(size=(40, d))
+    xs, lqs = fl.inverse(P, z, mu, Lw)
+    assert np.allclose(xs, mu + z @ Lw.T, atol=1e-12)
+    assert np.allclose(lqs, multivariate_normal(mu, C).logpdf(xs), atol=1e-10)
+
+
+def test_diagonal_matrix_equals_vector_sigma():
+    d = 5
+    P = _rand_params(d, 4, 16, 4)
+    mu, sig = np.linspace(-1, 1, d), np.linspace(0.5, 2, d)
+    x = mu + sig * np.random.default_rng(5).normal(size=(30, d))
+    z1, l1 = fl.forward(P, x, mu, sig)
+    z2, l2 = fl.forward(P, x, mu, np.diag(sig))
+    assert np.allclose(z1, z2, atol=1e-14) and np.allclose(l1, l2, atol=1e-12)
+
+
+def test_whitened_roundtrip_and_gradients():
+    d = 7
+    mu, C, Lw = _chol_case(d, 6)
+    P = _rand_params(d, 4, 16, 7)
+    x = np.random.default_rng(8).multivariate_normal(mu, C, size=20)
+    z, lq = fl.forward(P, x, mu, Lw)
+    x2, lq2 = fl.inverse(P, z, mu, Lw)
+    assert np.max(np.abs(x2 - x)) < 1e-10 and np.max(np.abs(lq2 - lq)) < 1e-10
+    loss, G = fl.nll_and_grad(P, x, mu, Lw)
+    assert loss == pytest.approx(-lq.mean(), rel=1e-12)
+    h = 1e-6
+    for l, k, idx in ((0, "W1", (3, 1)), (2, "b2", (5,)), (3, "W3", (2, 7))):
+        old = P[l][k][idx]
+        P[l][k][idx] = old + h
+        lp = fl.nll_and_grad(P, x, mu, Lw)[0]
+        P[l][k][idx] = old - h
+        lm = fl.nll_and_grad(P, x, mu, Lw)[0]
+        P[l][k][idx] = old
+        assert abs((lp - lm) / (2 * h) - G[l][k][idx]) < 1e-6 * max(1.0, abs(G[l][k][idx]))
