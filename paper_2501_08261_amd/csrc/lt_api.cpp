@@ -557,7 +557,7 @@ static lt_status band_power(lt_ctx* c, Plan* p, void* series, int64_t rows, int 
   {
     Prof pr(c, 3, s);
     LT_HIP(launch_fft_pass2(p->dev, series, rows, precision, 1, g->dt, nullptr, (const double*)c->wperm.p, 3,
-                            (double*)c->partial.p, s));
+                            (double*)c->partial.p, k_lo, k_hi, s));
   }
   return LT_OK;
 }
@@ -644,7 +644,7 @@ lt_status lt_rfft(lt_ctx* c, const void* x, int64_t rows, int64_t n, double dt, 
     LT_HIP(launch_fft_pass1(p->dev, c->work.p, rows, precision, s));
   }
   Prof pr(c, 3, s);
-  LT_HIP(launch_fft_pass2(p->dev, c->work.p, rows, precision, 0, dt, spec, nullptr, 3, nullptr, s));
+  LT_HIP(launch_fft_pass2(p->dev, c->work.p, rows, precision, 0, dt, spec, nullptr, 3, nullptr, 0, p->dev.n, s));
   return LT_OK;
 }
 

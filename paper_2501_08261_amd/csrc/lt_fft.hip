@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data) {
 template <typename R>
 __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, int mode, double dt,
                                                C2<R>* spec, const double* wperm, int64_t ch_rows,
-                                               double* partial) {
+                                               double* partial, int64_t kb_lo, int64_t kb_hi) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kFT / 64];
   const int n1 = p.n1, n2 = p.n2;
@@ -211,6 +211,7 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
       r = 0;
       k2 = 0;
     }
+    if (mode != 0 && (k < kb_lo || k > kb_hi)) continue;   // outside the band: weight 0, not read
     C2<R> zc = {Zm.x, -Zm.y};
     C2<R> s = sc(Zk + zc, (R)0.5), d = sc(Zk - zc, (R)0.5);
     C2<R> wk = (k == n) ? C2<R>{(R)-1, (R)0} : wN<R>(lo, hi, k);
@@ -313,7 +314,8 @@ __global__ __launch_bounds__(kFT) void k_pass1_512(FftPlanDev p, C2<R>* data) {
 // pass 2 for n2 = 1024: two row pairs (up to four rows) per workgroup
 template <typename R>
 __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* data, int mode, double dt,
-                                                    C2<R>* spec, const double* wperm, double* partial) {
+                                                    C2<R>* spec, const double* wperm, double* partial,
+                                                    int64_t kb_lo, int64_t kb_hi) {
   constexpr int N1 = 512, N2 = 1024, NR = 4;
   constexpr int64_t n = (int64_t)N1 * N2;
   __shared__ C2<R> buf[NR * N2];
@@ -369,6 +371,7 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       Zk = buf[0];
       Zm = buf[0];
     }
+    if (mode != 0 && (k < kb_lo || k > kb_hi)) continue;   // outside the band: weight 0, not read
     C2<R> zc = {Zm.x, -Zm.y};
     C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
     C2<R> wk = (k == n) ? C2<R>{(R)-1, (R)0} : wN<R>(lo, hi, k);
@@ -419,11 +422,12 @@ hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int p
 
 template <typename R>
 static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mode, double dt, void* spec,
-                     const double* wperm, int64_t ch_rows, double* partial, hipStream_t s) {
+                     const double* wperm, int64_t ch_rows, double* partial, int64_t kb_lo, int64_t kb_hi,
+                     hipStream_t s) {
   if (hot_plan(p)) {
     dim3 grid((unsigned)((p.n1 / 2 + 2) / 2), (unsigned)rows);
     hipLaunchKernelGGL(k_pass2_1024<R>, grid, dim3(kFT), 0, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
-                       partial);
+                       partial, kb_lo, kb_hi);
     return hipGetLastError();
   }
   size_t bytes = 4 * (size_t)p.n2 * sizeof(C2<R>);
@@ -431,14 +435,15 @@ static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mo
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)(p.n1 / 2 + 1), (unsigned)rows);
   hipLaunchKernelGGL(k_pass2<R>, grid, dim3(kFT), bytes, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
-                     ch_rows, partial);
+                     ch_rows, partial, kb_lo, kb_hi);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_pass2(const FftPlanDev& p, const void* data, int64_t rows, int precision, int mode, double dt,
-                            void* spec, const double* wperm, int64_t ch_rows, double* partial, hipStream_t s) {
-  return precision == 0 ? p2<double>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, s)
-                        : p2<float>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, s);
+                            void* spec, const double* wperm, int64_t ch_rows, double* partial, int64_t kb_lo,
+                            int64_t kb_hi, hipStream_t s) {
+  return precision == 0 ? p2<double>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, kb_lo, kb_hi, s)
+                        : p2<float>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, kb_lo, kb_hi, s);
 }
 
 // weights in pass-2 order: w[c][k1 * n2 + k2] = 1/S_c(k) inside the band of an
