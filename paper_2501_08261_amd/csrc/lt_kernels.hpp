@@ -17,6 +17,7 @@ struct TermTable {
   Term t[3][16];
   int n_groups[3], g_link[3][4], g_n[3][4], g_t[3][4][8];
   int max_delays;
+  double g_span;      // max over groups of (max - min) light times summed, + 5 % of the min (arm flexing)
 };
 
 // Orbit node table on the device: node j sits at grid sample (j - j0) * spacing;

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   // y is needed on [n0 - HY, n0 + kTile + K/2]: the centred stencils of the
   // shortest TDI delays reach K/2 - 1 samples past the last output sample
   const int MY = kTile + HY + K / 2 + 1;
-  const int MYP = MY + kYPad;
+  const int MYP = (MY + kYPad + 3) & ~3;   // multiple of 4: aligned vector reads in phase D
   R* yb = (R*)smem;
   R* hpb = yb + 6 * MYP;
   R* hxb = hpb + WMAX;
@@ -448,8 +448,10 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
             lo = min(lo, bq);
             hi = max(hi, bq + (tflag[e] == 2 ? 1 : K));
           }
-          // every read of phase D stays in [0, MYP): outputs sit within [-128, 124] of n_ref
-          if (hi - lo > JMAX || lo - 128 < 0 || hi + 130 > MYP) s_span_bad = 1;
+          lo &= ~3;     // 16-byte aligned start (lo > 128 > 0): the leading taps are zero
+          // every read of phase D stays in [0, MYP): outputs sit within [-128, 124] of n_ref and
+          // the last 4-tap block reads 8 samples
+          if (hi - lo > JMAX || lo - 128 < 0 || hi + 132 > MYP) s_span_bad = 1;
         }
         gj0[gi] = lo;
         gJ[gi] = hi - lo;
@@ -513,12 +515,19 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
           const R* G = F + JMAX;
           R a[4] = {(R)0, (R)0, (R)0, (R)0}, d[4] = {(R)0, (R)0, (R)0, (R)0};
           for (int j = 0; j < J; j += 4) {
-            R yv[7];
-#pragma unroll
-            for (int q = 0; q < 7; ++q) yv[q] = yl[j + q];
+            // yl, F, G and j are 16-byte aligned (gj0, MYP, JMAX and n - n_ref are multiples of 4):
+            // each lane reads 2 x 16 B, eight lanes cover the 32 LDS banks without conflict
+            R yv[8];
+            const float4 y0 = *reinterpret_cast<const float4*>(yl + j);
+            const float4 y1 = *reinterpret_cast<const float4*>(yl + j + 4);
+            yv[0] = y0.x; yv[1] = y0.y; yv[2] = y0.z; yv[3] = y0.w;
+            yv[4] = y1.x; yv[5] = y1.y; yv[6] = y1.z; yv[7] = y1.w;
+            const float4 f4 = *reinterpret_cast<const float4*>(F + j);
+            const float4 g4 = *reinterpret_cast<const float4*>(G + j);
+            const R fa[4] = {f4.x, f4.y, f4.z, f4.w}, ga[4] = {g4.x, g4.y, g4.z, g4.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const R f = F[j + i], gg = G[j + i];
+              const R f = fa[i], gg = ga[i];
 #pragma unroll
               for (int k = 0; k < 4; ++k) {
                 a[k] += f * yv[i + k];
@@ -632,7 +641,7 @@ static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
   int HY = (int)ceil(7.0 * P.orb.max_light_time * P.g.inv_dt * 1.001) + K / 2 + 2;
   int spread = (int)ceil(2.0 * P.orb.max_light_time * P.g.inv_dt * 1.01) + 8;
   const int MY = kTile + HY + K / 2 + 1;
-  const int MYP = MY + kYPad;
+  const int MYP = (MY + kYPad + 3) & ~3;
   int WMAX = MY + spread + K + 8;
   int NNMAX = MY / P.orb.spacing + 5;
   if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
@@ -643,8 +652,8 @@ static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
   size_t bytes = (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15) +
                  (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kTerms * kNV * (sizeof(double) + 2 * sizeof(int)) +
                  (size_t)kGroups * kNV * 2 * sizeof(int) + ((size_t)kTerms * kNV * (TAY ? 1 : 4) + taylor) * sizeof(R);
-  // combined filters: the longest group spans at most max_delays light times plus one stencil
-  const int span = (int)ceil(P.terms.max_delays * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K;
+  // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
+  const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
   const int comb = (TAY && P.comb && span <= JMAX) ? 1 : 0;
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -289,6 +289,42 @@ def test_single_template_loglike(lt):
         assert np.all(st.cpu().numpy() == 0)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_loglike_pipeline_equals_single_stream(lt, precision):
+    """Batches of 128 or more templates run as a two-stream pipeline (response of one chunk
+    while the FFT of the previous one runs): bit-identical to the single-stream path, and one
+    invalid template stays isolated to its own slot."""
+    lib, ctx = lt
+    n = 8192
+    g = inputs.grid(n, 5.0)
+    P = inputs.draw_templates(21, 130, g, precessing=True, before_end=1000.0)
+    P[77, 4] = 1.5                                  # |chi1| > 1: status 1, logL = -inf
+    S = _psd_dev(lib, g, 20)
+    cfg, orb, tdi = ctx.wf_cfg(MODES_ALL, True, precision=precision), ctx.orbit("kepler"), ctx.tdi_cfg(20, 7, 8)
+    d = torch.zeros((1, 3, n), dtype=lib.real_dtype(precision), device=DEV)
+    ctx.lisa_tdi_response(_dev(P[:1]), g, cfg, orb, tdi, d)
+    dd = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ctx.noise_inner(d, g, S, dd, precision=precision)
+    torch.cuda.synchronize()
+    Pd = _dev(P)
+    one = torch.zeros(130, dtype=torch.float64, device=DEV)
+    one_full = torch.zeros(130, dtype=torch.float64, device=DEV)
+    st1 = torch.full((130,), -7, dtype=torch.int32, device=DEV)
+    ctx.tdi_loglike(Pd, g, cfg, orb, tdi, S, d[0], float(dd.item()), one, one_full, st1)
+    two = torch.zeros(130, dtype=torch.float64, device=DEV)
+    two_full = torch.zeros(130, dtype=torch.float64, device=DEV)
+    st2 = torch.full((130,), -7, dtype=torch.int32, device=DEV)
+    for a, b in ((0, 100), (100, 130)):             # both below the pipeline threshold
+        ctx.tdi_loglike(Pd[a:b].contiguous(), g, cfg, orb, tdi, S, d[0], float(dd.item()), two[a:b], two_full[a:b],
+                        st2[a:b])
+    torch.cuda.synchronize()
+    assert torch.equal(one, two) and torch.equal(one_full, two_full) and torch.equal(st1, st2)
+    s1 = st1.cpu().numpy()
+    assert s1[77] == 1 and np.all(np.delete(s1, 77) == 0)
+    assert np.isneginf(one[77].item()) and np.all(np.isfinite(np.delete(one.cpu().numpy(), 77)))
+    assert one_full[0].item() == 0.0                # template 0 is the data
+
+
 def test_loglike_mixed_close(lt):
     """Mixed precision (FP32 response / FFT, FP64 phase, time and sums): error reported and bounded."""
     lib, ctx = lt
