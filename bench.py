@@ -21,7 +21,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic work per template-sample of the dominant kernels (design notes)
+# HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this script (scaled by the same process's 1 GiB copy
+# calibration), keyed by (kernel, batch, samples, taps, precision).  Any other
+# configuration, or a changed kernel, reports null.
+PMC_TRAFFIC = {
+    # profiles/k_tdi_precessing_k8_2p20_b256.md: FETCH 1.124 GiB + WRITE 0.750 GiB per 64-template launch
+    ("tdi_response", 64, 2 ** 20, 8, "mixed"): int((1.124 + 0.750) * 2 ** 30),
+}
+
 N_SAMPLES = 2 ** 20
 BATCH = 256
 TAPS = 8
@@ -258,18 +266,22 @@ def main():
     # roofline of the dominant kernel (algorithmic work per template-sample, design notes)
     rsz = 4 if prec == lib.LT_MIXED else 8
     fft_bytes = {"fft_pass1": 3 * 2 * rsz, "fft_pass2_band": 3 * rsz}      # per real sample, per template
-    dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+    # the dominant kernel: largest time per step; the templates one launch processes follow
+    # from its launch count (the likelihood runs in chunks)
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    per_launch = a.batch * a.profile_steps / max(kern[dom]["launches"], 1)     # templates per launch
+    kern[dom]["templates_per_launch"] = per_launch
     if dom in fft_bytes:
-        achieved = fft_bytes[dom] * a.n * a.batch / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+        achieved = fft_bytes[dom] * a.n * per_launch / (kern[dom]["avg_ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-                "traffic": None, "kernel": dom}
+                "traffic": PMC_TRAFFIC.get((dom, per_launch, a.n, TAPS, a.precision)), "kernel": dom}
     else:
         from paper_2501_08261_amd import workcount
         flops = workcount.tdi_flops_per_sample(TAPS, 20)
-        achieved = flops * a.n * a.batch / (kern[dom]["avg_ms"] * 1e-3) / 1e12
+        achieved = flops * a.n * per_launch / (kern[dom]["avg_ms"] * 1e-3) / 1e12
         peak = 78.6 if prec == lib.LT_FP64 else 157.3
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": dom}
+                "traffic": PMC_TRAFFIC.get((dom, per_launch, a.n, TAPS, a.precision)), "kernel": dom}
     out = {
         "metric": "logL evals/s (1M-sample precessing AET); ESS/s learned vs plain proposal",
         "value": value, "unit": "logL evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,

@@ -326,19 +326,21 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
       hxb[i] = in ? hg[N + j] : (R)0;
     }
     __syncthreads();
-    // C: link responses y_slr for m in [m_lo, m_hi]
-    for (int mi = tid; mi < MY; mi += kNT) {
+    // C: link responses y_slr for m in [m_lo, m_hi].  A thread's samples are kNT = S apart,
+    // one node interval: they share the cubic node weights, and the node index steps by one.
+    static_assert(kNT == S, "phase C strides by one node interval");
+    const int64_t q0 = floordiv(m_lo + tid, S);
+    double w[4];
+    cubic_w((double)(m_lo + tid - q0 * S) / (double)S, w);
+    const int jl0 = (int)(q0 + P.orb.j0 - jn_lo);
+    for (int mi = tid, it = 0; mi < MY; mi += kNT, ++it) {
       int64_t m = m_lo + mi;
       if (m < 0 || m >= N) {
 #pragma unroll
         for (int li = 0; li < 6; ++li) yb[li * MYP + mi] = (R)0;
         continue;
       }
-      int64_t q = floordiv(m, S);
-      int jl = (int)(q + P.orb.j0 - jn_lo);
-      double w[4];
-      cubic_w((double)(m - q * S) / (double)S, w);
-      const double* o0 = nd + (jl - 1) * kNodeVals;
+      const double* o0 = nd + (jl0 + it - 1) * kNodeVals;
       const double mloc = (double)(m - w0);
       R hpr[3], hxr[3];
 #pragma unroll
