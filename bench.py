@@ -61,7 +61,8 @@ def cpu_baseline(g, params, taps):
     from oracle.orbits import Orbit
     from oracle.response import Response
     from oracle.waveform import Template
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    from threadpoolctl import threadpool_limits
+    limiter = threadpool_limits(1)      # numpy's thread pools pinned: the oracle runs on one core
     n = g["n"]
     slice_len = 1 << 13
     r = Response(Template(params[0]), g["t0"], g["dt"], n, Orbit("kepler"), taps=taps, precessing=True,
@@ -76,7 +77,8 @@ def cpu_baseline(g, params, taps):
     olk.loglike(x, 0.5 * x, S, g["dt"])
     t_fft = time.perf_counter() - t0
     per = t_resp + t_fft
-    return {"value": 1.0 / per, "unit": "logL evals/s", "cores": threads if threads > 0 else 1,
+    limiter.restore_original_limits()
+    return {"value": 1.0 / per, "unit": "logL evals/s", "cores": 1,
             "kind": "oracle",
             "sample": "oracle on template 0: response+TDI on %d of %d samples (scaled x%.0f) + full-length "
                       "rfft/inner products; %.1f s measured" % (slice_len, n, n / slice_len,
