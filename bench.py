@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-sampler", action="store_true", help="skip the sampler-step and ESS measurements")
+    ap.add_argument("--ess-precessing", action="store_true",
+                    help="also measure ESS/s on the precessing 14-D posterior (slow to equilibrate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known traffic) to calibrate HBM counters")
     return ap.parse_args()
@@ -144,67 +146,106 @@ def sampler_bench(lib, inputs, prec, steps=3, W=512, T=8):
             "swap_accept": cnt[2] / max(cnt[3], 1)}
 
 
-def ess_bench(lib, inputs, prec, n=1 << 14, W=512, T=8, burn=300, m=1000, train_steps=2000):
-    """Effective samples per second of the cold chain, plain stretch moves
-    against stretch + learned-flow moves, on the same injection and GPU
-    (precessing 14-D, TDI-2 AET, 512 walkers x 8 temperatures, n samples
-    around the merger).  The flow (8 couplings, width 256) is whitened by the
-    Cholesky factor of the plain run's cold-sample covariance and trained on
-    those samples."""
+FISHER_STEPS_A10 = [1.0, 1.0, 1e-4, 1e-4, 1.0, 1e-5, 1e-5, 1e-5, 1e-5, 1e-5]
+
+
+def _record(smp, k):
+    import numpy as np
+    chain = []
+    for _ in range(k):
+        smp.step(1)
+        chain.append(smp.state()[0][0].copy())
+    return np.array(chain)
+
+
+def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=500, rounds=4, window=400,
+              train_steps=1500, m=1000):
+    """Effective samples per second of the cold chain, stretch moves alone against
+    stretch + learned-flow moves, on one injection and one GPU (TDI-2 AET, 512
+    walkers x 8 temperatures, n samples around the merger, Fisher-initialised).
+
+    The flow (8 couplings, width 256) learns from the sampler's own chain: after
+    `burn` plain steps, `rounds` times: whiten by the last `window` steps' cold
+    samples (Cholesky of their covariance), train `train_steps` Adam steps on them,
+    attach, run `window` more steps.  The flow is then frozen and both samplers
+    restart from the same state for `m` recorded steps; ESS = m W / max_q tau_q
+    (worst coordinate), ESS/s uses the time of 200 unrecorded steps."""
     import numpy as np
     import torch
     from paper_2501_08261_amd.diagnostics import autocorr_time
+    kind = "precessing14" if precessing else "aligned10"
+    modes = ((2, 2), (2, 1), (3, 3), (3, 2), (4, 4))
     ctx = lib.Context(0)
-    su = _tdi_setup(lib, inputs, ctx, n, prec)
-    smp = _sampler(lib, inputs, ctx, su, W, T, 5)
+    g = inputs.grid(n, 5.0)
+    cfg = ctx.wf_cfg(modes, precessing, precision=prec)
+    cfg64 = ctx.wf_cfg(modes, precessing, precision=lib.LT_FP64)
+    orb, tdi = ctx.orbit("kepler"), ctx.tdi_cfg(20, 7, TAPS)
+    S = torch.zeros((3, n // 2 + 1), dtype=torch.float64, device="cuda:0")
+    lib.psd_sangria(g, 20, S)
+    inj = inputs.tab1_injection(precessing, g)
+    d = torch.zeros((1, 3, n), dtype=lib.real_dtype(prec), device="cuda:0")
+    ctx.lisa_tdi_response(torch.tensor(inj[None], device="cuda:0"), g, cfg, orb, tdi, d)
+    dd = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ctx.noise_inner(d, g, S, dd, precision=prec)
+    x0, lo, hi = inputs.tab1_prior(precessing, inj)
+    dim = x0.size
+    G = lib.fisher(ctx, x0, kind, inj[11], FISHER_STEPS_P14 if precessing else FISHER_STEPS_A10, g, cfg64, orb,
+                   tdi, S)
+    smp = lib.Sampler(W, T, dim, lo, hi, 5, target="tdi", param_kind=kind, t_c=inj[11], g=g, cfg=cfg, orbit=orb,
+                      tdi=tdi, psd=S, data_aet=d[0], dd=float(dd.item()))
+    smp.set_state(lib.fisher_draw(x0, G, lo, hi, T * W, 5, 1e-12))
+    t0 = time.perf_counter()
     smp.step(burn)
-
-    def run(k):
+    flow = lib.Flow(dim, 8, 256, max(2048, W))
+    flow.set_params(lib.flow_init_params(dim, 8, 256, 3), np.zeros(dim), np.ones(dim))
+    t_train = 0.0
+    for r in range(rounds):
+        s = _record(smp, window).reshape(-1, dim)
+        flow.set_whitening(s.mean(0), np.linalg.cholesky(np.cov(s.T)))
+        xs = torch.tensor(s[np.random.default_rng(r).permutation(len(s))], device="cuda:0")
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
+        flow.train(xs, train_steps, 2048, 3e-4)
+        torch.cuda.synchronize()
+        t_train += time.perf_counter() - t1
+        smp.set_flow(flow)
+    _record(smp, window)
+    t_adapt = time.perf_counter() - t0
+    state = smp.state()[0]
+    res = {}
+    for label, fl in (("learned", flow), ("plain", None)):
+        smp.set_state(state)
+        smp.set_flow(fl)
+        smp.step(20)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         smp.step(200)
         torch.cuda.synchronize()
-        t_step = (time.perf_counter() - t0) / 200
-        chain = []
-        for _ in range(k):
-            smp.step(1)
-            chain.append(smp.state()[0][0])
-        return np.array(chain), t_step
-
-    start_state = smp.state()[0]
-    plain, t_plain = run(m)
-    acc_plain = smp.state()[4]
-    tau_plain = autocorr_time(plain)
-    samples = plain.reshape(-1, 14)
-    flow = lib.Flow(14, 8, 256, max(2048, W))
-    flow.set_params(lib.flow_init_params(14, 8, 256, 3), samples.mean(0), samples.std(0))
-    flow.set_whitening(samples.mean(0), np.linalg.cholesky(np.cov(samples.T)))
-    xs = torch.tensor(samples[np.random.default_rng(0).permutation(len(samples))], device="cuda:0")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    flow.train(xs, train_steps, 2048, 1e-3)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    smp.set_state(start_state)
-    smp.set_flow(flow)
-    smp.step(burn)
-    learned, t_learned = run(m)
-    acc_f, prop_f = smp.flow_counts()
-    tau_learned = autocorr_time(learned)
-    ess_plain = m * W / tau_plain.max()
-    ess_learned = m * W / tau_learned.max()
-    drift = np.max(np.abs(learned.reshape(-1, 14).mean(0) - samples.mean(0)) / samples.std(0))
+        t_step = (time.perf_counter() - t1) / 200
+        chain = _record(smp, m)
+        acc, prop = smp.flow_counts()
+        tau = autocorr_time(chain)
+        flat = chain.reshape(-1, dim)
+        res[label] = {"ess_per_s": m * W / float(tau.max()) / (m * t_step), "tau_max": float(tau.max()),
+                      "tau_median": float(np.median(tau)), "ms_per_step": 1e3 * t_step,
+                      "mean": flat.mean(0), "std": flat.std(0)}
+        if fl is not None:
+            res[label]["flow_accept"] = acc / max(prop, 1)
+        else:
+            res[label]["stretch_accept"] = smp.state()[4][0] / max(smp.state()[4][1], 1)
+    sd = res["plain"]["std"]
+    shift = float(np.max(np.abs(res["learned"]["mean"] - res["plain"]["mean"]) / sd))
+    std_ratio = (res["learned"]["std"] / sd).tolist()
+    for v in res.values():
+        del v["mean"], v["std"]
     smp.close()
     flow.close()
     ctx.close()
-    return {"n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
-            "plain": {"ess_per_s": ess_plain / (m * t_plain), "tau_max": float(tau_plain.max()),
-                      "ms_per_step": 1e3 * t_plain, "stretch_accept": acc_plain[0] / max(acc_plain[1], 1)},
-            "learned": {"ess_per_s": ess_learned / (m * t_learned), "tau_max": float(tau_learned.max()),
-                        "ms_per_step": 1e3 * t_learned, "flow_accept": acc_f / max(prop_f, 1),
-                        "train_s": t_train, "train_steps": train_steps},
-            "ratio": (ess_learned / (m * t_learned)) / (ess_plain / (m * t_plain)),
-            "posterior_mean_shift_sigma": float(drift)}
+    return {"target": kind, "n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
+            "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": rounds * train_steps,
+            "plain": res["plain"], "learned": res["learned"],
+            "ratio": res["learned"]["ess_per_s"] / res["plain"]["ess_per_s"],
+            "posterior_mean_shift_sigma": shift, "posterior_std_ratio": [round(x, 3) for x in std_ratio]}
 
 
 def main():
@@ -306,9 +347,12 @@ def main():
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4, "launches": 3}
     ctx.close()
     if not a.no_sampler:
-        for key, fn in (("sampler", sampler_bench), ("ess", ess_bench)):
+        runs = [("sampler", sampler_bench, {}), ("ess", ess_bench, {})]
+        if a.ess_precessing:
+            runs.append(("ess_precessing", ess_bench, {"precessing": True}))
+        for key, fn, kw in runs:
             try:
-                out[key] = fn(lib, inputs, prec)
+                out[key] = fn(lib, inputs, prec, **kw)
             except Exception as e:                      # reported, the throughput line still prints
                 out[key] = {"error": "%s: %s" % (type(e).__name__, e)}
             print("%s done" % key, file=sys.stderr, flush=True)
