@@ -243,18 +243,19 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
 // Compile-time plans for the hot size N = 2^20 (n = 2^19 = 512 x 1024).
 // Each stage reads all its butterfly inputs into registers, synchronises,
 // writes the outputs in Stockham order into the same LDS buffer, synchronises.
-// LS: distance between consecutive transforms in buf (>= L; padding avoids LDS bank conflicts)
-template <typename R, int L, int NFFT, int RAD, int NS, int LS = L>
+// LS: distance between consecutive transforms in buf (>= L; padding avoids LDS bank conflicts);
+// NT: threads of the workgroup
+template <typename R, int L, int NFFT, int RAD, int NS, int LS = L, int NT = kFT>
 __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
   constexpr int M = L / RAD;
   constexpr int JOBS = NFFT * M;
-  constexpr int PER = (JOBS + kFT - 1) / kFT;
+  constexpr int PER = (JOBS + NT - 1) / NT;
   constexpr int STEP = L / (NS * RAD);
   C2<R> v[PER][RAD];
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    const int job = threadIdx.x + p * kFT;
-    if (JOBS % kFT == 0 || job < JOBS) {
+    const int job = threadIdx.x + p * NT;
+    if (JOBS % NT == 0 || job < JOBS) {
       const int f = job / M, j = job % M, k = j % NS;
       const C2<R>* src = buf + f * LS + j;
 #pragma unroll
@@ -268,8 +269,8 @@ __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
   __syncthreads();
 #pragma unroll
   for (int p = 0; p < PER; ++p) {
-    const int job = threadIdx.x + p * kFT;
-    if (JOBS % kFT == 0 || job < JOBS) {
+    const int job = threadIdx.x + p * NT;
+    if (JOBS % NT == 0 || job < JOBS) {
       const int f = job / M, j = job % M, k = j % NS;
       C2<R>* dst = buf + f * LS + (j / NS) * NS * RAD + k;
 #pragma unroll
@@ -285,18 +286,19 @@ __device__ inline void ct_fft(C2<R>* buf, const C2<R>* tw) {
   if constexpr (sizeof...(REST) > 0) ct_fft<R, L, NFFT, NS * RAD, REST...>(buf, tw);
 }
 
-template <typename R, int L, int LS, int NFFT, int NS, int RAD, int... REST>
+template <typename R, int L, int LS, int NT, int NFFT, int NS, int RAD, int... REST>
 __device__ inline void ct_fft_strided(C2<R>* buf, const C2<R>* tw) {
-  ct_stage<R, L, NFFT, RAD, NS, LS>(buf, tw);
-  if constexpr (sizeof...(REST) > 0) ct_fft_strided<R, L, LS, NFFT, NS * RAD, REST...>(buf, tw);
+  ct_stage<R, L, NFFT, RAD, NS, LS, NT>(buf, tw);
+  if constexpr (sizeof...(REST) > 0) ct_fft_strided<R, L, LS, NT, NFFT, NS * RAD, REST...>(buf, tw);
 }
 
 // pass 1 for n1 = 512: CB columns (128 bytes of each row) per workgroup.  Column c
 // sits at buf[c * LP], LP = N1 + 1: the 16 lanes that move one 128-byte row segment
 // then touch 16 different bank pairs instead of one.
 constexpr int kP1Pad = 1;
+constexpr int kP1Threads = 512;   // 2 workgroups of 65.7 KB fit a CU: 16 waves
 template <typename R>
-__global__ __launch_bounds__(kFT) void k_pass1_512(FftPlanDev p, C2<R>* data) {
+__global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* data) {
   constexpr int N1 = 512, N2 = 1024, CB = 128 / (int)sizeof(C2<R>), LP = N1 + kP1Pad;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<R>* buf = (C2<R>*)smem;      // [CB][LP]
@@ -304,17 +306,17 @@ __global__ __launch_bounds__(kFT) void k_pass1_512(FftPlanDev p, C2<R>* data) {
   const int j2_0 = blockIdx.x * CB;
   C2<R>* z = data + row * ((int64_t)N1 * N2);
 #pragma unroll 4
-  for (int i = threadIdx.x; i < CB * N1; i += kFT) {
+  for (int i = threadIdx.x; i < CB * N1; i += kP1Threads) {
     const int j1 = i / CB, jj = i % CB;
     buf[jj * LP + j1] = z[(int64_t)j1 * N2 + j2_0 + jj];
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
-  ct_fft_strided<R, N1, LP, CB, 1, 8, 8, 8>(buf, tw);
+  ct_fft_strided<R, N1, LP, kP1Threads, CB, 1, 8, 8, 8>(buf, tw);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
 #pragma unroll 4
-  for (int i = threadIdx.x; i < CB * N1; i += kFT) {
+  for (int i = threadIdx.x; i < CB * N1; i += kP1Threads) {
     const int k1 = i / CB, jj = i % CB;
     const int j2 = j2_0 + jj;
     const int64_t m = (int64_t)j2 * k1;
@@ -419,7 +421,7 @@ static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, hipStream_t 
     hipError_t e = hipFuncSetAttribute((const void*)k_pass1_512<R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)(p.n2 / CB), (unsigned)rows);
-    hipLaunchKernelGGL(k_pass1_512<R>, grid, dim3(kFT), bytes, s, p, (C2<R>*)data);
+    hipLaunchKernelGGL(k_pass1_512<R>, grid, dim3(kP1Threads), bytes, s, p, (C2<R>*)data);
     return hipGetLastError();
   }
   size_t bytes = 2 * (size_t)kCB * p.n1 * sizeof(C2<R>);
