@@ -258,11 +258,10 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   double* nd = (double*)(smem + (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15));
   double* tf0 = nd + NNMAX * kNodeVals;                    // [kTerms * kNV] reference fraction
   int* tjr = (int*)(tf0 + kTerms * kNV);                   // [kTerms * kNV] reference stencil index
-  int* tflag = tjr + kTerms * kNV;                         // 0 Taylor, 1 direct, 2 zero delay
-  int* gj0 = tflag + kTerms * kNV;                         // [kGroups * kNV] combined-filter start
+  int* gj0 = tjr + kTerms * kNV;                           // [kGroups * kNV] combined-filter start
   int* gJ = gj0 + kGroups * kNV;                           // [kGroups * kNV] combined-filter length
   R* tdn = (R*)(gJ + kGroups * kNV);   // mixed: [kTerms * kNV] delay rate; FP64: [kTerms * kNV][4] node offsets
-  R* tco = tdn + kTerms * kNV * (TAY ? 1 : 4);             // mixed: [kTerms * kNV][2][K] Taylor weights
+  unsigned char* tflag = (unsigned char*)(tdn + kTerms * kNV * (TAY ? 1 : 4));   // 0 Taylor, 1 direct, 2 zero delay
   R* fg = hpb;                                             // later [kGroups * kNV][2][JMAX] combined filters
   const double inv_dt = P.g.inv_dt;
   const int64_t m_lo = n0 - HY, m_hi = m_lo + MY - 1;
@@ -412,26 +411,6 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     tflag[e] = flag;
   }
   __syncthreads();
-  if (TAY) {
-    constexpr LagDen<K> den;
-    for (int it = tid; it < kTerms * kNV * K; it += kNT) {
-      const int e = it / K, i = it - e * K;
-      const int tg = e / kNV;
-      if ((tg & 15) >= P.terms.n_terms[tg >> 4] || tflag[e] != 0) continue;
-      const double f0 = tf0[e];
-      double c0 = den.inv[i], c1 = 0.0;   // truncated product of (f0 + x - o_j), j != i
-      for (int j = 0; j < K; ++j) {
-        if (j == i) continue;
-        const double aj = f0 - (double)(j - K / 2 + 1);
-        c1 = c1 * aj + c0;
-        c0 = c0 * aj;
-      }
-      tco[(e * 2) * K + i] = (R)c0;
-      tco[(e * 2 + 1) * K + i] = (R)c1;
-    }
-  }
-  __syncthreads();
-
   // F: combined filters per (channel, link group, interval) -- mixed precision only
   int comb1 = 0;
   if (TAY) {
@@ -462,31 +441,41 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     __syncthreads();
     comb1 = comb0 && !s_span_bad;
     if (comb1) {
-      // written over the h window, which phase C has finished reading
-      for (int item = tid; item < kGroups * kNV * JMAX; item += kNT) {
-        const int gi = item / JMAX, j = item - gi * JMAX;
-        const int cg = gi / kNV, v = gi - cg * kNV, cc = cg >> 2, g = cg & 3;
-        R f = (R)0, gg = (R)0;
-        if (g < P.terms.n_groups[cc] && j < gJ[gi]) {
-          const int nrefl = v * S + S2 + HY;
-          const int at = gj0[gi] + j;
-          for (int q = 0; q < P.terms.g_n[cc][g]; ++q) {
-            const int t = P.terms.g_t[cc][g][q];
-            const int e = (cc * 16 + t) * kNV + v;
-            const R sg = (R)P.terms.t[cc][t].sign;
-            if (tflag[e] == 2) {
-              if (at == nrefl) f += sg;
-            } else {
-              const int i = at - (tjr[e] - K / 2 + 1);
-              if (i >= 0 && i < K) {
-                f += sg * tco[(e * 2) * K + i];
-                gg += sg * tdn[e] * tco[(e * 2 + 1) * K + i];
-              }
-            }
+      // written over the h window, which phase C has finished reading.  Each term adds its
+      // first-order weights c0, c1 (products of (f0 + x - o_j), j != i, truncated after x)
+      // to its group's filters, one term of every group per round: the sums run in term order.
+      for (int i = tid; i < kGroups * kNV * 2 * JMAX; i += kNT) fg[i] = (R)0;
+      int qmax = 0;
+      for (int cc = 0; cc < 3; ++cc)
+        for (int g = 0; g < P.terms.n_groups[cc]; ++g) qmax = max(qmax, P.terms.g_n[cc][g]);
+      __syncthreads();
+      constexpr LagDen<K> den;
+      for (int q = 0; q < qmax; ++q) {
+        for (int item = tid; item < kGroups * kNV * K; item += kNT) {
+          const int gi = item / K, i = item - gi * K;
+          const int cg = gi / kNV, v = gi - cg * kNV, cc = cg >> 2, g = cg & 3;
+          if (g >= P.terms.n_groups[cc] || q >= P.terms.g_n[cc][g]) continue;
+          const int t = P.terms.g_t[cc][g][q];
+          const int e = (cc * 16 + t) * kNV + v;
+          const R sg = (R)P.terms.t[cc][t].sign;
+          R* F = fg + (gi * 2) * JMAX;
+          if (tflag[e] == 2) {
+            if (i == 0) F[v * S + S2 + HY - gj0[gi]] += sg;   // n_ref - m_lo, relative to the start
+            continue;
           }
+          const double f0 = tf0[e];
+          double c0 = den.inv[i], c1 = 0.0;
+          for (int j = 0; j < K; ++j) {
+            if (j == i) continue;
+            const double aj = f0 - (double)(j - K / 2 + 1);
+            c1 = c1 * aj + c0;
+            c0 = c0 * aj;
+          }
+          const int at = tjr[e] - K / 2 + 1 + i - gj0[gi];
+          F[at] += sg * (R)c0;
+          F[JMAX + at] += sg * tdn[e] * (R)c1;
         }
-        fg[(gi * 2) * JMAX + j] = f;
-        fg[(gi * 2 + 1) * JMAX + j] = gg;
+        __syncthreads();
       }
     }
     __syncthreads();
@@ -574,31 +563,9 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
                       cw[k][3] * tdn[e * 4 + 3];
           }
           const int jb = tjr[e] + (int)(nb - nref);
-          if (TAY && flag == 0) {
-            int s0 = jb - K / 2 + 1;
-            s0 = s0 < 0 ? 0 : (s0 > MY - K - 3 ? MY - K - 3 : s0);   // memory safety only
-            R yv[K + 3];
+          const double f0 = tf0[e];
 #pragma unroll
-            for (int j = 0; j < K + 3; ++j) yv[j] = yl[s0 + j];
-            const R* c0 = tco + (e * 2) * K;
-            const R* c1 = c0 + K;
-            R a0[4] = {(R)0, (R)0, (R)0, (R)0}, a1[4] = {(R)0, (R)0, (R)0, (R)0};
-#pragma unroll
-            for (int i = 0; i < K; ++i) {
-              const R w0 = c0[i], w1 = c1[i];
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                a0[k] += w0 * yv[k + i];
-                a1[k] += w1 * yv[k + i];
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) val[k] = a0[k] - dl[k] * a1[k];
-          } else {
-            const double f0 = tf0[e];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) val[k] = lag1<R, K>(yl, MY, (double)(jb + k) + (f0 - (double)dl[k]));
-          }
+          for (int k = 0; k < 4; ++k) val[k] = lag1<R, K>(yl, MY, (double)(jb + k) + (f0 - (double)dl[k]));
         }
         if (tm.sign > 0) {
 #pragma unroll
@@ -649,11 +616,11 @@ static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
   if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
   if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
   constexpr int JMAX = CombLen<K>::value;
-  const size_t taylor = TAY ? (size_t)kTerms * kNV * 2 * K : 0;
   const int HREG = TAY ? std::max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
   size_t bytes = (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15) +
-                 (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kTerms * kNV * (sizeof(double) + 2 * sizeof(int)) +
-                 (size_t)kGroups * kNV * 2 * sizeof(int) + ((size_t)kTerms * kNV * (TAY ? 1 : 4) + taylor) * sizeof(R);
+                 (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kTerms * kNV * (sizeof(double) + sizeof(int)) +
+                 (size_t)kGroups * kNV * 2 * sizeof(int) + (size_t)kTerms * kNV * (TAY ? 1 : 4) * sizeof(R) +
+                 (size_t)kTerms * kNV;
   // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
   const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
   const int comb = (TAY && P.comb && span <= JMAX) ? 1 : 0;
