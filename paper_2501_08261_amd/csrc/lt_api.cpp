@@ -72,7 +72,7 @@ struct lt_ctx {
   int device = 0;
   std::map<int64_t, std::unique_ptr<Plan>> plans;
   std::map<std::tuple<int, double, double, double, double, double, double, int64_t>, std::unique_ptr<OrbitTab>> orbits;
-  DevBuf tpl, work, partial, wperm, status, wave;
+  DevBuf tpl, work, partial, wperm, status, wave, nodes, refs;
   // two-slot pipeline of lt_tdi_loglike: the FFT of one chunk (memory bound) runs on
   // `aux` while the response of the next (VALU bound) runs on the caller's stream
   DevBuf work2, partial2;
@@ -534,6 +534,13 @@ static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const l
   L.data = data;
   L.out = out;
   L.status = status;
+  size_t nb = 0, rb = 0;
+  tdi_scratch_bytes(L, &nb, &rb);
+  if (rb == 0) return fail(LT_ERR_UNSUPPORTED, "unsupported tap count");
+  LT_HIP(c->nodes.ensure(nb));
+  LT_HIP(c->refs.ensure(rb));
+  L.nodes = (double*)c->nodes.p;
+  L.refs = c->refs.p;
   Prof pr(c, 1, s);
   LT_HIP(launch_tdi(L, s));
   return LT_OK;

@@ -55,8 +55,12 @@ struct TdiLaunch {
   const void* data;   // [3][n] (residual mode)
   void* out;          // [batch][3][n]
   int32_t* status;    // nullable
+  double* nodes;      // scratch: response geometry per (template, orbit node)
+  void* refs;         // scratch: TDI term references and combined filters per tile
 };
 hipError_t launch_tdi(const TdiLaunch& L, hipStream_t s);
+// scratch bytes of launch_tdi for L (L.batch, taps, precision, grid and orbit set)
+void tdi_scratch_bytes(const TdiLaunch& L, size_t* nodes, size_t* refs);
 int tdi_tile();
 
 // ---------------------------------------------------------------- FFT

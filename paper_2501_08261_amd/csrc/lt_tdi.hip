@@ -202,19 +202,52 @@ __device__ inline void cubic_w(double x, double* w) {
   w[3] = xp1 * x * xm1 * (1.0 / 6.0);
 }
 
-// per node: for each link (P+, Px, D_s, L), then D_r for each spacecraft
-constexpr int kNL = 4;
+// Per node: for each link (P+, Px, D_s), then D_r for each spacecraft; a node record adds the
+// window bounds of its nine delays, ceil(D_max / dt) and floor(D_min / dt), as two int32.
+constexpr int kNL = 3;
 constexpr int kNodeVals = 6 * kNL + 3;
+constexpr int kNodeRec = kNodeVals + 1;
 __constant__ int kRecv[6] = {1, 2, 0, 2, 0, 1};     // receiver spacecraft (0-based) of links 1,2,3,-1,-2,-3
 __constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacecraft 1, 2, 3
 
-// ------------------------------------------------------- fused TDI kernel
-// One workgroup = one template x one tile of kTile output samples.
-//  B: per-link geometry at the orbit nodes covering the tile (LDS, FP64)
-//  A: h+, hx on the window of grid samples the six links read (LDS)
-//  C: y_slr for the tile plus the TDI halos; h is interpolated with K taps at
-//     the three receiver times and the six sender times (LDS)
-//  D: X, Y, Z from y interpolated at the TDI delays, then A, E, T (global)
+// ------------------------------------------------------- response geometry per (template, orbit node)
+// Projections P+ = (u.n)^2 - (v.n)^2) / 2 / (1 - k.n), Px = (u.n)(v.n) / (1 - k.n) and the
+// delays D_s = L + k.r_s / c (sender) and D_r = k.r_r / c (receiver) of Eq. (2.8), at every node
+// of the orbit table, computed once per template; [batch][n_nodes][kNodeRec] doubles.
+__global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb, double inv_dt, double* nodes) {
+  const int j = blockIdx.x * kNT + threadIdx.x;
+  const int b = blockIdx.y;
+  if (j >= orb.n_nodes) return;
+  const TplConst& c = tc[b];
+  double* o = nodes + ((int64_t)b * orb.n_nodes + j) * kNodeRec;
+  int dhi = -(1 << 30), dlo = 1 << 30;
+  for (int q = 0; q < 6; ++q) {
+    const double* e = orb.tab + (int64_t)j * kNodeStride + q * kNodeLink;
+    const double un = c.u[0] * e[7] + c.u[1] * e[8] + c.u[2] * e[9];
+    const double vn = c.v[0] * e[7] + c.v[1] * e[8] + c.v[2] * e[9];
+    const double kn = c.k[0] * e[7] + c.k[1] * e[8] + c.k[2] * e[9];
+    const double inv = 1.0 / (1.0 - kn);
+    const double dly = e[0] + (c.k[0] * e[4] + c.k[1] * e[5] + c.k[2] * e[6]);
+    o[q * kNL + 0] = 0.5 * (un * un - vn * vn) * inv;
+    o[q * kNL + 1] = un * vn * inv;
+    o[q * kNL + 2] = dly;
+    dhi = max(dhi, (int)ceil(dly * inv_dt));
+    dlo = min(dlo, (int)floor(dly * inv_dt));
+  }
+  for (int q = 0; q < 3; ++q) {
+    const double* e = orb.tab + (int64_t)j * kNodeStride + kRecvLink[q] * kNodeLink;
+    const double dly = c.k[0] * e[1] + c.k[1] * e[2] + c.k[2] * e[3];
+    o[6 * kNL + q] = dly;
+    dhi = max(dhi, (int)ceil(dly * inv_dt));
+    dlo = min(dlo, (int)floor(dly * inv_dt));
+  }
+  int2 wb;
+  wb.x = dhi;
+  wb.y = dlo;
+  *reinterpret_cast<int2*>(o + kNodeVals) = wb;
+}
+
+// ------------------------------------------------------- TDI term references per tile
 // Per (TDI term, node interval) reference: the stencil start and fraction at
 // the interval midpoint; the fraction of output n is f0 - delta(n) with
 // delta(n) = (D(t_n) - D(t_ref)) / dt, cubic in the node values dn (FP64
@@ -227,6 +260,9 @@ __constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacec
 //   G = sum_t s_t beta_t c1_t,
 // so that sum_t s_t y(n - D_t(n)) = (F * y)(n) - (n - n_ref) (G * y)(n),
 // with c0, c1 the first-order Taylor weights of each term.
+// The TDI delays are sums of arm light times, so all of this depends on the tile
+// and the orbit only: it is built once per launch, one workgroup per tile, and every
+// template's workgroup of that tile reads it.
 constexpr int kTerms = 48;          // 3 channels x at most 16 terms
 constexpr int kGroups = 12;         // 3 channels x at most 4 links
 constexpr int kNV = kTile / 256;    // node intervals per tile (node spacing 256)
@@ -236,138 +272,43 @@ struct CombLen {
   static constexpr int value = ((K + 16 + 3) / 4) * 4;   // filter length bound (multiple of 4)
 };
 
-template <typename R, int K, bool TAY>
-__global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX, int comb) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ long long s_w0;
-  __shared__ int s_W, s_skip, s_comb, s_span_bad;
-  constexpr int JMAX = CombLen<K>::value;
-  const int tid = threadIdx.x;
-  const int b = blockIdx.y;
-  const int64_t N = P.g.n;
-  const int64_t n0 = (int64_t)blockIdx.x * kTile;
-  const TplConst& c = P.tc[b];
-  // y is needed on [n0 - HY, n0 + kTile + K/2]: the centred stencils of the
-  // shortest TDI delays reach K/2 - 1 samples past the last output sample
-  const int MY = kTile + HY + K / 2 + 1;
-  const int MYP = (MY + kYPad + 3) & ~3;   // multiple of 4: aligned vector reads in phase D
-  R* yb = (R*)smem;
-  R* hpb = yb + 6 * MYP;
-  R* hxb = hpb + WMAX;
-  const int HREG = TAY ? max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
-  double* nd = (double*)(smem + (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15));
-  double* tf0 = nd + NNMAX * kNodeVals;                    // [kTerms * kNV] reference fraction
-  int* tjr = (int*)(tf0 + kTerms * kNV);                   // [kTerms * kNV] reference stencil index
-  int* gj0 = tjr + kTerms * kNV;                           // [kGroups * kNV] combined-filter start
-  int* gJ = gj0 + kGroups * kNV;                           // [kGroups * kNV] combined-filter length
-  R* tdn = (R*)(gJ + kGroups * kNV);   // mixed: [kTerms * kNV] delay rate; FP64: [kTerms * kNV][4] node offsets
-  unsigned char* tflag = (unsigned char*)(tdn + kTerms * kNV * (TAY ? 1 : 4));   // 0 Taylor, 1 direct, 2 zero delay
-  R* fg = hpb;                                             // later [kGroups * kNV][2][JMAX] combined filters
-  const double inv_dt = P.g.inv_dt;
-  const int64_t m_lo = n0 - HY, m_hi = m_lo + MY - 1;
-  constexpr int S = kTile / kNV;   // node spacing (the launch checks that the table uses it)
-  const int64_t jn_lo = floordiv(m_lo, S) - 1 + P.orb.j0;
-  const int64_t jn_hi = floordiv(m_hi, S) + 2 + P.orb.j0;
-  const int NN = (int)(jn_hi - jn_lo + 1);
+// byte layout of one tile's record
+template <typename R, int K>
+struct RefLayout {
+  static constexpr int JMAX = CombLen<K>::value;
+  static constexpr bool TAY = sizeof(R) == 4 && K <= 16;       // first-order weights (mixed, K <= 16)
+  static constexpr size_t f0 = 0;                                             // double [kTerms * kNV]
+  static constexpr size_t jr = f0 + sizeof(double) * kTerms * kNV;             // int [kTerms * kNV]
+  static constexpr size_t tdn = jr + sizeof(int) * kTerms * kNV;               // R [kTerms * kNV * (TAY ? 1 : 4)]
+  static constexpr size_t flag = tdn + sizeof(R) * kTerms * kNV * (TAY ? 1 : 4);   // uchar [kTerms * kNV]
+  static constexpr size_t gj = (flag + kTerms * kNV + 15) & ~(size_t)15;       // int [kGroups * kNV] start, length
+  static constexpr size_t comb = gj + sizeof(int) * 2 * kGroups * kNV;         // int: combined filters usable
+  static constexpr size_t fg = (comb + sizeof(int) + 15) & ~(size_t)15;        // R [kGroups * kNV][2][JMAX]
+  static constexpr size_t stride = (fg + (TAY ? sizeof(R) * kGroups * kNV * 2 * JMAX : 0) + 255) & ~(size_t)255;
+};
 
-  // B: node geometry
-  for (int i = tid; i < NN * 9; i += kNT) {
-    int nl = i / 9, q = i - nl * 9;
-    double* o = nd + nl * kNodeVals;
-    if (q < 6) {
-      const double* e = P.orb.tab + (jn_lo + nl) * kNodeStride + q * kNodeLink;
-      double un = c.u[0] * e[7] + c.u[1] * e[8] + c.u[2] * e[9];
-      double vn = c.v[0] * e[7] + c.v[1] * e[8] + c.v[2] * e[9];
-      double kn = c.k[0] * e[7] + c.k[1] * e[8] + c.k[2] * e[9];
-      double inv = 1.0 / (1.0 - kn);
-      o[q * kNL + 0] = 0.5 * (un * un - vn * vn) * inv;
-      o[q * kNL + 1] = un * vn * inv;
-      o[q * kNL + 2] = e[0] + (c.k[0] * e[4] + c.k[1] * e[5] + c.k[2] * e[6]);
-      o[q * kNL + 3] = e[0];
-    } else {
-      const double* e = P.orb.tab + (jn_lo + nl) * kNodeStride + kRecvLink[q - 6] * kNodeLink;
-      o[6 * kNL + (q - 6)] = c.k[0] * e[1] + c.k[1] * e[2] + c.k[2] * e[3];
-    }
-  }
-  __syncthreads();
+template <typename R, int K, bool TAY>
+__global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, int comb) {
+  using Lay = RefLayout<R, K>;
+  constexpr int JMAX = Lay::JMAX;
+  __shared__ double tf0[kTerms * kNV];
+  __shared__ int tjr[kTerms * kNV];
+  __shared__ R tdn[kTerms * kNV * (TAY ? 1 : 4)];
+  __shared__ unsigned char tflag[kTerms * kNV];
+  __shared__ int gj0[kGroups * kNV], gJ[kGroups * kNV];
+  __shared__ __align__(16) R fg[TAY ? kGroups * kNV * 2 * JMAX : 4];
+  __shared__ int s_comb, s_span_bad;
+  const int tid = threadIdx.x;
+  const int64_t n0 = (int64_t)blockIdx.x * kTile;
+  const int64_t m_lo = n0 - HY;
+  constexpr int S = kTile / kNV;
+  const double inv_dt = P.g.inv_dt;
+  for (int i = tid; i < kGroups * kNV; i += kNT) gj0[i] = gJ[i] = 0;
   if (tid == 0) {
-    double dmin = 1e300, dmax = -1e300;
-    for (int i = 0; i < NN; ++i) {
-      const double* o = nd + i * kNodeVals;
-      for (int q = 0; q < 6; ++q) { dmin = fmin(dmin, o[q * kNL + 2]); dmax = fmax(dmax, o[q * kNL + 2]); }
-      for (int q = 0; q < 3; ++q) { dmin = fmin(dmin, o[6 * kNL + q]); dmax = fmax(dmax, o[6 * kNL + q]); }
-    }
-    long long w0 = (long long)m_lo - (long long)ceil(dmax * inv_dt) - K / 2 - 2;
-    long long w1 = (long long)m_hi - (long long)floor(dmin * inv_dt) + K / 2 + 2;
-    int W = (int)(w1 - w0 + 1);
-    int bad = 0;
-    if (W > WMAX) { W = WMAX; bad = 1; }
-    s_w0 = w0;
-    s_W = W;
-    // every needed h sample precedes the f_low start (or the template is invalid): all zero
-    s_skip = (c.valid == 0.0 || (double)w1 < c.n_start - 2.0) ? 1 : 0;
     s_comb = comb;
     s_span_bad = 0;
-    if (bad && P.status) P.status[b] = 3;
   }
   __syncthreads();
-  const long long w0 = s_w0;
-  const int W = s_W;
-  const int skip = s_skip;
-
-  if (!skip) {
-    // A: polarisations of the window from the waveform buffer
-    const R* hg = (const R*)P.h + (2 * (int64_t)b) * N;
-    for (int i = tid; i < W; i += kNT) {
-      long long j = w0 + i;
-      bool in = j >= 0 && j < N;
-      hpb[i] = in ? hg[j] : (R)0;
-      hxb[i] = in ? hg[N + j] : (R)0;
-    }
-    __syncthreads();
-    // C: link responses y_slr for m in [m_lo, m_hi].  A thread's samples are kNT = S apart,
-    // one node interval: they share the cubic node weights, and the node index steps by one.
-    static_assert(kNT == S, "phase C strides by one node interval");
-    const int64_t q0 = floordiv(m_lo + tid, S);
-    double w[4];
-    cubic_w((double)(m_lo + tid - q0 * S) / (double)S, w);
-    const int jl0 = (int)(q0 + P.orb.j0 - jn_lo);
-    for (int mi = tid, it = 0; mi < MY; mi += kNT, ++it) {
-      int64_t m = m_lo + mi;
-      if (m < 0 || m >= N) {
-#pragma unroll
-        for (int li = 0; li < 6; ++li) yb[li * MYP + mi] = (R)0;
-        continue;
-      }
-      const double* o0 = nd + (jl0 + it - 1) * kNodeVals;
-      const double mloc = (double)(m - w0);
-      R hpr[3], hxr[3];
-#pragma unroll
-      for (int sc = 0; sc < 3; ++sc) {
-        double Dr = 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Dr += w[r] * o0[r * kNodeVals + 6 * kNL + sc];
-        lag2<R, K>(hpb, hxb, W, mloc - Dr * inv_dt, hpr[sc], hxr[sc]);
-      }
-#pragma unroll
-      for (int li = 0; li < 6; ++li) {
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double* o = o0 + r * kNodeVals + li * kNL;
-          v0 += w[r] * o[0];
-          v1 += w[r] * o[1];
-          v2 += w[r] * o[2];
-        }
-        R hps, hxs;
-        lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
-        const int rc = kRecv[li];
-        yb[li * MYP + mi] = (R)v0 * (hps - hpr[rc]) + (R)v1 * (hxs - hxr[rc]);
-      }
-    }
-    for (int i = tid; i < 6 * kYPad; i += kNT) yb[(i / kYPad) * MYP + MY + (i % kYPad)] = (R)0;
-    __syncthreads();
-  }
   // E: per (term, interval) references for the TDI delays
   const int S2 = S / 2;
   for (int e = tid; e < kTerms * kNV; e += kNT) {
@@ -376,12 +317,13 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     if (t >= P.terms.n_terms[cc]) continue;
     const Term& tm = P.terms.t[cc][t];
     const int64_t nv0 = n0 + (int64_t)v * S;
-    const int jlv = (int)(floordiv(nv0, S) + P.orb.j0 - jn_lo);
+    const int64_t jg = floordiv(nv0, S) + P.orb.j0;   // orbit node at the interval start
     double D[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       double a = 0.0;
-      for (int k = 0; k < tm.nd; ++k) a += (double)tm.dcnt[k] * nd[(jlv - 1 + r) * kNodeVals + tm.dlink[k] * kNL + 3];
+      for (int k = 0; k < tm.nd; ++k)
+        a += (double)tm.dcnt[k] * P.orb.tab[(jg - 1 + r) * kNodeStride + tm.dlink[k] * kNodeLink];
       D[r] = a;
     }
     // cubic interpolant at the interval midpoint (weights -1/16, 9/16, 9/16, -1/16)
@@ -441,9 +383,9 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     __syncthreads();
     comb1 = comb0 && !s_span_bad;
     if (comb1) {
-      // written over the h window, which phase C has finished reading.  Each term adds its
-      // first-order weights c0, c1 (products of (f0 + x - o_j), j != i, truncated after x)
-      // to its group's filters, one term of every group per round: the sums run in term order.
+      // each term adds its first-order weights c0, c1 (products of (f0 + x - o_j), j != i,
+      // truncated after x) to its group's filters, one term of every group per round: the sums
+      // run in term order
       for (int i = tid; i < kGroups * kNV * 2 * JMAX; i += kNT) fg[i] = (R)0;
       int qmax = 0;
       for (int cc = 0; cc < 3; ++cc)
@@ -481,17 +423,191 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     __syncthreads();
   }
 
+  // the record
+  unsigned char* rec = (unsigned char*)P.refs + (size_t)blockIdx.x * Lay::stride;
+  for (int i = tid; i < kTerms * kNV; i += kNT) {
+    ((double*)(rec + Lay::f0))[i] = tf0[i];
+    ((int*)(rec + Lay::jr))[i] = tjr[i];
+    (rec + Lay::flag)[i] = tflag[i];
+  }
+  for (int i = tid; i < kTerms * kNV * (TAY ? 1 : 4); i += kNT) ((R*)(rec + Lay::tdn))[i] = tdn[i];
+  for (int i = tid; i < kGroups * kNV; i += kNT) {
+    ((int*)(rec + Lay::gj))[i] = gj0[i];
+    ((int*)(rec + Lay::gj))[kGroups * kNV + i] = gJ[i];
+  }
+  if (tid == 0) *(int*)(rec + Lay::comb) = comb1;
+  if (TAY && comb1)
+    for (int i = tid; i < kGroups * kNV * 2 * JMAX; i += kNT) ((R*)(rec + Lay::fg))[i] = fg[i];
+}
+
+// ------------------------------------------------------- fused TDI kernel
+// One workgroup = one template x one tile of kTile output samples.
+//  B: the template's node records covering the tile (LDS, FP64)
+//  A: h+, hx on the window of grid samples the six links read (LDS)
+//  C: y_slr for the tile plus the TDI halos; h is interpolated with K taps at
+//     the three receiver and the six sender times (LDS)
+//  D: X, Y, Z from y at the TDI delays (the tile's combined filters, copied over
+//     the h window, or per term), then A, E, T (global)
+template <typename R, int K, bool TAY>
+__global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
+  using Lay = RefLayout<R, K>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_dhi, s_dlo;
+  constexpr int JMAX = Lay::JMAX;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int64_t N = P.g.n;
+  const int64_t n0 = (int64_t)blockIdx.x * kTile;
+  const TplConst& c = P.tc[b];
+  // y is needed on [n0 - HY, n0 + kTile + K/2]: the centred stencils of the
+  // shortest TDI delays reach K/2 - 1 samples past the last output sample
+  const int MY = kTile + HY + K / 2 + 1;
+  const int MYP = (MY + kYPad + 3) & ~3;   // multiple of 4: aligned vector reads in phase D
+  R* yb = (R*)smem;
+  R* hpb = yb + 6 * MYP;
+  R* hxb = hpb + WMAX;
+  const int HREG = TAY ? max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
+  double* nd = (double*)(smem + (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15));
+  int* gj0 = (int*)(nd + NNMAX * kNodeVals);               // [kGroups * kNV] combined-filter start
+  int* gJ = gj0 + kGroups * kNV;                           // [kGroups * kNV] combined-filter length
+  R* fg = hpb;                                             // later [kGroups * kNV][2][JMAX] combined filters
+  const unsigned char* rec = (const unsigned char*)P.refs + (size_t)blockIdx.x * Lay::stride;
+  const double* tf0 = (const double*)(rec + Lay::f0);
+  const int* tjr = (const int*)(rec + Lay::jr);
+  const R* tdn = (const R*)(rec + Lay::tdn);
+  const unsigned char* tflag = rec + Lay::flag;
+  const double inv_dt = P.g.inv_dt;
+  const int64_t m_lo = n0 - HY, m_hi = m_lo + MY - 1;
+  constexpr int S = kTile / kNV;   // node spacing (the launch checks that the table uses it)
+  const int S2 = S / 2;
+  const int64_t jn_lo = floordiv(m_lo, S) - 1 + P.orb.j0;
+  const int64_t jn_hi = floordiv(m_hi, S) + 2 + P.orb.j0;
+  const int NN = (int)(jn_hi - jn_lo + 1);
+
+  if (tid == 0) {
+    s_dhi = -(1 << 30);
+    s_dlo = 1 << 30;
+  }
+  __syncthreads();
+  // B: the template's node records; their window bounds give the h window (integer LDS
+  // min / max: the result does not depend on the order)
+  {
+    const double* ng = P.nodes + ((int64_t)b * P.orb.n_nodes + jn_lo) * kNodeRec;
+    for (int i = tid; i < NN * kNodeRec; i += kNT) {
+      const int nl = i / kNodeRec, q = i - nl * kNodeRec;
+      if (q < kNodeVals) {
+        nd[nl * kNodeVals + q] = ng[i];
+      } else {
+        const int2 wb = *reinterpret_cast<const int2*>(ng + i);
+        atomicMax(&s_dhi, wb.x);
+        atomicMin(&s_dlo, wb.y);
+      }
+    }
+  }
+  __syncthreads();
+  const long long w0 = (long long)m_lo - s_dhi - K / 2 - 2;
+  const long long w1 = (long long)m_hi - s_dlo + K / 2 + 2;
+  int W = (int)(w1 - w0 + 1);
+  if (W > WMAX) {
+    W = WMAX;
+    if (tid == 0 && P.status) P.status[b] = 3;
+  }
+  // every needed h sample precedes the f_low start (or the template is invalid): all zero
+  const int skip = (c.valid == 0.0 || (double)w1 < c.n_start - 2.0) ? 1 : 0;
+
+  if (!skip) {
+    // A: polarisations of the window from the waveform buffer, every load issued before the
+    // first LDS store (one memory latency per kA * kNT samples)
+    constexpr int kA = 6;
+    const R* hg = (const R*)P.h + (2 * (int64_t)b) * N;
+    for (int i0 = 0; i0 < W; i0 += kA * kNT) {
+      R vp[kA], vx[kA];
+#pragma unroll
+      for (int r = 0; r < kA; ++r) {
+        const long long j = w0 + i0 + r * kNT + tid;
+        const bool in = i0 + r * kNT + tid < W && j >= 0 && j < N;
+        vp[r] = in ? hg[j] : (R)0;
+        vx[r] = in ? hg[N + j] : (R)0;
+      }
+#pragma unroll
+      for (int r = 0; r < kA; ++r) {
+        const int i = i0 + r * kNT + tid;
+        if (i < W) {
+          hpb[i] = vp[r];
+          hxb[i] = vx[r];
+        }
+      }
+    }
+    __syncthreads();
+    // C: link responses y_slr for m in [m_lo, m_hi].  A thread's samples are kNT = S apart,
+    // one node interval: they share the cubic node weights, and the node index steps by one.
+    static_assert(kNT == S, "phase C strides by one node interval");
+    const int64_t q0 = floordiv(m_lo + tid, S);
+    double w[4];
+    cubic_w((double)(m_lo + tid - q0 * S) / (double)S, w);
+    const int jl0 = (int)(q0 + P.orb.j0 - jn_lo);
+    for (int mi = tid, it = 0; mi < MY; mi += kNT, ++it) {
+      int64_t m = m_lo + mi;
+      if (m < 0 || m >= N) {
+#pragma unroll
+        for (int li = 0; li < 6; ++li) yb[li * MYP + mi] = (R)0;
+        continue;
+      }
+      const double* o0 = nd + (jl0 + it - 1) * kNodeVals;
+      const double mloc = (double)(m - w0);
+      R hpr[3], hxr[3];
+#pragma unroll
+      for (int sc = 0; sc < 3; ++sc) {
+        double Dr = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Dr += w[r] * o0[r * kNodeVals + 6 * kNL + sc];
+        lag2<R, K>(hpb, hxb, W, mloc - Dr * inv_dt, hpr[sc], hxr[sc]);
+      }
+#pragma unroll
+      for (int li = 0; li < 6; ++li) {
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double* o = o0 + r * kNodeVals + li * kNL;
+          v0 += w[r] * o[0];
+          v1 += w[r] * o[1];
+          v2 += w[r] * o[2];
+        }
+        R hps, hxs;
+        lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
+        const int rc = kRecv[li];
+        yb[li * MYP + mi] = (R)v0 * (hps - hpr[rc]) + (R)v1 * (hxs - hxr[rc]);
+      }
+    }
+    for (int i = tid; i < 6 * kYPad; i += kNT) yb[(i / kYPad) * MYP + MY + (i % kYPad)] = (R)0;
+    __syncthreads();
+  }
+
+  // the tile's combined filters, written over the h window (phase C has finished reading it)
+  const int comb1 = (TAY && !skip) ? *(const int*)(rec + Lay::comb) : 0;
+  if (comb1) {
+    const float4* src = (const float4*)(rec + Lay::fg);
+    float4* dst = (float4*)fg;
+    for (int i = tid; i < kGroups * kNV * 2 * JMAX * (int)sizeof(R) / 16; i += kNT) dst[i] = src[i];
+    for (int i = tid; i < 2 * kGroups * kNV; i += kNT) gj0[i] = ((const int*)(rec + Lay::gj))[i];
+    __syncthreads();
+  }
+
   // D: TDI and A, E, T; each thread owns four consecutive output samples
   const R* data = (const R*)P.data;
   R* out = (R*)P.out;
   const int nl0 = 4 * tid;
   const int64_t nb = n0 + nl0;
   if (nb >= N) return;
-  R ch[3][4];
+  R ch[3][4], dv[3][4];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) ch[cc][k] = (R)0;
+    for (int k = 0; k < 4; ++k) {
+      ch[cc][k] = (R)0;
+      // the data of the residual, loaded before the filters run
+      dv[cc][k] = (P.out_mode == 2 && nb + k < N) ? data[cc * N + nb + k] : (R)0;
+    }
   if (!skip) {
     const int v = nl0 / S;
     const int64_t nref = n0 + (int64_t)v * S + S2;
@@ -586,15 +702,16 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     if (P.out_mode == 1) {
       o0 = ch[0][k]; o1 = ch[1][k]; o2 = ch[2][k];
     } else {
+      // no contraction: A, E, T are rounded before the data is subtracted, so a template equal
+      // to the data leaves a residual of exactly zero
+#pragma clang fp contract(off)
       const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
       o0 = (ch[2][k] - ch[0][k]) * r2;
       o1 = (ch[0][k] - (R)2 * ch[1][k] + ch[2][k]) * r6;
       o2 = (ch[0][k] + ch[1][k] + ch[2][k]) * r3;
-      if (P.out_mode == 2) {
-        o0 -= data[n];
-        o1 -= data[N + n];
-        o2 -= data[2 * N + n];
-      }
+      o0 -= dv[0][k];   // zero unless the residual is written
+      o1 -= dv[1][k];
+      o2 -= dv[2][k];
     }
     const int64_t base = (int64_t)b * 3 * N + n;
     out[base] = o0;
@@ -605,8 +722,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
 
 template <typename R, int K>
 static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
-  // first-order Taylor weights in FP32 for K <= 16; direct weights otherwise
-  constexpr bool TAY = sizeof(R) == 4 && K <= 16;
+  constexpr bool TAY = RefLayout<R, K>::TAY;
   int HY = (int)ceil(7.0 * P.orb.max_light_time * P.g.inv_dt * 1.001) + K / 2 + 2;
   int spread = (int)ceil(2.0 * P.orb.max_light_time * P.g.inv_dt * 1.01) + 8;
   const int MY = kTile + HY + K / 2 + 1;
@@ -615,22 +731,48 @@ static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
   int NNMAX = MY / P.orb.spacing + 5;
   if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
   if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
+  if (!P.nodes || !P.refs) return hipErrorInvalidValue;
   constexpr int JMAX = CombLen<K>::value;
   const int HREG = TAY ? std::max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
   size_t bytes = (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15) +
-                 (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kTerms * kNV * (sizeof(double) + sizeof(int)) +
-                 (size_t)kGroups * kNV * 2 * sizeof(int) + (size_t)kTerms * kNV * (TAY ? 1 : 4) * sizeof(R) +
-                 (size_t)kTerms * kNV;
+                 (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kGroups * kNV * 2 * sizeof(int);
   // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
   const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
   const int comb = (TAY && P.comb && span <= JMAX) ? 1 : 0;
   if (bytes > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)bytes);
+  const unsigned ntile = (unsigned)((P.g.n + kTile - 1) / kTile);
+  hipLaunchKernelGGL(k_nodes, dim3((unsigned)((P.orb.n_nodes + kNT - 1) / kNT), (unsigned)P.batch), dim3(kNT), 0, s,
+                     P.tc, P.orb, P.g.inv_dt, P.nodes);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)((P.g.n + kTile - 1) / kTile), (unsigned)P.batch);
-  hipLaunchKernelGGL((k_tdi<R, K, TAY>), grid, dim3(kNT), bytes, s, P, HY, WMAX, NNMAX, comb);
+  hipLaunchKernelGGL((k_tdi_refs<R, K, TAY>), dim3(ntile), dim3(kNT), 0, s, P, HY, MYP, comb);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_tdi<R, K, TAY>), dim3(ntile, (unsigned)P.batch), dim3(kNT), bytes, s, P, HY, WMAX, NNMAX);
   return hipGetLastError();
+}
+
+template <typename R>
+static size_t refs_stride_k(int taps) {
+  switch (taps) {
+    case 2: return RefLayout<R, 2>::stride;
+    case 4: return RefLayout<R, 4>::stride;
+    case 6: return RefLayout<R, 6>::stride;
+    case 8: return RefLayout<R, 8>::stride;
+    case 12: return RefLayout<R, 12>::stride;
+    case 16: return RefLayout<R, 16>::stride;
+    case 24: return RefLayout<R, 24>::stride;
+    case 32: return RefLayout<R, 32>::stride;
+    default: return 0;
+  }
+}
+
+void tdi_scratch_bytes(const TdiLaunch& P, size_t* nodes, size_t* refs) {
+  *nodes = (size_t)P.batch * (size_t)P.orb.n_nodes * kNodeRec * sizeof(double);
+  const size_t stride = P.precision == 0 ? refs_stride_k<double>(P.taps) : refs_stride_k<float>(P.taps);
+  *refs = (size_t)((P.g.n + kTile - 1) / kTile) * stride;
 }
 
 template <typename R>
