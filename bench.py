@@ -30,6 +30,7 @@ PMC_TRAFFIC = {
 
 N_SAMPLES = 2 ** 20
 BATCH = 256
+PROFILE_CHUNK = 64      # templates per launch of the pipelined likelihood
 TAPS = 8
 
 
@@ -306,10 +307,15 @@ def main():
     value = a.batch * a.steps / elapsed
     print("timed %d steps: %.3f ms/step" % (a.steps, ms_per_step), file=sys.stderr, flush=True)
 
-    # per-kernel averages from HIP events recorded on the launch stream
+    # per-kernel averages from HIP events recorded on the launch stream.  The pipelined call runs
+    # a chunk's FFT beside the next chunk's response kernel, which stretches both durations; this
+    # pass makes the same 64-template launches one call at a time (one stream), so each event
+    # pair times its kernel alone
     ctx.profile_enable(True)
     for _ in range(a.profile_steps):
-        step()
+        for c0 in range(0, a.batch, PROFILE_CHUNK):
+            c1 = min(a.batch, c0 + PROFILE_CHUNK)
+            ctx.tdi_loglike(params[c0:c1], g, cfg, orb, tdi, S, d[0], ddv, logl[c0:c1], status=status[c0:c1])
     torch.cuda.synchronize()
     ms, cnt = ctx.profile_read(5)
     ctx.profile_enable(False)

@@ -541,8 +541,12 @@ static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const l
   LT_HIP(c->refs.ensure(rb));
   L.nodes = (double*)c->nodes.p;
   L.refs = c->refs.p;
+  {
+    Prof pr(c, 0, s);
+    LT_HIP(launch_tdi(L, 0, s));
+  }
   Prof pr(c, 1, s);
-  LT_HIP(launch_tdi(L, s));
+  LT_HIP(launch_tdi(L, 1, s));
   return LT_OK;
 }
 

@@ -58,7 +58,9 @@ struct TdiLaunch {
   double* nodes;      // scratch: response geometry per (template, orbit node)
   void* refs;         // scratch: TDI term references and combined filters per tile
 };
-hipError_t launch_tdi(const TdiLaunch& L, hipStream_t s);
+// stage 0: the per-launch tables (node geometry, term references, combined filters);
+// stage 1: the response kernel itself
+hipError_t launch_tdi(const TdiLaunch& L, int stage, hipStream_t s);
 // scratch bytes of launch_tdi for L (L.batch, taps, precision, grid and orbit set)
 void tdi_scratch_bytes(const TdiLaunch& L, size_t* nodes, size_t* refs);
 int tdi_tile();

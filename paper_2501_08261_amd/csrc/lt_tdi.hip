@@ -455,9 +455,14 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   __shared__ int s_dhi, s_dlo;
   constexpr int JMAX = Lay::JMAX;
   const int tid = threadIdx.x;
-  const int b = blockIdx.y;
+  // workgroups in dispatch order take the templates of one tile back to back, so that its record
+  // stays in L2; the template order rotates with the tile, so that the round-robin placement of
+  // workgroups on the XCDs gives each XCD every template (lengths differ) over the tiles
+  const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const int64_t tile = wg / P.batch;
+  const int b = (int)((wg % P.batch + tile) % P.batch);
   const int64_t N = P.g.n;
-  const int64_t n0 = (int64_t)blockIdx.x * kTile;
+  const int64_t n0 = tile * kTile;
   const TplConst& c = P.tc[b];
   // y is needed on [n0 - HY, n0 + kTile + K/2]: the centred stencils of the
   // shortest TDI delays reach K/2 - 1 samples past the last output sample
@@ -471,7 +476,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   int* gj0 = (int*)(nd + NNMAX * kNodeVals);               // [kGroups * kNV] combined-filter start
   int* gJ = gj0 + kGroups * kNV;                           // [kGroups * kNV] combined-filter length
   R* fg = hpb;                                             // later [kGroups * kNV][2][JMAX] combined filters
-  const unsigned char* rec = (const unsigned char*)P.refs + (size_t)blockIdx.x * Lay::stride;
+  const unsigned char* rec = (const unsigned char*)P.refs + (size_t)tile * Lay::stride;
   const double* tf0 = (const double*)(rec + Lay::f0);
   const int* tjr = (const int*)(rec + Lay::jr);
   const R* tdn = (const R*)(rec + Lay::tdn);
@@ -720,37 +725,54 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   }
 }
 
+// launch geometry of the response kernel (host)
 template <typename R, int K>
-static hipError_t launch_tdi_t(const TdiLaunch& P, hipStream_t s) {
+struct TdiGeom {
+  int HY, MYP, WMAX, NNMAX, comb;
+  unsigned ntile;
+  size_t bytes;
+  hipError_t make(const TdiLaunch& P) {
+    constexpr bool TAY = RefLayout<R, K>::TAY;
+    HY = (int)ceil(7.0 * P.orb.max_light_time * P.g.inv_dt * 1.001) + K / 2 + 2;
+    const int spread = (int)ceil(2.0 * P.orb.max_light_time * P.g.inv_dt * 1.01) + 8;
+    const int MY = kTile + HY + K / 2 + 1;
+    MYP = (MY + kYPad + 3) & ~3;
+    WMAX = MY + spread + K + 8;
+    NNMAX = MY / P.orb.spacing + 5;
+    if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
+    if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
+    if (!P.nodes || !P.refs) return hipErrorInvalidValue;
+    constexpr int JMAX = CombLen<K>::value;
+    const int HREG = TAY ? std::max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
+    bytes = (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15) +
+            (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kGroups * kNV * 2 * sizeof(int);
+    if (bytes > 160 * 1024) return hipErrorInvalidValue;
+    // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
+    const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
+    comb = (TAY && P.comb && span <= JMAX) ? 1 : 0;
+    ntile = (unsigned)((P.g.n + kTile - 1) / kTile);
+    return hipSuccess;
+  }
+};
+
+template <typename R, int K>
+static hipError_t launch_tdi_t(const TdiLaunch& P, int stage, hipStream_t s) {
   constexpr bool TAY = RefLayout<R, K>::TAY;
-  int HY = (int)ceil(7.0 * P.orb.max_light_time * P.g.inv_dt * 1.001) + K / 2 + 2;
-  int spread = (int)ceil(2.0 * P.orb.max_light_time * P.g.inv_dt * 1.01) + 8;
-  const int MY = kTile + HY + K / 2 + 1;
-  const int MYP = (MY + kYPad + 3) & ~3;
-  int WMAX = MY + spread + K + 8;
-  int NNMAX = MY / P.orb.spacing + 5;
-  if (HY + 8 > P.orb.spacing || K / 2 + 9 > P.orb.spacing) return hipErrorInvalidValue;   // node table covers one spacing of halo
-  if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
-  if (!P.nodes || !P.refs) return hipErrorInvalidValue;
-  constexpr int JMAX = CombLen<K>::value;
-  const int HREG = TAY ? std::max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
-  size_t bytes = (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15) +
-                 (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kGroups * kNV * 2 * sizeof(int);
-  // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
-  const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
-  const int comb = (TAY && P.comb && span <= JMAX) ? 1 : 0;
-  if (bytes > 160 * 1024) return hipErrorInvalidValue;
-  const unsigned ntile = (unsigned)((P.g.n + kTile - 1) / kTile);
-  hipLaunchKernelGGL(k_nodes, dim3((unsigned)((P.orb.n_nodes + kNT - 1) / kNT), (unsigned)P.batch), dim3(kNT), 0, s,
-                     P.tc, P.orb, P.g.inv_dt, P.nodes);
-  hipError_t e = hipGetLastError();
+  TdiGeom<R, K> G;
+  hipError_t e = G.make(P);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_tdi_refs<R, K, TAY>), dim3(ntile), dim3(kNT), 0, s, P, HY, MYP, comb);
-  e = hipGetLastError();
+  if (stage == 0) {
+    hipLaunchKernelGGL(k_nodes, dim3((unsigned)((P.orb.n_nodes + kNT - 1) / kNT), (unsigned)P.batch), dim3(kNT), 0,
+                       s, P.tc, P.orb, P.g.inv_dt, P.nodes);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_tdi_refs<R, K, TAY>), dim3(G.ntile), dim3(kNT), 0, s, P, G.HY, G.MYP, G.comb);
+    return hipGetLastError();
+  }
+  e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.bytes);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_tdi<R, K, TAY>), dim3(ntile, (unsigned)P.batch), dim3(kNT), bytes, s, P, HY, WMAX, NNMAX);
+  hipLaunchKernelGGL((k_tdi<R, K, TAY>), dim3(G.ntile, (unsigned)P.batch), dim3(kNT), G.bytes, s, P, G.HY, G.WMAX,
+                     G.NNMAX);
   return hipGetLastError();
 }
 
@@ -776,22 +798,22 @@ void tdi_scratch_bytes(const TdiLaunch& P, size_t* nodes, size_t* refs) {
 }
 
 template <typename R>
-static hipError_t launch_tdi_k(const TdiLaunch& P, hipStream_t s) {
+static hipError_t launch_tdi_k(const TdiLaunch& P, int stage, hipStream_t s) {
   switch (P.taps) {
-    case 2: return launch_tdi_t<R, 2>(P, s);
-    case 4: return launch_tdi_t<R, 4>(P, s);
-    case 6: return launch_tdi_t<R, 6>(P, s);
-    case 8: return launch_tdi_t<R, 8>(P, s);
-    case 12: return launch_tdi_t<R, 12>(P, s);
-    case 16: return launch_tdi_t<R, 16>(P, s);
-    case 24: return launch_tdi_t<R, 24>(P, s);
-    case 32: return launch_tdi_t<R, 32>(P, s);
+    case 2: return launch_tdi_t<R, 2>(P, stage, s);
+    case 4: return launch_tdi_t<R, 4>(P, stage, s);
+    case 6: return launch_tdi_t<R, 6>(P, stage, s);
+    case 8: return launch_tdi_t<R, 8>(P, stage, s);
+    case 12: return launch_tdi_t<R, 12>(P, stage, s);
+    case 16: return launch_tdi_t<R, 16>(P, stage, s);
+    case 24: return launch_tdi_t<R, 24>(P, stage, s);
+    case 32: return launch_tdi_t<R, 32>(P, stage, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_tdi(const TdiLaunch& P, hipStream_t s) {
-  return P.precision == 0 ? launch_tdi_k<double>(P, s) : launch_tdi_k<float>(P, s);
+hipError_t launch_tdi(const TdiLaunch& P, int stage, hipStream_t s) {
+  return P.precision == 0 ? launch_tdi_k<double>(P, stage, s) : launch_tdi_k<float>(P, stage, s);
 }
 
 }  // namespace lt
