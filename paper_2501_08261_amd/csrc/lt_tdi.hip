@@ -626,14 +626,20 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
           const R* F = fg + (gi * 2) * JMAX;
           const R* G = F + JMAX;
           R a[4] = {(R)0, (R)0, (R)0, (R)0}, d[4] = {(R)0, (R)0, (R)0, (R)0};
+          // yl, F, G and j are 16-byte aligned (gj0, MYP, JMAX and n - n_ref are multiples of 4):
+          // one 16 B read of y per four taps, the window of eight samples kept in registers; eight
+          // lanes of a 16 B read cover the 32 LDS banks without conflict
+          // (volatile: the compiler would otherwise split the 16 B reads into 4 B reads that
+          // conflict four ways)
+          typedef float v4f __attribute__((ext_vector_type(4)));
+          typedef const volatile __attribute__((address_space(3))) v4f lds_v4f;
+          v4f y0 = *(lds_v4f*)(yl);
           for (int j = 0; j < J; j += 4) {
-            // yl, F, G and j are 16-byte aligned (gj0, MYP, JMAX and n - n_ref are multiples of 4):
-            // each lane reads 2 x 16 B, eight lanes cover the 32 LDS banks without conflict
             R yv[8];
-            const float4 y0 = *reinterpret_cast<const float4*>(yl + j);
-            const float4 y1 = *reinterpret_cast<const float4*>(yl + j + 4);
+            const v4f y1 = *(lds_v4f*)(yl + j + 4);
             yv[0] = y0.x; yv[1] = y0.y; yv[2] = y0.z; yv[3] = y0.w;
             yv[4] = y1.x; yv[5] = y1.y; yv[6] = y1.z; yv[7] = y1.w;
+            y0 = y1;
             const float4 f4 = *reinterpret_cast<const float4*>(F + j);
             const float4 g4 = *reinterpret_cast<const float4*>(G + j);
             const R fa[4] = {f4.x, f4.y, f4.z, f4.w}, ga[4] = {g4.x, g4.y, g4.z, g4.w};
