@@ -597,7 +597,7 @@ static lt_status band_power(lt_ctx* c, Plan* p, void* series, int64_t rows, int 
   LT_HIP(c->wperm.ensure((size_t)3 * (n + 1) * sizeof(double)));
   LT_HIP(c->partial.ensure((size_t)rows * (p->dev.n1 / 2 + 1) * sizeof(double)));
   {
-    Prof pr(c, 3, s);
+    Prof pr(c, 0, s);   // per-call table, timed with the setup
     LT_HIP(launch_weights(p->dev, psd->S, k_lo, k_hi, channels, (double*)c->wperm.p, s));
   }
   {
@@ -674,7 +674,7 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
   }
   LT_HIP(c->wperm.ensure((size_t)3 * (g->n / 2 + 1) * sizeof(double)));
   {
-    Prof pr(c, 3, s);
+    Prof pr(c, 0, s);   // per-call table, timed with the setup
     LT_HIP(launch_weights(p->dev, psd->S, k_lo, k_hi, t->channels, (double*)c->wperm.p, s));
   }
   LT_HIP(hipEventRecord(c->ev_fork, s));

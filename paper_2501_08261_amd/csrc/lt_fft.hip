@@ -346,11 +346,18 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
     rowk1[3] = (r2 <= N1 / 2 && r3 != r2) ? r3 : -1;
   }
   __syncthreads();
-#pragma unroll 4
-  for (int i = threadIdx.x; i < NR * N2; i += kFT) {
-    const int r = i / N2, j2 = i % N2;
-    const int k1 = rowk1[r];
-    buf[i] = k1 >= 0 ? z[(int64_t)k1 * N2 + j2] : C2<R>{(R)0, (R)0};
+  {
+    // every load of the four rows issued before the first LDS store (one memory latency)
+    constexpr int PT = NR * N2 / kFT;
+    C2<R> v[PT];
+#pragma unroll
+    for (int m = 0; m < PT; ++m) {
+      const int i = threadIdx.x + m * kFT;
+      const int k1 = rowk1[i / N2];
+      v[m] = k1 >= 0 ? z[(int64_t)k1 * N2 + (i % N2)] : C2<R>{(R)0, (R)0};
+    }
+#pragma unroll
+    for (int m = 0; m < PT; ++m) buf[threadIdx.x + m * kFT] = v[m];
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw2d, p.tw2f);
@@ -359,7 +366,56 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   double acc = 0.0;
   const int64_t ch = row % 3;
-  for (int i = threadIdx.x; i < NR * N2 + 1; i += kFT) {
+  if (mode != 0) {
+    // band power.  Bin k = k1 + N1 k2 lies in [kb_lo, kb_hi] only for k2 <= kb_hi / N1; a thread
+    // takes k2 = threadIdx.x + kFT m0 in each of the four rows, with the weights and twiddles
+    // of the four rows loaded together before they are used.  Per thread the bins are summed
+    // row by row within each m0.
+    const int k2max = kb_hi / N1 < N2 - 1 ? (int)(kb_hi / N1) : N2 - 1;
+    for (int m0 = 0; m0 * kFT <= k2max; ++m0) {
+      const int k2 = threadIdx.x + m0 * kFT;
+      bool on[NR];
+      double wv[NR];
+      C2<R> lk[NR], hk[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int k1 = rowk1[r];
+        const int64_t k = k1 + (int64_t)N1 * k2;
+        on[r] = k1 >= 0 && k2 < N2 && k >= kb_lo && k <= kb_hi;
+        wv[r] = on[r] ? wperm[ch * (n + 1) + (int64_t)k1 * N2 + k2] : 0.0;
+        lk[r] = on[r] ? lo[k & 1023] : C2<R>{(R)0, (R)0};
+        hk[r] = on[r] ? hi[k >> 10] : C2<R>{(R)0, (R)0};
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (!on[r]) continue;
+        const int k1 = rowk1[r];
+        const C2<R> Zk = buf[r * N2 + k2];
+        C2<R> Zm;
+        if (k1 == 0) {
+          Zm = buf[r * N2 + (N2 - k2) % N2];
+        } else {
+          const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
+          Zm = buf[rm * N2 + (N2 - 1 - k2)];
+        }
+        const C2<R> zc = {Zm.x, -Zm.y};
+        const C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
+        const C2<R> X = sm + mi(cm(cm(lk[r], hk[r]), df));
+        const double xr = (double)X.x, xi = (double)X.y;
+        acc += wv[r] * (xr * xr + xi * xi);
+      }
+    }
+    if (pa == 0 && threadIdx.x == 0 && n >= kb_lo && n <= kb_hi) {
+      // Nyquist: Z_n = Z_0, twiddle -1
+      const C2<R> Zk = buf[0], zc = {buf[0].x, -buf[0].y};
+      const C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
+      const C2<R> X = sm + mi(cm(C2<R>{(R)-1, (R)0}, df));
+      const double xr = (double)X.x, xi = (double)X.y;
+      acc += wperm[ch * (n + 1) + n] * (xr * xr + xi * xi);
+    }
+  }
+  // full spectrum (mode 0)
+  for (int i = threadIdx.x; mode == 0 && i < NR * N2 + 1; i += kFT) {
     int64_t k;
     C2<R> Zk, Zm;
     int k1, k2;
@@ -384,19 +440,11 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       Zk = buf[0];
       Zm = buf[0];
     }
-    if (mode != 0 && (k < kb_lo || k > kb_hi)) continue;   // outside the band: weight 0, not read
     C2<R> zc = {Zm.x, -Zm.y};
     C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
     C2<R> wk = (k == n) ? C2<R>{(R)-1, (R)0} : wN<R>(lo, hi, k);
     C2<R> X = sm + mi(cm(wk, df));
-    if (mode == 0) {
-      spec[row * (n + 1) + k] = sc(X, (R)dt);
-    } else {
-      const int64_t widx = (k == n) ? n : (int64_t)k1 * N2 + k2;
-      const double wv = wperm[ch * (n + 1) + widx];
-      const double xr = (double)X.x, xi = (double)X.y;
-      acc += wv * (xr * xr + xi * xi);
-    }
+    spec[row * (n + 1) + k] = sc(X, (R)dt);
   }
   if (mode != 0) {
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);

@@ -584,7 +584,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
         yb[li * MYP + mi] = (R)v0 * (hps - hpr[rc]) + (R)v1 * (hxs - hxr[rc]);
       }
     }
-    for (int i = tid; i < 6 * kYPad; i += kNT) yb[(i / kYPad) * MYP + MY + (i % kYPad)] = (R)0;
+    // zero the tail of each y series up to its padded length: filter taps beyond the data read it
+    for (int i = tid; i < 6 * (MYP - MY); i += kNT) yb[(i / (MYP - MY)) * MYP + MY + (i % (MYP - MY))] = (R)0;
     __syncthreads();
   }
 
