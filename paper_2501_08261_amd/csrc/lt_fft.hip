@@ -305,22 +305,39 @@ __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* d
   const int64_t row = blockIdx.y;
   const int j2_0 = blockIdx.x * CB;
   C2<R>* z = data + row * ((int64_t)N1 * N2);
-#pragma unroll 4
-  for (int i = threadIdx.x; i < CB * N1; i += kP1Threads) {
-    const int j1 = i / CB, jj = i % CB;
-    buf[jj * LP + j1] = z[(int64_t)j1 * N2 + j2_0 + jj];
+  constexpr int PT = CB * N1 / kP1Threads;   // elements per thread
+  {
+    // every load issued before the first LDS store (one memory latency)
+    C2<R> v[PT];
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int i = threadIdx.x + t * kP1Threads, j1 = i / CB, jj = i % CB;
+      v[t] = z[(int64_t)j1 * N2 + j2_0 + jj];
+    }
+#pragma unroll
+    for (int t = 0; t < PT; ++t) {
+      const int i = threadIdx.x + t * kP1Threads, j1 = i / CB, jj = i % CB;
+      buf[jj * LP + j1] = v[t];
+    }
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
   ct_fft_strided<R, N1, LP, kP1Threads, CB, 1, 8, 8, 8>(buf, tw);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
-#pragma unroll 4
-  for (int i = threadIdx.x; i < CB * N1; i += kP1Threads) {
-    const int k1 = i / CB, jj = i % CB;
-    const int j2 = j2_0 + jj;
-    const int64_t m = (int64_t)j2 * k1;
-    z[(int64_t)k1 * N2 + j2] = cm(buf[jj * LP + k1], wN<R>(lo, hi, 2 * m));
+  // twiddle tables read for all of this thread's elements before the first product
+  C2<R> tl[PT], th[PT];
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+    const int i = threadIdx.x + t * kP1Threads, k1 = i / CB, jj = i % CB;
+    const int64_t m2 = 2 * (int64_t)(j2_0 + jj) * k1;
+    tl[t] = lo[m2 & 1023];
+    th[t] = hi[m2 >> 10];
+  }
+#pragma unroll
+  for (int t = 0; t < PT; ++t) {
+    const int i = threadIdx.x + t * kP1Threads, k1 = i / CB, jj = i % CB;
+    z[(int64_t)k1 * N2 + j2_0 + jj] = cm(buf[jj * LP + k1], cm(tl[t], th[t]));
   }
 }
 
