@@ -170,7 +170,14 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     samples (Cholesky of their covariance), train `train_steps` Adam steps on them,
     attach, run `window` more steps.  The flow is then frozen and both samplers
     restart from the same state for `m` recorded steps; ESS = m W / max_q tau_q
-    (worst coordinate), ESS/s uses the time of 200 unrecorded steps."""
+    (worst coordinate), ESS/s uses the time of 200 unrecorded steps.
+
+    The waveform carries exp(2 i psi), so the likelihood is invariant under
+    psi -> psi + pi and the prior range [-pi, pi] holds two copies of every psi.
+    The flow works on psi folded into a window of width pi centred on the chain's
+    circular mean of 2 psi (lt_sampler_set_flow_fold); its proposals land on either
+    copy.  Autocorrelation times and moments are computed on the folded psi for both
+    chains, since only psi mod pi is identified."""
     import numpy as np
     import torch
     from paper_2501_08261_amd.diagnostics import autocorr_time
@@ -199,9 +206,20 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     smp.step(burn)
     flow = lib.Flow(dim, 8, 256, max(2048, W))
     flow.set_params(lib.flow_init_params(dim, 8, 256, 3), np.zeros(dim), np.ones(dim))
+    ipsi = dim - 1
+
+    def fold(X, start):
+        X = np.array(X, copy=True)
+        X[..., ipsi] = start + np.mod(X[..., ipsi] - start, np.pi)
+        return X
+
     t_train = 0.0
     for r in range(rounds):
         s = _record(smp, window).reshape(-1, dim)
+        two = 2.0 * s[:, ipsi]
+        start = 0.5 * np.arctan2(np.sin(two).mean(), np.cos(two).mean()) - 0.5 * np.pi
+        s = fold(s, start)
+        smp.set_flow_fold(ipsi, np.pi, start)
         flow.set_whitening(s.mean(0), np.linalg.cholesky(np.cov(s.T)))
         xs = torch.tensor(s[np.random.default_rng(r).permutation(len(s))], device="cuda:0")
         torch.cuda.synchronize()
@@ -223,7 +241,7 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         smp.step(200)
         torch.cuda.synchronize()
         t_step = (time.perf_counter() - t1) / 200
-        chain = _record(smp, m)
+        chain = fold(_record(smp, m), start)
         acc, prop = smp.flow_counts()
         tau = autocorr_time(chain)
         flat = chain.reshape(-1, dim)

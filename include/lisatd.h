@@ -302,6 +302,17 @@ lt_status lt_flow_train(lt_flow* f, const double* x, int64_t n, int steps, int b
  * sampler or be detached first.  Retraining the attached flow between
  * lt_sampler_step calls changes the proposal in place. */
 lt_status lt_sampler_set_flow(lt_sampler* s, lt_flow* flow);
+/* Symmetry fold of the flow move, for a target invariant under x_i -> x_i + period
+ * (the polarisation angle psi with period pi: h carries exp(2 i psi), Eq. (2.6)).
+ * The flow then works on folded coordinates: the sampler maps x_i into the window
+ * [start, start + period) before evaluating log q(x), and a flow sample y whose y_i
+ * lies in the window becomes one of its copies y_i + k period inside the prior range
+ * [lo_i, hi_i], chosen uniformly with u from Philox counter (step, 0x600, walker, 0);
+ * a sample outside the window is rejected.  Both densities carry the factor
+ * 1 / (number of copies), so the acceptance above stays exact.  index = -1 removes
+ * the fold; period must be positive and finite.  The flow should be trained on folded
+ * samples.  Rebuilds the captured step on the next lt_sampler_step. */
+lt_status lt_sampler_set_flow_fold(lt_sampler* s, int index, double period, double start);
 /* Flow moves accepted and proposed since lt_sampler_set_state (host int64 [2]). */
 lt_status lt_sampler_flow_counts(lt_sampler* s, int64_t* counts);
 

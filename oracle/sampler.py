@@ -21,6 +21,14 @@ of the GPU sampler:
   (Philox counter (step, 0x400, walker, q) -> coordinates 4q..4q+3), accepted
   when ln u < beta_0 (logL_y - logL_x) + (logP_y - logP_x) + ln q(x) - ln q(y)
   (independence Metropolis-Hastings), u from counter (step, 0x500, walker, 0);
+* optional symmetry fold of that move, for a target invariant under
+  x_i -> x_i + P (the polarisation angle, P = pi: h carries exp(2 i psi)):
+  the flow sees x_i folded into [c, c + P); a flow sample y_f with its i-th
+  coordinate in that window becomes the copy y_i = y_f,i + (k_min + j) P,
+  j = floor(u n) of the n copies inside [lo_i, hi_i], u from counter
+  (step, 0x600, walker, 0), and both ln q carry - ln n (the proposal density
+  of a copy is q_flow(y_f) / n), so the ratio stays exact; a y_f outside the
+  window is outside the proposal's range and is rejected;
 * random numbers from Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011) keyed
   by the seed, counter (step, purpose, slot, 0), uniforms (u + 1/2) 2^-32.
 """
@@ -33,7 +41,7 @@ from . import flow as _flow
 M0, M1 = 0xD2511F53, 0xCD9E8D57
 W0, W1 = 0x9E3779B9, 0xBB67AE85
 MASK = 0xFFFFFFFF
-TAG_MOVE, TAG_SHIFT, TAG_SWAP, TAG_FLOWZ, TAG_FLOWU = 0x100, 0x200, 0x300, 0x400, 0x500
+TAG_MOVE, TAG_SHIFT, TAG_SWAP, TAG_FLOWZ, TAG_FLOWU, TAG_FLOWC = 0x100, 0x200, 0x300, 0x400, 0x500, 0x600
 
 
 def philox4x32_10(ctr, key):
@@ -100,11 +108,22 @@ class PTSampler:
         self.step_count = 0
         self.acc = self.prop = self.sacc = self.sprop = 0
         self.flow = None
+        self.fold = None
         self.facc = self.fprop = 0
 
     def set_flow(self, P, mu, sigma):
         """Attach a flow (oracle.flow parameters; None detaches)."""
         self.flow = None if P is None else (P, np.asarray(mu, float), np.asarray(sigma, float))
+
+    def set_flow_fold(self, index, period=math.pi, start=0.0):
+        """Fold coordinate `index` into [start, start + period) for the flow move (index < 0: none)."""
+        self.fold = None if index < 0 else (int(index), float(period), float(start))
+
+    def _copies(self, v, i, P):
+        """Copies v + k P inside [lo_i, hi_i]: (k_min, count)."""
+        a = np.ceil((self.lo[i] - v) / P)
+        b = np.floor((self.hi[i] - v) / P)
+        return a, np.where(b >= a, b - a + 1, 0).astype(np.int64)
 
     def flow_normals(self, s):
         """Base samples z [W][d] of step s."""
@@ -127,12 +146,31 @@ class PTSampler:
         P, mu, sigma = self.flow
         W = self.W
         y, lqy = _flow.inverse(P, self.flow_normals(s), mu, sigma)
-        _, lqx = _flow.forward(P, self.X[0], mu, sigma)
-        lpy = self.log_prior(y)
+        xf = self.X[0].copy()
+        lkx = np.zeros(W)
+        out = np.zeros(W, dtype=bool)
+        if self.fold is not None:
+            i, Pf, c0 = self.fold
+            x = self.X[0, :, i]
+            xf[:, i] = c0 + ((x - c0) - Pf * np.floor((x - c0) / Pf))
+            _, nx = self._copies(xf[:, i], i, Pf)
+            lkx = np.where(nx > 0, np.log(np.maximum(nx, 1).astype(np.float64)), 0.0)
+            v = y[:, i].copy()
+            inwin = (v >= c0) & (v < c0 + Pf)
+            km, ny = self._copies(v, i, Pf)
+            ny = np.where(inwin, ny, 0)
+            ru_c = philox4x32_10(_ctr(s, TAG_FLOWC, np.arange(W)), self.key)
+            j = np.minimum(np.floor(u01(ru_c[:, 0]) * ny.astype(np.float64)).astype(np.int64), ny - 1)
+            okc = ny > 0
+            y[okc, i] = v[okc] + (km[okc] + j[okc].astype(np.float64)) * Pf
+            lqy = np.where(okc, lqy - np.log(np.maximum(ny, 1).astype(np.float64)), lqy)
+            out = ~okc
+        _, lqx = _flow.forward(P, xf, mu, sigma)
+        lpy = np.where(out, -np.inf, self.log_prior(y))
         lly = np.asarray(self.logl_fn(y), dtype=np.float64)
         ru = philox4x32_10(_ctr(s, TAG_FLOWU, np.arange(W)), self.key)
         with np.errstate(invalid="ignore"):
-            la = self.beta[0] * (lly - self.logl[0]) + (lpy - self.logp[0]) + (lqx - lqy)
+            la = self.beta[0] * (lly - self.logl[0]) + (lpy - self.logp[0]) + ((lqx - lkx) - lqy)
             ok = (lpy > -np.inf) & ~np.isnan(lly) & (lly > -np.inf) & ~np.isnan(la) & (np.log(u01(ru[:, 0])) < la)
         self.X[0, ok] = y[ok]
         self.logl[0, ok] = lly[ok]

@@ -27,6 +27,7 @@ __host__ __device__ inline void philox4x32_10(uint32_t* c, uint32_t k0, uint32_t
 __host__ __device__ inline double u01(uint32_t u) { return ((double)u + 0.5) * 2.3283064365386963e-10; }
 
 // purposes (second counter word)
-constexpr uint32_t kTagMove = 0x100, kTagShift = 0x200, kTagSwap = 0x300, kTagFlowZ = 0x400, kTagFlowU = 0x500;
+constexpr uint32_t kTagMove = 0x100, kTagShift = 0x200, kTagSwap = 0x300, kTagFlowZ = 0x400, kTagFlowU = 0x500,
+                   kTagFlowC = 0x600;
 
 }  // namespace lt_rng

@@ -40,6 +40,12 @@ struct Dev {
   // flow move on the cold rung (beta_0 = 1)
   double *fy, *fqy, *fqx, *fylogl, *fylogp;
   int64_t *facc, *fprop;
+  // symmetry fold of the flow move: coordinate fold_i (-1: none) is mapped into the window
+  // [fold_c0, fold_c0 + fold_p) before the flow sees it; a proposal takes one of the copies
+  // y + k fold_p inside the prior range, uniformly
+  int fold_i;
+  double fold_p, fold_c0;
+  double *fxf, *flkx;       // folded cold positions [W][d]; log(number of copies) of each
 };
 
 __device__ inline void to_params(const Dev& D, const double* x, double* p) {
@@ -145,11 +151,58 @@ __global__ void k_accept(Dev D, int h) {
 }
 
 // flow proposals y (one per cold walker): prior and parameter rows
-__global__ void k_flow_prep(Dev D) {
+// copies v + k P of a folded value v inside [lo, hi]: k in [k_min, k_min + n)
+__device__ inline int fold_copies(double v, double P, double lo, double hi, double* k_min) {
+  const double a = ceil((lo - v) / P), b = floor((hi - v) / P);
+  *k_min = a;
+  return b >= a ? (int)(b - a) + 1 : 0;
+}
+
+// cold positions folded for the flow, and log(number of copies) of each
+__global__ void k_flow_fold(Dev D) {
+#pragma clang fp contract(off)
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.W) return;
-  const double* y = D.fy + (int64_t)k * D.d;
-  D.fylogp[k] = log_prior(D, y);
+  const double* x = D.X + (int64_t)k * D.d;
+  double* xf = D.fxf + (int64_t)k * D.d;
+  for (int i = 0; i < D.d; ++i) xf[i] = x[i];
+  double lk = 0.0;
+  if (D.fold_i >= 0) {
+    const int i = D.fold_i;
+    const double v = D.fold_c0 + ((x[i] - D.fold_c0) - D.fold_p * floor((x[i] - D.fold_c0) / D.fold_p));
+    xf[i] = v;
+    double km;
+    const int n = fold_copies(v, D.fold_p, D.lo[i], D.hi[i], &km);
+    lk = n > 0 ? log((double)n) : 0.0;
+  }
+  D.flkx[k] = lk;
+}
+
+// proposals: unfolded into a uniformly drawn copy (log q(y) less log(number of copies)), prior,
+// likelihood parameters
+__global__ void k_flow_prep(Dev D) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.W) return;
+  double* y = D.fy + (int64_t)k * D.d;
+  bool out = false;
+  if (D.fold_i >= 0) {
+    const int i = D.fold_i;
+    const double v = y[i];
+    double km;
+    const int n = (v >= D.fold_c0 && v < D.fold_c0 + D.fold_p) ? fold_copies(v, D.fold_p, D.lo[i], D.hi[i], &km) : 0;
+    if (n > 0) {
+      uint32_t c[4] = {(uint32_t)*D.step, kTagFlowC, (uint32_t)k, 0u};
+      philox4x32_10(c, D.k0, D.k1);
+      int j = (int)(u01(c[0]) * (double)n);
+      j = j < n - 1 ? j : n - 1;
+      y[i] = v + (km + (double)j) * D.fold_p;
+      D.fqy[k] -= log((double)n);
+    } else {
+      out = true;      // outside the fold window: no copy of it is proposed
+    }
+  }
+  D.fylogp[k] = out ? -INFINITY : log_prior(D, y);
   if (D.target == LT_TARGET_TDI) to_params(D, y, D.params + (int64_t)k * 16);
 }
 
@@ -161,7 +214,7 @@ __global__ void k_flow_accept(Dev D) {
   uint32_t c[4] = {(uint32_t)*D.step, kTagFlowU, (uint32_t)k, 0u};
   philox4x32_10(c, D.k0, D.k1);
   const double lly = D.fylogl[k], lpy = D.fylogp[k];
-  const double la = D.beta[0] * (lly - D.logl[k]) + (lpy - D.logp[k]) + (D.fqx[k] - D.fqy[k]);
+  const double la = D.beta[0] * (lly - D.logl[k]) + (lpy - D.logp[k]) + ((D.fqx[k] - D.flkx[k]) - D.fqy[k]);
   const bool ok = lpy > -INFINITY && !isnan(lly) && lly > -INFINITY && !isnan(la) && log(u01(c[0])) < la;
   if (ok) {
     const double* y = D.fy + (int64_t)k * D.d;
@@ -288,7 +341,9 @@ static lt_status record_step(lt_sampler* s, hipStream_t st) {
   if (s->flow) {
     const int W = s->cfg.n_walkers;
     S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st));
-    S_HIP(lt::flow_logq(s->flow, s->D.X, W, s->D.fqx, st));
+    hipLaunchKernelGGL(k_flow_fold, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
+    S_HIP(hipGetLastError());
+    S_HIP(lt::flow_logq(s->flow, s->D.fxf, W, s->D.fqx, st));
     hipLaunchKernelGGL(k_flow_prep, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());
     lt_status r = eval_logl(s, s->D.fy, W, s->D.fylogl, st);
@@ -338,6 +393,9 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
   Dev& D = s->D;
   D.T = T; D.W = W; D.d = d; D.kind = cfg->param_kind; D.target = cfg->target; D.n_gauss = cfg->n_gauss;
   D.a = cfg->stretch_a; D.t_c = cfg->t_c;
+  D.fold_i = -1;
+  D.fold_p = 1.0;
+  D.fold_c0 = 0.0;
   D.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
   D.k1 = (uint32_t)(cfg->seed >> 32);
   lt_status r = LT_OK;
@@ -350,7 +408,8 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
       (r = salloc(s, &D.acc, TW)) || (r = salloc(s, &D.prop, TW)) || (r = salloc(s, &D.sacc, TW)) ||
       (r = salloc(s, &D.sprop, TW)) || (r = salloc(s, &D.fy, (size_t)W * d)) || (r = salloc(s, &D.fqy, W)) ||
       (r = salloc(s, &D.fqx, W)) || (r = salloc(s, &D.fylogl, W)) || (r = salloc(s, &D.fylogp, W)) ||
-      (r = salloc(s, &D.facc, W)) || (r = salloc(s, &D.fprop, W))) {
+      (r = salloc(s, &D.facc, W)) || (r = salloc(s, &D.fprop, W)) || (r = salloc(s, &D.fxf, (size_t)W * d)) ||
+      (r = salloc(s, &D.flkx, W))) {
     lt_sampler_destroy(s);
     return r;
   }
@@ -461,6 +520,23 @@ lt_status lt_sampler_set_flow(lt_sampler* s, lt_flow* flow) {
   s->exec = nullptr;
   s->graph = nullptr;
   s->flow = flow;
+  return LT_OK;
+}
+
+lt_status lt_sampler_set_flow_fold(lt_sampler* s, int index, double period, double start) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  if (index < -1 || index >= s->cfg.dim) return sfail(LT_ERR_CONFIG, "fold index");
+  if (index >= 0 && !(period > 0.0 && std::isfinite(period) && std::isfinite(start)))
+    return sfail(LT_ERR_CONFIG, "fold period must be positive and finite, start finite");
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->exec = nullptr;
+  s->graph = nullptr;
+  s->D.fold_i = index;
+  s->D.fold_p = index >= 0 ? period : 1.0;
+  s->D.fold_c0 = index >= 0 ? start : 0.0;
   return LT_OK;
 }
 

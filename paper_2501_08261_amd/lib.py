@@ -91,6 +91,7 @@ _sig = {
     "lt_sampler_step": ([_P, ctypes.c_int, _P], ctypes.c_int),
     "lt_sampler_get_state": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "lt_sampler_set_flow": ([_P, _P], ctypes.c_int),
+    "lt_sampler_set_flow_fold": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_double], ctypes.c_int),
     "lt_sampler_flow_counts": ([_P, _P], ctypes.c_int),
     "lt_fisher": ([_P, _P, ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid),
                    ctypes.POINTER(Orbit), ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), _P], ctypes.c_int),
@@ -306,6 +307,10 @@ class Sampler:
         """Attach a Flow (None: detach) for independence moves on the cold rung."""
         _check(_lib.lt_sampler_set_flow(self.h, flow.h if flow is not None else None))
         self._flow = flow
+
+    def set_flow_fold(self, index, period=math.pi, start=0.0):
+        """Fold coordinate `index` (-1: none) into [start, start + period) for the flow move."""
+        _check(_lib.lt_sampler_set_flow_fold(self.h, int(index), float(period), float(start)))
 
     def flow_counts(self):
         import numpy as np

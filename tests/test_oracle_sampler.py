@@ -159,3 +159,65 @@ def test_package_autocorr_time_matches_oracle():
     for t in range(1, n):
         x[t] = rhos * x[t - 1] + e[t]
     assert np.allclose(autocorr_time(x), integrated_time(x), rtol=1e-9)
+
+
+def _fold_target(m0, s0, P, c0, lo0, hi0, with_copies):
+    """log density in x0 of N(fold(x0); m0, s0) on [lo0, hi0], fold into [c0, c0 + P);
+    with_copies: divided by the number of copies of fold(x0) in the range (then it equals
+    the density the folded flow move proposes, copies chosen uniformly)."""
+    def f(x):
+        v = c0 + ((x[:, 0] - c0) - P * np.floor((x[:, 0] - c0) / P))
+        out = -0.5 * ((v - m0) / s0) ** 2 - 0.5 * x[:, 1] ** 2
+        if with_copies:
+            n = np.floor((hi0 - v) / P) - np.ceil((lo0 - v) / P) + 1
+            out = out - np.log(n)
+        return out
+    return f
+
+
+def test_flow_fold_exact_proposal_always_accepted():
+    """P29: with the fold, a flow equal to the folded target accepts every proposal inside the
+    window and rejects the rest (the copy count differs across the range: a move that dropped
+    the -ln n terms would reject some)."""
+    P, c0, lo0, hi0 = 2.0, -1.0, -2.0, 1.5
+    m, sd = np.array([0.2, 0.0]), np.array([0.4, 1.0])
+    s = PTSampler(_fold_target(m[0], sd[0], P, c0, lo0, hi0, True), [lo0, -50], [hi0, 50], 16, 1, 2, seed=21)
+    rng = np.random.default_rng(1)
+    s.set_state(np.stack([rng.uniform(-0.9, 0.9, 16), rng.normal(size=16)], 1)[None])
+    s.set_flow(_identity_flow(2), m, sd)
+    s.set_flow_fold(0, P, c0)
+    expect = 0
+    for _ in range(20):
+        yf = m[0] + sd[0] * s.flow_normals(s.step_count)[:, 0]
+        expect += int(np.sum((yf >= c0) & (yf < c0 + P)))
+        s.step()
+    assert s.fprop == 320 and 0 < s.fprop - expect
+    assert s.facc == expect
+
+
+def test_flow_fold_keeps_the_target():
+    """P29: with the fold and a mismatched flow, the chain spreads over the copies of the
+    symmetric target with the target's masses (two modes 5 sd apart: the stretch moves alone
+    rarely cross)."""
+    from scipy.stats import norm
+    P, c0, lo0, hi0 = 2.0, -1.0, -2.0, 1.5
+    m0, s0 = 0.2, 0.4
+    s = PTSampler(_fold_target(m0, s0, P, c0, lo0, hi0, False), [lo0, -50], [hi0, 50], 32, 1, 2, seed=23)
+    rng = np.random.default_rng(2)
+    s.set_state(np.stack([m0 + s0 * rng.normal(size=32), rng.normal(size=32)], 1)[None])
+    s.set_flow(_identity_flow(2), np.array([0.0, 0.5]), np.array([0.6, 1.5]))
+    s.set_flow_fold(0, P, c0)
+    chain = []
+    for i in range(3000):
+        s.step()
+        if i >= 200:
+            chain.append(s.X[0, :, 0].copy())
+    x = np.array(chain)
+    cdf = lambda a, b: norm.cdf(b, m0, s0) - norm.cdf(a, m0, s0)
+    mass = np.array([cdf(0.0, 1.0), cdf(-1.0, 1.0), cdf(-1.0, -0.5)])     # x0 in [-2,-1), [-1,1), [1,1.5]
+    mass /= mass.sum()
+    frac = np.array([np.mean(x < -1.0), np.mean((x >= -1.0) & (x < 1.0)), np.mean(x >= 1.0)])
+    tau = integrated_time(x[:, :, None]).max()
+    err = np.sqrt(mass * (1 - mass) / (x.size / tau))
+    assert np.all(np.abs(frac - mass) < 5 * err + 1e-3), (frac, mass)
+    assert 0.2 < s.facc / s.fprop < 0.95
