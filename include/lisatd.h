@@ -53,7 +53,7 @@ typedef enum {
 typedef struct lt_ctx lt_ctx;   /* opaque: FFT plans, twiddles, orbit tables, scratch */
 
 enum { LT_FP64 = 0, LT_MIXED = 1 };                         /* lt_wf_cfg.precision */
-enum { LT_ORBIT_STATIC_EQUAL = 0, LT_ORBIT_KEPLER = 1 };    /* lt_orbit.kind */
+enum { LT_ORBIT_STATIC_EQUAL = 0, LT_ORBIT_KEPLER = 1, LT_ORBIT_TABLE = 2 };   /* lt_orbit.kind */
 enum { LT_CH_A = 1, LT_CH_E = 2, LT_CH_T = 4 };             /* lt_tdi_cfg.channels */
 enum { LT_MODE_22 = 1, LT_MODE_21 = 2, LT_MODE_33 = 4, LT_MODE_32 = 8, LT_MODE_44 = 16 };
 
@@ -72,8 +72,27 @@ typedef struct { int mode_mask; int precessing; double f_low, f_ref; int precisi
  * side arm_m centred at (au_m, 0, 0), plane inclined 60 deg; KEPLER: three
  * exact Keplerian ellipses (semi-major axis au_m, eccentricity
  * arm_m / (2 sqrt(3) au_m), inclination sqrt(3) times that), mean anomalies
- * offset by 2 pi/3, guiding centre at longitude phase0 at time t_ref. */
-typedef struct { int kind; double arm_m, au_m, phase0, t_ref; } lt_orbit;
+ * offset by 2 pi/3, guiding centre at longitude phase0 at time t_ref.
+ * TABLE: positions and light travel times sampled on a uniform time grid, as
+ * orbit files give them (the paper's unequal-arm runs read ESA files, Sec. II.B):
+ * pos [n_tab][3][3] (spacecraft 1..3, SSB x, y, z in m) and ltt [n_tab][6]
+ * (links 1, 2, 3, -1, -2, -3, light time in s for reception at that time) at
+ * times tab_t0 + j tab_dt, host memory.  Between samples both are interpolated
+ * with four-point Lagrange weights (samples j-1 .. j+2 around t); the receiver
+ * sits at the reception time t and the sender at t - L(t).  The table must cover
+ * the grid, with one sample interval and the longest light time to spare (else
+ * LT_ERR_CONFIG), and n_tab >= 4.  arm_m stays the nominal arm (PSD, halo bound;
+ * the table's light times must not exceed 1.01 arm_m / c); au_m, phase0, t_ref
+ * are unused.  The library reads the arrays during the call and caches the
+ * device node table under a hash of their contents; a sampler copies them. */
+typedef struct {
+  int kind;
+  double arm_m, au_m, phase0, t_ref;
+  int64_t n_tab;
+  double tab_t0, tab_dt;
+  const double* pos;
+  const double* ltt;
+} lt_orbit;
 
 /* TDI options (Sec. II.B): generation 15 (Eq. 2.9) or 20 (Eq. 2.10);
  * channels: OR of LT_CH_* used by the likelihood; taps: even Lagrange

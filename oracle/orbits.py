@@ -7,6 +7,9 @@ two analytic orbit kinds are defined here (reading of the orbit input):
 * "static": an exact equilateral triangle of side L, centroid at (1 AU, 0, 0),
   plane inclined 60 degrees to the ecliptic (normal tilted towards the Sun);
   every light travel time is exactly L / c.
+* "table": positions and light travel times sampled on a uniform time grid
+  (an orbit file), interpolated with four-point Lagrange weights on the
+  samples j-1 .. j+2 around t; receiver at t, sender at t - L(t).
 * "kepler": three exact heliocentric Keplerian ellipses with semi-major axis
   1 AU, eccentricity e = L / (2 sqrt(3) AU) and inclination sqrt(3) e (the
   first-order "cartwheel" parameters), perihelion longitudes and mean
@@ -32,11 +35,32 @@ def link_ends(l):
     return (s, r) if l > 0 else (r, s)
 
 
+def _table_interp(t, t0, dt, v):
+    """Four-point Lagrange interpolation of rows v[j] (time t0 + j dt) at times t: [len(t), ...]."""
+    x = (np.asarray(t, dtype=np.float64) - t0) / dt
+    j = np.floor(x)
+    if np.any(j < 1) or np.any(j + 2 > len(v) - 1):
+        raise ValueError("orbit table does not cover the requested times")
+    f = x - j
+    j = j.astype(np.int64)
+    w = [-f * (f - 1) * (f - 2) / 6.0, (f + 1) * (f - 1) * (f - 2) / 2.0, -(f + 1) * f * (f - 2) / 2.0,
+         (f + 1) * f * (f - 1) / 6.0]
+    out = 0.0
+    for m in range(4):
+        wm = w[m].reshape(w[m].shape + (1,) * (v.ndim - 1))
+        out = out + wm * v[j - 1 + m]
+    return out
+
+
 class Orbit:
-    def __init__(self, kind="static", arm=ARM_SI, au=AU_SI, phase0=0.0, t_ref=0.0):
-        if kind not in ("static", "kepler"):
+    def __init__(self, kind="static", arm=ARM_SI, au=AU_SI, phase0=0.0, t_ref=0.0, table=None):
+        if kind not in ("static", "kepler", "table"):
             raise ValueError(kind)
         self.kind, self.arm, self.au, self.phase0, self.t_ref = kind, arm, au, phase0, t_ref
+        if kind == "table":
+            self.tab_t0, self.tab_dt, pos, ltt = table
+            self.tab_pos = np.asarray(pos, dtype=np.float64)
+            self.tab_ltt = np.asarray(ltt, dtype=np.float64)
         self.ecc = arm / (2.0 * math.sqrt(3.0) * au)
         self.incl = math.sqrt(3.0) * self.ecc
         self.Omega = 2.0 * math.pi / YEAR_SI
@@ -44,6 +68,8 @@ class Orbit:
     def position(self, k, t):
         """Position [3, len(t)] of spacecraft k (1..3) at times t [s]."""
         t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+        if self.kind == "table":
+            return _table_interp(t, self.tab_t0, self.tab_dt, self.tab_pos[:, k - 1, :]).T
         sig = 2.0 * math.pi * (k - 1) / 3.0
         if self.kind == "static":
             rho = self.arm / math.sqrt(3.0)
@@ -68,6 +94,8 @@ class Orbit:
     def light_time(self, l, t):
         """Light travel time [s] of link l for reception time t."""
         t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+        if self.kind == "table":
+            return _table_interp(t, self.tab_t0, self.tab_dt, self.tab_ltt[:, LINK_LABELS.index(l)])
         if self.kind == "static":
             return np.full(t.shape, self.arm / C_SI)
         s, r = link_ends(l)

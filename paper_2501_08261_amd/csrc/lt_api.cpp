@@ -71,7 +71,9 @@ struct OrbitTab {
 struct lt_ctx {
   int device = 0;
   std::map<int64_t, std::unique_ptr<Plan>> plans;
-  std::map<std::tuple<int, double, double, double, double, double, double, int64_t>, std::unique_ptr<OrbitTab>> orbits;
+  std::map<std::tuple<int, double, double, double, double, double, double, int64_t, uint64_t>,
+           std::unique_ptr<OrbitTab>>
+      orbits;
   DevBuf tpl, work, partial, wperm, status, wave, nodes, refs;
   // two-slot pipeline of lt_tdi_loglike: the FFT of one chunk (memory bound) runs on
   // `aux` while the response of the next (VALU bound) runs on the caller's stream
@@ -220,7 +222,37 @@ static void link_ends(int l, int* s, int* r) {
   if (l > 0) { *s = a; *r = b; } else { *s = b; *r = a; }
 }
 
+// four-point Lagrange weights of a uniform table at time t: samples j0 .. j0 + 3 around t
+// (false outside the table)
+static bool tab_weights(const lt_orbit& o, double t, int64_t* j0, double* w) {
+  const double x = (t - o.tab_t0) / o.tab_dt;
+  const double fj = std::floor(x);
+  if (!(fj >= 1.0 && fj + 2.0 <= (double)(o.n_tab - 1))) return false;
+  const double f = x - fj;
+  const double fm1 = f - 1.0, fm2 = f - 2.0, fp1 = f + 1.0;
+  w[0] = -f * fm1 * fm2 * (1.0 / 6.0);
+  w[1] = fp1 * fm1 * fm2 * 0.5;
+  w[2] = -fp1 * f * fm2 * 0.5;
+  w[3] = fp1 * f * fm1 * (1.0 / 6.0);
+  *j0 = (int64_t)fj - 1;
+  return true;
+}
+
+// interpolated table column: v[(j) * stride + col]
+static double tab_value(const lt_orbit& o, const double* v, int stride, int col, double t) {
+  int64_t j0 = 0;
+  double w[4];
+  tab_weights(o, t, &j0, w);   // coverage checked before any evaluation
+  double a = 0.0;
+  for (int m = 0; m < 4; ++m) a += w[m] * v[(j0 + m) * stride + col];
+  return a;
+}
+
 static void sc_position(const lt_orbit& o, int k, double t, double* r) {
+  if (o.kind == LT_ORBIT_TABLE) {
+    for (int q = 0; q < 3; ++q) r[q] = tab_value(o, o.pos, 9, (k - 1) * 3 + q, t);
+    return;
+  }
   const double sig = 2.0 * M_PI * (k - 1) / 3.0;
   if (o.kind == LT_ORBIT_STATIC_EQUAL) {
     const double rho = o.arm_m / std::sqrt(3.0);
@@ -253,6 +285,12 @@ static double light_time(const lt_orbit& o, int l, double t, double* rr, double*
   int s, r;
   link_ends(l, &s, &r);
   sc_position(o, r, t, rr);
+  if (o.kind == LT_ORBIT_TABLE) {
+    const int li = l > 0 ? l - 1 : 2 - l;   // column of link l: 1, 2, 3, -1, -2, -3
+    const double L = tab_value(o, o.ltt, 6, li, t);
+    sc_position(o, s, t - L, rs);
+    return L;
+  }
   if (o.kind == LT_ORBIT_STATIC_EQUAL) {
     sc_position(o, s, t, rs);
     return o.arm_m / kC;
@@ -275,8 +313,28 @@ static double light_time(const lt_orbit& o, int l, double t, double* rr, double*
 static constexpr int kNodeSpacing = 256;
 static constexpr int kNodeJ0 = 2;
 
+// FNV-1a over the bytes of a table orbit's arrays (0 for the analytic kinds)
+static uint64_t orbit_hash(const lt_orbit* o) {
+  if (o->kind != LT_ORBIT_TABLE) return 0;
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(&o->n_tab, sizeof(o->n_tab));
+  mix(&o->tab_t0, sizeof(double));
+  mix(&o->tab_dt, sizeof(double));
+  mix(o->pos, (size_t)o->n_tab * 9 * sizeof(double));
+  mix(o->ltt, (size_t)o->n_tab * 6 * sizeof(double));
+  return h;
+}
+
 static lt_status get_orbit(lt_ctx* c, const lt_orbit* o, const lt_grid* g, OrbitDev* out) {
-  auto key = std::make_tuple(o->kind, o->arm_m, o->au_m, o->phase0, o->t_ref, g->t0, g->dt, (int64_t)g->n);
+  auto key = std::make_tuple(o->kind, o->arm_m, o->au_m, o->phase0, o->t_ref, g->t0, g->dt, (int64_t)g->n,
+                             orbit_hash(o));
   auto it = c->orbits.find(key);
   if (it != c->orbits.end()) {
     *out = it->second->dev;
@@ -285,6 +343,17 @@ static lt_status get_orbit(lt_ctx* c, const lt_orbit* o, const lt_grid* g, Orbit
   const int64_t ntile = (g->n + tdi_tile() - 1) / tdi_tile();
   const int64_t last = ntile * tdi_tile() - 1;
   const int n_nodes = (int)(last / kNodeSpacing + 3 + kNodeJ0 + 2);
+  if (o->kind == LT_ORBIT_TABLE) {
+    // every node time, and every emission time up to the longest light time before it
+    double maxL = 0.0;
+    for (int64_t j = 0; j < o->n_tab * 6; ++j) maxL = std::fmax(maxL, o->ltt[j]);
+    const double t_lo = g->t0 + (double)((int64_t)(0 - kNodeJ0) * kNodeSpacing) * g->dt - maxL;
+    const double t_hi = g->t0 + (double)((int64_t)(n_nodes - 1 - kNodeJ0) * kNodeSpacing) * g->dt;
+    int64_t j0;
+    double w[4];
+    if (!tab_weights(*o, t_lo, &j0, w) || !tab_weights(*o, t_hi, &j0, w))
+      return fail(LT_ERR_CONFIG, "orbit table does not cover the grid (nodes, light times and one interval)");
+  }
   std::vector<double> tab((size_t)n_nodes * kNodeStride);
   double maxL = 0.0;
   for (int j = 0; j < n_nodes; ++j) {
@@ -431,8 +500,20 @@ static lt_status check_common(lt_ctx* c, const double* params, int64_t batch, co
 
 static lt_status check_tdi(const lt_orbit* o, const lt_tdi_cfg* t, const lt_grid* g) {
   if (!o || !t) return fail(LT_ERR_NULL, "null orbit or tdi config");
-  if (o->kind != LT_ORBIT_STATIC_EQUAL && o->kind != LT_ORBIT_KEPLER) return fail(LT_ERR_UNSUPPORTED, "orbit kind");
-  if (!(o->arm_m > 0.0) || !(o->au_m > 0.0) || o->arm_m > 0.1 * o->au_m) return fail(LT_ERR_CONFIG, "bad arm / au");
+  if (o->kind != LT_ORBIT_STATIC_EQUAL && o->kind != LT_ORBIT_KEPLER && o->kind != LT_ORBIT_TABLE)
+    return fail(LT_ERR_UNSUPPORTED, "orbit kind");
+  if (o->kind == LT_ORBIT_TABLE) {
+    if (!o->pos || !o->ltt) return fail(LT_ERR_NULL, "orbit table arrays");
+    if (o->n_tab < 4 || !(o->tab_dt > 0.0) || !std::isfinite(o->tab_t0)) return fail(LT_ERR_CONFIG, "orbit table grid");
+    if (!(o->arm_m > 0.0)) return fail(LT_ERR_CONFIG, "bad arm");
+    for (int64_t j = 0; j < o->n_tab * 6; ++j)
+      if (!(o->ltt[j] > 0.0 && o->ltt[j] <= 1.01 * o->arm_m / kC))
+        return fail(LT_ERR_CONFIG, "orbit table light times must lie in (0, 1.01 arm_m / c]");
+    for (int64_t j = 0; j < o->n_tab * 9; ++j)
+      if (!std::isfinite(o->pos[j])) return fail(LT_ERR_CONFIG, "orbit table positions must be finite");
+  } else if (!(o->arm_m > 0.0) || !(o->au_m > 0.0) || o->arm_m > 0.1 * o->au_m) {
+    return fail(LT_ERR_CONFIG, "bad arm / au");
+  }
   if (t->generation != 15 && t->generation != 20) return fail(LT_ERR_CONFIG, "generation must be 15 or 20");
   int K = t->taps;
   if (!(K == 2 || K == 4 || K == 6 || K == 8 || K == 12 || K == 16 || K == 24 || K == 32))

@@ -279,6 +279,7 @@ struct lt_sampler {
   lt_wf_cfg wf{};
   lt_grid grid{};
   lt_orbit orbit{};
+  std::vector<double> orbit_pos, orbit_ltt;   // owned copy of a table orbit's arrays
   lt_tdi_cfg tdi{};
   lt_psd psd{};
   lt_data data{};
@@ -384,6 +385,12 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
   s->cfg = *cfg;
   if (cfg->target == LT_TARGET_TDI) {
     s->wf = *wf; s->grid = *grid; s->orbit = *orbit; s->tdi = *tdi; s->psd = *psd; s->data = *data;
+    if (orbit->kind == LT_ORBIT_TABLE && orbit->pos && orbit->ltt && orbit->n_tab > 0) {
+      s->orbit_pos.assign(orbit->pos, orbit->pos + orbit->n_tab * 9);
+      s->orbit_ltt.assign(orbit->ltt, orbit->ltt + orbit->n_tab * 6);
+      s->orbit.pos = s->orbit_pos.data();
+      s->orbit.ltt = s->orbit_ltt.data();
+    }
     if (lt_ctx_create(hip_device, &s->ctx) != LT_OK) {
       delete s;
       return sfail(LT_ERR_DEVICE, "context");

@@ -117,3 +117,73 @@ def draw_templates(seed, batch, g, precessing, before_end=2000.0):
 def random_series(seed, shape, scale=1.0):
     rng = np.random.Generator(np.random.PCG64(seed))
     return scale * rng.standard_normal(shape)
+
+
+def colored_noise(seed, S, dt):
+    """Stationary Gaussian noise [3][n] with one-sided PSDs S [3][n/2+1] (bin 0 ignored).
+
+    Drawn in the frequency domain with E|n~_k|^2 = S_k / (2 df), n~ = dt * DFT(n), df = 1/(n dt):
+    real and imaginary parts N(0, S_k / (4 df)) for 0 < k < n/2, a real Nyquist bin of
+    variance S / (2 df), no DC; then n = inverse real DFT of n~ / dt.  With the inner product
+    (a|b) = 4 df Re sum a~ conj(b~) / S, each band bin adds a chi-square with two degrees of
+    freedom to (n|n): mean 2 per bin."""
+    S = np.asarray(S, dtype=np.float64)
+    nb = S.shape[-1]
+    n = 2 * (nb - 1)
+    df = 1.0 / (n * dt)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    re = rng.standard_normal((3, nb))
+    im = rng.standard_normal((3, nb))
+    sig = np.zeros_like(S)
+    sig[:, 1:] = np.sqrt(S[:, 1:] / (4.0 * df))
+    nf = sig * (re + 1j * im)
+    nf[:, 0] = 0.0
+    nf[:, -1] = np.sqrt(2.0) * sig[:, -1] * re[:, -1]
+    return np.fft.irfft(nf / dt, n=n, axis=-1)
+
+
+# synthetic orbit files: published constants (c by definition, the IAU astronomical unit,
+# one sidereal year) and the nominal LISA arm
+_C, _AU, _YEAR, _ARM = 299792458.0, 1.495978707e11, 31558149.763545603, 2.5e9
+
+
+def orbit_table(t0, dt, n, arm=_ARM, au=_AU, phase0=0.0, t_ref=0.0):
+    """A synthetic orbit file on the times t0 + j dt, j < n, in the layout of
+    lt_orbit's table kind: positions [n][3][3] (spacecraft 1..3, x y z in m) and light
+    times [n][6] (links 1, 2, 3, -1, -2, -3, for reception at each time).
+
+    The spacecraft fly first-order "cartwheel" Keplerian ellipses around the Sun
+    (semi-major axis au, eccentricity arm / (2 sqrt(3) au), inclination sqrt(3) times
+    the eccentricity, mean anomalies and perihelion longitudes 2 pi / 3 apart); Kepler's
+    equation is solved by Newton's method, and each light time L by iterating
+    L = |r_receiver(t) - r_sender(t - L)| / c.  Link l: sender (|l| + 1) mod 3 + 1 and
+    receiver |l| mod 3 + 1 for l > 0, swapped for l < 0.
+    Returns (t0, dt, pos, ltt)."""
+    t = t0 + dt * np.arange(n, dtype=np.float64)
+    e = arm / (2.0 * math.sqrt(3.0) * au)
+    inc = math.sqrt(3.0) * e
+
+    def pos(k, tt):
+        sig = 2.0 * math.pi * (k - 1) / 3.0
+        M = 2.0 * math.pi / _YEAR * (tt - t_ref) + phase0 - sig
+        E = M.copy()
+        for _ in range(60):
+            E = E - (E - e * np.sin(E) - M) / (1.0 - e * np.cos(E))
+        xo = au * (np.cos(E) - e)
+        yo = au * math.sqrt(1.0 - e * e) * np.sin(E)
+        x1, z1 = xo * math.cos(inc), xo * math.sin(inc)
+        return np.stack([math.cos(sig) * x1 - math.sin(sig) * yo, math.sin(sig) * x1 + math.cos(sig) * yo, z1], -1)
+
+    P = np.stack([pos(k, t) for k in (1, 2, 3)], 1)                 # [n][3][3]
+    L = np.zeros((n, 6))
+    for c, l in enumerate((1, 2, 3, -1, -2, -3)):
+        a = abs(l)
+        s, r = (a + 1) % 3 + 1, a % 3 + 1
+        if l < 0:
+            s, r = r, s
+        rr = P[:, r - 1]
+        Ll = np.linalg.norm(rr - P[:, s - 1], axis=-1) / _C
+        for _ in range(30):
+            Ll = np.linalg.norm(rr - pos(s, t - Ll), axis=-1) / _C
+        L[:, c] = Ll
+    return t0, dt, P, L

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblisatd.so")
 
 LT_FP64, LT_MIXED = 0, 1
-LT_ORBIT_STATIC_EQUAL, LT_ORBIT_KEPLER = 0, 1
+LT_ORBIT_STATIC_EQUAL, LT_ORBIT_KEPLER, LT_ORBIT_TABLE = 0, 1, 2
 LT_CH_A, LT_CH_E, LT_CH_T = 1, 2, 4
 MODE_BITS = {(2, 2): 1, (2, 1): 2, (3, 3): 4, (3, 2): 8, (4, 4): 16}
 MODE_ORDER = ((2, 2), (2, 1), (3, 3), (3, 2), (4, 4))
@@ -39,7 +39,9 @@ class WfCfg(ctypes.Structure):
 
 class Orbit(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("arm_m", ctypes.c_double), ("au_m", ctypes.c_double),
-                ("phase0", ctypes.c_double), ("t_ref", ctypes.c_double)]
+                ("phase0", ctypes.c_double), ("t_ref", ctypes.c_double), ("n_tab", ctypes.c_int64),
+                ("tab_t0", ctypes.c_double), ("tab_dt", ctypes.c_double), ("pos", ctypes.c_void_p),
+                ("ltt", ctypes.c_void_p)]
 
 
 class TdiCfg(ctypes.Structure):
@@ -184,7 +186,18 @@ class Context:
         return WfCfg(mode_mask(modes), int(precessing), f_low, f_ref, precision)
 
     @staticmethod
-    def orbit(kind="static", arm=ARM_M, au=AU_M, phase0=0.0, t_ref=0.0):
+    def orbit(kind="static", arm=ARM_M, au=AU_M, phase0=0.0, t_ref=0.0, table=None):
+        """kind "static", "kepler" or "table"; table = (t0, dt, pos [n][3][3] m, ltt [n][6] s)."""
+        if kind == "table":
+            import numpy as np
+            t0, dt, pos, ltt = table
+            pos = np.ascontiguousarray(pos, dtype=np.float64)
+            ltt = np.ascontiguousarray(ltt, dtype=np.float64)
+            if pos.ndim != 3 or pos.shape[1:] != (3, 3) or ltt.shape != (pos.shape[0], 6):
+                raise ValueError("table: pos [n][3][3], ltt [n][6]")
+            o = Orbit(LT_ORBIT_TABLE, arm, au, phase0, t_ref, pos.shape[0], t0, dt, pos.ctypes.data, ltt.ctypes.data)
+            o._keep = (pos, ltt)          # the arrays live as long as the struct
+            return o
         k = LT_ORBIT_STATIC_EQUAL if kind == "static" else LT_ORBIT_KEPLER
         return Orbit(k, arm, au, phase0, t_ref)
 

@@ -117,6 +117,39 @@ def test_tdi_parity(lt, orbit, gen, taps, precessing):
         _assert_aet(got[b], want, 1e-9, b)
 
 
+@pytest.mark.parametrize("gen,taps,precessing", [(20, 8, True), (15, 2, False)])
+def test_tdi_parity_orbit_table(lt, gen, taps, precessing):
+    """N4: an orbit file (hourly positions and light times, Keplerian ellipses sampled by the
+    input generator) read through the table orbit kind: FP64 response against the oracle on
+    the same table, and close to the analytic Kepler orbit it samples (the table's
+    interpolation moves positions by ~1 mm and light times by < 1e-11 s)."""
+    lib, ctx = lt
+    n = 5000                                    # ragged last tile
+    g = inputs.grid(n, 5.0)
+    tab = inputs.orbit_table(-86400.0, 3600.0, 60)
+    P = inputs.draw_templates(300 + taps, 3, g, precessing=precessing, before_end=1000.0)
+    outs = []
+    for orb in (ctx.orbit("table", table=tab), ctx.orbit("kepler")):
+        out = torch.zeros((P.shape[0], 3, n), dtype=torch.float64, device=DEV)
+        st = torch.full((P.shape[0],), -7, dtype=torch.int32, device=DEV)
+        ctx.lisa_tdi_response(_dev(P), g, ctx.wf_cfg(MODES_ALL, precessing), orb, ctx.tdi_cfg(gen, 7, taps), out, st)
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() == 0)
+        outs.append(out.cpu().numpy())
+    for b in range(P.shape[0]):
+        r = Response(Template(P[b]), g["t0"], g["dt"], n, OOrbit("table", table=tab), taps=taps, modes=MODES_ALL,
+                     precessing=precessing, generation=gen)
+        r.cache_full_grid()
+        want = np.array(r.aet(np.arange(n)))
+        _assert_aet(outs[0][b], want, 1e-9, b)
+        _assert_aet(outs[0][b], outs[1][b], 1e-6, b)
+    short = inputs.orbit_table(-86400.0, 3600.0, 20)          # ends before the grid does
+    with pytest.raises(lib.LisaTDError):
+        ctx.lisa_tdi_response(_dev(P), g, ctx.wf_cfg(MODES_ALL, precessing), ctx.orbit("table", table=short),
+                              ctx.tdi_cfg(gen, 7, taps), torch.zeros((P.shape[0], 3, n), dtype=torch.float64,
+                                                                     device=DEV))
+
+
 # Mixed precision (FP32 response and TDI, FP64 times and delays): the output
 # error is set by FP32 rounding of h, which y = h(t_s) - h(t_r) turns into an
 # absolute error of order u max|h| (u = 2^-24) whatever the size of y, and
@@ -287,6 +320,46 @@ def test_single_template_loglike(lt):
         assert abs(gl[0] - l0) < tol
         assert abs(gl[1] - l1) < tol and abs(gf[1] - f1) < tol
         assert np.all(st.cpu().numpy() == 0)
+
+
+def test_noisy_data_loglike(lt):
+    """N3: Gaussian noise drawn from the PSD added to the injection (one-day case, static arms,
+    TDI 1.5, K = 8, FP64): logL and logL_full of the injection and a template against the
+    oracle on the same noisy data, and logL_full at the injection equals -(n|n)/2."""
+    lib, ctx = lt
+    g, inj, tmpl = inputs.single_template_case()
+    S = _psd_dev(lib, g, 15)
+    Snp = olk.channel_psds(g["n"], g["dt"], 15)
+    noise = inputs.colored_noise(31, S.cpu().numpy(), g["dt"])
+    cfg = ctx.wf_cfg(((2, 2),))
+    orb, tdi = ctx.orbit("static"), ctx.tdi_cfg(15, 7, 8)
+    h = torch.zeros((1, 3, g["n"]), dtype=torch.float64, device=DEV)
+    ctx.lisa_tdi_response(_dev(inj[None]), g, cfg, orb, tdi, h)
+    nz = _dev(noise[None])
+    d = h + nz
+    dd = torch.zeros(1, dtype=torch.float64, device=DEV)
+    nn = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ctx.noise_inner(d, g, S, dd)
+    ctx.noise_inner(nz, g, S, nn)
+    logl = torch.zeros(2, dtype=torch.float64, device=DEV)
+    full = torch.zeros(2, dtype=torch.float64, device=DEV)
+    st = torch.zeros(2, dtype=torch.int32, device=DEV)
+    ctx.tdi_loglike(_dev(np.stack([inj, tmpl])), g, cfg, orb, tdi, S, d[0], float(dd.item()), logl, full, st)
+    torch.cuda.synchronize()
+    od = _oracle_aet(inj, g, "static", 8, ((2, 2),), False, 15)
+    oh = _oracle_aet(tmpl, g, "static", 8, ((2, 2),), False, 15)
+    dn = od + noise
+    want_dd = olk.noise_inner(dn, Snp, g["dt"])
+    want_nn = olk.noise_inner(noise, Snp, g["dt"])
+    tol = 1e-6 + 1e-11 * want_dd
+    assert abs(dd.item() - want_dd) < 1e-11 * want_dd
+    assert abs(nn.item() - want_nn) < 1e-11 * want_nn
+    gl, gf = logl.cpu().numpy(), full.cpu().numpy()
+    for j, oo in enumerate((od, oh)):
+        l, f = olk.loglike(dn, oo, Snp, g["dt"])
+        assert abs(gl[j] - l) < tol and abs(gf[j] - f) < tol, j
+    assert abs(gf[0] + 0.5 * nn.item()) < 1e-6 + 1e-11 * nn.item()
+    assert np.all(st.cpu().numpy() == 0)
 
 
 @pytest.mark.parametrize("precision", [0, 1])

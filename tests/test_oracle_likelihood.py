@@ -69,3 +69,46 @@ def test_snr_order_of_magnitude():
     aet = np.array(r.aet(np.arange(g["n"])))
     snr = math.sqrt(lk.noise_inner(aet, lk.channel_psds(g["n"], g["dt"]), g["dt"]))
     assert 500 < snr < 20000
+
+
+def test_colored_noise_matches_its_psd():
+    """N3 input: noise drawn from the PSD gives (n|n) = sum of chi-square(2) over the band
+    (mean 2 per bin, standard deviation 2 sqrt(bins)), per channel, over several draws."""
+    from paper_2501_08261_amd import inputs
+    n, dt = 1 << 14, 5.0
+    S = lk.channel_psds(n, dt, 20)
+    k_lo, k_hi = lk.band(n, dt, 3e-4, 0.02)
+    nbins = k_hi - k_lo + 1
+    vals = []
+    for seed in range(8):
+        x = inputs.colored_noise(seed, S, dt)
+        for c in range(3):
+            xf = lk.rfft_dt(x[c], dt)
+            vals.append(lk.inner(xf, xf, S[c], k_lo, k_hi, 1.0 / (n * dt)))
+    vals = np.array(vals) / nbins
+    assert abs(vals.mean() - 2.0) < 5 * 2.0 / np.sqrt(nbins * len(vals))
+    assert abs(vals.std() - 2.0 / np.sqrt(nbins)) < 0.6 * 2.0 / np.sqrt(nbins)
+
+
+def test_orbit_table_reproduces_kepler():
+    """N4: an orbit file sampled every hour from Keplerian ellipses (the input generator's own
+    implementation), read by the table orbit's four-point Lagrange interpolation, against the
+    oracle's analytic Kepler orbit: positions within the interpolation error bound
+    max|r''''| (9/16) h^4 / 4!, where the ellipse's second harmonic (amplitude ~ 3 a e / 2 at
+    2 omega) adds 24 e to |r''''| / (a omega^4) = 1 (bound taken with 30 e), plus 1e-4 m of
+    rounding on 1.5e11 m coordinates; light times within 1e-11 s."""
+    from paper_2501_08261_amd import inputs
+    from oracle.phys import AU_SI, YEAR_SI
+    h = 3600.0
+    tab = inputs.orbit_table(-86400.0, h, 240)
+    ot, ok = Orbit("table", table=tab), Orbit("kepler")
+    t = np.linspace(0.0, 6e5, 1001)
+    om = 2.0 * math.pi / YEAR_SI
+    ecc = 2.5e9 / (2.0 * math.sqrt(3.0) * AU_SI)
+    bound = AU_SI * om ** 4 * (1.0 + 30.0 * ecc) * (9.0 / 16.0) * h ** 4 / 24.0 + 1e-4
+    for k in (1, 2, 3):
+        assert np.max(np.abs(ot.position(k, t) - ok.position(k, t))) < bound
+    for l in (1, 2, 3, -1, -2, -3):
+        assert np.max(np.abs(ot.light_time(l, t) - ok.light_time(l, t))) < 1e-11
+    with pytest.raises(ValueError):
+        ot.position(1, np.array([-86400.0 + 0.5 * h]))      # before the second sample: not covered
