@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--n", type=int, default=N_SAMPLES)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--coarse", type=int, choices=[1, 2], default=1,
+                    help="2: waveform on every second sample, linear in between (paper's 10 s -> 5 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-sampler", action="store_true", help="skip the sampler-step and ESS measurements")
@@ -255,6 +257,17 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     sd = res["plain"]["std"]
     shift = float(np.max(np.abs(res["learned"]["mean"] - res["plain"]["mean"]) / sd))
     std_ratio = (res["learned"]["std"] / sd).tolist()
+    # Fisher widths at the injection against the MCMC widths (the paper's Tabs. II-III compare
+    # the two): sqrt(diag(Gamma^-1)), eigenvalues floored at 1e-12 of the largest as for the draws
+    ev, V = np.linalg.eigh(G)
+    ev = np.maximum(ev, 1e-12 * ev.max())
+    sig_f = np.sqrt(np.diag((V / ev) @ V.T))
+    names = (["m1", "m2", "a1", "theta1", "phi1", "a2", "theta2", "phi2"] if precessing else
+             ["m1", "m2", "chi1z", "chi2z"]) + ["D_L", "iota", "phi_ref", "beta", "lambda", "psi"]
+    fisher = {"names": names, "sigma_fisher": [float("%.4g" % v) for v in sig_f],
+              "sigma_mcmc": [float("%.4g" % v) for v in sd],
+              "mcmc_over_fisher": [round(float(v), 3) for v in sd / sig_f],
+              "prior_width": [float("%.4g" % v) for v in (hi - lo)]}
     for v in res.values():
         del v["mean"], v["std"]
     smp.close()
@@ -264,7 +277,8 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
             "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": rounds * train_steps,
             "plain": res["plain"], "learned": res["learned"],
             "ratio": res["learned"]["ess_per_s"] / res["plain"]["ess_per_s"],
-            "posterior_mean_shift_sigma": shift, "posterior_std_ratio": [round(x, 3) for x in std_ratio]}
+            "posterior_mean_shift_sigma": shift, "posterior_std_ratio": [round(x, 3) for x in std_ratio],
+            "fisher_vs_mcmc": fisher}
 
 
 def main():
@@ -282,7 +296,7 @@ def main():
     g = inputs.grid(a.n, 5.0)
     ctx = lib.Context(0)
     modes = ((2, 2), (2, 1), (3, 3), (3, 2), (4, 4))
-    cfg = ctx.wf_cfg(modes, True, precision=prec)
+    cfg = ctx.wf_cfg(modes, True, precision=prec, coarse=a.coarse)
     orb = ctx.orbit("kepler")
     tdi = ctx.tdi_cfg(20, 7, TAPS)
     S = torch.zeros((3, a.n // 2 + 1), dtype=torch.float64, device=dev)
@@ -371,7 +385,8 @@ def main():
                                "K=%d Lagrange, batch %d uneven lengths" % (TAPS, a.batch),
                    "global_batch": a.batch, "seq_len": a.n, "parallelism": "single GPU",
                    "active_sample_fraction": active_frac,
-                   "precision": a.precision, "templates_valid": n_ok},
+                   "precision": a.precision, "waveform_grid": "every sample" if a.coarse == 1 else
+                   "every second sample, linear in between", "templates_valid": n_ok},
         "kernels_ms": kern,
         "roofline": roof,
     }

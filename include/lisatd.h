@@ -65,8 +65,14 @@ typedef struct { double t0, dt; int64_t n; } lt_grid;
  * (IMRPhenomT / THM form), 1 = twisted-up precessing (TP / TPHM form).
  * f_low: hard start of the (2,2) mode [Hz]; f_ref: reference frequency of the
  * orbital phase and spins [Hz].  precision: LT_FP64 or LT_MIXED (phase and
- * time FP64; stored polarisations, response, FFT FP32; reductions FP64). */
-typedef struct { int mode_mask; int precessing; double f_low, f_ref; int precision; } lt_wf_cfg;
+ * time FP64; stored polarisations, response, FFT FP32; reductions FP64).
+ * coarse: 0 or 1 evaluates the polarisations on every grid sample; 2 evaluates
+ * them on every second sample (even indices, a grid of step 2 dt) and takes
+ * the mean of the two neighbours on the others (the paper's 10 s waveform grid
+ * linearly upsampled to 5 s, Sec. II.C): half the waveform work, at a relative
+ * error up to (2 pi f dt)^2 / 2 at frequency f.  Affects the polarisations,
+ * the response and the likelihood, not lt_phenomt_modes. */
+typedef struct { int mode_mask; int precessing; double f_low, f_ref; int precision; int coarse; } lt_wf_cfg;
 
 /* Spacecraft orbits (Sec. II.B).  STATIC_EQUAL: rigid equilateral triangle of
  * side arm_m centred at (au_m, 0, 0), plane inclined 60 deg; KEPLER: three

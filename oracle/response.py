@@ -103,9 +103,13 @@ class Response:
     """One template on one grid with one orbit (hot-path steps a4-a8)."""
 
     def __init__(self, tpl, t0, dt, N, orbit, taps=2, modes=MODES_ALL, precessing=False,
-                 generation=15, hfun=None, sky=None):
+                 generation=15, hfun=None, sky=None, coarse=1):
         """hfun: optional callable t -> (h+, hx) replacing the waveform (used by
-        the plane-wave checks); sky: optional (lambda, beta) overriding tpl's."""
+        the plane-wave checks); sky: optional (lambda, beta) overriding tpl's;
+        coarse = 2: the polarisations on the grid are the waveform on every second
+        sample (even indices) and the mean of the two neighbours on the others
+        (linear interpolation from a grid of twice the step, Sec. II.C)."""
+        self.coarse = int(coarse)
         self.tpl, self.t0, self.dt, self.N = tpl, float(t0), float(dt), int(N)
         self.hfun = hfun
         self.orbit, self.K, self.modes = orbit, int(taps), modes
@@ -124,9 +128,20 @@ class Response:
         idx = np.asarray(idx, dtype=np.int64)
         if self._hcache is not None:
             return self._hcache[0][idx], self._hcache[1][idx]
+        if self.coarse == 2:
+            lo = idx - (idx % 2)
+            a = self.h_exact(self.t0 + lo * self.dt)
+            b = self.h_exact(self.t0 + (lo + 2) * self.dt)
+            odd = (idx % 2) == 1
+            return tuple(np.where(odd, 0.5 * (a[q] + b[q]), a[q]) for q in range(2))
         return self.h_exact(self.t0 + idx * self.dt)
 
     def cache_full_grid(self):
+        if self.coarse == 2:
+            self._hcache = None
+            hp, hc = self.h_grid(np.arange(self.N))
+            self._hcache = (hp, hc)
+            return
         hp, hc = self.h_exact(self.t0 + np.arange(self.N) * self.dt)
         self._hcache = (hp, hc)
 

@@ -494,6 +494,7 @@ static lt_status check_common(lt_ctx* c, const double* params, int64_t batch, co
   if (cfg->precessing != 0 && cfg->precessing != 1) return fail(LT_ERR_CONFIG, "precessing must be 0 or 1");
   if (cfg->precision != LT_FP64 && cfg->precision != LT_MIXED) return fail(LT_ERR_CONFIG, "bad precision");
   if (!(cfg->f_low > 0.0) || !(cfg->f_ref > 0.0)) return fail(LT_ERR_CONFIG, "f_low and f_ref must be positive");
+  if (cfg->coarse < 0 || cfg->coarse > 2) return fail(LT_ERR_CONFIG, "coarse must be 0, 1 or 2");
   LT_HIP(hipSetDevice(c->device));
   return LT_OK;
 }
@@ -582,7 +583,8 @@ lt_status lt_phenomt_polarizations(lt_ctx* c, const double* params, int64_t batc
   st = do_setup(c, params, batch, cfg, g, nullptr, s);
   if (st) return st;
   Prof pr(c, 0, s);
-  LT_HIP(launch_polarizations((TplConst*)c->tpl.p, batch, cfg->mode_mask, cfg->precessing, gdev(g), hpc, s));
+  LT_HIP(launch_polarizations((TplConst*)c->tpl.p, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, gdev(g), hpc,
+                              s));
   return LT_OK;
 }
 
@@ -598,7 +600,8 @@ static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const l
   LT_HIP(c->wave.ensure((size_t)batch * 2 * g->n * rsz));
   {
     Prof pr(c, 0, s);
-    LT_HIP(launch_wave((const TplConst*)c->tpl.p, batch, cfg->mode_mask, cfg->precessing, cfg->precision, gdev(g),
+    LT_HIP(launch_wave((const TplConst*)c->tpl.p, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, cfg->precision,
+                       gdev(g),
                        c->wave.p, s));
   }
   TdiLaunch L;

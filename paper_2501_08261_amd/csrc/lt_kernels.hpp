@@ -36,11 +36,12 @@ hipError_t launch_setup(const double* params, int64_t batch, double f_low, doubl
                         TplConst* tc, int32_t* status, hipStream_t s);
 hipError_t launch_modes(const TplConst* tc, int64_t batch, int mode_mask, GridDev g, double* modes,
                         hipStream_t s);
-hipError_t launch_polarizations(const TplConst* tc, int64_t batch, int mode_mask, int precessing, GridDev g,
-                                double* hpc, hipStream_t s);
+// coarse 2: waveform on the even samples, odd samples the mean of their neighbours
+hipError_t launch_polarizations(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int coarse,
+                                GridDev g, double* hpc, hipStream_t s);
 // h: [batch][2][n], double (precision 0) or float (precision 1)
-hipError_t launch_wave(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int precision, GridDev g,
-                       void* h, hipStream_t s);
+hipError_t launch_wave(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int coarse, int precision,
+                       GridDev g, void* h, hipStream_t s);
 
 // out_mode: 0 write A,E,T; 1 write X,Y,Z; 2 write A,E,T minus data (residual)
 struct TdiLaunch {

@@ -69,9 +69,44 @@ __global__ __launch_bounds__(kNT) void k_wave(const TplConst* tc, int mode_mask,
   h[(2 * (int64_t)b + 1) * g.n + n] = -v.im;
 }
 
+// The same on a grid of twice the step: a workgroup evaluates the waveform at kNT even
+// samples 2m (m = m0 .. m0 + kNT - 1, LDS) and writes the fine samples 2m and 2m + 1 for
+// the first kNT - 1 of them, the odd one as the mean of its two neighbours.
+template <typename R, bool PREC>
+__global__ __launch_bounds__(kNT) void k_wave_coarse(const TplConst* tc, int mode_mask, GridDev g, R* h) {
+  __shared__ cx<R> hv[kNT];
+  const int b = blockIdx.y;
+  const int64_t m = (int64_t)blockIdx.x * (kNT - 1) + threadIdx.x;
+  const int64_t n = 2 * m;
+  const TplConst& c = tc[b];
+  cx<R> v{(R)0, (R)0};
+  if (c.valid != 0.0 && (double)n >= c.n_start - 1.0 && n <= g.n)
+    v = polarization_t<R, PREC>(c, mode_mask, g.t0 + (double)n * g.dt);
+  hv[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == kNT - 1) return;
+  const cx<R> w = hv[threadIdx.x + 1];
+  if (n < g.n) {
+    h[(2 * (int64_t)b) * g.n + n] = v.re;
+    h[(2 * (int64_t)b + 1) * g.n + n] = -v.im;
+  }
+  if (n + 1 < g.n) {
+    h[(2 * (int64_t)b) * g.n + n + 1] = (R)0.5 * (v.re + w.re);
+    h[(2 * (int64_t)b + 1) * g.n + n + 1] = -((R)0.5 * (v.im + w.im));
+  }
+}
+
 template <typename R>
-static hipError_t launch_wave_t(const TplConst* tc, int64_t batch, int mode_mask, int precessing, GridDev g, R* h,
-                                hipStream_t s) {
+static hipError_t launch_wave_t(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int coarse,
+                                GridDev g, R* h, hipStream_t s) {
+  if (coarse == 2) {
+    dim3 grid((unsigned)((g.n + 2 * (kNT - 1) - 1) / (2 * (kNT - 1))), (unsigned)batch);
+    if (precessing)
+      hipLaunchKernelGGL((k_wave_coarse<R, true>), grid, dim3(kNT), 0, s, tc, mode_mask, g, h);
+    else
+      hipLaunchKernelGGL((k_wave_coarse<R, false>), grid, dim3(kNT), 0, s, tc, mode_mask, g, h);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((g.n + kNT - 1) / kNT), (unsigned)batch);
   if (precessing)
     hipLaunchKernelGGL((k_wave<R, true>), grid, dim3(kNT), 0, s, tc, mode_mask, g, h);
@@ -80,15 +115,15 @@ static hipError_t launch_wave_t(const TplConst* tc, int64_t batch, int mode_mask
   return hipGetLastError();
 }
 
-hipError_t launch_polarizations(const TplConst* tc, int64_t batch, int mode_mask, int precessing, GridDev g,
-                                double* hpc, hipStream_t s) {
-  return launch_wave_t<double>(tc, batch, mode_mask, precessing, g, hpc, s);
+hipError_t launch_polarizations(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int coarse,
+                                GridDev g, double* hpc, hipStream_t s) {
+  return launch_wave_t<double>(tc, batch, mode_mask, precessing, coarse, g, hpc, s);
 }
 
-hipError_t launch_wave(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int precision, GridDev g,
-                       void* h, hipStream_t s) {
-  if (precision == 0) return launch_wave_t<double>(tc, batch, mode_mask, precessing, g, (double*)h, s);
-  return launch_wave_t<float>(tc, batch, mode_mask, precessing, g, (float*)h, s);
+hipError_t launch_wave(const TplConst* tc, int64_t batch, int mode_mask, int precessing, int coarse, int precision,
+                       GridDev g, void* h, hipStream_t s) {
+  if (precision == 0) return launch_wave_t<double>(tc, batch, mode_mask, precessing, coarse, g, (double*)h, s);
+  return launch_wave_t<float>(tc, batch, mode_mask, precessing, coarse, g, (float*)h, s);
 }
 
 // ------------------------------------------------------- Lagrange weights

@@ -34,7 +34,7 @@ class Grid(ctypes.Structure):
 
 class WfCfg(ctypes.Structure):
     _fields_ = [("mode_mask", ctypes.c_int), ("precessing", ctypes.c_int), ("f_low", ctypes.c_double),
-                ("f_ref", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("f_ref", ctypes.c_double), ("precision", ctypes.c_int), ("coarse", ctypes.c_int)]
 
 
 class Orbit(ctypes.Structure):
@@ -182,8 +182,9 @@ class Context:
         return Grid(g["t0"], g["dt"], g["n"])
 
     @staticmethod
-    def wf_cfg(modes=((2, 2),), precessing=False, f_low=1e-4, f_ref=1e-4, precision=LT_FP64):
-        return WfCfg(mode_mask(modes), int(precessing), f_low, f_ref, precision)
+    def wf_cfg(modes=((2, 2),), precessing=False, f_low=1e-4, f_ref=1e-4, precision=LT_FP64, coarse=1):
+        """coarse=2: waveform on every second sample, linear in between (see lt_wf_cfg)."""
+        return WfCfg(mode_mask(modes), int(precessing), f_low, f_ref, precision, int(coarse))
 
     @staticmethod
     def orbit(kind="static", arm=ARM_M, au=AU_M, phase0=0.0, t_ref=0.0, table=None):

@@ -97,6 +97,43 @@ def _oracle_aet(p, g, orbit, taps, modes, precessing, gen, xyz=False):
     return np.array(r.xyz(idx) if xyz else r.aet(idx))
 
 
+@pytest.mark.parametrize("precessing,n", [(False, 6001), (True, 5998)])
+def test_polarization_parity_coarse(lt, precessing, n):
+    """N2: the waveform on every second sample, the mean of the neighbours in between, against
+    the oracle's definition (odd and even grid lengths: the last odd sample needs the waveform
+    one step past the grid)."""
+    lib, ctx = lt
+    g = inputs.grid(n, 5.0)
+    P = inputs.draw_templates(7 + precessing, 6, g, precessing=precessing, before_end=1000.0)
+    out = torch.zeros((P.shape[0], 2, n), dtype=torch.float64, device=DEV)
+    ctx.phenomt_polarizations(_dev(P), g, ctx.wf_cfg(MODES_ALL, precessing, coarse=2), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for b in range(P.shape[0]):
+        r = Response(Template(P[b]), g["t0"], g["dt"], n, OOrbit("static"), modes=MODES_ALL, precessing=precessing,
+                     coarse=2)
+        hp, hc = r.h_grid(np.arange(n))
+        assert relerr(got[b, 0], hp) < 1e-9 and relerr(got[b, 1], hc) < 1e-9, b
+
+
+def test_tdi_parity_coarse(lt):
+    """N2: response and TDI from the coarse-grid waveform (FP64) against the oracle."""
+    lib, ctx = lt
+    n = 5000
+    g = inputs.grid(n, 5.0)
+    P = inputs.draw_templates(55, 3, g, precessing=True, before_end=1000.0)
+    out = torch.zeros((P.shape[0], 3, n), dtype=torch.float64, device=DEV)
+    ctx.lisa_tdi_response(_dev(P), g, ctx.wf_cfg(MODES_ALL, True, coarse=2), ctx.orbit("kepler"),
+                          ctx.tdi_cfg(20, 7, 8), out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for b in range(P.shape[0]):
+        r = Response(Template(P[b]), g["t0"], g["dt"], n, OOrbit("kepler"), taps=8, modes=MODES_ALL,
+                     precessing=True, generation=20, coarse=2)
+        r.cache_full_grid()
+        _assert_aet(got[b], np.array(r.aet(np.arange(n))), 1e-9, b)
+
+
 @pytest.mark.parametrize("orbit,gen,taps,precessing", [
     ("static", 15, 2, False), ("static", 15, 8, False), ("kepler", 20, 2, False),
     ("kepler", 20, 8, True), ("kepler", 20, 32, True), ("static", 20, 4, True), ("kepler", 15, 6, False)])

@@ -225,3 +225,17 @@ def test_interpolation_error_falls_with_taps(orbit):
     # amplified by the TDI cancellation X/h ~ 1e-3) is reached
     assert errs[0] > 100 * errs[1] > 100 * errs[2]
     assert errs[2] < 1e-8 and errs[3] < 1e-8
+
+
+def test_coarse_grid_closed_form():
+    """N2: on the coarse grid an odd sample is the mean of its neighbours; for a sinusoid
+    h = sin(w t) that is sin(w t) cos(w dt) exactly (and the even samples are untouched), which
+    also gives the method's error (1 - cos(w dt)) ~ (w dt)^2 / 2."""
+    w, dt, n = 0.07, 5.0, 101
+    hfun = lambda t: (np.sin(w * t), np.cos(w * t))
+    r = Response(None, 0.0, dt, n, Orbit("static"), hfun=hfun, sky=(0.3, 0.2), coarse=2)
+    hp, hc = r.h_grid(np.arange(n))
+    t = np.arange(n) * dt
+    fac = np.where(np.arange(n) % 2 == 1, np.cos(w * dt), 1.0)
+    assert np.max(np.abs(hp - np.sin(w * t) * fac)) < 1e-14
+    assert np.max(np.abs(hc - np.cos(w * t) * fac)) < 1e-14
