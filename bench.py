@@ -258,10 +258,13 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     shift = float(np.max(np.abs(res["learned"]["mean"] - res["plain"]["mean"]) / sd))
     std_ratio = (res["learned"]["std"] / sd).tolist()
     # Fisher widths at the injection against the MCMC widths (the paper's Tabs. II-III compare
-    # the two): sqrt(diag(Gamma^-1)), eigenvalues floored at 1e-12 of the largest as for the draws
-    ev, V = np.linalg.eigh(G)
-    ev = np.maximum(ev, 1e-12 * ev.max())
-    sig_f = np.sqrt(np.diag((V / ev) @ V.T))
+    # the two): sqrt(diag(Gamma^-1)), inverted in the basis where Gamma has a unit diagonal (the
+    # coordinates span many orders of magnitude: masses in Msun beside angles), eigenvalues of
+    # that correlation-like matrix floored at 1e-15 of the largest
+    dg = np.sqrt(np.diag(G))
+    ev, V = np.linalg.eigh(G / np.outer(dg, dg))
+    ev = np.maximum(ev, 1e-15 * ev.max())
+    sig_f = np.sqrt(np.diag((V / ev) @ V.T)) / dg
     names = (["m1", "m2", "a1", "theta1", "phi1", "a2", "theta2", "phi2"] if precessing else
              ["m1", "m2", "chi1z", "chi2z"]) + ["D_L", "iota", "phi_ref", "beta", "lambda", "psi"]
     fisher = {"names": names, "sigma_fisher": [float("%.4g" % v) for v in sig_f],
