@@ -481,8 +481,8 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
 //  A: h+, hx on the window of grid samples the six links read (LDS)
 //  C: y_slr for the tile plus the TDI halos; h is interpolated with K taps at
 //     the three receiver and the six sender times (LDS)
-//  D: X, Y, Z from y at the TDI delays (the tile's combined filters, copied over
-//     the h window, or per term), then A, E, T (global)
+//  D: X, Y, Z from y at the TDI delays (the tile's combined filters, read as scalars from
+//     its record, or per term), then A, E, T (global)
 template <typename R, int K, bool TAY>
 __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
   using Lay = RefLayout<R, K>;
@@ -506,11 +506,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   R* yb = (R*)smem;
   R* hpb = yb + 6 * MYP;
   R* hxb = hpb + WMAX;
-  const int HREG = TAY ? max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
-  double* nd = (double*)(smem + (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15));
-  int* gj0 = (int*)(nd + NNMAX * kNodeVals);               // [kGroups * kNV] combined-filter start
-  int* gJ = gj0 + kGroups * kNV;                           // [kGroups * kNV] combined-filter length
-  R* fg = hpb;                                             // later [kGroups * kNV][2][JMAX] combined filters
+  double* nd = (double*)(smem + (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15));
   const unsigned char* rec = (const unsigned char*)P.refs + (size_t)tile * Lay::stride;
   const double* tf0 = (const double*)(rec + Lay::f0);
   const int* tjr = (const int*)(rec + Lay::jr);
@@ -624,15 +620,12 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     __syncthreads();
   }
 
-  // the tile's combined filters, written over the h window (phase C has finished reading it)
-  const int comb1 = (TAY && !skip) ? *(const int*)(rec + Lay::comb) : 0;
-  if (comb1) {
-    const float4* src = (const float4*)(rec + Lay::fg);
-    float4* dst = (float4*)fg;
-    for (int i = tid; i < kGroups * kNV * 2 * JMAX * (int)sizeof(R) / 16; i += kNT) dst[i] = src[i];
-    for (int i = tid; i < 2 * kGroups * kNV; i += kNT) gj0[i] = ((const int*)(rec + Lay::gj))[i];
-    __syncthreads();
-  }
+  // the tile's combined filters are read from its record in the constant address space: they
+  // are the same for every lane of a wave (one wave = one node interval), so they arrive in
+  // scalar registers and feed the multiply-adds as scalar operands
+  typedef const __attribute__((address_space(4))) unsigned char crec_t;
+  crec_t* crec = (crec_t*)rec;
+  const int comb1 = (TAY && !skip) ? *(const __attribute__((address_space(4))) int*)(crec + Lay::comb) : 0;
 
   // D: TDI and A, E, T; each thread owns four consecutive output samples
   const R* data = (const R*)P.data;
@@ -654,13 +647,18 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     const int64_t nref = n0 + (int64_t)v * S + S2;
     if (TAY && comb1) {
       const int dn0 = (int)(nb - nref);
+      const int vw = __builtin_amdgcn_readfirstlane(v);
+      typedef float v4c __attribute__((ext_vector_type(4)));
+      typedef const __attribute__((address_space(4))) int cint_t;
+      typedef const __attribute__((address_space(4))) v4c cf4_t;
+      cint_t* gjs = (cint_t*)(crec + Lay::gj);
       for (int cc = 0; cc < 3; ++cc) {
         for (int g = 0; g < P.terms.n_groups[cc]; ++g) {
-          const int gi = (cc * 4 + g) * kNV + v;
-          const int J = gJ[gi];
-          const R* yl = yb + P.terms.g_link[cc][g] * MYP + gj0[gi] + dn0;
-          const R* F = fg + (gi * 2) * JMAX;
-          const R* G = F + JMAX;
+          const int gi = (cc * 4 + g) * kNV + vw;
+          const int J = gjs[kGroups * kNV + gi];
+          const R* yl = yb + P.terms.g_link[cc][g] * MYP + gjs[gi] + dn0;
+          cf4_t* F = (cf4_t*)(crec + Lay::fg + (size_t)(gi * 2) * JMAX * sizeof(R));
+          cf4_t* G = F + JMAX / 4;
           R a[4] = {(R)0, (R)0, (R)0, (R)0}, d[4] = {(R)0, (R)0, (R)0, (R)0};
           // yl, F, G and j are 16-byte aligned (gj0, MYP, JMAX and n - n_ref are multiples of 4):
           // one 16 B read of y per four taps, the window of eight samples kept in registers; eight
@@ -676,8 +674,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
             yv[0] = y0.x; yv[1] = y0.y; yv[2] = y0.z; yv[3] = y0.w;
             yv[4] = y1.x; yv[5] = y1.y; yv[6] = y1.z; yv[7] = y1.w;
             y0 = y1;
-            const float4 f4 = *reinterpret_cast<const float4*>(F + j);
-            const float4 g4 = *reinterpret_cast<const float4*>(G + j);
+            const v4c f4 = F[j / 4];
+            const v4c g4 = G[j / 4];
             const R fa[4] = {f4.x, f4.y, f4.z, f4.w}, ga[4] = {g4.x, g4.y, g4.z, g4.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -785,9 +783,7 @@ struct TdiGeom {
     if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
     if (!P.nodes || !P.refs) return hipErrorInvalidValue;
     constexpr int JMAX = CombLen<K>::value;
-    const int HREG = TAY ? std::max(2 * WMAX, kGroups * kNV * 2 * JMAX) : 2 * WMAX;
-    bytes = (((size_t)(6 * MYP + HREG) * sizeof(R) + 15) & ~(size_t)15) +
-            (size_t)NNMAX * kNodeVals * sizeof(double) + (size_t)kGroups * kNV * 2 * sizeof(int);
+    bytes = (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) + (size_t)NNMAX * kNodeVals * sizeof(double);
     if (bytes > 160 * 1024) return hipErrorInvalidValue;
     // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
     const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
