@@ -160,7 +160,7 @@ def _record(smp, k):
 
 
 def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=500, rounds=4, window=400,
-              train_steps=1500, m=1000):
+              train_steps=1500, m=1000, walk=0.0):
     """Effective samples per second of the cold chain, stretch moves alone against
     stretch + learned-flow moves, on one injection and one GPU (TDI-2 AET, 512
     walkers x 8 temperatures, n samples around the merger, Fisher-initialised).
@@ -177,7 +177,10 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     The flow works on psi folded into a window of width pi centred on the chain's
     circular mean of 2 psi (lt_sampler_set_flow_fold); its proposals land on either
     copy.  Autocorrelation times and moments are computed on the folded psi for both
-    chains, since only psi mod pi is identified."""
+    chains, since only psi mod pi is identified.
+
+    walk > 0 replaces the flow's independence proposals by a random walk of that step in
+    its latent space (lt_sampler_set_flow_walk)."""
     import numpy as np
     import torch
     from paper_2501_08261_amd.diagnostics import autocorr_time
@@ -220,6 +223,7 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         start = 0.5 * np.arctan2(np.sin(two).mean(), np.cos(two).mean()) - 0.5 * np.pi
         s = fold(s, start)
         smp.set_flow_fold(ipsi, np.pi, start)
+        smp.set_flow_walk(walk)
         flow.set_whitening(s.mean(0), np.linalg.cholesky(np.cov(s.T)))
         xs = torch.tensor(s[np.random.default_rng(r).permutation(len(s))], device="cuda:0")
         torch.cuda.synchronize()
@@ -274,7 +278,8 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     smp.close()
     flow.close()
     ctx.close()
-    return {"target": kind, "n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
+    return {"target": kind, "flow_move": "latent walk, step %g" % walk if walk > 0 else "independence",
+            "n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
             "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": rounds * train_steps,
             "plain": res["plain"], "learned": res["learned"],
             "ratio": res["learned"]["ess_per_s"] / res["plain"]["ess_per_s"],

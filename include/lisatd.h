@@ -338,6 +338,14 @@ lt_status lt_sampler_set_flow(lt_sampler* s, lt_flow* flow);
  * the fold; period must be positive and finite.  The flow should be trained on folded
  * samples.  Rebuilds the captured step on the next lt_sampler_step. */
 lt_status lt_sampler_set_flow_fold(lt_sampler* s, int index, double period, double start);
+/* Turns the flow move into a random walk in the flow's latent space (step > 0;
+ * 0 restores independence proposals): z = f(x) for the (folded) cold position,
+ * z' = z + step eps with eps standard normal from Philox counter (step, 0x700,
+ * walker, q) (two Box-Muller pairs per counter), y = f^-1(z').  The latent walk is
+ * symmetric, so the acceptance above holds with log q(x) - log N(z) in place of
+ * log q(x) and log q(y) - log N(z') in place of log q(y) (the ratio of the flow's
+ * Jacobians); the fold applies as before.  Rebuilds the captured step. */
+lt_status lt_sampler_set_flow_walk(lt_sampler* s, double step);
 /* Flow moves accepted and proposed since lt_sampler_set_state (host int64 [2]). */
 lt_status lt_sampler_flow_counts(lt_sampler* s, int64_t* counts);
 

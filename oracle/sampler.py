@@ -29,6 +29,12 @@ of the GPU sampler:
   (step, 0x600, walker, 0), and both ln q carry - ln n (the proposal density
   of a copy is q_flow(y_f) / n), so the ratio stays exact; a y_f outside the
   window is outside the proposal's range and is rejected;
+* optional latent random walk in place of the independence proposal:
+  z = f(x) (the flow's forward map of the folded position), z' = z + w eps,
+  eps standard normal from counter (step, 0x700, walker, q) like the base
+  samples, y = f^-1(z'); the walk is symmetric in z, so q(x) and q(y) above
+  become q(x) / N(z) and q(y) / N(z') (the Jacobians of f), with
+  ln N(z) = -|z|^2 / 2 - (d / 2) ln 2 pi summed in coordinate order;
 * random numbers from Philox4x32-10 (Salmon, Moraes, Dror, Shaw 2011) keyed
   by the seed, counter (step, purpose, slot, 0), uniforms (u + 1/2) 2^-32.
 """
@@ -41,7 +47,8 @@ from . import flow as _flow
 M0, M1 = 0xD2511F53, 0xCD9E8D57
 W0, W1 = 0x9E3779B9, 0xBB67AE85
 MASK = 0xFFFFFFFF
-TAG_MOVE, TAG_SHIFT, TAG_SWAP, TAG_FLOWZ, TAG_FLOWU, TAG_FLOWC = 0x100, 0x200, 0x300, 0x400, 0x500, 0x600
+TAG_MOVE, TAG_SHIFT, TAG_SWAP, TAG_FLOWZ, TAG_FLOWU, TAG_FLOWC, TAG_FLOWW = (0x100, 0x200, 0x300, 0x400, 0x500,
+                                                                     0x600, 0x700)
 
 
 def philox4x32_10(ctr, key):
@@ -109,6 +116,7 @@ class PTSampler:
         self.acc = self.prop = self.sacc = self.sprop = 0
         self.flow = None
         self.fold = None
+        self.walk = 0.0
         self.facc = self.fprop = 0
 
     def set_flow(self, P, mu, sigma):
@@ -119,19 +127,23 @@ class PTSampler:
         """Fold coordinate `index` into [start, start + period) for the flow move (index < 0: none)."""
         self.fold = None if index < 0 else (int(index), float(period), float(start))
 
+    def set_flow_walk(self, step):
+        """Latent random walk of this step as the flow move (0: independence proposals)."""
+        self.walk = float(step)
+
     def _copies(self, v, i, P):
         """Copies v + k P inside [lo_i, hi_i]: (k_min, count)."""
         a = np.ceil((self.lo[i] - v) / P)
         b = np.floor((self.hi[i] - v) / P)
         return a, np.where(b >= a, b - a + 1, 0).astype(np.int64)
 
-    def flow_normals(self, s):
-        """Base samples z [W][d] of step s."""
+    def flow_normals(self, s, tag=TAG_FLOWZ):
+        """Standard normals [W][d] of step s (base samples; the walk's steps with TAG_FLOWW)."""
         W, d = self.W, self.d
         z = np.zeros((W, d))
         k = np.arange(W)
         for q in range((d + 3) // 4):
-            r = philox4x32_10(_ctr(s, TAG_FLOWZ, k, q), self.key)
+            r = philox4x32_10(_ctr(s, tag, k, q), self.key)
             for p in (0, 1):
                 rad = np.sqrt(-2.0 * np.log(u01(r[:, 2 * p])))
                 ph = 2.0 * math.pi * u01(r[:, 2 * p + 1])
@@ -142,10 +154,16 @@ class PTSampler:
                     z[:, i0 + 1] = rad * np.sin(ph)
         return z
 
+    @staticmethod
+    def _log_normal(z):
+        acc = np.zeros(z.shape[0])
+        for i in range(z.shape[1]):
+            acc = acc + z[:, i] * z[:, i]
+        return -0.5 * acc - 0.5 * z.shape[1] * math.log(2.0 * math.pi)
+
     def flow_move(self, s):
         P, mu, sigma = self.flow
         W = self.W
-        y, lqy = _flow.inverse(P, self.flow_normals(s), mu, sigma)
         xf = self.X[0].copy()
         lkx = np.zeros(W)
         out = np.zeros(W, dtype=bool)
@@ -155,6 +173,17 @@ class PTSampler:
             xf[:, i] = c0 + ((x - c0) - Pf * np.floor((x - c0) / Pf))
             _, nx = self._copies(xf[:, i], i, Pf)
             lkx = np.where(nx > 0, np.log(np.maximum(nx, 1).astype(np.float64)), 0.0)
+        if self.walk > 0.0:
+            z, lqx = _flow.forward(P, xf, mu, sigma)
+            zn = z + self.walk * self.flow_normals(s, TAG_FLOWW)
+            lqx = lqx - self._log_normal(z)
+            y, lqy = _flow.inverse(P, zn, mu, sigma)
+            lqy = lqy - self._log_normal(zn)
+        else:
+            y, lqy = _flow.inverse(P, self.flow_normals(s), mu, sigma)
+            _, lqx = _flow.forward(P, xf, mu, sigma)
+        if self.fold is not None:
+            i, Pf, c0 = self.fold
             v = y[:, i].copy()
             inwin = (v >= c0) & (v < c0 + Pf)
             km, ny = self._copies(v, i, Pf)
@@ -165,7 +194,6 @@ class PTSampler:
             y[okc, i] = v[okc] + (km[okc] + j[okc].astype(np.float64)) * Pf
             lqy = np.where(okc, lqy - np.log(np.maximum(ny, 1).astype(np.float64)), lqy)
             out = ~okc
-        _, lqx = _flow.forward(P, xf, mu, sigma)
         lpy = np.where(out, -np.inf, self.log_prior(y))
         lly = np.asarray(self.logl_fn(y), dtype=np.float64)
         ru = philox4x32_10(_ctr(s, TAG_FLOWU, np.arange(W)), self.key)

@@ -247,6 +247,44 @@ __global__ void k_base_normal(const uint64_t* step, uint32_t k0, uint32_t k1, in
   }
 }
 
+// latent random walk for walker k: u <- u + sigma eps, eps standard normal from Philox counter
+// (step, kTagFlowW, k, q), two Box-Muller pairs per counter as above; with
+// log N(z) = -|z|^2 / 2 - (d / 2) log(2 pi) (squares summed in coordinate order):
+// lq_x = logq - log N(u), lnz2 = log N(u + sigma eps)
+__global__ void k_walk(const uint64_t* step, uint32_t k0, uint32_t k1, int n, int d, double sigma, double* u,
+                       const double* logq, double* lq_x, double* lnz2) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t st = (uint32_t)*step;
+  double e[4 * 16];
+  for (int q = 0; 4 * q < d; ++q) {
+    uint32_t c[4] = {st, lt_rng::kTagFlowW, (uint32_t)k, (uint32_t)q};
+    lt_rng::philox4x32_10(c, k0, k1);
+    for (int p = 0; p < 2; ++p) {
+      const double r = sqrt(-2.0 * log(lt_rng::u01(c[2 * p])));
+      const double ph = 2.0 * M_PI * lt_rng::u01(c[2 * p + 1]);
+      e[4 * q + 2 * p] = r * cos(ph);
+      e[4 * q + 2 * p + 1] = r * sin(ph);
+    }
+  }
+  double z2 = 0.0, w2 = 0.0;
+  for (int i = 0; i < d; ++i) {
+    const double z = u[(int64_t)k * d + i];
+    const double w = z + sigma * e[i];
+    z2 = z2 + z * z;
+    w2 = w2 + w * w;
+    u[(int64_t)k * d + i] = w;
+  }
+  const double c0 = 0.5 * (double)d * log(2.0 * M_PI);
+  lq_x[k] = logq[k] - (-0.5 * z2 - c0);
+  lnz2[k] = -0.5 * w2 - c0;
+}
+
+__global__ void k_sub(double* a, const double* b, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) a[k] -= b[k];
+}
+
 __global__ void k_adam(float* w, bf16* wb, const float* g, float* m, float* v, int64_t count, float lr, float b1,
                        float b2, float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -288,6 +326,7 @@ struct lt_flow {
   int64_t t = 0;
   // per-row state (maxB rows) and per-layer activations kept for the backward pass
   double *u = nullptr, *gu = nullptr, *logdet = nullptr, *logq = nullptr, *s = nullptr, *ub = nullptr;
+  double* lnz = nullptr;   // log N of the walked latent rows
   float *a1 = nullptr, *a2 = nullptr, *o = nullptr, *tmpH = nullptr, *go = nullptr, *tmpA = nullptr;
   bf16 *uA = nullptr, *h1 = nullptr, *h2 = nullptr, *gob = nullptr, *gH = nullptr;
   std::vector<void*> allocs;
@@ -444,6 +483,17 @@ hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream
   hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, st, f->logq, (int64_t)n, logq);
   return hipGetLastError();
 }
+// latent random walk from the rows of x: z = f(x), y = f^-1(z + sigma eps);
+// lq_x = log q(x) - log N(z), lq_y = log q(y) - log N(z + sigma eps)
+hipError_t flow_walk(lt_flow* f, const double* x, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double sigma,
+                     double* y, double* lq_y, double* lq_x, hipStream_t st) {
+  logq_rows(f, x, n, 0, n, false, st);
+  hipLaunchKernelGGL(k_walk, dim3(blocks(n, 64)), dim3(64), 0, st, step, k0, k1, n, f->d, sigma, f->u, f->logq, lq_x,
+                     f->lnz);
+  sample_rows(f, n, y, lq_y, st);
+  hipLaunchKernelGGL(k_sub, dim3(blocks(n)), dim3(256), 0, st, lq_y, f->lnz, n);
+  return hipGetLastError();
+}
 }  // namespace lt
 
 extern "C" {
@@ -484,7 +534,7 @@ lt_status lt_flow_create(int hip_device, int dim, int n_layers, int hidden, int 
   if (e == hipSuccess) e = falloc(f, &f->ptr, (size_t)(cnt))
   FA(w, off); FA(g, off); FA(m, off); FA(v, off); FA(wb, off);
   FA(mu, dim); FA(Lw, (int64_t)dim * dim);
-  FA(u, B * dim); FA(gu, B * dim); FA(logdet, B); FA(logq, B);
+  FA(u, B * dim); FA(gu, B * dim); FA(logdet, B); FA(logq, B); FA(lnz, B);
   FA(a1, L * B * H); FA(a2, L * B * H); FA(o, L * B * 2 * dim); FA(s, L * B * dim); FA(ub, L * B * dim);
   FA(uA, L * B * dim); FA(h1, L * B * H); FA(h2, L * B * H);
   FA(tmpH, B * H); FA(go, B * 2 * dim); FA(gob, B * 2 * dim); FA(gH, B * H); FA(tmpA, B * dim);

@@ -46,6 +46,7 @@ struct Dev {
   int fold_i;
   double fold_p, fold_c0;
   double *fxf, *flkx;       // folded cold positions [W][d]; log(number of copies) of each
+  double walk;              // > 0: the flow move is a random walk of this step in the flow's latent space
 };
 
 __device__ inline void to_params(const Dev& D, const double* x, double* p) {
@@ -271,6 +272,8 @@ int flow_device(const lt_flow* f);
 hipError_t flow_propose(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y, double* logq_y,
                         hipStream_t st);
 hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st);
+hipError_t flow_walk(lt_flow* f, const double* x, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double sigma,
+                     double* y, double* lq_y, double* lq_x, hipStream_t st);
 }
 
 struct lt_sampler {
@@ -341,10 +344,16 @@ static lt_status record_step(lt_sampler* s, hipStream_t st) {
   }
   if (s->flow) {
     const int W = s->cfg.n_walkers;
-    S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st));
     hipLaunchKernelGGL(k_flow_fold, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());
-    S_HIP(lt::flow_logq(s->flow, s->D.fxf, W, s->D.fqx, st));
+    if (s->D.walk > 0.0) {
+      // y = f^-1(f(x) + walk eps): fqx, fqy carry log q - log N of the two latent points
+      S_HIP(lt::flow_walk(s->flow, s->D.fxf, W, s->D.step, s->D.k0, s->D.k1, s->D.walk, s->D.fy, s->D.fqy, s->D.fqx,
+                          st));
+    } else {
+      S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st));
+      S_HIP(lt::flow_logq(s->flow, s->D.fxf, W, s->D.fqx, st));
+    }
     hipLaunchKernelGGL(k_flow_prep, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());
     lt_status r = eval_logl(s, s->D.fy, W, s->D.fylogl, st);
@@ -401,6 +410,7 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
   D.T = T; D.W = W; D.d = d; D.kind = cfg->param_kind; D.target = cfg->target; D.n_gauss = cfg->n_gauss;
   D.a = cfg->stretch_a; D.t_c = cfg->t_c;
   D.fold_i = -1;
+  D.walk = 0.0;
   D.fold_p = 1.0;
   D.fold_c0 = 0.0;
   D.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
@@ -544,6 +554,19 @@ lt_status lt_sampler_set_flow_fold(lt_sampler* s, int index, double period, doub
   s->D.fold_i = index;
   s->D.fold_p = index >= 0 ? period : 1.0;
   s->D.fold_c0 = index >= 0 ? start : 0.0;
+  return LT_OK;
+}
+
+lt_status lt_sampler_set_flow_walk(lt_sampler* s, double step) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  if (!(step >= 0.0 && std::isfinite(step))) return sfail(LT_ERR_CONFIG, "walk step must be finite and >= 0");
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->exec = nullptr;
+  s->graph = nullptr;
+  s->D.walk = step;
   return LT_OK;
 }
 

@@ -94,6 +94,7 @@ _sig = {
     "lt_sampler_get_state": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "lt_sampler_set_flow": ([_P, _P], ctypes.c_int),
     "lt_sampler_set_flow_fold": ([_P, ctypes.c_int, ctypes.c_double, ctypes.c_double], ctypes.c_int),
+    "lt_sampler_set_flow_walk": ([_P, ctypes.c_double], ctypes.c_int),
     "lt_sampler_flow_counts": ([_P, _P], ctypes.c_int),
     "lt_fisher": ([_P, _P, ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid),
                    ctypes.POINTER(Orbit), ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), _P], ctypes.c_int),
@@ -325,6 +326,10 @@ class Sampler:
     def set_flow_fold(self, index, period=math.pi, start=0.0):
         """Fold coordinate `index` (-1: none) into [start, start + period) for the flow move."""
         _check(_lib.lt_sampler_set_flow_fold(self.h, int(index), float(period), float(start)))
+
+    def set_flow_walk(self, step):
+        """Latent-space random walk of this step as the flow move (0: independence proposals)."""
+        _check(_lib.lt_sampler_set_flow_walk(self.h, float(step)))
 
     def flow_counts(self):
         import numpy as np

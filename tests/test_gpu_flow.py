@@ -291,6 +291,48 @@ def test_sampler_flow_fold_parity(lib, T):
     fg.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("fold", [False, True])
+def test_sampler_flow_walk_parity(lib, fold):
+    """P30: the latent random-walk flow move (walk normals from Philox, log q - log N at both
+    ends), with and without the symmetry fold, against the oracle chain step by step."""
+    d, W, T, seed, i, Pd, c0 = 4, 16, 2, 5151, 2, 2.0, -1.0
+    rng = np.random.default_rng(40 + fold)
+    A = rng.normal(size=(d, d))
+    icov = np.linalg.inv(0.05 * (A @ A.T) + 0.2 * np.eye(d))
+    m = rng.normal(size=d)
+    m[i] = 0.1
+    means = np.stack([m, m + Pd * np.eye(d)[i]])
+    lo, hi = -30 * np.ones(d), 30 * np.ones(d)
+    lo[i], hi[i] = -1.7, 2.6
+    P = fl.init_params(d, 4, 32, 3)
+    mu, sig = m + 0.1, np.full(d, 0.7)
+    start = np.clip(means[0] + 0.3 * rng.normal(size=(T, W, d)), lo + 1e-3, hi - 1e-3)
+    fg = lib.Flow(d, 4, 32, W)
+    fg.set_params(lib.flow_pack(P), mu, sig)
+    g = lib.Sampler(W, T, d, lo, hi, seed, target="gauss", param_kind="raw", t_max=5.0, means=means, icov=icov)
+    o = PTSampler(gaussian_logl(means, icov), lo, hi, W, T, d, seed, t_max=5.0)
+    g.set_flow(fg)
+    o.set_flow(P, mu, sig)
+    if fold:
+        g.set_flow_fold(i, Pd, c0)
+        o.set_flow_fold(i, Pd, c0)
+    g.set_flow_walk(0.6)
+    o.set_flow_walk(0.6)
+    g.set_state(start)
+    o.set_state(start)
+    for s in range(25):
+        g.step(1)
+        o.step()
+        pos, logl, _, step, cnt = g.state()
+        assert np.max(np.abs(pos - o.X)) < 1e-12 * (1 + np.max(np.abs(o.X))), s
+        assert cnt[0] == o.acc and cnt[2] == o.sacc
+        assert g.flow_counts() == (o.facc, o.fprop), s
+    assert 0 < o.facc < o.fprop
+    g.close()
+    fg.close()
+
+
 def test_learned_proposal_raises_ess(lib):
     """A flow trained on burn-in samples lowers the cold chain's integrated autocorrelation time."""
     d, W = 4, 64

@@ -221,3 +221,40 @@ def test_flow_fold_keeps_the_target():
     err = np.sqrt(mass * (1 - mass) / (x.size / tau))
     assert np.all(np.abs(frac - mass) < 5 * err + 1e-3), (frac, mass)
     assert 0.2 < s.facc / s.fprop < 0.95
+
+
+def _curved_flow(d, seed=7, scale=0.25):
+    """A nonlinear flow: random output layers, so the Jacobian varies over the space."""
+    from oracle import flow as fl
+    P = fl.init_params(d, 4, 16, seed)
+    rng = np.random.default_rng(seed + 1)
+    for p in P:
+        p["W3"] = rng.normal(size=p["W3"].shape) * scale / np.sqrt(p["W3"].shape[1])
+        p["b3"] = rng.normal(size=p["b3"].shape) * 0.1
+    return P
+
+
+def test_flow_walk_keeps_the_target():
+    """P30: the latent random walk through a curved flow samples the target: the acceptance
+    carries the ratio of the flow's Jacobians, log q - log N at both ends (dropping the log N
+    terms, or the Jacobians, biases the moments below by many standard errors)."""
+    rng = np.random.default_rng(8)
+    d = 2
+    C = np.array([[1.0, 0.5], [0.5, 1.5]])
+    m = np.array([0.3, -0.7])
+    s = PTSampler(gaussian_logl(m, np.linalg.inv(C)), [-40] * d, [40] * d, 32, 1, d, seed=31)
+    s.set_state(m + rng.multivariate_normal(np.zeros(d), C, size=(1, 32)))
+    s.set_flow(_curved_flow(d), m + np.array([0.5, 0.2]), np.array([1.3, 0.9]))
+    s.set_flow_walk(0.9)
+    chain = []
+    for i in range(3000):
+        s.step()
+        if i >= 200:
+            chain.append(s.X[0].copy())
+    chain = np.array(chain)
+    flat = chain.reshape(-1, d)
+    tau = integrated_time(chain).max()
+    err = np.sqrt(np.diag(C) / (flat.shape[0] / tau))
+    assert np.all(np.abs(flat.mean(0) - m) < 5 * err)
+    assert np.allclose(np.cov(flat.T), C, atol=0.12)
+    assert 0.2 < s.facc / s.fprop < 0.95
