@@ -245,7 +245,15 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
 // writes the outputs in Stockham order into the same LDS buffer, synchronises.
 // LS: distance between consecutive transforms in buf (>= L; padding avoids LDS bank conflicts);
 // NT: threads of the workgroup
-template <typename R, int L, int NFFT, int RAD, int NS, int LS = L, int NT = kFT>
+// PAD8: element i of a series sits at i + i / 8 (one spare slot per eight elements).  A
+// stage with NS < 32 writes each lane's RAD outputs NS elements apart; without the slots,
+// 8-byte elements 8 apart fall on two bank groups of the 32 LDS banks.
+template <bool PAD8>
+__device__ inline int lix(int i) {
+  return PAD8 ? i + (i >> 3) : i;
+}
+
+template <typename R, int L, int NFFT, int RAD, int NS, int LS = L, int NT = kFT, bool PAD8 = false>
 __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
   constexpr int M = L / RAD;
   constexpr int JOBS = NFFT * M;
@@ -257,10 +265,10 @@ __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
     const int job = threadIdx.x + p * NT;
     if (JOBS % NT == 0 || job < JOBS) {
       const int f = job / M, j = job % M, k = j % NS;
-      const C2<R>* src = buf + f * LS + j;
+      const C2<R>* src = buf + f * LS;
 #pragma unroll
       for (int r = 0; r < RAD; ++r) {
-        v[p][r] = src[r * M];
+        v[p][r] = src[lix<PAD8>(j + r * M)];
         if (NS > 1 && r > 0) v[p][r] = cm(v[p][r], tw[r * k * STEP]);
       }
       dft<R, RAD>(v[p]);
@@ -272,9 +280,10 @@ __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
     const int job = threadIdx.x + p * NT;
     if (JOBS % NT == 0 || job < JOBS) {
       const int f = job / M, j = job % M, k = j % NS;
-      C2<R>* dst = buf + f * LS + (j / NS) * NS * RAD + k;
+      C2<R>* dst = buf + f * LS;
+      const int d0 = (j / NS) * NS * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) dst[r * NS] = v[p][r];
+      for (int r = 0; r < RAD; ++r) dst[lix<PAD8>(d0 + r * NS)] = v[p][r];
     }
   }
   __syncthreads();
@@ -286,16 +295,17 @@ __device__ inline void ct_fft(C2<R>* buf, const C2<R>* tw) {
   if constexpr (sizeof...(REST) > 0) ct_fft<R, L, NFFT, NS * RAD, REST...>(buf, tw);
 }
 
-template <typename R, int L, int LS, int NT, int NFFT, int NS, int RAD, int... REST>
+template <typename R, int L, int LS, int NT, bool PAD8, int NFFT, int NS, int RAD, int... REST>
 __device__ inline void ct_fft_strided(C2<R>* buf, const C2<R>* tw) {
-  ct_stage<R, L, NFFT, RAD, NS, LS, NT>(buf, tw);
-  if constexpr (sizeof...(REST) > 0) ct_fft_strided<R, L, LS, NT, NFFT, NS * RAD, REST...>(buf, tw);
+  ct_stage<R, L, NFFT, RAD, NS, LS, NT, PAD8>(buf, tw);
+  if constexpr (sizeof...(REST) > 0) ct_fft_strided<R, L, LS, NT, PAD8, NFFT, NS * RAD, REST...>(buf, tw);
 }
 
 // pass 1 for n1 = 512: CB columns (128 bytes of each row) per workgroup.  Column c
-// sits at buf[c * LP], LP = N1 + 1: the 16 lanes that move one 128-byte row segment
-// then touch 16 different bank pairs instead of one.
-constexpr int kP1Pad = 1;
+// sits at buf[c * LP], LP = N1 + N1 / 8 + 1 (the column with a spare slot per eight
+// elements, plus one): the 16 lanes that move one 128-byte row segment then touch 16
+// different bank pairs instead of one.
+constexpr int kP1Pad = 512 / 8 + 1;
 constexpr int kP1Threads = 512;   // 2 workgroups of 65.7 KB fit a CU: 16 waves
 template <typename R>
 __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* data) {
@@ -317,12 +327,12 @@ __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* d
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
       const int i = threadIdx.x + t * kP1Threads, j1 = i / CB, jj = i % CB;
-      buf[jj * LP + j1] = v[t];
+      buf[jj * LP + lix<true>(j1)] = v[t];
     }
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
-  ct_fft_strided<R, N1, LP, kP1Threads, CB, 1, 8, 8, 8>(buf, tw);
+  ct_fft_strided<R, N1, LP, kP1Threads, true, CB, 1, 8, 8, 8>(buf, tw);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   // twiddle tables read for all of this thread's elements before the first product
@@ -337,7 +347,7 @@ __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* d
 #pragma unroll
   for (int t = 0; t < PT; ++t) {
     const int i = threadIdx.x + t * kP1Threads, k1 = i / CB, jj = i % CB;
-    z[(int64_t)k1 * N2 + j2_0 + jj] = cm(buf[jj * LP + k1], cm(tl[t], th[t]));
+    z[(int64_t)k1 * N2 + j2_0 + jj] = cm(buf[jj * LP + lix<true>(k1)], cm(tl[t], th[t]));
   }
 }
 
