@@ -588,24 +588,27 @@ lt_status lt_phenomt_polarizations(lt_ctx* c, const double* params, int64_t batc
   return LT_OK;
 }
 
+// tc: the templates' constants when the caller has set them up already (null: set up here)
 static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
                          const lt_orbit* o, const lt_tdi_cfg* t, int out_mode, const void* data, void* out,
-                         int32_t* status, hipStream_t s) {
+                         int32_t* status, hipStream_t s, const TplConst* tc = nullptr) {
   OrbitDev od;
   lt_status st = get_orbit(c, o, g, &od);
   if (st) return st;
-  st = do_setup(c, params, batch, cfg, g, status, s);
-  if (st) return st;
+  if (!tc) {
+    st = do_setup(c, params, batch, cfg, g, status, s);
+    if (st) return st;
+    tc = (const TplConst*)c->tpl.p;
+  }
   const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
   LT_HIP(c->wave.ensure((size_t)batch * 2 * g->n * rsz));
   {
     Prof pr(c, 0, s);
-    LT_HIP(launch_wave((const TplConst*)c->tpl.p, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, cfg->precision,
-                       gdev(g),
-                       c->wave.p, s));
+    LT_HIP(launch_wave(tc, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, cfg->precision, gdev(g), c->wave.p,
+                       s));
   }
   TdiLaunch L;
-  L.tc = (const TplConst*)c->tpl.p;
+  L.tc = tc;
   L.batch = batch;
   L.h = c->wave.p;
   L.taps = t->taps;
@@ -718,6 +721,9 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
   }
   const double scale = 4.0 * g->dt / (double)g->n;
   const int64_t nfold = p->dev.n1 / 2 + 1;
+  // every template's constants once (one launch); the chunks below reuse them
+  st = do_setup(c, params, batch, cfg, g, stat, s);
+  if (st) return st;
   if (batch < 2 * kPipeChunk) {
     // one stream; templates in chunks so that the workspace stays bounded
     // (per chunk: 2 waveform + 3 TDI series of n samples per template)
@@ -725,7 +731,8 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
     LT_HIP(c->work.ensure((size_t)chunk * 3 * g->n * rsz));
     for (int64_t off = 0; off < batch; off += chunk) {
       const int64_t b = batch - off < chunk ? batch - off : chunk;
-      st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, c->work.p, stat + off, s);
+      st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, c->work.p, stat + off, s,
+                   (const TplConst*)c->tpl.p + off);
       if (st) return st;
       st = band_power(c, p, c->work.p, b * 3, cfg->precision, psd, g, t->channels, s);
       if (st) return st;
@@ -768,7 +775,8 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
     const int slot = (int)(i & 1);
     const int64_t b = batch - off < chunk ? batch - off : chunk;
     if (i >= 2) LT_HIP(hipStreamWaitEvent(s, c->ev_fft[slot], 0));
-    st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, work[slot]->p, stat + off, s);
+    st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, work[slot]->p, stat + off, s,
+                 (const TplConst*)c->tpl.p + off);
     if (st) return st;
     LT_HIP(hipEventRecord(c->ev_tdi[slot], s));
     LT_HIP(hipStreamWaitEvent(c->aux, c->ev_tdi[slot], 0));
