@@ -56,8 +56,9 @@ struct TdiLaunch {
   const void* data;   // [3][n] (residual mode)
   void* out;          // [batch][3][n]
   int32_t* status;    // nullable
-  double* nodes;      // scratch: response geometry per (template, orbit node)
+  double* nodes;      // scratch: response geometry per (template, orbit node), then the window bounds
   void* refs;         // scratch: TDI term references and combined filters per tile
+  int* win;           // set by launch_tdi: window bounds per (template, tile), after the node records
 };
 // stage 0: the per-launch tables (node geometry, term references, combined filters);
 // stage 1: the response kernel itself

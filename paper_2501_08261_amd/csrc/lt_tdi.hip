@@ -282,6 +282,26 @@ __global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb,
   *reinterpret_cast<int2*>(o + kNodeVals) = wb;
 }
 
+// window bounds of every (template, tile): the largest and smallest delay in samples over
+// the orbit nodes the tile interpolates (nodes jn_lo .. jn_hi, as in k_tdi), two int32
+__global__ __launch_bounds__(kNT) void k_windows(const double* nodes, OrbitDev orb, int64_t batch, int ntile,
+                                                 int HY, int MY, int* win) {
+  const int64_t idx = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (idx >= batch * ntile) return;
+  const int64_t b = idx / ntile, tile = idx - b * ntile;
+  constexpr int S = kTile / (kTile / 256);
+  const int64_t m_lo = tile * kTile - HY, m_hi = m_lo + MY - 1;
+  const int64_t jn_lo = floordiv(m_lo, S) - 1 + orb.j0, jn_hi = floordiv(m_hi, S) + 2 + orb.j0;
+  int dhi = -(1 << 30), dlo = 1 << 30;
+  for (int64_t j = jn_lo; j <= jn_hi; ++j) {
+    const int2 wb = *reinterpret_cast<const int2*>(nodes + (b * orb.n_nodes + j) * kNodeRec + kNodeVals);
+    dhi = max(dhi, wb.x);
+    dlo = min(dlo, wb.y);
+  }
+  win[2 * idx] = dhi;
+  win[2 * idx + 1] = dlo;
+}
+
 // ------------------------------------------------------- TDI term references per tile
 // Per (TDI term, node interval) reference: the stencil start and fraction at
 // the interval midpoint; the fraction of output n is f0 - delta(n) with
@@ -487,7 +507,6 @@ template <typename R, int K, bool TAY>
 __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
   using Lay = RefLayout<R, K>;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_dhi, s_dlo;
   constexpr int JMAX = Lay::JMAX;
   const int tid = threadIdx.x;
   // workgroups in dispatch order take the templates of one tile back to back, so that its record
@@ -520,29 +539,11 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   const int64_t jn_hi = floordiv(m_hi, S) + 2 + P.orb.j0;
   const int NN = (int)(jn_hi - jn_lo + 1);
 
-  if (tid == 0) {
-    s_dhi = -(1 << 30);
-    s_dlo = 1 << 30;
-  }
-  __syncthreads();
-  // B: the template's node records; their window bounds give the h window (integer LDS
-  // min / max: the result does not depend on the order)
-  {
-    const double* ng = P.nodes + ((int64_t)b * P.orb.n_nodes + jn_lo) * kNodeRec;
-    for (int i = tid; i < NN * kNodeRec; i += kNT) {
-      const int nl = i / kNodeRec, q = i - nl * kNodeRec;
-      if (q < kNodeVals) {
-        nd[nl * kNodeVals + q] = ng[i];
-      } else {
-        const int2 wb = *reinterpret_cast<const int2*>(ng + i);
-        atomicMax(&s_dhi, wb.x);
-        atomicMin(&s_dlo, wb.y);
-      }
-    }
-  }
-  __syncthreads();
-  const long long w0 = (long long)m_lo - s_dhi - K / 2 - 2;
-  const long long w1 = (long long)m_hi - s_dlo + K / 2 + 2;
+  // the tile's window bounds (k_windows): largest and smallest delay over its nodes, in samples
+  typedef const __attribute__((address_space(4))) int cwin_t;
+  cwin_t* wp = (cwin_t*)(P.win + 2 * ((int64_t)b * gridDim.x + tile));
+  const long long w0 = (long long)m_lo - wp[0] - K / 2 - 2;
+  const long long w1 = (long long)m_hi - wp[1] + K / 2 + 2;
   int W = (int)(w1 - w0 + 1);
   if (W > WMAX) {
     W = WMAX;
@@ -552,8 +553,13 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   const int skip = (c.valid == 0.0 || (double)w1 < c.n_start - 2.0) ? 1 : 0;
 
   if (!skip) {
-    // A: polarisations of the window from the waveform buffer, every load issued before the
-    // first LDS store (one memory latency per kA * kNT samples)
+    // B: the template's node records and A: the polarisations of the window, every load
+    // issued before the first LDS store (one memory latency per kA * kNT samples)
+    const double* ng = P.nodes + ((int64_t)b * P.orb.n_nodes + jn_lo) * kNodeRec;
+    const int nval = NN * kNodeVals;
+    double nv = 0.0;
+    if (tid < nval) nv = ng[(tid / kNodeVals) * kNodeRec + tid % kNodeVals];
+    for (int i = tid + kNT; i < nval; i += kNT) nd[i] = ng[(i / kNodeVals) * kNodeRec + i % kNodeVals];
     constexpr int kA = 6;
     const R* hg = (const R*)P.h + (2 * (int64_t)b) * N;
     for (int i0 = 0; i0 < W; i0 += kA * kNT) {
@@ -574,6 +580,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
         }
       }
     }
+    if (tid < nval) nd[tid] = nv;
     __syncthreads();
     // C: link responses y_slr for m in [m_lo, m_hi].  A thread's samples are kNT = S apart,
     // one node interval: they share the cubic node weights, and the node index steps by one.
@@ -794,14 +801,21 @@ struct TdiGeom {
 };
 
 template <typename R, int K>
-static hipError_t launch_tdi_t(const TdiLaunch& P, int stage, hipStream_t s) {
+static hipError_t launch_tdi_t(const TdiLaunch& P0, int stage, hipStream_t s) {
   constexpr bool TAY = RefLayout<R, K>::TAY;
+  TdiLaunch P = P0;
+  P.win = (int*)(P.nodes + (int64_t)P.batch * P.orb.n_nodes * kNodeRec);
   TdiGeom<R, K> G;
   hipError_t e = G.make(P);
   if (e != hipSuccess) return e;
   if (stage == 0) {
     hipLaunchKernelGGL(k_nodes, dim3((unsigned)((P.orb.n_nodes + kNT - 1) / kNT), (unsigned)P.batch), dim3(kNT), 0,
                        s, P.tc, P.orb, P.g.inv_dt, P.nodes);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t nw = P.batch * (int64_t)G.ntile;
+    hipLaunchKernelGGL(k_windows, dim3((unsigned)((nw + kNT - 1) / kNT)), dim3(kNT), 0, s, P.nodes, P.orb, P.batch,
+                       (int)G.ntile, G.HY, kTile + G.HY + K / 2 + 1, P.win);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tdi_refs<R, K, TAY>), dim3(G.ntile), dim3(kNT), 0, s, P, G.HY, G.MYP, G.comb);
@@ -830,7 +844,9 @@ static size_t refs_stride_k(int taps) {
 }
 
 void tdi_scratch_bytes(const TdiLaunch& P, size_t* nodes, size_t* refs) {
-  *nodes = (size_t)P.batch * (size_t)P.orb.n_nodes * kNodeRec * sizeof(double);
+  // node records, then two int32 window bounds per (template, tile)
+  *nodes = (size_t)P.batch * (size_t)P.orb.n_nodes * kNodeRec * sizeof(double) +
+           (size_t)P.batch * (size_t)((P.g.n + kTile - 1) / kTile) * 2 * sizeof(int);
   const size_t stride = P.precision == 0 ? refs_stride_k<double>(P.taps) : refs_stride_k<float>(P.taps);
   *refs = (size_t)((P.g.n + kTile - 1) / kTile) * stride;
 }
