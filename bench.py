@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 # calibration), keyed by (kernel, batch, samples, taps, precision).  Any other
 # configuration, or a changed kernel, reports null.
 PMC_TRAFFIC = {
+    # profiles/k_tdi_precessing_k8_2p20_b256.md: FETCH 0.774 GiB + WRITE 0.750 GiB per 64-template launch
+    ("tdi_response", 64, 2 ** 20, 8, "mixed"): int((0.774 + 0.750) * 2 ** 30),
 }
 
 N_SAMPLES = 2 ** 20
