@@ -257,8 +257,11 @@ lt_status lt_fisher(lt_ctx* ctx, const double* x0, int param_kind, double t_c, c
                     const lt_psd* psd, double* gamma);
 
 /* Draws count starting points from N(x0, Gamma^-1) (host FP64): Gamma is
- * symmetrised and its eigenvalues floored at reg * max eigenvalue (near-
- * degenerate directions of 22-only models), normal deviates from Philox4x32-10
+ * symmetrised and scaled to unit diagonal, C = D Gamma D with
+ * D = diag(Gamma_ii^-1/2) (1 where Gamma_ii <= 0); the eigenvalues of C are
+ * floored at reg * its max eigenvalue (near-degenerate directions of 22-only
+ * models) and x = x0 + D V W^-1/2 z, which has covariance Gamma^-1 exactly
+ * when no eigenvalue is floored.  Normal deviates from Philox4x32-10
  * (Box-Muller); draws outside [lo, hi] are redrawn (up to 64 times, then
  * clipped).  out: host [count][dim]. */
 lt_status lt_fisher_draw(const double* x0, const double* gamma, int dim, const double* lo, const double* hi,

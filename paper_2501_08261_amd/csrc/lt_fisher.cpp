@@ -186,9 +186,14 @@ lt_status lt_fisher_draw(const double* x0, const double* gamma, int dim, const d
   if (!x0 || !gamma || !lo || !hi || !out) return ferr(LT_ERR_NULL, "null argument");
   if (dim < 1 || dim > 64 || count < 0) return ferr(LT_ERR_SHAPE, "dim / count");
   if (!(reg >= 0.0)) return ferr(LT_ERR_CONFIG, "reg must be >= 0");
-  std::vector<double> a((size_t)dim * dim), w, v;
+  // The eigen floor is applied to D Gamma D with D = diag(Gamma_ii^-1/2): in that unit-diagonal basis
+  // the floor is relative to the best-measured combination of comparably scaled coordinates, so a
+  // parameter measured in large units (mass, distance) is not flattened by one measured in small ones.
+  std::vector<double> a((size_t)dim * dim), w, v, dg(dim);
+  for (int i = 0; i < dim; ++i) dg[i] = gamma[i * dim + i] > 0.0 ? std::sqrt(gamma[i * dim + i]) : 1.0;
   for (int i = 0; i < dim; ++i)
-    for (int j = 0; j < dim; ++j) a[i * dim + j] = 0.5 * (gamma[i * dim + j] + gamma[j * dim + i]);
+    for (int j = 0; j < dim; ++j)
+      a[i * dim + j] = 0.5 * (gamma[i * dim + j] + gamma[j * dim + i]) / (dg[i] * dg[j]);
   jacobi(a, dim, w, v);
   double wmax = 0.0;
   for (double x : w) wmax = std::fmax(wmax, x);
@@ -212,7 +217,9 @@ lt_status lt_fisher_draw(const double* x0, const double* gamma, int dim, const d
       inside = true;
       for (int i = 0; i < dim; ++i) {
         double acc = x0[i];
-        for (int k = 0; k < dim; ++k) acc += v[i * dim + k] * sd[k] * z[k];
+        double y = 0.0;
+        for (int k = 0; k < dim; ++k) y += v[i * dim + k] * sd[k] * z[k];
+        acc += y / dg[i];
         o[i] = acc;
         if (!(acc >= lo[i] && acc <= hi[i])) inside = false;
       }

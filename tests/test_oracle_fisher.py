@@ -73,3 +73,38 @@ def test_fisher_draw_covariance():
     box_lo, box_hi = x0 - 0.5, x0 + 0.5
     st = f(x0.ctypes.data, G.ctypes.data, d, box_lo.ctypes.data, box_hi.ctypes.data, 1000, 7, 0.0, out.ctypes.data)
     assert st == 0 and np.all(out[:1000] >= box_lo) and np.all(out[:1000] <= box_hi)
+
+
+def test_fisher_draw_badly_scaled():
+    """The eigen floor acts in the unit-diagonal basis: a Fisher matrix whose coordinates differ by
+    ten decades in scale (masses next to angles) is sampled exactly at reg = 1e-12, where a floor on
+    the raw eigenvalues would flatten the large-unit directions."""
+    from paper_2501_08261_amd import build
+    so = os.path.join(ROOT, "paper_2501_08261_amd", "liblisatd.so")
+    if not os.path.exists(so):
+        build.build(verbose=False)
+    lib = ctypes.CDLL(so)
+    f = lib.lt_fisher_draw
+    f.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    rng = np.random.default_rng(1)
+    d = 4
+    A = rng.normal(size=(d, d))
+    R = A @ A.T + 0.5 * np.eye(d)
+    S = np.diag([1e5, 1.0, 1e-5, 1.0])
+    G = S @ R @ S
+    w = np.linalg.eigvalsh(G)
+    assert w.min() < 1e-12 * w.max()          # a raw-basis floor at 1e-12 would change this matrix
+    x0 = np.array([1.0, 2.0, -1.0, 0.5])
+    C = np.linalg.inv(G)
+    sd = np.sqrt(np.diag(C))
+    lo, hi = x0 - 100 * sd, x0 + 100 * sd
+    n = 40000
+    out = np.zeros((n, d))
+    st = f(x0.ctypes.data, G.ctypes.data, d, lo.ctypes.data, hi.ctypes.data, n, 11, 1e-12, out.ctypes.data)
+    assert st == 0
+    z = (out - x0) / sd
+    Cz = C / np.outer(sd, sd)
+    assert np.allclose(z.mean(0), 0.0, atol=4 / np.sqrt(n))
+    assert np.allclose(np.cov(z.T), Cz, rtol=0.05, atol=0.03)
