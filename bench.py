@@ -26,13 +26,12 @@ sys.path.insert(0, ROOT)
 # calibration), keyed by (kernel, batch, samples, taps, precision).  Any other
 # configuration, or a changed kernel, reports null.
 PMC_TRAFFIC = {
-    # profiles/k_tdi_precessing_k8_2p20_b256.md: FETCH 0.774 GiB + WRITE 0.750 GiB per 64-template launch
-    ("tdi_response", 64, 2 ** 20, 8, "mixed"): int((0.774 + 0.750) * 2 ** 30),
+    # profiles/k_tdi_precessing_k8_2p20_b256.md: FETCH 2.412 GiB + WRITE 3.000 GiB per 256-template launch
+    ("tdi_response", 256, 2 ** 20, 8, "mixed"): int((2.412 + 3.000) * 2 ** 30),
 }
 
 N_SAMPLES = 2 ** 20
 BATCH = 256
-PROFILE_CHUNK = 64      # templates per launch of the pipelined likelihood
 TAPS = 8
 
 
@@ -349,15 +348,11 @@ def main():
     value = a.batch * a.steps / elapsed
     print("timed %d steps: %.3f ms/step" % (a.steps, ms_per_step), file=sys.stderr, flush=True)
 
-    # per-kernel averages from HIP events recorded on the launch stream.  The pipelined call runs
-    # a chunk's FFT beside the next chunk's response kernel, which stretches both durations; this
-    # pass makes the same 64-template launches one call at a time (one stream), so each event
-    # pair times its kernel alone
+    # per-kernel averages from HIP events that the library records around each launch on its
+    # stream (every launch of the likelihood is on the caller's stream), over a few more steps
     ctx.profile_enable(True)
     for _ in range(a.profile_steps):
-        for c0 in range(0, a.batch, PROFILE_CHUNK):
-            c1 = min(a.batch, c0 + PROFILE_CHUNK)
-            ctx.tdi_loglike(params[c0:c1], g, cfg, orb, tdi, S, d[0], ddv, logl[c0:c1], status=status[c0:c1])
+        step()
     torch.cuda.synchronize()
     ms, cnt = ctx.profile_read(5)
     ctx.profile_enable(False)

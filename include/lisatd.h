@@ -147,15 +147,11 @@ lt_status lt_lisa_tdi_response(lt_ctx* ctx, const double* params, int64_t batch,
  * with (a|b) = 4 df Re sum_{band} a~ conj(b~) / S (Eq. 2.13), a~ = dt * DFT.
  * Computed as -(r|r)/2 + dd/2 with the residual r = h - d formed in the time
  * domain.  logl, logl_full (nullable): device FP64 [batch]; status (nullable):
- * device int32 [batch].  Scratch memory is owned by the context.  Batches
- * below 128 run on `stream` in chunks of up to 256 templates.  Larger
- * batches run as a pipeline in chunks of 64: the response of one chunk on
- * `stream` while the FFT, band sums and logL of the previous chunk run on a
- * second stream owned by the context.  Fork and join are event dependencies,
- * so the whole call is ordered on `stream` and can be captured into a HIP
- * graph.  Results are bit-identical either way.  Scratch holds at most
- * 5 x 256 series of n samples (FP64 or FP32 by precision), whatever the
- * batch.  Calls sharing a context must be ordered (same stream, or
+ * device int32 [batch].  Scratch memory is owned by the context.  Every
+ * launch runs on `stream`, in chunks of up to 256 templates, so the call can
+ * be captured into a HIP graph; a template's results do not depend on the
+ * batch it came in.  Scratch holds at most 5 x 256 series of n samples (FP64
+ * or FP32 by precision), whatever the batch.  Calls sharing a context must be ordered (same stream, or
  * synchronised by the caller). */
 lt_status lt_tdi_loglike(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
                          const lt_grid* grid, const lt_orbit* orbit, const lt_tdi_cfg* tdi,

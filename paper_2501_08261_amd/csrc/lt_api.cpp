@@ -75,16 +75,6 @@ struct lt_ctx {
            std::unique_ptr<OrbitTab>>
       orbits;
   DevBuf tpl, work, partial, wperm, status, wave, nodes, refs;
-  // two-slot pipeline of lt_tdi_loglike: the FFT of one chunk (memory bound) runs on
-  // `aux` while the response of the next (VALU bound) runs on the caller's stream
-  DevBuf work2, partial2;
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_tdi[2] = {nullptr, nullptr}, ev_fft[2] = {nullptr, nullptr};
-  ~lt_ctx() {
-    for (hipEvent_t e : {ev_fork, ev_tdi[0], ev_tdi[1], ev_fft[0], ev_fft[1]})
-      if (e) (void)hipEventDestroy(e);
-    if (aux) (void)hipStreamDestroy(aux);
-  }
   bool profiling = false;
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
@@ -480,8 +470,9 @@ static TermTable make_terms(int gen) {
 }
 
 // ------------------------------------------------------------------ checks
-constexpr int64_t kLoglikeChunk = 256;   // single-stream chunk
-constexpr int64_t kPipeChunk = 64;       // pipelined chunk (batches of at least 2 x 64)
+// templates per launch of lt_tdi_loglike: bounds the workspace (2 waveform + 3 TDI series
+// of n samples per template) and amortises the per-launch tables and the launch tails
+constexpr int64_t kLoglikeChunk = 256;
 
 static lt_status check_common(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g) {
   if (!c) return fail(LT_ERR_NULL, "null context");
@@ -724,73 +715,31 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
   // every template's constants once (one launch); the chunks below reuse them
   st = do_setup(c, params, batch, cfg, g, stat, s);
   if (st) return st;
-  if (batch < 2 * kPipeChunk) {
-    // one stream; templates in chunks so that the workspace stays bounded
-    // (per chunk: 2 waveform + 3 TDI series of n samples per template)
-    const int64_t chunk = batch < kLoglikeChunk ? batch : kLoglikeChunk;
-    LT_HIP(c->work.ensure((size_t)chunk * 3 * g->n * rsz));
-    for (int64_t off = 0; off < batch; off += chunk) {
-      const int64_t b = batch - off < chunk ? batch - off : chunk;
-      st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, c->work.p, stat + off, s,
-                   (const TplConst*)c->tpl.p + off);
-      if (st) return st;
-      st = band_power(c, p, c->work.p, b * 3, cfg->precision, psd, g, t->channels, s);
-      if (st) return st;
-      Prof pr(c, 4, s);
-      LT_HIP(launch_finalize((const double*)c->partial.p, b, nfold, scale, data->dd, stat + off,
-                             logl ? logl + off : nullptr, logl_full ? logl_full + off : nullptr, nullptr, s));
-    }
-    return LT_OK;
-  }
-  // Pipelined: chunk i's response runs on s into slot i % 2 while chunk i - 1's FFT, band
-  // reduction and logL run on c->aux; s waits for the FFT of chunk i - 2 before reusing a slot.
-  // Fork and join go through events, so the whole call can be captured into a graph.
-  if (!c->aux) {
-    LT_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-    LT_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-    for (int i = 0; i < 2; ++i) {
-      LT_HIP(hipEventCreateWithFlags(&c->ev_tdi[i], hipEventDisableTiming));
-      LT_HIP(hipEventCreateWithFlags(&c->ev_fft[i], hipEventDisableTiming));
-    }
-  }
   int k_lo, k_hi;
   st = band_bins(g, psd, &k_lo, &k_hi);
   if (st) return st;
-  const int64_t chunk = kPipeChunk;
-  DevBuf* work[2] = {&c->work, &c->work2};
-  DevBuf* part[2] = {&c->partial, &c->partial2};
-  for (int i = 0; i < 2; ++i) {
-    LT_HIP(work[i]->ensure((size_t)chunk * 3 * g->n * rsz));
-    LT_HIP(part[i]->ensure((size_t)chunk * 3 * nfold * sizeof(double)));
-  }
-  LT_HIP(c->wperm.ensure((size_t)3 * (g->n / 2 + 1) * sizeof(double)));
+  // one stream, chunks of kLoglikeChunk templates: the response kernel already fills the
+  // GPU, and running a chunk's FFT beside the next chunk's response on a second stream
+  // measured no faster than this
+  const int64_t chunk = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+  LT_HIP(c->work.ensure((size_t)chunk * 3 * g->n * rsz));
+  LT_HIP(c->partial.ensure((size_t)chunk * 3 * nfold * sizeof(double)));
+  LT_HIP(c->wperm.ensure((size_t)3 * (p->dev.n + 1) * sizeof(double)));
   {
     Prof pr(c, 0, s);   // per-call table, timed with the setup
     LT_HIP(launch_weights(p->dev, psd->S, k_lo, k_hi, t->channels, (double*)c->wperm.p, s));
   }
-  LT_HIP(hipEventRecord(c->ev_fork, s));
-  LT_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-  int64_t i = 0;
-  for (int64_t off = 0; off < batch; off += chunk, ++i) {
-    const int slot = (int)(i & 1);
+  for (int64_t off = 0; off < batch; off += chunk) {
     const int64_t b = batch - off < chunk ? batch - off : chunk;
-    if (i >= 2) LT_HIP(hipStreamWaitEvent(s, c->ev_fft[slot], 0));
-    st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, work[slot]->p, stat + off, s,
+    st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, c->work.p, stat + off, s,
                  (const TplConst*)c->tpl.p + off);
     if (st) return st;
-    LT_HIP(hipEventRecord(c->ev_tdi[slot], s));
-    LT_HIP(hipStreamWaitEvent(c->aux, c->ev_tdi[slot], 0));
-    st = fft_band(c, p, work[slot]->p, b * 3, cfg->precision, k_lo, k_hi, g, (double*)part[slot]->p, c->aux);
+    st = fft_band(c, p, c->work.p, b * 3, cfg->precision, k_lo, k_hi, g, (double*)c->partial.p, s);
     if (st) return st;
-    {
-      Prof pr(c, 4, c->aux);
-      LT_HIP(launch_finalize((const double*)part[slot]->p, b, nfold, scale, data->dd, stat + off,
-                             logl ? logl + off : nullptr, logl_full ? logl_full + off : nullptr, nullptr, c->aux));
-    }
-    LT_HIP(hipEventRecord(c->ev_fft[slot], c->aux));
+    Prof pr(c, 4, s);
+    LT_HIP(launch_finalize((const double*)c->partial.p, b, nfold, scale, data->dd, stat + off,
+                           logl ? logl + off : nullptr, logl_full ? logl_full + off : nullptr, nullptr, s));
   }
-  // join: the caller's stream sees every chunk's logL (the last record covers all of aux)
-  LT_HIP(hipStreamWaitEvent(s, c->ev_fft[(int)((i - 1) & 1)], 0));
   return LT_OK;
 }
 

@@ -400,14 +400,14 @@ def test_noisy_data_loglike(lt):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_loglike_pipeline_equals_single_stream(lt, precision):
-    """Batches of 128 or more templates run as a two-stream pipeline (response of one chunk
-    while the FFT of the previous one runs): bit-identical to the single-stream path, and one
-    invalid template stays isolated to its own slot."""
+def test_loglike_chunks_equal_split_calls(lt, precision):
+    """Batches above 256 templates run in chunks of 256: bit-identical to the same templates
+    split over smaller calls, and one invalid template stays isolated to its own slot."""
     lib, ctx = lt
     n = 8192
     g = inputs.grid(n, 5.0)
-    P = inputs.draw_templates(21, 130, g, precessing=True, before_end=1000.0)
+    B = 300
+    P = inputs.draw_templates(21, B, g, precessing=True, before_end=1000.0)
     P[77, 4] = 1.5                                  # |chi1| > 1: status 1, logL = -inf
     S = _psd_dev(lib, g, 20)
     cfg, orb, tdi = ctx.wf_cfg(MODES_ALL, True, precision=precision), ctx.orbit("kepler"), ctx.tdi_cfg(20, 7, 8)
@@ -417,14 +417,14 @@ def test_loglike_pipeline_equals_single_stream(lt, precision):
     ctx.noise_inner(d, g, S, dd, precision=precision)
     torch.cuda.synchronize()
     Pd = _dev(P)
-    one = torch.zeros(130, dtype=torch.float64, device=DEV)
-    one_full = torch.zeros(130, dtype=torch.float64, device=DEV)
-    st1 = torch.full((130,), -7, dtype=torch.int32, device=DEV)
+    one = torch.zeros(B, dtype=torch.float64, device=DEV)
+    one_full = torch.zeros(B, dtype=torch.float64, device=DEV)
+    st1 = torch.full((B,), -7, dtype=torch.int32, device=DEV)
     ctx.tdi_loglike(Pd, g, cfg, orb, tdi, S, d[0], float(dd.item()), one, one_full, st1)
-    two = torch.zeros(130, dtype=torch.float64, device=DEV)
-    two_full = torch.zeros(130, dtype=torch.float64, device=DEV)
-    st2 = torch.full((130,), -7, dtype=torch.int32, device=DEV)
-    for a, b in ((0, 100), (100, 130)):             # both below the pipeline threshold
+    two = torch.zeros(B, dtype=torch.float64, device=DEV)
+    two_full = torch.zeros(B, dtype=torch.float64, device=DEV)
+    st2 = torch.full((B,), -7, dtype=torch.int32, device=DEV)
+    for a, b in ((0, 100), (100, 130), (130, B)):   # chunk boundaries elsewhere
         ctx.tdi_loglike(Pd[a:b].contiguous(), g, cfg, orb, tdi, S, d[0], float(dd.item()), two[a:b], two_full[a:b],
                         st2[a:b])
     torch.cuda.synchronize()

@@ -173,10 +173,10 @@ def test_fisher_parity(lib):
     ctx.close()
 
 
-def test_captured_pipeline_matches_direct_loglike(lib):
-    """Half-steps of 128 templates use the two-stream likelihood pipeline inside the captured
-    graph: after set-up and after captured steps every walker's logL equals a direct
-    single-stream evaluation of its position (bit for bit)."""
+def test_captured_step_matches_direct_loglike(lib):
+    """Half-steps of 128 templates run the likelihood inside the captured graph: after set-up
+    and after captured steps every walker's logL equals a direct evaluation of its position in
+    smaller calls (bit for bit)."""
     from paper_2501_08261_amd.lib import Context
     n = 4096
     gr = inputs.grid(n, 5.0)
@@ -200,7 +200,7 @@ def test_captured_pipeline_matches_direct_loglike(lib):
     def direct(pos):
         P = torch.tensor(to_params(pos.reshape(-1, 10), "aligned10", inj[11]), device=DEV)
         out = torch.zeros(P.shape[0], dtype=torch.float64, device=DEV)
-        for a in range(0, P.shape[0], 100):                    # single-stream chunks
+        for a in range(0, P.shape[0], 100):                    # calls of 100 templates
             b = min(a + 100, P.shape[0])
             ctx.tdi_loglike(P[a:b].contiguous(), gr, cfg, orb, tdi, S, d_aet[0], dd.item(), out[a:b])
         torch.cuda.synchronize()
