@@ -291,7 +291,7 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % a.gpus,
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
