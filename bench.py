@@ -68,7 +68,7 @@ def cpu_baseline(g, params, taps):
     from threadpoolctl import threadpool_limits
     limiter = threadpool_limits(1)      # numpy's thread pools pinned: the oracle runs on one core
     n = g["n"]
-    slice_len = 1 << 13
+    slice_len = 1 << 17
     r = Response(Template(params[0]), g["t0"], g["dt"], n, Orbit("kepler"), taps=taps, precessing=True,
                  generation=20)
     idx = np.arange(n - slice_len - 4096, n - 4096)

@@ -351,14 +351,18 @@ __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* d
   }
 }
 
-// pass 2 for n2 = 1024: two row pairs (up to four rows) per workgroup
+// pass 2 for n2 = 1024: two row pairs (up to four rows) per workgroup.  In FP32 a row keeps a
+// spare LDS slot per eight elements (row stride LS = N2 + N2 / 8 + 1), as in pass 1: the
+// Stockham stages' strided writes then spread over the banks.
 template <typename R>
 __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* data, int mode, double dt,
                                                     C2<R>* spec, const double* wperm, double* partial,
                                                     int64_t kb_lo, int64_t kb_hi) {
   constexpr int N1 = 512, N2 = 1024, NR = 4;
+  constexpr bool PAD = sizeof(R) == 4;
+  constexpr int LS = PAD ? N2 + N2 / 8 + 1 : N2;
   constexpr int64_t n = (int64_t)N1 * N2;
-  __shared__ C2<R> buf[NR * N2];
+  __shared__ C2<R> buf[NR * LS];
   __shared__ int rowk1[NR];
   __shared__ double red[kFT / 64];
   const int64_t row = blockIdx.y;
@@ -384,11 +388,14 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       v[m] = k1 >= 0 ? z[(int64_t)k1 * N2 + (i % N2)] : C2<R>{(R)0, (R)0};
     }
 #pragma unroll
-    for (int m = 0; m < PT; ++m) buf[threadIdx.x + m * kFT] = v[m];
+    for (int m = 0; m < PT; ++m) {
+      const int i = threadIdx.x + m * kFT;
+      buf[(i / N2) * LS + lix<PAD>(i % N2)] = v[m];
+    }
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw2d, p.tw2f);
-  ct_fft<R, N2, NR, 1, 4, 4, 8, 8>(buf, tw);
+  ct_fft_strided<R, N2, LS, kFT, PAD, NR, 1, 4, 4, 8, 8>(buf, tw);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   double acc = 0.0;
@@ -417,13 +424,13 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       for (int r = 0; r < NR; ++r) {
         if (!on[r]) continue;
         const int k1 = rowk1[r];
-        const C2<R> Zk = buf[r * N2 + k2];
+        const C2<R> Zk = buf[r * LS + lix<PAD>(k2)];
         C2<R> Zm;
         if (k1 == 0) {
-          Zm = buf[r * N2 + (N2 - k2) % N2];
+          Zm = buf[r * LS + lix<PAD>((N2 - k2) % N2)];
         } else {
           const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
-          Zm = buf[rm * N2 + (N2 - 1 - k2)];
+          Zm = buf[rm * LS + lix<PAD>(N2 - 1 - k2)];
         }
         const C2<R> zc = {Zm.x, -Zm.y};
         const C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
@@ -452,12 +459,12 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       k1 = rowk1[r];
       if (k1 < 0) continue;
       k = k1 + (int64_t)N1 * k2;
-      Zk = buf[i];
+      Zk = buf[r * LS + lix<PAD>(k2)];
       if (k1 == 0) {
-        Zm = buf[r * N2 + (N2 - k2) % N2];
+        Zm = buf[r * LS + lix<PAD>((N2 - k2) % N2)];
       } else {
         const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
-        Zm = buf[rm * N2 + (N2 - 1 - k2)];
+        Zm = buf[rm * LS + lix<PAD>(N2 - 1 - k2)];
       }
     } else {
       if (pa != 0) continue;
