@@ -26,8 +26,6 @@ sys.path.insert(0, ROOT)
 # calibration), keyed by (kernel, batch, samples, taps, precision).  Any other
 # configuration, or a changed kernel, reports null.
 PMC_TRAFFIC = {
-    # profiles/k_tdi_precessing_k8_2p20_b256.md: FETCH 2.412 GiB + WRITE 3.000 GiB per 256-template launch
-    ("tdi_response", 256, 2 ** 20, 8, "mixed"): int((2.412 + 3.000) * 2 ** 30),
 }
 
 N_SAMPLES = 2 ** 20

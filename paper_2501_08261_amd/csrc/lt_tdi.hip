@@ -526,6 +526,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   R* hpb = yb + 6 * MYP;
   R* hxb = hpb + WMAX;
   double* nd = (double*)(smem + (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15));
+  // FP32 copies of the projections P+, Px of each node (mixed precision: they scale an FP32 product)
+  float* ndp = (float*)(nd + NNMAX * kNodeVals);
   const unsigned char* rec = (const unsigned char*)P.refs + (size_t)tile * Lay::stride;
   const double* tf0 = (const double*)(rec + Lay::f0);
   const int* tjr = (const int*)(rec + Lay::jr);
@@ -560,6 +562,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     double nv = 0.0;
     if (tid < nval) nv = ng[(tid / kNodeVals) * kNodeRec + tid % kNodeVals];
     for (int i = tid + kNT; i < nval; i += kNT) nd[i] = ng[(i / kNodeVals) * kNodeRec + i % kNodeVals];
+    if constexpr (sizeof(R) == 4)
+      for (int i = tid; i < NN * 12; i += kNT) ndp[i] = (float)ng[(i / 12) * kNodeRec + (i % 12 / 2) * kNL + (i & 1)];
     constexpr int kA = 6;
     const R* hg = (const R*)P.h + (2 * (int64_t)b) * N;
     for (int i0 = 0; i0 < W; i0 += kA * kNT) {
@@ -588,6 +592,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     const int64_t q0 = floordiv(m_lo + tid, S);
     double w[4];
     cubic_w((double)(m_lo + tid - q0 * S) / (double)S, w);
+    const float wp[4] = {(float)w[0], (float)w[1], (float)w[2], (float)w[3]};
     const int jl0 = (int)(q0 + P.orb.j0 - jn_lo);
     for (int mi = tid, it = 0; mi < MY; mi += kNT, ++it) {
       int64_t m = m_lo + mi;
@@ -608,18 +613,25 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
       }
 #pragma unroll
       for (int li = 0; li < 6; ++li) {
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        R v0 = (R)0, v1 = (R)0;
+        double v2 = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const double* o = o0 + r * kNodeVals + li * kNL;
-          v0 += w[r] * o[0];
-          v1 += w[r] * o[1];
+          if constexpr (sizeof(R) == 4) {
+            const float* op = ndp + (jl0 + it - 1 + r) * 12 + 2 * li;
+            v0 += wp[r] * op[0];
+            v1 += wp[r] * op[1];
+          } else {
+            v0 += w[r] * o[0];
+            v1 += w[r] * o[1];
+          }
           v2 += w[r] * o[2];
         }
         R hps, hxs;
         lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
         const int rc = kRecv[li];
-        yb[li * MYP + mi] = (R)v0 * (hps - hpr[rc]) + (R)v1 * (hxs - hxr[rc]);
+        yb[li * MYP + mi] = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
       }
     }
     // zero the tail of each y series up to its padded length: filter taps beyond the data read it
@@ -790,7 +802,8 @@ struct TdiGeom {
     if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
     if (!P.nodes || !P.refs) return hipErrorInvalidValue;
     constexpr int JMAX = CombLen<K>::value;
-    bytes = (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) + (size_t)NNMAX * kNodeVals * sizeof(double);
+    bytes = (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) + (size_t)NNMAX * kNodeVals * sizeof(double) +
+            (sizeof(R) == 4 ? (size_t)NNMAX * 12 * sizeof(float) : 0);
     if (bytes > 160 * 1024) return hipErrorInvalidValue;
     // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
     const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
