@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 # calibration), keyed by (kernel, batch, samples, taps, precision).  Any other
 # configuration, or a changed kernel, reports null.
 PMC_TRAFFIC = {
+    # profiles/k_tdi_precessing_k8_2p20_b256.md: FETCH 2.412 GiB + WRITE 3.000 GiB per 256-template launch
+    ("tdi_response", 256, 2 ** 20, 8, "mixed"): int((2.412 + 3.000) * 2 ** 30),
 }
 
 N_SAMPLES = 2 ** 20
@@ -87,6 +89,11 @@ def cpu_baseline(g, params, taps):
                                                               per * slice_len / n + t_fft)}
 
 
+# eigenvalue floor of the Fisher draws, relative to the largest eigenvalue of the unit-diagonal
+# Fisher matrix (lt_fisher_draw): near-degenerate directions start at most 1000 times wider than
+# the conditional widths.  At 1e-12 the precessing start spreads over the prior box and 2100
+# burn-in steps leave the chains far from equilibrium (autocorrelation times near 100 steps)
+FISHER_REG = 1e-6
 FISHER_STEPS_P14 = [1.0, 1.0, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1e-4, 1.0, 1e-5, 1e-5, 1e-5, 1e-5, 1e-5]
 
 
@@ -116,7 +123,7 @@ def _sampler(lib, inputs, ctx, su, W, T, seed):
     x0, lo, hi = inputs.tab1_prior(True, su["inj"])
     G = lib.fisher(ctx, x0, "precessing14", su["inj"][11], FISHER_STEPS_P14, su["g"], su["cfg64"], su["orb"],
                    su["tdi"], su["S"])
-    start = lib.fisher_draw(x0, G, lo, hi, T * W, seed, 1e-12)
+    start = lib.fisher_draw(x0, G, lo, hi, T * W, seed, FISHER_REG)
     smp = lib.Sampler(W, T, 14, lo, hi, seed, target="tdi", param_kind="precessing14", t_c=su["inj"][11],
                       g=su["g"], cfg=su["cfg"], orbit=su["orb"], tdi=su["tdi"], psd=su["S"], data_aet=su["d"][0],
                       dd=su["dd"])
@@ -158,8 +165,41 @@ def _record(smp, k):
     return np.array(chain)
 
 
+def dominant_mode(s, min_sep=8.0, min_frac=0.02, axes=4):
+    """The samples of the more populated of two clusters when s holds two well separated modes,
+    else all of s; and the fraction kept.  Two-means on coordinates scaled by their standard
+    deviations, started from a split at the median along each of the first `axes` principal
+    axes; the best separated split counts when the Mahalanobis distance between its means
+    under the pooled within-cluster covariance is at least min_sep (a median split of one
+    Gaussian gives about 2.7) and its smaller part holds at least min_frac of the samples."""
+    import numpy as np
+    z = (s - s.mean(0)) / s.std(0)
+    vt = np.linalg.svd(z, full_matrices=False)[2]
+    best, best_sep = None, 0.0
+    for a in range(min(axes, z.shape[1])):
+        p = z @ vt[a]
+        lab = p > np.median(p)
+        for _ in range(50):
+            new = ((z - z[lab].mean(0)) ** 2).sum(1) < ((z - z[~lab].mean(0)) ** 2).sum(1)
+            if np.array_equal(new, lab) or new.all() or not new.any():
+                break
+            lab = new
+        if lab.all() or not lab.any():
+            continue
+        d = z[lab].mean(0) - z[~lab].mean(0)
+        f = lab.mean()
+        sw = f * np.cov(z[lab].T) + (1.0 - f) * np.cov(z[~lab].T)
+        sep = float(np.sqrt(d @ np.linalg.solve(sw, d)))
+        if sep > best_sep:
+            best, best_sep = lab, sep
+    if best is None or best_sep < min_sep or min(best.mean(), 1.0 - best.mean()) < min_frac:
+        return s, 1.0
+    keep = best if best.mean() >= 0.5 else ~best
+    return s[keep], float(keep.mean())
+
+
 def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=500, rounds=4, window=400,
-              train_steps=1500, m=1000, walk=0.0):
+              train_steps=1500, m=1000, walk=0.0, split_modes=True):
     """Effective samples per second of the cold chain, stretch moves alone against
     stretch + learned-flow moves, on one injection and one GPU (TDI-2 AET, 512
     walkers x 8 temperatures, n samples around the merger, Fisher-initialised).
@@ -203,7 +243,7 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
                    tdi, S)
     smp = lib.Sampler(W, T, dim, lo, hi, 5, target="tdi", param_kind=kind, t_c=inj[11], g=g, cfg=cfg, orbit=orb,
                       tdi=tdi, psd=S, data_aet=d[0], dd=float(dd.item()))
-    smp.set_state(lib.fisher_draw(x0, G, lo, hi, T * W, 5, 1e-12))
+    smp.set_state(lib.fisher_draw(x0, G, lo, hi, T * W, 5, FISHER_REG))
     t0 = time.perf_counter()
     smp.step(burn)
     flow = lib.Flow(dim, 8, 256, max(2048, W))
@@ -216,11 +256,15 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         return X
 
     t_train = 0.0
+    mode_frac = []
     for r in range(rounds):
         s = _record(smp, window).reshape(-1, dim)
         two = 2.0 * s[:, ipsi]
         start = 0.5 * np.arctan2(np.sin(two).mean(), np.cos(two).mean()) - 0.5 * np.pi
         s = fold(s, start)
+        if split_modes:
+            s, kept = dominant_mode(s)
+            mode_frac.append(kept)
         smp.set_flow_fold(ipsi, np.pi, start)
         smp.set_flow_walk(walk)
         flow.set_whitening(s.mean(0), np.linalg.cholesky(np.cov(s.T)))
@@ -279,6 +323,7 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     ctx.close()
     return {"target": kind, "flow_move": "latent walk, step %g" % walk if walk > 0 else "independence",
             "n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
+            "flow_training_share": mode_frac,
             "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": rounds * train_steps,
             "plain": res["plain"], "learned": res["learned"],
             "ratio": res["learned"]["ess_per_s"] / res["plain"]["ess_per_s"],

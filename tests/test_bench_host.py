@@ -1,0 +1,40 @@
+"""Host logic of bench.py that runs without a GPU: the training-set selection of the learned
+proposal (two-cluster split of the cold samples)."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_dominant_mode_splits_two_separated_modes():
+    rng = np.random.default_rng(0)
+    a = 0.01 * rng.standard_normal((8000, 14))
+    b = 0.01 * rng.standard_normal((2000, 14))
+    b[:, 5] += 0.15
+    b[:, 6] += 0.4
+    kept, frac = bench.dominant_mode(np.vstack([a, b]))
+    assert frac == 0.8 and kept.shape == (8000, 14)
+    assert np.abs(kept[:, 5]).max() < 0.075           # every kept sample from the larger mode
+
+
+def test_dominant_mode_keeps_unimodal_samples():
+    rng = np.random.default_rng(1)
+    g = rng.standard_normal((10000, 14))
+    kept, frac = bench.dominant_mode(g)
+    assert frac == 1.0 and kept.shape == g.shape
+    c = rng.standard_normal((10000, 14))
+    c[:, 1] = 0.99 * c[:, 0] + 0.01 * c[:, 1]          # a narrow correlated ridge is one mode
+    kept, frac = bench.dominant_mode(c)
+    assert frac == 1.0
+
+
+def test_dominant_mode_ignores_a_tiny_cluster():
+    rng = np.random.default_rng(2)
+    a = 0.01 * rng.standard_normal((9950, 6))
+    b = 0.01 * rng.standard_normal((50, 6)) + 1.0      # 0.5 %: below the 2 % floor
+    kept, frac = bench.dominant_mode(np.vstack([a, b]))
+    assert frac == 1.0
