@@ -276,6 +276,49 @@ def test_tdi_full_size_sampled(lt, precision):
             assert np.max(np.abs(got - want)) < 24.0 * math.sqrt(K) * U32 * hmax, b
 
 
+def test_loglike_full_size_composition(lt):
+    """The bench workload at full size in its launch configuration (256 precessing templates,
+    2^20 samples, Kepler arms, TDI 2.0, K = 8, mixed precision, one launch per kernel): a
+    template equal to the data has logL_full exactly 0 and logL = dd / 2; for the lightest, a
+    median and the heaviest template, logL_full equals -1/2 (r|r) of the residual r = h - d
+    built from the response (checked against the oracle at this size in
+    test_tdi_full_size_sampled) and the band inner product (checked against the oracle at
+    2^20 in test_band_inner_parity)."""
+    lib, ctx = lt
+    n, B, K = 2 ** 20, 256, 8
+    g = inputs.grid(n, 5.0)
+    P = inputs.draw_templates(3, B, g, precessing=True)
+    inj = inputs.tab1_injection(True, g)
+    P[17] = inj
+    cfg = ctx.wf_cfg(MODES_ALL, True, precision=lib.LT_MIXED)
+    orb, tdi = ctx.orbit("kepler"), ctx.tdi_cfg(20, 7, K)
+    S = _psd_dev(lib, g, 20)
+    d = torch.zeros((1, 3, n), dtype=torch.float32, device=DEV)
+    ctx.lisa_tdi_response(_dev(inj[None]), g, cfg, orb, tdi, d)
+    dd = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ctx.noise_inner(d, g, S, dd, precision=lib.LT_MIXED)
+    torch.cuda.synchronize()
+    ddv = float(dd.item())
+    logl = torch.zeros(B, dtype=torch.float64, device=DEV)
+    full = torch.zeros(B, dtype=torch.float64, device=DEV)
+    st = torch.full((B,), -7, dtype=torch.int32, device=DEV)
+    ctx.tdi_loglike(_dev(P), g, cfg, orb, tdi, S, d[0], ddv, logl, full, st)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    assert full[17].item() == 0.0 and logl[17].item() == 0.5 * ddv
+    M = P[:, 0] + P[:, 1]
+    pick = [int(np.argmin(M)), int(np.argsort(M)[B // 2]), int(np.argmax(M))]
+    h = torch.zeros((3, 3, n), dtype=torch.float32, device=DEV)
+    ctx.lisa_tdi_response(_dev(P[pick]), g, cfg, orb, tdi, h)
+    rr = torch.zeros(3, dtype=torch.float64, device=DEV)
+    ctx.noise_inner((h - d).contiguous(), g, S, rr, precision=lib.LT_MIXED)
+    torch.cuda.synchronize()
+    want = -0.5 * rr.cpu().numpy()
+    got = full.cpu().numpy()[pick]
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-9 * ddv), (got, want)
+    assert np.allclose(logl.cpu().numpy()[pick], got + 0.5 * ddv, rtol=1e-12, atol=1e-9 * ddv)
+
+
 def test_xyz_output(lt):
     lib, ctx = lt
     n = 3000
