@@ -165,6 +165,14 @@ def _record(smp, k):
     return np.array(chain)
 
 
+def flow_gemm_flops(d, layers=8, hidden=256):
+    """Matrix-core work of one training sample of the flow: per coupling the products with
+    W1[H][|A|], W2[H][H] and W3[2|B|][H] (|A| = floor(d/2), |B| = d - |A|), 2 flops per
+    multiply-add, three times over (forward, input gradients, weight gradients)."""
+    a = d // 2
+    return 3 * layers * 2 * (hidden * a + hidden * hidden + 2 * (d - a) * hidden)
+
+
 def dominant_mode(s, min_sep=8.0, min_frac=0.02, axes=4):
     """The samples of the more populated of two clusters when s holds two well separated modes,
     else all of s; and the fraction kept.  Two-means on coordinates scaled by their standard
@@ -325,6 +333,7 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
             "n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
             "flow_training_share": mode_frac,
             "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": rounds * train_steps,
+            "flow_train_tflops": flow_gemm_flops(dim) * 2048 * rounds * train_steps / t_train / 1e12,
             "plain": res["plain"], "learned": res["learned"],
             "ratio": res["learned"]["ess_per_s"] / res["plain"]["ess_per_s"],
             "posterior_mean_shift_sigma": shift, "posterior_std_ratio": [round(x, 3) for x in std_ratio],

@@ -38,3 +38,11 @@ def test_dominant_mode_ignores_a_tiny_cluster():
     b = 0.01 * rng.standard_normal((50, 6)) + 1.0      # 0.5 %: below the 2 % floor
     kept, frac = bench.dominant_mode(np.vstack([a, b]))
     assert frac == 1.0
+
+
+def test_flow_gemm_flops_counts_every_weight_three_times():
+    # one multiply-add per weight of W1[H][|A|], W2[H][H], W3[2|B|][H] in each pass
+    for d, layers, hidden in ((10, 8, 256), (14, 8, 256), (5, 3, 16)):
+        a, b = d // 2, d - d // 2
+        weights = layers * (hidden * a + hidden * hidden + 2 * b * hidden)
+        assert bench.flow_gemm_flops(d, layers, hidden) == 3 * 2 * weights
