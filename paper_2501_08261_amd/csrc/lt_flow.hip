@@ -64,7 +64,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
   float16v acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = 0; k0 < K; k0 += 8) {
+  // K in rounds of 64: the operand fragments of eight products are loaded before the first of
+  // them runs (one memory latency per round instead of one per product); same product order
+  constexpr int KU = 8;
+  int k0 = 0;
+  for (; k0 + 8 * KU <= K; k0 += 8 * KU) {
+    short4v a[KU], b[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + 8 * u + lk + j;
+        a[u][j] = m < M ? (short)A[(int64_t)m * sAm + (int64_t)k * sAk] : (short)0;
+        b[u][j] = n < N ? (short)B[(int64_t)k * sBk + (int64_t)n * sBn] : (short)0;
+      }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[u], b[u], acc, 0, 0, 0);
+  }
+  for (; k0 < K; k0 += 8) {
     short4v a, b;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
