@@ -147,10 +147,31 @@ def sampler_bench(lib, inputs, prec, steps=3, W=512, T=8):
     dt = (time.perf_counter() - t0) / steps
     _, _, _, k, cnt = smp.state()
     smp.close()
+    # the likelihood alone: two calls of T W / 2 templates a step (the step's two half-ensembles),
+    # templates next to the injection (every one spans the whole grid, as the walkers' do)
+    import numpy as np
+    rng = np.random.default_rng(12)
+    P = np.repeat(su["inj"][None], T * W // 2, axis=0)
+    P[:, 0] *= 1.0 + 1e-5 * rng.standard_normal(T * W // 2)
+    P[:, 1] *= 1.0 + 1e-5 * rng.standard_normal(T * W // 2)
+    params = torch.tensor(P, device="cuda:0")
+    out = torch.zeros(T * W // 2, dtype=torch.float64, device="cuda:0")
+
+    def half():
+        ctx.tdi_loglike(params, su["g"], su["cfg"], su["orb"], su["tdi"], su["S"], su["d"][0], su["dd"], out)
+
+    half()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2 * steps):
+        half()
+    torch.cuda.synchronize()
+    dl = (time.perf_counter() - t0) / steps
     ctx.close()
     return {"walkers": W, "temps": T, "steps": steps, "ms_per_step": 1e3 * dt, "steps_per_s": 1.0 / dt,
             "logl_per_s": T * W / dt, "stretch_accept": cnt[0] / max(cnt[1], 1),
-            "swap_accept": cnt[2] / max(cnt[3], 1)}
+            "swap_accept": cnt[2] / max(cnt[3], 1), "loglike_only_ms_per_step": 1e3 * dl,
+            "overhead_ms_per_step": 1e3 * (dt - dl)}
 
 
 FISHER_STEPS_A10 = [1.0, 1.0, 1e-4, 1e-4, 1.0, 1e-5, 1e-5, 1e-5, 1e-5, 1e-5]
