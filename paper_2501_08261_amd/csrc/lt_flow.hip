@@ -115,14 +115,12 @@ __global__ void k_gather(const double* u, int n, int d, int c0, int w, bf16* out
 
 // coupling: s = S tanh(o_s / S); forward u_B <- u_B e^s + t, inverse
 // u_B <- (u_B - t) e^-s; logdet += sum s (the forward log-det in both cases)
-__global__ void k_couple(double* u, int n, int d, int b0, int nb, const float* o, double* s_out, double* ub_in,
-                         double* logdet, int inverse) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
+__device__ inline void couple_row(double* u, int r, int d, int b0, int nb, const float* orow, double* s_out,
+                                  double* ub_in, double* logdet, int inverse) {
   double ld = 0.0;
   for (int j = 0; j < nb; ++j) {
-    const double s = kSMax * tanh((double)o[(int64_t)r * 2 * nb + j] / kSMax);
-    const double t = (double)o[(int64_t)r * 2 * nb + nb + j];
+    const double s = kSMax * tanh((double)orow[j] / kSMax);
+    const double t = (double)orow[nb + j];
     double& x = u[(int64_t)r * d + b0 + j];
     if (ub_in) ub_in[(int64_t)r * nb + j] = x;
     if (s_out) s_out[(int64_t)r * nb + j] = s;
@@ -130,6 +128,108 @@ __global__ void k_couple(double* u, int n, int d, int b0, int nb, const float* o
     ld += s;
   }
   logdet[r] += ld;
+}
+
+__global__ void k_couple(double* u, int n, int d, int b0, int nb, const float* o, double* s_out, double* ub_in,
+                         double* logdet, int inverse) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  couple_row(u, r, d, b0, nb, o + (int64_t)r * 2 * nb, s_out, ub_in, logdet, inverse);
+}
+
+// One 32 x 32 output tile of act(A W^T + bias) for the fused coupling: A rows from LDS (BF16,
+// row stride lda, K columns), W [N][K] BF16 in global memory; the same operands, products and
+// product order as k_gemm, so the result is bit-identical to the unfused layer.
+__device__ inline float16v tile_mma(const bf16* A, int lda, const bf16* W, int K, int N, int n0, int lane) {
+  const int lm = lane & 31, lk = (lane >> 5) * 4;
+  const int n = n0 + lm;
+  float16v acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  constexpr int KU = 8;
+  int k0 = 0;
+  for (; k0 + 8 * KU <= K; k0 += 8 * KU) {
+    short4v a[KU], b[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + 8 * u + lk + j;
+        a[u][j] = (short)A[lm * lda + k];
+        b[u][j] = n < N ? (short)W[(int64_t)n * K + k] : (short)0;
+      }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[u], b[u], acc, 0, 0, 0);
+  }
+  for (; k0 < K; k0 += 8) {
+    short4v a, b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + lk + j;
+      a[j] = k < K ? (short)A[lm * lda + k] : (short)0;
+      b[j] = (k < K && n < N) ? (short)W[(int64_t)n * K + k] : (short)0;
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// A whole coupling layer for 32 rows, when its activations need not be kept (sampling and
+// log q without gradients): gather u_A, h1 = relu(u_A W1^T + b1), h2 = relu(h1 W2^T + b2) (BF16
+// in LDS, rounded where the unfused layer writes its BF16 copies), o = h2 W3^T + b3, coupling.
+// LDS: u_A [32][KA], h1 and h2 [32][H] BF16, o [32][2 nb] FP32.
+__global__ __launch_bounds__(256) void k_couple_fused(double* u, int n, int d, int a0, int na, int b0, int nb,
+                                                      int H, const bf16* W1, const float* bias1, const bf16* W2,
+                                                      const float* bias2, const bf16* W3, const float* bias3,
+                                                      double* logdet, int inverse) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int KA = (na + 7) & ~7;
+  bf16* uA = (bf16*)sm;
+  bf16* h1 = uA + 32 * KA;
+  bf16* h2 = h1 + 32 * H;
+  float* o = (float*)(h2 + 32 * H);
+  const int r0 = blockIdx.x * 32;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < 32 * KA; i += 256) {
+    const int r = i / KA, c = i - (i / KA) * KA;
+    uA[i] = (r0 + r < n && c < na) ? to_bf16((float)u[(int64_t)(r0 + r) * d + a0 + c]) : (bf16)0;
+  }
+  __syncthreads();
+  const int ntile = H / 32;
+  for (int t = wave; t < ntile; t += 4) {
+    const float16v acc = tile_mma(uA, KA, W1, na, H, 32 * t, lane);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3), col = 32 * t + (lane & 31);
+      float v = acc[r] + bias1[col];
+      v = v > 0.0f ? v : 0.0f;
+      h1[row * H + col] = to_bf16(v);
+    }
+  }
+  __syncthreads();
+  for (int t = wave; t < ntile; t += 4) {
+    const float16v acc = tile_mma(h1, H, W2, H, H, 32 * t, lane);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3), col = 32 * t + (lane & 31);
+      float v = acc[r] + bias2[col];
+      v = v > 0.0f ? v : 0.0f;
+      h2[row * H + col] = to_bf16(v);
+    }
+  }
+  __syncthreads();
+  const int no = 2 * nb;
+  for (int t = wave; t < (no + 31) / 32; t += 4) {
+    const float16v acc = tile_mma(h2, H, W3, H, no, 32 * t, lane);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3), col = 32 * t + (lane & 31);
+      if (col < no) o[row * no + col] = acc[r] + bias3[col];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && r0 + (int)threadIdx.x < n)
+    couple_row(u, r0 + threadIdx.x, d, b0, nb, o + threadIdx.x * no, nullptr, nullptr, logdet, inverse);
 }
 
 // coupling backward: gu holds dL/dy on entry and dL/du_B on exit; writes g_o (FP32 + BF16)
@@ -401,12 +501,26 @@ Slots slots(const lt_flow* f, int l, int n) {
   return S;
 }
 
-// forward (inverse = 0) or inverse pass over the n rows of f->u; logdet accumulates sum s
-void pass(lt_flow* f, int n, int inverse, hipStream_t st) {
+// LDS of k_couple_fused for one layer (0: the layer runs unfused)
+size_t fused_bytes(const lt_flow* f, const LayerOff& Lo) {
+  if (f->H % 32 != 0 || f->H > 256) return 0;
+  return (size_t)32 * ((Lo.na + 7) & ~7) * 2 + (size_t)2 * 32 * f->H * 2 + (size_t)32 * 2 * Lo.nb * 4;
+}
+
+// forward (inverse = 0) or inverse pass over the n rows of f->u; logdet accumulates sum s.
+// keep = false (no backward pass follows): each layer is one fused launch where it fits.
+void pass(lt_flow* f, int n, int inverse, hipStream_t st, bool keep) {
   const int d = f->d, H = f->H;
   for (int q = 0; q < f->L; ++q) {
     const int l = inverse ? f->L - 1 - q : q;
     const LayerOff& Lo = f->lay[l];
+    const size_t fb = keep ? 0 : fused_bytes(f, Lo);
+    if (fb > 0) {
+      hipLaunchKernelGGL(k_couple_fused, dim3(blocks(n, 32)), dim3(256), fb, st, f->u, n, d, Lo.a0, Lo.na, Lo.b0,
+                         Lo.nb, H, f->wb + Lo.W1, f->w + Lo.b1, f->wb + Lo.W2, f->w + Lo.b2, f->wb + Lo.W3,
+                         f->w + Lo.b3, f->logdet, inverse);
+      continue;
+    }
     Slots S = slots(f, l, n);
     hipLaunchKernelGGL(k_gather, dim3(blocks((int64_t)n * Lo.na)), dim3(256), 0, st, f->u, n, d, Lo.a0, Lo.na, S.uA);
     gemm(st, n, H, Lo.na, S.uA, Lo.na, 1, f->wb + Lo.W1, 1, Lo.na, S.a1, H, S.h1, f->w + Lo.b1, 1);
@@ -421,7 +535,7 @@ void pass(lt_flow* f, int n, int inverse, hipStream_t st) {
 void logq_rows(lt_flow* f, const double* x, int64_t n_src, int64_t start, int n, bool grad, hipStream_t st) {
   hipLaunchKernelGGL(k_standardise, dim3(blocks(n, 64)), dim3(64), 0, st, x, n_src, start, n, f->d, f->mu, f->Lw,
                      f->u, f->logdet);
-  pass(f, n, 0, st);
+  pass(f, n, 0, st, grad);
   hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, f->d, f->logdet, f->lsig, f->logq,
                      grad ? f->gu : (double*)nullptr, 1.0 / n);
 }
@@ -431,7 +545,7 @@ void sample_rows(lt_flow* f, int n, double* x, double* logq, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3(blocks(n)), dim3(256), 0, st, f->logdet, (int64_t)n);
   hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, f->d, f->logdet, 0.0, logq,
                      (double*)nullptr, 0.0);
-  pass(f, n, 1, st);
+  pass(f, n, 1, st, false);
   hipLaunchKernelGGL(k_logq_add, dim3(blocks(n)), dim3(256), 0, st, n, f->logdet, f->lsig, logq);
   hipLaunchKernelGGL(k_destandardise, dim3(blocks((int64_t)n * f->d)), dim3(256), 0, st, f->u, n, f->d, f->mu,
                      f->Lw, x);
