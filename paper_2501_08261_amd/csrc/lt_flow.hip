@@ -178,7 +178,8 @@ __device__ inline float16v tile_mma(const bf16* A, int lda, const bf16* W, int K
 // log q without gradients): gather u_A, h1 = relu(u_A W1^T + b1), h2 = relu(h1 W2^T + b2) (BF16
 // in LDS, rounded where the unfused layer writes its BF16 copies), o = h2 W3^T + b3, coupling.
 // LDS: u_A [32][KA], h1 and h2 [32][H] BF16, o [32][2 nb] FP32.
-__global__ __launch_bounds__(256) void k_couple_fused(double* u, int n, int d, int a0, int na, int b0, int nb,
+constexpr int kFusedThreads = 512;   // eight wavefronts: one 32-column tile of h each at H = 256
+__global__ __launch_bounds__(kFusedThreads) void k_couple_fused(double* u, int n, int d, int a0, int na, int b0, int nb,
                                                       int H, const bf16* W1, const float* bias1, const bf16* W2,
                                                       const float* bias2, const bf16* W3, const float* bias3,
                                                       double* logdet, int inverse) {
@@ -189,14 +190,15 @@ __global__ __launch_bounds__(256) void k_couple_fused(double* u, int n, int d, i
   bf16* h2 = h1 + 32 * H;
   float* o = (float*)(h2 + 32 * H);
   const int r0 = blockIdx.x * 32;
+  constexpr int NW = kFusedThreads / 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < 32 * KA; i += 256) {
+  for (int i = threadIdx.x; i < 32 * KA; i += kFusedThreads) {
     const int r = i / KA, c = i - (i / KA) * KA;
     uA[i] = (r0 + r < n && c < na) ? to_bf16((float)u[(int64_t)(r0 + r) * d + a0 + c]) : (bf16)0;
   }
   __syncthreads();
   const int ntile = H / 32;
-  for (int t = wave; t < ntile; t += 4) {
+  for (int t = wave; t < ntile; t += NW) {
     const float16v acc = tile_mma(uA, KA, W1, na, H, 32 * t, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(256) void k_couple_fused(double* u, int n, int d, i
     }
   }
   __syncthreads();
-  for (int t = wave; t < ntile; t += 4) {
+  for (int t = wave; t < ntile; t += NW) {
     const float16v acc = tile_mma(h1, H, W2, H, H, 32 * t, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(256) void k_couple_fused(double* u, int n, int d, i
   }
   __syncthreads();
   const int no = 2 * nb;
-  for (int t = wave; t < (no + 31) / 32; t += 4) {
+  for (int t = wave; t < (no + 31) / 32; t += NW) {
     const float16v acc = tile_mma(h2, H, W3, H, no, 32 * t, lane);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -516,7 +518,7 @@ void pass(lt_flow* f, int n, int inverse, hipStream_t st, bool keep) {
     const LayerOff& Lo = f->lay[l];
     const size_t fb = keep ? 0 : fused_bytes(f, Lo);
     if (fb > 0) {
-      hipLaunchKernelGGL(k_couple_fused, dim3(blocks(n, 32)), dim3(256), fb, st, f->u, n, d, Lo.a0, Lo.na, Lo.b0,
+      hipLaunchKernelGGL(k_couple_fused, dim3(blocks(n, 32)), dim3(kFusedThreads), fb, st, f->u, n, d, Lo.a0, Lo.na, Lo.b0,
                          Lo.nb, H, f->wb + Lo.W1, f->w + Lo.b1, f->wb + Lo.W2, f->w + Lo.b2, f->wb + Lo.W3,
                          f->w + Lo.b3, f->logdet, inverse);
       continue;
