@@ -147,17 +147,23 @@ __device__ inline float16v tile_mma(const bf16* A, int lda, const bf16* W, int K
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
   constexpr int KU = 8;
+  // 8-byte fragment reads: A rows sit at multiples of 4 elements of an 8-byte aligned LDS block;
+  // W rows too when K is a multiple of 4 and W itself is 8-byte aligned (a uniform test)
+  const bool wvec = (K % 4 == 0) && ((reinterpret_cast<uintptr_t>(W) & 7) == 0);
   int k0 = 0;
   for (; k0 + 8 * KU <= K; k0 += 8 * KU) {
     short4v a[KU], b[KU];
 #pragma unroll
-    for (int u = 0; u < KU; ++u)
+    for (int u = 0; u < KU; ++u) {
+      const int k = k0 + 8 * u + lk;
+      a[u] = *(const short4v*)(A + lm * lda + k);
+      if (n < N && wvec) {
+        b[u] = *(const short4v*)(W + (int64_t)n * K + k);
+      } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = k0 + 8 * u + lk + j;
-        a[u][j] = (short)A[lm * lda + k];
-        b[u][j] = n < N ? (short)W[(int64_t)n * K + k] : (short)0;
+        for (int j = 0; j < 4; ++j) b[u][j] = n < N ? (short)W[(int64_t)n * K + k + j] : (short)0;
       }
+    }
 #pragma unroll
     for (int u = 0; u < KU; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[u], b[u], acc, 0, 0, 0);
   }
