@@ -29,7 +29,7 @@ import numpy as np
 from .phys import C_SI
 from .orbits import link_ends
 from .twist import polarizations
-from .waveform import MODES_ALL
+from .waveform import MODES_ALL, real_array
 
 
 def k_u_v(lam, beta):
@@ -48,8 +48,8 @@ def lagrange_offsets(K):
 def lagrange_weights(frac, K):
     """w_i(frac) = prod_{j != i} (frac - o_j) / (o_i - o_j), offsets o = -K/2+1..K/2."""
     o = lagrange_offsets(K)
-    frac = np.asarray(frac, dtype=np.float64)
-    w = np.ones(frac.shape + (K,))
+    frac = real_array(frac)
+    w = np.ones(frac.shape + (K,), dtype=frac.dtype)
     for i in range(K):
         for j in range(K):
             if j != i:
@@ -103,12 +103,15 @@ class Response:
     """One template on one grid with one orbit (hot-path steps a4-a8)."""
 
     def __init__(self, tpl, t0, dt, N, orbit, taps=2, modes=MODES_ALL, precessing=False,
-                 generation=15, hfun=None, sky=None, coarse=1):
+                 generation=15, hfun=None, sky=None, coarse=1, real=np.float64):
         """hfun: optional callable t -> (h+, hx) replacing the waveform (used by
         the plane-wave checks); sky: optional (lambda, beta) overriding tpl's;
         coarse = 2: the polarisations on the grid are the waveform on every second
         sample (even indices) and the mean of the two neighbours on the others
-        (linear interpolation from a grid of twice the step, Sec. II.C)."""
+        (linear interpolation from a grid of twice the step, Sec. II.C); real:
+        np.float64, or np.longdouble for the sample and delayed times of the
+        extended-precision reference (with a Template of the same precision)."""
+        self.real = real
         self.coarse = int(coarse)
         self.tpl, self.t0, self.dt, self.N = tpl, float(t0), float(dt), int(N)
         self.hfun = hfun
@@ -119,10 +122,16 @@ class Response:
         self._hcache = None
 
     # -- polarisations ------------------------------------------------------
+    def _times(self, idx):
+        """Sample times t0 + idx dt in the response's precision."""
+        if self.real is np.float64:
+            return self.t0 + idx * self.dt
+        return self.real(self.t0) + np.asarray(idx).astype(self.real) * self.real(self.dt)
+
     def h_exact(self, t):
         if self.hfun is not None:
-            return self.hfun(np.asarray(t, dtype=np.float64))
-        return polarizations(self.tpl, np.asarray(t, dtype=np.float64), self.modes, self.precessing)
+            return self.hfun(real_array(t))
+        return polarizations(self.tpl, real_array(t), self.modes, self.precessing)
 
     def h_grid(self, idx):
         idx = np.asarray(idx, dtype=np.int64)
@@ -130,11 +139,11 @@ class Response:
             return self._hcache[0][idx], self._hcache[1][idx]
         if self.coarse == 2:
             lo = idx - (idx % 2)
-            a = self.h_exact(self.t0 + lo * self.dt)
-            b = self.h_exact(self.t0 + (lo + 2) * self.dt)
+            a = self.h_exact(self._times(lo))
+            b = self.h_exact(self._times(lo + 2))
             odd = (idx % 2) == 1
             return tuple(np.where(odd, 0.5 * (a[q] + b[q]), a[q]) for q in range(2))
-        return self.h_exact(self.t0 + idx * self.dt)
+        return self.h_exact(self._times(idx))
 
     def cache_full_grid(self):
         if self.coarse == 2:
@@ -142,7 +151,7 @@ class Response:
             hp, hc = self.h_grid(np.arange(self.N))
             self._hcache = (hp, hc)
             return
-        hp, hc = self.h_exact(self.t0 + np.arange(self.N) * self.dt)
+        hp, hc = self.h_exact(self._times(np.arange(self.N)))
         self._hcache = (hp, hc)
 
     # -- one link -----------------------------------------------------------
@@ -164,7 +173,7 @@ class Response:
     def y_method(self, l, idx):
         """ORACLE-M link response y_l on grid indices idx (h interpolated)."""
         idx = np.asarray(idx, dtype=np.int64)
-        tau = self.t0 + idx * self.dt
+        tau = self._times(idx)
         pp, pc, t_s, t_r = self.link_geometry(l, tau)
         ns, ws = _stencil((t_s - self.t0) / self.dt, self.K)
         nr, wr = _stencil((t_r - self.t0) / self.dt, self.K)
@@ -176,7 +185,7 @@ class Response:
 
     def y_exact(self, l, tau):
         """ORACLE-X link response at arbitrary reception times (no interpolation)."""
-        pp, pc, t_s, t_r = self.link_geometry(l, np.asarray(tau, dtype=np.float64))
+        pp, pc, t_s, t_r = self.link_geometry(l, real_array(tau))
         hs, hr = self.h_exact(t_s), self.h_exact(t_r)
         return pp * (hs[0] - hr[0]) + pc * (hs[1] - hr[1])
 
@@ -184,7 +193,7 @@ class Response:
     def xyz(self, idx, exact=False):
         """X, Y, Z at output grid indices idx (ORACLE-M, or ORACLE-X if exact)."""
         idx = np.asarray(idx, dtype=np.int64)
-        t = self.t0 + idx * self.dt
+        t = self._times(idx)
         Lt = {l: self.orbit.light_time(l, t) for l in (1, 2, 3, -1, -2, -3)}
         terms = []
         for ch in range(3):

@@ -19,7 +19,7 @@ Conventions fixed here (readings of the paper, listed in the design notes):
 import math
 import numpy as np
 
-from .waveform import cp_modes, MODES_ALL
+from .waveform import cp_modes, complex_of, real_array, MODES_ALL
 
 
 # ---------------------------------------------------------------- quaternions
@@ -35,15 +35,14 @@ def quat_mul(a, b):
 
 
 def quat_conj(q):
-    q = np.array(q, dtype=np.float64)
+    q = np.array(real_array(q))
     q[..., 1:] *= -1.0
     return q
 
 
 def quat_from_euler(alpha, beta, gamma):
     """Normalised Eq. (2.5): q for the z-y-z rotation R_z(alpha) R_y(beta) R_z(gamma)."""
-    alpha, beta, gamma = np.broadcast_arrays(np.asarray(alpha, float), np.asarray(beta, float),
-                                             np.asarray(gamma, float))
+    alpha, beta, gamma = np.broadcast_arrays(real_array(alpha), real_array(beta), real_array(gamma))
     cb, sb = np.cos(0.5 * beta), np.sin(0.5 * beta)
     sp, dm = 0.5 * (alpha + gamma), 0.5 * (alpha - gamma)
     return np.stack([cb * np.cos(sp), -sb * np.sin(dm), sb * np.cos(dm), cb * np.sin(sp)], axis=-1)
@@ -132,18 +131,21 @@ class Precession:
 
     def __init__(self, tpl):
         self.tpl = tpl
+        fp64 = tpl.real is np.float64
+        R = float if fp64 else tpl.real
+        hypot, atan2 = (math.hypot, math.atan2) if fp64 else (np.hypot, np.arctan2)
         S = tpl.chi1 * tpl.m1f ** 2 + tpl.chi2 * tpl.m2f ** 2
         eta = tpl.eta
-        self.Sl = float(S[2])
-        self.Sp = math.hypot(float(S[0]), float(S[1]))
+        self.Sl = R(S[2])
+        self.Sp = hypot(R(S[0]), R(S[1]))
         self.sig = self.Sl / eta
         self.vsig = self.Sp / eta
         qs = min(tpl.m1f, tpl.m2f) / max(tpl.m1f, tpl.m2f)
         self.C = 5.0 * (4.0 + 3.0 * qs) / 256.0
         self.u_ref = (math.pi * tpl.Ms * tpl.f_ref) ** (1.0 / 3.0)
         J = np.array([S[0], S[1], eta / self.u_ref + S[2]])
-        self.beta_ref = math.atan2(math.hypot(J[0], J[1]), J[2])
-        self.phi_J = math.atan2(J[1], J[0])
+        self.beta_ref = atan2(hypot(J[0], J[1]), J[2])
+        self.phi_J = atan2(J[1], J[0])
         self.kappa = self.phi_J - math.pi
         self.a_ref = self.a_of_u(self.u_ref)
         self.g_ref = self.g_of_u(self.u_ref)
@@ -189,7 +191,7 @@ def polarizations(tpl, t_ssb, modes=MODES_ALL, precessing=False):
     h+ - i hx = sum_{l, m} h^CP_lm sqrt((2l+1)/4pi) W^l_m(Q(t)), with the
     composite rotor Q = conj(q_CP->J(t)) conj(q_J->L0) q(phi, iota, 0).
     """
-    t = np.asarray(t_ssb, dtype=np.float64)
+    t = real_array(t_ssb)
     q_los = quat_from_euler(tpl.phi_ref, tpl.iota, 0.0)
     if precessing:
         pr = Precession(tpl)
@@ -199,7 +201,7 @@ def polarizations(tpl, t_ssb, modes=MODES_ALL, precessing=False):
     else:
         Q = np.broadcast_to(q_los, t.shape + (4,))
     Qa, Qb = Q_ab(Q)
-    h = np.zeros(t.shape, dtype=np.complex128)
+    h = np.zeros(t.shape, dtype=complex_of(t))
     for l, m, hlm in _modes_with_negative(tpl, t, modes):
         h = h + hlm * math.sqrt((2 * l + 1) / (4 * math.pi)) * W_lm(l, m, Qa, Qb)
     h = _apply_psi(tpl, h)

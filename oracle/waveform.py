@@ -39,6 +39,20 @@ THETA_MATCH = 0.7          # inspiral / merger matching point in theta
 MODES_ALL = ((2, 2), (2, 1), (3, 3), (3, 2), (4, 4))
 
 
+def real_array(x):
+    """x as a float64 array, or as np.longdouble when it already is one.  Every function of
+    the time and phase path keeps the caller's precision, so the same code evaluates the
+    model in FP64 (the parity target) and in x87 extended precision (the reference that
+    measures FP64's own rounding floor)."""
+    x = np.asarray(x)
+    return x if x.dtype == np.longdouble else np.asarray(x, dtype=np.float64)
+
+
+def complex_of(x):
+    """The complex dtype matching x's real precision."""
+    return np.result_type(np.asarray(x).dtype, np.complex64)
+
+
 def _remnant(eta, m1f, m2f, chi1l, chi2l):
     """Builder-defined remnant spin and mass fraction (parity unpinned)."""
     af = 2.0 * math.sqrt(3.0) * eta - 3.871 * eta ** 2 + 4.028 * eta ** 3 \
@@ -58,9 +72,14 @@ def _qnm22(af):
 class Template:
     """Per-template scalars (hot-path step a1) for the PhenomT-form model."""
 
-    def __init__(self, p, f_low=1e-4, f_ref=1e-4, pn=True, spins_aligned=True):
+    def __init__(self, p, f_low=1e-4, f_ref=1e-4, pn=True, spins_aligned=True, real=np.float64):
+        """real: np.float64 (the oracle) or np.longdouble (the extended-precision reference of
+        the same model, same FP64 coefficients, for measuring FP64's rounding floor)."""
+        R = float if real is np.float64 else real
+        tanh = math.tanh if real is np.float64 else np.tanh
+        self.real = real
         p = np.asarray(p, dtype=np.float64)
-        m1, m2 = float(p[P_M1]), float(p[P_M2])
+        m1, m2 = R(p[P_M1]), R(p[P_M2])
         self.valid = True
         if not (m1 > 0 and m2 > 0):
             self.valid = False
@@ -71,19 +90,19 @@ class Template:
         self.eta = m1 * m2 / M ** 2
         self.delta = (m1 - m2) / M
         self.m1f, self.m2f = m1 / M, m2 / M
-        chi1 = np.array(p[P_CHI1], dtype=np.float64)
-        chi2 = np.array(p[P_CHI2], dtype=np.float64)
+        chi1 = np.array(p[P_CHI1], dtype=real)
+        chi2 = np.array(p[P_CHI2], dtype=real)
         if np.linalg.norm(chi1) >= 1.0 or np.linalg.norm(chi2) >= 1.0:
             self.valid = False
         self.chi1, self.chi2 = chi1, chi2
-        self.chi1l, self.chi2l = float(chi1[2]), float(chi2[2])
-        self.DL = float(p[P_DL])
+        self.chi1l, self.chi2l = R(chi1[2]), R(chi2[2])
+        self.DL = R(p[P_DL])
         if not self.DL > 0:
             self.valid = False
             self.DL = 1.0
-        self.iota, self.phi_ref = float(p[P_IOTA]), float(p[P_PHI])
-        self.tc = float(p[P_TC])
-        self.lam, self.beta, self.psi = float(p[P_LAM]), float(p[P_BETA]), float(p[P_PSI])
+        self.iota, self.phi_ref = R(p[P_IOTA]), R(p[P_PHI])
+        self.tc = R(p[P_TC])
+        self.lam, self.beta, self.psi = R(p[P_LAM]), R(p[P_BETA]), R(p[P_PSI])
         self.f_low, self.f_ref = f_low, f_ref
         eta = self.eta
         # TaylorT3 phase coefficients (2PN, spin-orbit at 1.5PN)
@@ -112,16 +131,16 @@ class Template:
         if not (self.w_rd > self.w22_m and 0.0 < target < 0.2784):
             self.valid = False
             target = 0.1
-        lo, hi = 0.6392, 60.0
+        lo, hi = R(0.6392), R(60.0)
         for _ in range(200):
             mid = 0.5 * (lo + hi)
-            if mid * (1.0 - math.tanh(mid)) > target:
+            if mid * (1.0 - tanh(mid)) > target:
                 lo = mid
             else:
                 hi = mid
         s = 0.5 * (lo + hi)
         self.w = self.T / s
-        sig_m = 0.5 * (1.0 - math.tanh(s))
+        sig_m = 0.5 * (1.0 - tanh(s))
         self.Delta = (self.w_rd - self.w22_m) / (1.0 - sig_m)
         self.w_lo = self.w_rd - self.Delta
         # reference and start points (inspiral only)
@@ -158,7 +177,7 @@ class Template:
 
     def theta_of_t(self, t):
         """theta(t) = [eta (0 - t) / (5 M)]^(-1/8), model time (peak at t = 0)."""
-        return (self.eta * (-np.asarray(t, dtype=np.float64)) / (5.0 * self.Ms)) ** (-0.125)
+        return (self.eta * (-real_array(t)) / (5.0 * self.Ms)) ** (-0.125)
 
     def solve_theta(self, w_orb):
         """Inspiral theta at which the orbital frequency equals w_orb (Newton)."""
@@ -174,7 +193,7 @@ class Template:
 
     # --- full (2,2) frequency, phase, amplitude ----------------------------
     def omega22(self, t):
-        t = np.asarray(t, dtype=np.float64)
+        t = real_array(t)
         out = np.empty_like(t)
         ins = t < self.t_m
         out[ins] = 2.0 * self.omega_orb_theta(self.theta_of_t(t[ins]))
@@ -183,7 +202,7 @@ class Template:
         return out
 
     def phi22(self, t):
-        t = np.asarray(t, dtype=np.float64)
+        t = real_array(t)
         out = np.empty_like(t)
         ins = t < self.t_m
         out[ins] = 2.0 * (self.Phi_theta(self.theta_of_t(t[ins])) - self.Phi_ref)
@@ -197,7 +216,7 @@ class Template:
         return (self.Ms * self.omega22(t) / 2.0) ** (2.0 / 3.0)
 
     def amp22(self, t):
-        t = np.asarray(t, dtype=np.float64)
+        t = real_array(t)
         out = np.empty_like(t)
         ins = t < self.t_m
         out[ins] = self.K_amp * self.x_of_t(t[ins])
@@ -211,7 +230,7 @@ class Template:
         """Leading-PN amplitude ratio H_lm(x) / H_22 (complex)."""
         eta, d = self.eta, self.delta
         if (l, m) == (2, 2):
-            return np.ones_like(x, dtype=np.complex128)
+            return np.ones_like(x, dtype=complex_of(x))
         if (l, m) == (2, 1):
             return (1j / 3.0) * d * np.sqrt(x)
         if (l, m) == (3, 3):
@@ -235,8 +254,8 @@ def cp_modes(tpl, t_ssb, modes=MODES_ALL):
     with phi_orb = phi22 / 2.  Negative m follow from h_{l,-m} = (-1)^l conj(h_lm).
     Returns complex array [len(modes)][len(t)].
     """
-    t = np.asarray(t_ssb, dtype=np.float64) - tpl.tc
-    out = np.zeros((len(modes), t.size), dtype=np.complex128)
+    t = real_array(t_ssb) - tpl.tc
+    out = np.zeros((len(modes), t.size), dtype=complex_of(t))
     on = t >= tpl.t_start
     ts = t[on]
     A = tpl.amp22(ts)
