@@ -27,8 +27,9 @@
  *  - Time series are [batch][3][n]; spectra [rows][n/2+1] complex interleaved.
  *  - Host-checkable faults (null pointers, bad sizes, unsupported options)
  *    return an error synchronously and launch nothing.  Domain faults of a
- *    template (unphysical parameters) are reported per template in `status`
- *    (1 = unphysical, 2 = non-finite result) and give logL = -inf.
+ *    template are reported per template in `status` (1 = unphysical
+ *    parameters, 2 = non-finite result, 3 = delay window overflow; see
+ *    lt_tdi_loglike) and give logL = -inf.
  */
 #ifndef LISATD_H
 #define LISATD_H
@@ -146,17 +147,37 @@ lt_status lt_lisa_tdi_response(lt_ctx* ctx, const double* params, int64_t batch,
  *   logl_full[b] = -1/2 sum_c (h_c - d_c | h_c - d_c) = logl[b] - dd/2
  * with (a|b) = 4 df Re sum_{band} a~ conj(b~) / S (Eq. 2.13), a~ = dt * DFT.
  * Computed as -(r|r)/2 + dd/2 with the residual r = h - d formed in the time
- * domain.  logl, logl_full (nullable): device FP64 [batch]; status (nullable):
- * device int32 [batch].  Scratch memory is owned by the context.  Every
- * launch runs on `stream`, in chunks of up to 256 templates, so the call can
- * be captured into a HIP graph; a template's results do not depend on the
- * batch it came in.  Scratch holds at most 5 x 256 series of n samples (FP64
- * or FP32 by precision), whatever the batch.  Calls sharing a context must be ordered (same stream, or
+ * domain.  logl, logl_full (nullable, not both): device FP64 [batch]; status
+ * (nullable): device int32 [batch], written per template: 0 ok, 1 unphysical
+ * parameters, 2 non-finite result, 3 the template's delayed reads spread over
+ * more samples than the response kernel's window holds (a grid step far below
+ * the orbit's light times); any nonzero status gives logL = logl_full = -inf.
+ * Every launch runs on `stream`, in chunks of templates, so the call can be
+ * captured into a HIP graph; a template's results do not depend on the batch
+ * it came in or the chunk size.
+ * Memory: workspace (nullable) is caller-owned device memory of
+ * workspace_bytes, used for every per-call array (see lt_workspace_size); the
+ * call then allocates and synchronises nothing, except that the first call
+ * with a new grid length or orbit builds that grid's FFT plan and orbit node
+ * table in the context (host work, an upload, kept for later calls).  The
+ * chunk is the largest (up to 256 templates) that fits the workspace; one
+ * smaller than a single template's needs is LT_ERR_WORKSPACE.  With
+ * workspace = null the context keeps its own scratch, grown on demand (growth
+ * synchronises the device before the old block is freed) to chunks of 256:
+ * 5 series of n samples per template plus the tables.  The workspace, like the
+ * context's scratch, is in use until the stream reaches the end of the call:
+ * calls sharing a workspace or a context must be ordered (same stream, or
  * synchronised by the caller). */
 lt_status lt_tdi_loglike(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
                          const lt_grid* grid, const lt_orbit* orbit, const lt_tdi_cfg* tdi,
                          const lt_psd* psd, const lt_data* data, double* logl, double* logl_full,
-                         int32_t* status, void* stream);
+                         int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace of lt_tdi_loglike for `batch` templates with this configuration:
+ * bytes (nullable) for full-size chunks (min(batch, 256) templates per chunk),
+ * min_bytes (nullable) for chunks of one template.  Host only; no device work. */
+lt_status lt_workspace_size(lt_ctx* ctx, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* grid,
+                            const lt_tdi_cfg* tdi, size_t* bytes, size_t* min_bytes);
 
 /* sum over the enabled channels of (x_c|x_c) (Eq. 2.13) for time series x
  * [batch][3][n] (double if precision == LT_FP64, else float); out: device FP64

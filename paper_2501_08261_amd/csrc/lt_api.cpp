@@ -74,7 +74,8 @@ struct lt_ctx {
   std::map<std::tuple<int, double, double, double, double, double, double, int64_t, uint64_t>,
            std::unique_ptr<OrbitTab>>
       orbits;
-  DevBuf tpl, work, partial, wperm, status, wave, nodes, refs;
+  DevBuf tpl, work, partial, wperm, wave, nodes, refs;
+  DevBuf ws;              // lt_tdi_loglike's scratch when the caller passes no workspace
   bool profiling = false;
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
@@ -156,13 +157,10 @@ static hipError_t upload(DevBuf& dd, DevBuf& df, const std::vector<double>& h) {
   return hipMemcpy(df.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice);
 }
 
-static lt_status get_plan(lt_ctx* c, int64_t N, Plan** out) {
-  auto it = c->plans.find(N);
-  if (it != c->plans.end()) {
-    *out = it->second.get();
-    return LT_OK;
-  }
-  if (N < 8 || N % 2 != 0) return fail(LT_ERR_SHAPE, "FFT length must be even and >= 8");
+// n = N/2 = n1 * n2 with n1 even, both <= 1024 and built from the supported radices, the two
+// factors as close as possible (false when no such split exists)
+static bool plan_shape(int64_t N, int* n1, int* n2) {
+  if (N < 8 || N % 2 != 0) return false;
   int64_t n = N / 2;
   int best1 = -1, best2 = -1;
   double bestscore = 1e300;
@@ -175,8 +173,26 @@ static lt_status get_plan(lt_ctx* c, int64_t N, Plan** out) {
     double score = std::fabs(std::log((double)d) - std::log((double)e)) + (e < d ? 1e-3 : 0.0);
     if (score < bestscore) { bestscore = score; best1 = (int)d; best2 = (int)e; }
   }
-  if (best1 < 0)
+  *n1 = best1;
+  *n2 = best2;
+  return best1 > 0;
+}
+
+// The context's FFT plan for length N, built and uploaded on first use (may_alloc false: only
+// an existing plan, LT_ERR_CONFIG otherwise)
+static lt_status get_plan(lt_ctx* c, int64_t N, Plan** out, bool may_alloc = true) {
+  auto it = c->plans.find(N);
+  if (it != c->plans.end()) {
+    *out = it->second.get();
+    return LT_OK;
+  }
+  if (N < 8 || N % 2 != 0) return fail(LT_ERR_SHAPE, "FFT length must be even and >= 8");
+  int64_t n = N / 2;
+  int best1, best2;
+  if (!plan_shape(N, &best1, &best2))
     return fail(LT_ERR_UNSUPPORTED, "N/2 must factor as n1*n2 (n1 even, both <= 1024) over radices 2,3,5");
+  if (!may_alloc)
+    return fail(LT_ERR_CONFIG, "no FFT plan for this grid length in the context (a call that may allocate builds it)");
   auto p = std::make_unique<Plan>();
   FftPlanDev& d = p->dev;
   d.N = N;
@@ -322,7 +338,16 @@ static uint64_t orbit_hash(const lt_orbit* o) {
   return h;
 }
 
-static lt_status get_orbit(lt_ctx* c, const lt_orbit* o, const lt_grid* g, OrbitDev* out) {
+// orbit nodes of a grid: every tile's nodes, one interval and the j0 offset on each side
+static int orbit_node_count(const lt_grid* g) {
+  const int64_t ntile = (g->n + tdi_tile() - 1) / tdi_tile();
+  const int64_t last = ntile * tdi_tile() - 1;
+  return (int)(last / kNodeSpacing + 3 + kNodeJ0 + 2);
+}
+
+// The context's orbit node table for (orbit, grid), built on the host and uploaded on first use
+// (may_alloc false: only an existing table, LT_ERR_CONFIG otherwise)
+static lt_status get_orbit(lt_ctx* c, const lt_orbit* o, const lt_grid* g, OrbitDev* out, bool may_alloc = true) {
   auto key = std::make_tuple(o->kind, o->arm_m, o->au_m, o->phase0, o->t_ref, g->t0, g->dt, (int64_t)g->n,
                              orbit_hash(o));
   auto it = c->orbits.find(key);
@@ -330,9 +355,9 @@ static lt_status get_orbit(lt_ctx* c, const lt_orbit* o, const lt_grid* g, Orbit
     *out = it->second->dev;
     return LT_OK;
   }
-  const int64_t ntile = (g->n + tdi_tile() - 1) / tdi_tile();
-  const int64_t last = ntile * tdi_tile() - 1;
-  const int n_nodes = (int)(last / kNodeSpacing + 3 + kNodeJ0 + 2);
+  if (!may_alloc)
+    return fail(LT_ERR_CONFIG, "no node table for this orbit and grid in the context (a call that may allocate builds it)");
+  const int n_nodes = orbit_node_count(g);
   if (o->kind == LT_ORBIT_TABLE) {
     // every node time, and every emission time up to the longest light time before it
     double maxL = 0.0;
@@ -579,29 +604,20 @@ lt_status lt_phenomt_polarizations(lt_ctx* c, const double* params, int64_t batc
   return LT_OK;
 }
 
-// tc: the templates' constants when the caller has set them up already (null: set up here)
-static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
-                         const lt_orbit* o, const lt_tdi_cfg* t, int out_mode, const void* data, void* out,
-                         int32_t* status, hipStream_t s, const TplConst* tc = nullptr) {
-  OrbitDev od;
-  lt_status st = get_orbit(c, o, g, &od);
-  if (st) return st;
-  if (!tc) {
-    st = do_setup(c, params, batch, cfg, g, status, s);
-    if (st) return st;
-    tc = (const TplConst*)c->tpl.p;
-  }
-  const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
-  LT_HIP(c->wave.ensure((size_t)batch * 2 * g->n * rsz));
+// Response kernels for `batch` templates whose constants tc are set up: waveform into `wave`
+// ([batch][2][n] in the precision's real type), the per-launch tables into `nodes` and `refs`
+// (sizes from tdi_scratch_bytes), the fused response into `out`.
+static lt_status run_tdi_core(lt_ctx* c, const TplConst* tc, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                              const OrbitDev& od, const lt_tdi_cfg* t, int out_mode, const void* data, void* out,
+                              int32_t* status, void* wave, double* nodes, void* refs, hipStream_t s) {
   {
     Prof pr(c, 0, s);
-    LT_HIP(launch_wave(tc, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, cfg->precision, gdev(g), c->wave.p,
-                       s));
+    LT_HIP(launch_wave(tc, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, cfg->precision, gdev(g), wave, s));
   }
   TdiLaunch L;
   L.tc = tc;
   L.batch = batch;
-  L.h = c->wave.p;
+  L.h = wave;
   L.taps = t->taps;
   L.comb = 1;
   L.precision = cfg->precision;
@@ -612,13 +628,8 @@ static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const l
   L.data = data;
   L.out = out;
   L.status = status;
-  size_t nb = 0, rb = 0;
-  tdi_scratch_bytes(L, &nb, &rb);
-  if (rb == 0) return fail(LT_ERR_UNSUPPORTED, "unsupported tap count");
-  LT_HIP(c->nodes.ensure(nb));
-  LT_HIP(c->refs.ensure(rb));
-  L.nodes = (double*)c->nodes.p;
-  L.refs = c->refs.p;
+  L.nodes = nodes;
+  L.refs = refs;
   {
     Prof pr(c, 0, s);
     LT_HIP(launch_tdi(L, 0, s));
@@ -628,6 +639,39 @@ static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const l
   return LT_OK;
 }
 
+// scratch bytes of the per-launch tables for `batch` templates (0 for an unsupported tap count)
+static void tdi_table_bytes(int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g, const lt_tdi_cfg* t,
+                            size_t* nb, size_t* rb) {
+  TdiLaunch L;
+  std::memset(&L, 0, sizeof(L));
+  L.batch = batch;
+  L.taps = t->taps;
+  L.precision = cfg->precision;
+  L.g = gdev(g);
+  L.orb.n_nodes = orbit_node_count(g);
+  tdi_scratch_bytes(L, nb, rb);
+}
+
+// the response entry point: the whole batch in one launch, scratch owned by the context
+static lt_status run_tdi(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                         const lt_orbit* o, const lt_tdi_cfg* t, int out_mode, void* out, int32_t* status,
+                         hipStream_t s) {
+  OrbitDev od;
+  lt_status st = get_orbit(c, o, g, &od);
+  if (st) return st;
+  st = do_setup(c, params, batch, cfg, g, status, s);
+  if (st) return st;
+  const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
+  LT_HIP(c->wave.ensure((size_t)batch * 2 * g->n * rsz));
+  size_t nb = 0, rb = 0;
+  tdi_table_bytes(batch, cfg, g, t, &nb, &rb);
+  if (rb == 0) return fail(LT_ERR_UNSUPPORTED, "unsupported tap count");
+  LT_HIP(c->nodes.ensure(nb));
+  LT_HIP(c->refs.ensure(rb));
+  return run_tdi_core(c, (const TplConst*)c->tpl.p, batch, cfg, g, od, t, out_mode, nullptr, out, status, c->wave.p,
+                      (double*)c->nodes.p, c->refs.p, s);
+}
+
 lt_status lt_lisa_tdi_response(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
                                const lt_orbit* o, const lt_tdi_cfg* t, void* out, int32_t* status, void* stream) {
   lt_status st = check_common(c, params, batch, cfg, g);
@@ -635,7 +679,7 @@ lt_status lt_lisa_tdi_response(lt_ctx* c, const double* params, int64_t batch, c
   st = check_tdi(o, t, g);
   if (st) return st;
   if (!out) return fail(LT_ERR_NULL, "null output");
-  return run_tdi(c, params, batch, cfg, g, o, t, t->out_xyz ? 1 : 0, nullptr, out, status, (hipStream_t)stream);
+  return run_tdi(c, params, batch, cfg, g, o, t, t->out_xyz ? 1 : 0, out, status, (hipStream_t)stream);
 }
 
 static lt_status band_bins(const lt_grid* g, const lt_psd* psd, int* k_lo, int* k_hi) {
@@ -652,16 +696,15 @@ static lt_status band_bins(const lt_grid* g, const lt_psd* psd, int* k_lo, int* 
 }
 
 // FFT both passes over rows of [rows][n] (in place), band power into `partial`
-// (band weights already in c->wperm)
+// (band weights in wperm)
 static lt_status fft_band(lt_ctx* c, Plan* p, void* series, int64_t rows, int precision, int k_lo, int k_hi,
-                          const lt_grid* g, double* partial, hipStream_t s) {
+                          const lt_grid* g, double* partial, const double* wperm, hipStream_t s) {
   {
     Prof pr(c, 2, s);
     LT_HIP(launch_fft_pass1(p->dev, series, rows, precision, s));
   }
   Prof pr(c, 3, s);
-  LT_HIP(launch_fft_pass2(p->dev, series, rows, precision, 1, g->dt, nullptr, (const double*)c->wperm.p, 3, partial,
-                          k_lo, k_hi, s));
+  LT_HIP(launch_fft_pass2(p->dev, series, rows, precision, 1, g->dt, nullptr, wperm, 3, partial, k_lo, k_hi, s));
   return LT_OK;
 }
 
@@ -690,9 +733,66 @@ static lt_status band_power(lt_ctx* c, Plan* p, void* series, int64_t rows, int 
   return LT_OK;
 }
 
-lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
-                         const lt_orbit* o, const lt_tdi_cfg* t, const lt_psd* psd, const lt_data* data, double* logl,
-                         double* logl_full, int32_t* status, void* stream) {
+// ------------------------------------------------------------ likelihood scratch
+// One block of device memory per lt_tdi_loglike call, carved into the arrays one chunk of
+// templates needs; each array starts on a 256-byte boundary.
+struct LoglikeScratch {
+  TplConst* tpl;      // [chunk] template constants
+  int32_t* status;    // [chunk] when the caller passes no status array
+  double* wperm;      // [3][n + 1] band weights in pass-2 order
+  void* work;         // [chunk][3][n] residual, transformed in place
+  double* partial;    // [chunk][3][n1/2 + 1] band partial sums
+  void* wave;         // [chunk][2][n] polarisations
+  double* nodes;      // per-launch node records and window bounds
+  void* refs;         // per-launch term references and combined filters
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// bytes of the scratch for chunks of `chunk` templates, and (base != null) the arrays within it
+static size_t loglike_layout(int64_t chunk, const lt_wf_cfg* cfg, const lt_grid* g, const lt_tdi_cfg* t, int nfold,
+                             unsigned char* base, LoglikeScratch* out) {
+  const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
+  size_t nb = 0, rb = 0;
+  tdi_table_bytes(chunk, cfg, g, t, &nb, &rb);
+  const size_t parts[8] = {(size_t)chunk * sizeof(TplConst), (size_t)chunk * sizeof(int32_t),
+                           (size_t)3 * (g->n + 1) * sizeof(double), (size_t)chunk * 3 * g->n * rsz,
+                           (size_t)chunk * 3 * nfold * sizeof(double), (size_t)chunk * 2 * g->n * rsz, nb, rb};
+  size_t off[8], total = 0;
+  for (int i = 0; i < 8; ++i) {
+    off[i] = total;
+    total += align256(parts[i]);
+  }
+  if (base && out) {
+    out->tpl = (TplConst*)(base + off[0]);
+    out->status = (int32_t*)(base + off[1]);
+    out->wperm = (double*)(base + off[2]);
+    out->work = base + off[3];
+    out->partial = (double*)(base + off[4]);
+    out->wave = base + off[5];
+    out->nodes = (double*)(base + off[6]);
+    out->refs = base + off[7];
+  }
+  return total;
+}
+
+// largest chunk (at most kLoglikeChunk and the batch) whose scratch fits `bytes`; 0 if none does
+static int64_t loglike_chunk_for(size_t bytes, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                                 const lt_tdi_cfg* t, int nfold) {
+  int64_t hi = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+  if (loglike_layout(hi, cfg, g, t, nfold, nullptr, nullptr) <= bytes) return hi;
+  int64_t lo = 0;   // invariant: layout(lo) fits (or lo = 0), layout(hi) does not
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) / 2;
+    if (loglike_layout(mid, cfg, g, t, nfold, nullptr, nullptr) <= bytes) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+static lt_status check_loglike(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                               const lt_grid* g, const lt_orbit* o, const lt_tdi_cfg* t, const lt_psd* psd,
+                               const lt_data* data, const double* logl, const double* logl_full, int* nfold) {
   lt_status st = check_common(c, params, batch, cfg, g);
   if (st) return st;
   st = check_tdi(o, t, g);
@@ -700,47 +800,96 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
   if (!psd || !psd->S[0] || !psd->S[1] || !psd->S[2]) return fail(LT_ERR_NULL, "null PSD");
   if (!data || !data->aet) return fail(LT_ERR_NULL, "null data");
   if (!logl && !logl_full) return fail(LT_ERR_NULL, "no output requested");
-  hipStream_t s = (hipStream_t)stream;
+  int n1, n2;
+  if (!plan_shape(g->n, &n1, &n2))
+    return fail(LT_ERR_UNSUPPORTED, "N/2 must factor as n1*n2 (n1 even, both <= 1024) over radices 2,3,5");
+  *nfold = n1 / 2 + 1;
+  size_t nb = 0, rb = 0;
+  tdi_table_bytes(1, cfg, g, t, &nb, &rb);
+  if (rb == 0) return fail(LT_ERR_UNSUPPORTED, "unsupported tap count");
+  return LT_OK;
+}
+
+// The likelihood over `batch` templates in chunks of `chunk`, with all per-call memory in `base`
+// (laid out by loglike_layout for that chunk).  may_alloc false: the FFT plan and the orbit
+// table must already be in the context.
+static lt_status loglike_run(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                             const lt_orbit* o, const lt_tdi_cfg* t, const lt_psd* psd, const lt_data* data,
+                             double* logl, double* logl_full, int32_t* status, int nfold, int64_t chunk,
+                             unsigned char* base, bool may_alloc, hipStream_t s) {
   Plan* p;
-  st = get_plan(c, g->n, &p);
+  lt_status st = get_plan(c, g->n, &p, may_alloc);
   if (st) return st;
-  const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
-  int32_t* stat = status;
-  if (!stat) {
-    LT_HIP(c->status.ensure((size_t)batch * sizeof(int32_t)));
-    stat = (int32_t*)c->status.p;
-  }
-  const double scale = 4.0 * g->dt / (double)g->n;
-  const int64_t nfold = p->dev.n1 / 2 + 1;
-  // every template's constants once (one launch); the chunks below reuse them
-  st = do_setup(c, params, batch, cfg, g, stat, s);
+  OrbitDev od;
+  st = get_orbit(c, o, g, &od, may_alloc);
   if (st) return st;
   int k_lo, k_hi;
   st = band_bins(g, psd, &k_lo, &k_hi);
   if (st) return st;
-  // one stream, chunks of kLoglikeChunk templates: the response kernel already fills the
-  // GPU, and running a chunk's FFT beside the next chunk's response on a second stream
-  // measured no faster than this
-  const int64_t chunk = batch < kLoglikeChunk ? batch : kLoglikeChunk;
-  LT_HIP(c->work.ensure((size_t)chunk * 3 * g->n * rsz));
-  LT_HIP(c->partial.ensure((size_t)chunk * 3 * nfold * sizeof(double)));
-  LT_HIP(c->wperm.ensure((size_t)3 * (p->dev.n + 1) * sizeof(double)));
+  LoglikeScratch w;
+  loglike_layout(chunk, cfg, g, t, nfold, base, &w);
+  const double scale = 4.0 * g->dt / (double)g->n;
   {
     Prof pr(c, 0, s);   // per-call table, timed with the setup
-    LT_HIP(launch_weights(p->dev, psd->S, k_lo, k_hi, t->channels, (double*)c->wperm.p, s));
+    LT_HIP(launch_weights(p->dev, psd->S, k_lo, k_hi, t->channels, w.wperm, s));
   }
+  // one stream, chunks of templates: the response kernel already fills the GPU, and running a
+  // chunk's FFT beside the next chunk's response on a second stream measured no faster than this
   for (int64_t off = 0; off < batch; off += chunk) {
     const int64_t b = batch - off < chunk ? batch - off : chunk;
-    st = run_tdi(c, params + off * 16, b, cfg, g, o, t, 2, data->aet, c->work.p, stat + off, s,
-                 (const TplConst*)c->tpl.p + off);
+    int32_t* stat = status ? status + off : w.status;
+    {
+      Prof pr(c, 0, s);
+      LT_HIP(launch_setup(params + off * 16, b, cfg->f_low, cfg->f_ref, gdev(g), w.tpl, stat, s));
+    }
+    st = run_tdi_core(c, w.tpl, b, cfg, g, od, t, 2, data->aet, w.work, stat, w.wave, w.nodes, w.refs, s);
     if (st) return st;
-    st = fft_band(c, p, c->work.p, b * 3, cfg->precision, k_lo, k_hi, g, (double*)c->partial.p, s);
+    st = fft_band(c, p, w.work, b * 3, cfg->precision, k_lo, k_hi, g, w.partial, w.wperm, s);
     if (st) return st;
     Prof pr(c, 4, s);
-    LT_HIP(launch_finalize((const double*)c->partial.p, b, nfold, scale, data->dd, stat + off,
-                           logl ? logl + off : nullptr, logl_full ? logl_full + off : nullptr, nullptr, s));
+    LT_HIP(launch_finalize(w.partial, b, nfold, scale, data->dd, stat, logl ? logl + off : nullptr,
+                           logl_full ? logl_full + off : nullptr, nullptr, s));
   }
   return LT_OK;
+}
+
+lt_status lt_workspace_size(lt_ctx* c, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g, const lt_tdi_cfg* t,
+                            size_t* bytes, size_t* min_bytes) {
+  if (!c || !cfg || !g || !t || (!bytes && !min_bytes)) return fail(LT_ERR_NULL, "null argument");
+  if (batch < 1 || batch > 65535) return fail(LT_ERR_SHAPE, "batch must be in [1, 65535]");
+  if (g->n < 8 || g->n > ((int64_t)1 << 26)) return fail(LT_ERR_SHAPE, "grid n must be in [8, 2^26]");
+  if (cfg->precision != LT_FP64 && cfg->precision != LT_MIXED) return fail(LT_ERR_CONFIG, "bad precision");
+  int n1, n2;
+  if (!plan_shape(g->n, &n1, &n2))
+    return fail(LT_ERR_UNSUPPORTED, "N/2 must factor as n1*n2 (n1 even, both <= 1024) over radices 2,3,5");
+  size_t nb = 0, rb = 0;
+  tdi_table_bytes(1, cfg, g, t, &nb, &rb);
+  if (rb == 0) return fail(LT_ERR_UNSUPPORTED, "taps must be one of 2,4,6,8,12,16,24,32");
+  const int64_t full = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+  if (bytes) *bytes = loglike_layout(full, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
+  if (min_bytes) *min_bytes = loglike_layout(1, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
+  return LT_OK;
+}
+
+lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                         const lt_orbit* o, const lt_tdi_cfg* t, const lt_psd* psd, const lt_data* data, double* logl,
+                         double* logl_full, int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+  int nfold;
+  lt_status st = check_loglike(c, params, batch, cfg, g, o, t, psd, data, logl, logl_full, &nfold);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t chunk;
+  unsigned char* base;
+  if (workspace) {
+    chunk = loglike_chunk_for(workspace_bytes, batch, cfg, g, t, nfold);
+    if (chunk < 1) return fail(LT_ERR_WORKSPACE, "workspace smaller than one template needs (lt_workspace_size)");
+    base = (unsigned char*)workspace;
+  } else {
+    chunk = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+    LT_HIP(c->ws.ensure(loglike_layout(chunk, cfg, g, t, nfold, nullptr, nullptr)));
+    base = (unsigned char*)c->ws.p;
+  }
+  return loglike_run(c, params, batch, cfg, g, o, t, psd, data, logl, logl_full, status, nfold, chunk, base, true, s);
 }
 
 lt_status lt_noise_inner(lt_ctx* c, const void* x, int64_t batch, const lt_grid* g, const lt_psd* psd, int channels,

@@ -572,38 +572,62 @@ hipError_t launch_weights(const FftPlanDev& p, const double* const* S, int k_lo,
   return hipGetLastError();
 }
 
-// per template: sum over 3 channels x npairs partial sums in a fixed order
-// (per-thread compensated strided sums, then a pairwise wavefront / block tree)
+// Error-free sum of two doubles (Knuth's TwoSum): a + b = s + e exactly.
+__device__ inline void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// per template: sum over 3 channels x npairs partial sums in a fixed order.  Every step is
+// compensated: each thread keeps a (sum, error) pair over its strided partials (TwoSum per
+// term), and the pairs are merged by TwoSum through the wavefront and block tree, the errors
+// added at the end.  A non-finite result marks the template with status 2 and logL = -inf.
 __global__ __launch_bounds__(256) void k_finalize(const double* partial, int npairs, double scale, double dd,
-                                                  const int32_t* status, double* logl, double* logl_full,
+                                                  int32_t* status, double* logl, double* logl_full,
                                                   double* inner) {
-  __shared__ double red[4];
+  __shared__ double red[4], rede[4];
   const int64_t b = blockIdx.x;
   const double* q = partial + b * 3 * npairs;
   const int total = 3 * npairs;
-  double cs = 0.0, comp = 0.0;
+  double cs = 0.0, ce = 0.0;
   for (int i = threadIdx.x; i < total; i += 256) {
-    double y = q[i] - comp;
-    double t = cs + y;
-    comp = (t - cs) - y;
-    cs = t;
+    double e;
+    two_sum(cs, q[i], cs, e);
+    ce += e;
   }
-  for (int off = 32; off > 0; off >>= 1) cs += __shfl_down(cs, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cs;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double os = __shfl_down(cs, off, 64), oe = __shfl_down(ce, off, 64);
+    double e;
+    two_sum(cs, os, cs, e);
+    ce += oe + e;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = cs;
+    rede[threadIdx.x >> 6] = ce;
+  }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double s = (red[0] + red[1]) + (red[2] + red[3]);
-  const double rr = scale * s;
+  double s = red[0], se = rede[0];
+  for (int i = 1; i < 4; ++i) {
+    double e;
+    two_sum(s, red[i], s, e);
+    se += rede[i] + e;
+  }
+  const double rr = scale * (s + se);
   if (inner) inner[b] = rr;
   const bool bad = status && status[b] != 0;
   double full = bad ? -INFINITY : -0.5 * rr;
-  if (!bad && !isfinite(full)) full = -INFINITY;
+  if (!bad && !isfinite(full)) {
+    full = -INFINITY;
+    if (status) status[b] = 2;
+  }
   if (logl_full) logl_full[b] = full;
   if (logl) logl[b] = full + 0.5 * dd;
 }
 
 hipError_t launch_finalize(const double* partial, int64_t batch, int npairs, double scale, double dd,
-                           const int32_t* status, double* logl, double* logl_full, double* inner, hipStream_t s) {
+                           int32_t* status, double* logl, double* logl_full, double* inner, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3((unsigned)batch), dim3(256), 0, s, partial, npairs, scale, dd, status, logl,
                      logl_full, inner);
   return hipGetLastError();

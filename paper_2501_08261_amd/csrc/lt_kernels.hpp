@@ -88,7 +88,7 @@ hipError_t launch_weights(const FftPlanDev& p, const double* const* S, int k_lo,
                           double* wperm, hipStream_t s);
 // out[b] = scale * sum_{c, pairs} partial; logl variant adds dd/2 and handles status
 hipError_t launch_finalize(const double* partial, int64_t batch, int npairs, double scale, double dd,
-                           const int32_t* status, double* logl, double* logl_full, double* inner,
+                           int32_t* status, double* logl, double* logl_full, double* inner,
                            hipStream_t s);
 
 }  // namespace lt

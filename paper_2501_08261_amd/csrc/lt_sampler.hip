@@ -293,6 +293,8 @@ struct lt_sampler {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   lt_flow* flow = nullptr;
+  void* ws = nullptr;          // likelihood workspace (TDI target), sized for the whole ensemble
+  size_t ws_bytes = 0;
 };
 
 #define S_HIP(call)                                                                  \
@@ -326,7 +328,7 @@ static lt_status eval_logl(lt_sampler* s, const double* xs, int64_t count, doubl
     return LT_OK;
   }
   lt_status r = lt_tdi_loglike(s->ctx, s->D.params, count, &s->wf, &s->grid, &s->orbit, &s->tdi, &s->psd, &s->data,
-                               out, nullptr, nullptr, st);
+                               out, nullptr, nullptr, s->ws, s->ws_bytes, st);
   if (r != LT_OK) lt::set_error(std::string("logL: ") + lt_last_error());
   return r;
 }
@@ -438,6 +440,17 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
   if (cfg->target == LT_TARGET_GAUSS) {
     S_HIP(hipMemcpy(D.gmean, cfg->gauss_mean, (size_t)cfg->n_gauss * d * sizeof(double), hipMemcpyHostToDevice));
     S_HIP(hipMemcpy(D.gicov, cfg->gauss_icov, (size_t)d * d * sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    // one workspace for every likelihood call of the sampler (at most the whole ensemble per
+    // call), so that a captured step allocates nothing
+    size_t wsb = 0;
+    lt_status r2 = lt_workspace_size(s->ctx, TW, &s->wf, &s->grid, &s->tdi, &wsb, nullptr);
+    if (r2 == LT_OK) r2 = salloc(s, (unsigned char**)&s->ws, wsb);
+    if (r2 != LT_OK) {
+      lt_sampler_destroy(s);
+      return r2;
+    }
+    s->ws_bytes = wsb;
   }
   S_HIP(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
   s->cfg.lo = s->cfg.hi = s->cfg.gauss_mean = s->cfg.gauss_icov = nullptr;

@@ -237,18 +237,27 @@ __device__ inline void cubic_w(double x, double* w) {
   w[3] = xp1 * x * xm1 * (1.0 / 6.0);
 }
 
-// Per node: for each link (P+, Px, D_s), then D_r for each spacecraft; a node record adds the
-// window bounds of its nine delays, ceil(D_max / dt) and floor(D_min / dt), as two int32.
-constexpr int kNL = 3;
+// Per node: for each link (N+, Nx, D_s, 1 - k.n), then D_r for each spacecraft; a node record
+// adds the window bounds of its nine delays, ceil(D_max / dt) and floor(D_min / dt), as two
+// int32, and the smallest 1 - k.n of its links.
+constexpr int kNL = 4;
 constexpr int kNodeVals = 6 * kNL + 3;
-constexpr int kNodeRec = kNodeVals + 1;
+constexpr int kNodeRec = kNodeVals + 2;
+// Below this 1 - k.n, somewhere among a tile's nodes, the response kernel interpolates N+, Nx
+// and 1 - k.n separately and divides per sample; above it (every sky position more than ~11
+// degrees from the arms over the tile) the quotients P = N / (1 - k.n) are smooth enough to be
+// interpolated themselves.
+constexpr double kSmoothKn = 0.02;
 __constant__ int kRecv[6] = {1, 2, 0, 2, 0, 1};     // receiver spacecraft (0-based) of links 1,2,3,-1,-2,-3
 __constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacecraft 1, 2, 3
 
 // ------------------------------------------------------- response geometry per (template, orbit node)
-// Projections P+ = (u.n)^2 - (v.n)^2) / 2 / (1 - k.n), Px = (u.n)(v.n) / (1 - k.n) and the
-// delays D_s = L + k.r_s / c (sender) and D_r = k.r_r / c (receiver) of Eq. (2.8), at every node
-// of the orbit table, computed once per template; [batch][n_nodes][kNodeRec] doubles.
+// Projection numerators N+ = ((u.n)^2 - (v.n)^2) / 2, Nx = (u.n)(v.n), the denominator 1 - k.n
+// and the delays D_s = L + k.r_s / c (sender) and D_r = k.r_r / c (receiver) of Eq. (2.8), at
+// every node of the orbit table, computed once per template; [batch][n_nodes][kNodeRec] doubles.
+// The three geometric factors are smooth in time and can be interpolated separately between
+// the nodes; their quotient is not, where the wave travels almost along an arm (k.n -> 1: the
+// quotient then turns through its range within a node interval, while y itself vanishes).
 __global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb, double inv_dt, double* nodes) {
   const int j = blockIdx.x * kNT + threadIdx.x;
   const int b = blockIdx.y;
@@ -256,16 +265,18 @@ __global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb,
   const TplConst& c = tc[b];
   double* o = nodes + ((int64_t)b * orb.n_nodes + j) * kNodeRec;
   int dhi = -(1 << 30), dlo = 1 << 30;
+  double dmin = 2.0;
   for (int q = 0; q < 6; ++q) {
     const double* e = orb.tab + (int64_t)j * kNodeStride + q * kNodeLink;
     const double un = c.u[0] * e[7] + c.u[1] * e[8] + c.u[2] * e[9];
     const double vn = c.v[0] * e[7] + c.v[1] * e[8] + c.v[2] * e[9];
     const double kn = c.k[0] * e[7] + c.k[1] * e[8] + c.k[2] * e[9];
-    const double inv = 1.0 / (1.0 - kn);
     const double dly = e[0] + (c.k[0] * e[4] + c.k[1] * e[5] + c.k[2] * e[6]);
-    o[q * kNL + 0] = 0.5 * (un * un - vn * vn) * inv;
-    o[q * kNL + 1] = un * vn * inv;
+    o[q * kNL + 0] = 0.5 * (un * un - vn * vn);
+    o[q * kNL + 1] = un * vn;
     o[q * kNL + 2] = dly;
+    o[q * kNL + 3] = 1.0 - kn;
+    dmin = fmin(dmin, 1.0 - kn);
     dhi = max(dhi, (int)ceil(dly * inv_dt));
     dlo = min(dlo, (int)floor(dly * inv_dt));
   }
@@ -280,10 +291,12 @@ __global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb,
   wb.x = dhi;
   wb.y = dlo;
   *reinterpret_cast<int2*>(o + kNodeVals) = wb;
+  o[kNodeVals + 1] = dmin;
 }
 
 // window bounds of every (template, tile): the largest and smallest delay in samples over
-// the orbit nodes the tile interpolates (nodes jn_lo .. jn_hi, as in k_tdi), two int32
+// the orbit nodes the tile interpolates (nodes jn_lo .. jn_hi, as in k_tdi), and whether the
+// projection quotients are smooth over them (1 - k.n >= kSmoothKn on every link), four int32
 __global__ __launch_bounds__(kNT) void k_windows(const double* nodes, OrbitDev orb, int64_t batch, int ntile,
                                                  int HY, int MY, int* win) {
   const int64_t idx = (int64_t)blockIdx.x * kNT + threadIdx.x;
@@ -293,13 +306,18 @@ __global__ __launch_bounds__(kNT) void k_windows(const double* nodes, OrbitDev o
   const int64_t m_lo = tile * kTile - HY, m_hi = m_lo + MY - 1;
   const int64_t jn_lo = floordiv(m_lo, S) - 1 + orb.j0, jn_hi = floordiv(m_hi, S) + 2 + orb.j0;
   int dhi = -(1 << 30), dlo = 1 << 30;
+  double dmin = 2.0;
   for (int64_t j = jn_lo; j <= jn_hi; ++j) {
-    const int2 wb = *reinterpret_cast<const int2*>(nodes + (b * orb.n_nodes + j) * kNodeRec + kNodeVals);
+    const double* rec = nodes + (b * orb.n_nodes + j) * kNodeRec;
+    const int2 wb = *reinterpret_cast<const int2*>(rec + kNodeVals);
     dhi = max(dhi, wb.x);
     dlo = min(dlo, wb.y);
+    dmin = fmin(dmin, rec[kNodeVals + 1]);
   }
-  win[2 * idx] = dhi;
-  win[2 * idx + 1] = dlo;
+  win[4 * idx] = dhi;
+  win[4 * idx + 1] = dlo;
+  win[4 * idx + 2] = dmin >= kSmoothKn ? 1 : 0;
+  win[4 * idx + 3] = 0;
 }
 
 // ------------------------------------------------------- TDI term references per tile
@@ -338,8 +356,10 @@ struct RefLayout {
   static constexpr size_t flag = tdn + sizeof(R) * kTerms * kNV * (TAY ? 1 : 4);   // uchar [kTerms * kNV]
   static constexpr size_t gj = (flag + kTerms * kNV + 15) & ~(size_t)15;       // int [kGroups * kNV] start, length
   static constexpr size_t comb = gj + sizeof(int) * 2 * kGroups * kNV;         // int: combined filters usable
-  static constexpr size_t fg = (comb + sizeof(int) + 15) & ~(size_t)15;        // R [kGroups * kNV][2][JMAX]
-  static constexpr size_t stride = (fg + (TAY ? sizeof(R) * kGroups * kNV * 2 * JMAX : 0) + 255) & ~(size_t)255;
+  static constexpr size_t fg = (comb + sizeof(int) + 15) & ~(size_t)15;        // R G [kGroups * kNV][JMAX]
+  static constexpr size_t fd = (fg + (TAY ? sizeof(R) * kGroups * kNV * JMAX : 0) + 31) & ~(size_t)31;
+  //                                                                          double F [kGroups * kNV][JMAX]
+  static constexpr size_t stride = (fd + (TAY ? sizeof(double) * kGroups * kNV * JMAX : 0) + 255) & ~(size_t)255;
 };
 
 template <typename R, int K, bool TAY>
@@ -352,6 +372,7 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
   __shared__ unsigned char tflag[kTerms * kNV];
   __shared__ int gj0[kGroups * kNV], gJ[kGroups * kNV];
   __shared__ __align__(16) R fg[TAY ? kGroups * kNV * 2 * JMAX : 4];
+  __shared__ double fgd[TAY ? kGroups * kNV * JMAX : 1];     // F summed in FP64
   __shared__ int s_comb, s_span_bad;
   const int tid = threadIdx.x;
   const int64_t n0 = (int64_t)blockIdx.x * kTile;
@@ -442,6 +463,7 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
       // truncated after x) to its group's filters, one term of every group per round: the sums
       // run in term order
       for (int i = tid; i < kGroups * kNV * 2 * JMAX; i += kNT) fg[i] = (R)0;
+      for (int i = tid; i < kGroups * kNV * JMAX; i += kNT) fgd[i] = 0.0;
       int qmax = 0;
       for (int cc = 0; cc < 3; ++cc)
         for (int g = 0; g < P.terms.n_groups[cc]; ++g) qmax = max(qmax, P.terms.g_n[cc][g]);
@@ -455,9 +477,11 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
           const int t = P.terms.g_t[cc][g][q];
           const int e = (cc * 16 + t) * kNV + v;
           const R sg = (R)P.terms.t[cc][t].sign;
+          const double sgd = (double)P.terms.t[cc][t].sign;
           R* F = fg + (gi * 2) * JMAX;
+          double* Fd = fgd + gi * JMAX;
           if (tflag[e] == 2) {
-            if (i == 0) F[v * S + S2 + HY - gj0[gi]] += sg;   // n_ref - m_lo, relative to the start
+            if (i == 0) Fd[v * S + S2 + HY - gj0[gi]] += sgd;   // n_ref - m_lo, relative to the start
             continue;
           }
           const double f0 = tf0[e];
@@ -469,7 +493,7 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
             c0 = c0 * aj;
           }
           const int at = tjr[e] - K / 2 + 1 + i - gj0[gi];
-          F[at] += sg * (R)c0;
+          Fd[at] += sgd * c0;
           F[JMAX + at] += sg * tdn[e] * (R)c1;
         }
         __syncthreads();
@@ -492,7 +516,15 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
   }
   if (tid == 0) *(int*)(rec + Lay::comb) = comb1;
   if (TAY && comb1)
-    for (int i = tid; i < kGroups * kNV * 2 * JMAX; i += kNT) ((R*)(rec + Lay::fg))[i] = fg[i];
+    // F stays FP64: the TDI 2.0 filters cancel the signal to (2 pi f L)^2 of y and below at
+    // low frequencies, and an FP32 rounding of every tap (an error the same for all outputs of
+    // the interval) would not cancel with it.  G only carries the delay drift (~1e-5 of F's
+    // contribution) and is FP32.
+    for (int i = tid; i < kGroups * kNV * JMAX; i += kNT) {
+      const int gi = i / JMAX, j = i - gi * JMAX;
+      ((double*)(rec + Lay::fd))[i] = fgd[i];
+      ((R*)(rec + Lay::fg))[i] = fg[(gi * 2 + 1) * JMAX + j];
+    }
 }
 
 // ------------------------------------------------------- fused TDI kernel
@@ -526,7 +558,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   R* hpb = yb + 6 * MYP;
   R* hxb = hpb + WMAX;
   double* nd = (double*)(smem + (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15));
-  // FP32 copies of the projections P+, Px of each node (mixed precision: they scale an FP32 product)
+  // FP32 copies of the node geometry (mixed precision: it scales an FP32 product): P+, Px per
+  // link (12 per node) where the tile is smooth, else N+, Nx, 1 - k.n (18 per node)
   float* ndp = (float*)(nd + NNMAX * kNodeVals);
   const unsigned char* rec = (const unsigned char*)P.refs + (size_t)tile * Lay::stride;
   const double* tf0 = (const double*)(rec + Lay::f0);
@@ -543,7 +576,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
 
   // the tile's window bounds (k_windows): largest and smallest delay over its nodes, in samples
   typedef const __attribute__((address_space(4))) int cwin_t;
-  cwin_t* wp = (cwin_t*)(P.win + 2 * ((int64_t)b * gridDim.x + tile));
+  cwin_t* wp = (cwin_t*)(P.win + 4 * ((int64_t)b * gridDim.x + tile));
+  const int smooth = wp[2];
   const long long w0 = (long long)m_lo - wp[0] - K / 2 - 2;
   const long long w1 = (long long)m_hi - wp[1] + K / 2 + 2;
   int W = (int)(w1 - w0 + 1);
@@ -562,8 +596,19 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     double nv = 0.0;
     if (tid < nval) nv = ng[(tid / kNodeVals) * kNodeRec + tid % kNodeVals];
     for (int i = tid + kNT; i < nval; i += kNT) nd[i] = ng[(i / kNodeVals) * kNodeRec + i % kNodeVals];
-    if constexpr (sizeof(R) == 4)
-      for (int i = tid; i < NN * 12; i += kNT) ndp[i] = (float)ng[(i / 12) * kNodeRec + (i % 12 / 2) * kNL + (i & 1)];
+    if constexpr (sizeof(R) == 4) {
+      if (smooth) {
+        for (int i = tid; i < NN * 12; i += kNT) {
+          const double* o = ng + (i / 12) * kNodeRec + (i % 12 / 2) * kNL;
+          ndp[i] = (float)(o[i & 1] / o[3]);
+        }
+      } else {
+        for (int i = tid; i < NN * 18; i += kNT) {
+          const int f = i % 3;
+          ndp[i] = (float)ng[(i / 18) * kNodeRec + (i % 18 / 3) * kNL + (f == 2 ? 3 : f)];
+        }
+      }
+    }
     constexpr int kA = 6;
     const R* hg = (const R*)P.h + (2 * (int64_t)b) * N;
     for (int i0 = 0; i0 < W; i0 += kA * kNT) {
@@ -611,27 +656,52 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
         for (int r = 0; r < 4; ++r) Dr += w[r] * o0[r * kNodeVals + 6 * kNL + sc];
         lag2<R, K>(hpb, hxb, W, mloc - Dr * inv_dt, hpr[sc], hxr[sc]);
       }
+      if (sizeof(R) == 4 && smooth) {
 #pragma unroll
-      for (int li = 0; li < 6; ++li) {
-        R v0 = (R)0, v1 = (R)0;
-        double v2 = 0.0;
+        for (int li = 0; li < 6; ++li) {
+          R v0 = (R)0, v1 = (R)0;
+          double v2 = 0.0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double* o = o0 + r * kNodeVals + li * kNL;
-          if constexpr (sizeof(R) == 4) {
+          for (int r = 0; r < 4; ++r) {
             const float* op = ndp + (jl0 + it - 1 + r) * 12 + 2 * li;
             v0 += wp[r] * op[0];
             v1 += wp[r] * op[1];
-          } else {
-            v0 += w[r] * o[0];
-            v1 += w[r] * o[1];
+            v2 += w[r] * o0[r * kNodeVals + li * kNL + 2];
           }
-          v2 += w[r] * o[2];
+          R hps, hxs;
+          lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
+          const int rc = kRecv[li];
+          yb[li * MYP + mi] = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
         }
-        R hps, hxs;
-        lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
-        const int rc = kRecv[li];
-        yb[li * MYP + mi] = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
+      } else {
+#pragma unroll
+        for (int li = 0; li < 6; ++li) {
+          R v0 = (R)0, v1 = (R)0, v3 = (R)0;
+          double v2 = 0.0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const double* o = o0 + r * kNodeVals + li * kNL;
+            if constexpr (sizeof(R) == 4) {
+              const float* op = ndp + (jl0 + it - 1 + r) * 18 + 3 * li;
+              v0 += wp[r] * op[0];
+              v1 += wp[r] * op[1];
+              v3 += wp[r] * op[2];
+            } else {
+              v0 += w[r] * o[0];
+              v1 += w[r] * o[1];
+              v3 += w[r] * o[3];
+            }
+            v2 += w[r] * o[2];
+          }
+          R hps, hxs;
+          lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
+          const int rc = kRecv[li];
+          const R num = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
+          if constexpr (sizeof(R) == 4)
+            yb[li * MYP + mi] = num * __builtin_amdgcn_rcpf(v3);
+          else
+            yb[li * MYP + mi] = num / v3;
+        }
       }
     }
     // zero the tail of each y series up to its padded length: filter taps beyond the data read it
@@ -646,18 +716,22 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   crec_t* crec = (crec_t*)rec;
   const int comb1 = (TAY && !skip) ? *(const __attribute__((address_space(4))) int*)(crec + Lay::comb) : 0;
 
-  // D: TDI and A, E, T; each thread owns four consecutive output samples
+  // D: TDI and A, E, T; each thread owns four consecutive output samples.  The channels
+  // accumulate in FP64 in both precisions: the terms of a channel cancel against each other at
+  // low frequencies, and X, Y and Z against each other in T, so FP32 rounding of their sums
+  // would set the error of T, the channel with the lowest noise.
   const R* data = (const R*)P.data;
   R* out = (R*)P.out;
   const int nl0 = 4 * tid;
   const int64_t nb = n0 + nl0;
   if (nb >= N) return;
-  R ch[3][4], dv[3][4];
+  double ch[3][4];
+  R dv[3][4];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      ch[cc][k] = (R)0;
+      ch[cc][k] = 0.0;
       // the data of the residual, loaded before the filters run
       dv[cc][k] = (P.out_mode == 2 && nb + k < N) ? data[cc * N + nb + k] : (R)0;
     }
@@ -676,9 +750,13 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
           const int gi = (cc * 4 + g) * kNV + vw;
           const int J = gjs[kGroups * kNV + gi];
           const R* yl = yb + P.terms.g_link[cc][g] * MYP + gjs[gi] + dn0;
-          cf4_t* F = (cf4_t*)(crec + Lay::fg + (size_t)(gi * 2) * JMAX * sizeof(R));
-          cf4_t* G = F + JMAX / 4;
-          R a[4] = {(R)0, (R)0, (R)0, (R)0}, d[4] = {(R)0, (R)0, (R)0, (R)0};
+          typedef double v4d __attribute__((ext_vector_type(4)));
+          typedef const __attribute__((address_space(4))) v4d cd4_t;
+          cd4_t* F = (cd4_t*)(crec + Lay::fd + (size_t)gi * JMAX * sizeof(double));
+          cf4_t* G = (cf4_t*)(crec + Lay::fg + (size_t)gi * JMAX * sizeof(R));
+          // F's products and sums in FP64 (y is exact in FP64); the drift term in FP32
+          double a[4] = {0.0, 0.0, 0.0, 0.0};
+          R d[4] = {(R)0, (R)0, (R)0, (R)0};
           // yl, F, G and j are 16-byte aligned (gj0, MYP, JMAX and n - n_ref are multiples of 4):
           // one 16 B read of y per four taps, the window of eight samples kept in registers; eight
           // lanes of a 16 B read cover the 32 LDS banks without conflict
@@ -687,27 +765,35 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
           typedef float v4f __attribute__((ext_vector_type(4)));
           typedef const volatile __attribute__((address_space(3))) v4f lds_v4f;
           v4f y0 = *(lds_v4f*)(yl);
+          double yd0[4] = {(double)y0.x, (double)y0.y, (double)y0.z, (double)y0.w};
           for (int j = 0; j < J; j += 4) {
             R yv[8];
+            double yd[8];
             const v4f y1 = *(lds_v4f*)(yl + j + 4);
             yv[0] = y0.x; yv[1] = y0.y; yv[2] = y0.z; yv[3] = y0.w;
             yv[4] = y1.x; yv[5] = y1.y; yv[6] = y1.z; yv[7] = y1.w;
-            y0 = y1;
-            const v4c f4 = F[j / 4];
-            const v4c g4 = G[j / 4];
-            const R fa[4] = {f4.x, f4.y, f4.z, f4.w}, ga[4] = {g4.x, g4.y, g4.z, g4.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              const R f = fa[i], gg = ga[i];
+              yd[i] = yd0[i];
+              yd[4 + i] = (double)yv[4 + i];
+              yd0[i] = yd[4 + i];
+            }
+            y0 = y1;
+            const v4d f4 = F[j / 4];
+            const v4c g4 = G[j / 4];
+            const double fa[4] = {f4.x, f4.y, f4.z, f4.w};
+            const R ga[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
 #pragma unroll
               for (int k = 0; k < 4; ++k) {
-                a[k] += f * yv[i + k];
-                d[k] += gg * yv[i + k];
+                a[k] = fma(fa[i], yd[i + k], a[k]);
+                d[k] += ga[i] * yv[i + k];
               }
             }
           }
 #pragma unroll
-          for (int k = 0; k < 4; ++k) ch[cc][k] += a[k] - (R)(dn0 + k) * d[k];
+          for (int k = 0; k < 4; ++k) ch[cc][k] += a[k] - (double)((R)(dn0 + k) * d[k]);
         }
       }
     } else {
@@ -764,15 +850,15 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
     if (n >= N) break;
     R o0, o1, o2;
     if (P.out_mode == 1) {
-      o0 = ch[0][k]; o1 = ch[1][k]; o2 = ch[2][k];
+      o0 = (R)ch[0][k]; o1 = (R)ch[1][k]; o2 = (R)ch[2][k];
     } else {
-      // no contraction: A, E, T are rounded before the data is subtracted, so a template equal
-      // to the data leaves a residual of exactly zero
+      // no contraction: A, E, T are formed in FP64 and rounded to R before the data is
+      // subtracted, so a template equal to the data leaves a residual of exactly zero
 #pragma clang fp contract(off)
-      const R r2 = (R)0.70710678118654752440, r6 = (R)0.40824829046386301637, r3 = (R)0.57735026918962576451;
-      o0 = (ch[2][k] - ch[0][k]) * r2;
-      o1 = (ch[0][k] - (R)2 * ch[1][k] + ch[2][k]) * r6;
-      o2 = (ch[0][k] + ch[1][k] + ch[2][k]) * r3;
+      const double r2 = 0.70710678118654752440, r6 = 0.40824829046386301637, r3 = 0.57735026918962576451;
+      o0 = (R)((ch[2][k] - ch[0][k]) * r2);
+      o1 = (R)((ch[0][k] - 2.0 * ch[1][k] + ch[2][k]) * r6);
+      o2 = (R)((ch[0][k] + ch[1][k] + ch[2][k]) * r3);
       o0 -= dv[0][k];   // zero unless the residual is written
       o1 -= dv[1][k];
       o2 -= dv[2][k];
@@ -803,7 +889,7 @@ struct TdiGeom {
     if (!P.nodes || !P.refs) return hipErrorInvalidValue;
     constexpr int JMAX = CombLen<K>::value;
     bytes = (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) + (size_t)NNMAX * kNodeVals * sizeof(double) +
-            (sizeof(R) == 4 ? (size_t)NNMAX * 12 * sizeof(float) : 0);
+            (sizeof(R) == 4 ? (size_t)NNMAX * 18 * sizeof(float) : 0);
     if (bytes > 160 * 1024) return hipErrorInvalidValue;
     // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
     const int span = (int)ceil(P.terms.g_span * P.orb.max_light_time * P.g.inv_dt * 1.001) + 2 + K + 3;
@@ -859,7 +945,7 @@ static size_t refs_stride_k(int taps) {
 void tdi_scratch_bytes(const TdiLaunch& P, size_t* nodes, size_t* refs) {
   // node records, then two int32 window bounds per (template, tile)
   *nodes = (size_t)P.batch * (size_t)P.orb.n_nodes * kNodeRec * sizeof(double) +
-           (size_t)P.batch * (size_t)((P.g.n + kTile - 1) / kTile) * 2 * sizeof(int);
+           (size_t)P.batch * (size_t)((P.g.n + kTile - 1) / kTile) * 4 * sizeof(int);
   const size_t stride = P.precision == 0 ? refs_stride_k<double>(P.taps) : refs_stride_k<float>(P.taps);
   *refs = (size_t)((P.g.n + kTile - 1) / kTile) * stride;
 }

@@ -79,8 +79,10 @@ _sig = {
     "lt_lisa_tdi_response": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
                               ctypes.POINTER(TdiCfg), _P, _P, _P], ctypes.c_int),
     "lt_tdi_loglike": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
-                        ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data), _P, _P, _P, _P],
-                       ctypes.c_int),
+                        ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data), _P, _P, _P, _P,
+                        ctypes.c_size_t, _P], ctypes.c_int),
+    "lt_workspace_size": ([_P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(TdiCfg),
+                           ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "lt_noise_inner": ([_P, _P, _I64, ctypes.POINTER(Grid), ctypes.POINTER(Psd), ctypes.c_int, ctypes.c_int, _P, _P],
                        ctypes.c_int),
     "lt_rfft": ([_P, _P, _I64, _I64, ctypes.c_double, ctypes.c_int, _P, _P], ctypes.c_int),
@@ -131,14 +133,39 @@ def _check(status):
         raise LisaTDError("liblisatd error %d: %s" % (status, _lib.lt_last_error().decode()))
 
 
-def _ptr(t):
+def _ptr(t, name="tensor", dtype=None, numel=None, shape=None, device=None):
+    """Data pointer of a device tensor after the checks that keep a kernel inside its buffers:
+    a contiguous tensor on a ROCm device (on `device` when given), of `dtype`, with exactly
+    `numel` elements or the given shape (None entries match any size).  Raises ValueError
+    before anything reaches the library."""
     if t is None:
         return None
-    if not t.is_cuda:
-        raise ValueError("device tensor required")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s: torch tensor required" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s: dtype %s, expected %s" % (name, t.dtype, dtype))
+    if shape is not None and (t.dim() != len(shape) or
+                              any(w is not None and int(w) != int(a) for a, w in zip(t.shape, shape))):
+        raise ValueError("%s: shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    if numel is not None and t.numel() != int(numel):
+        raise ValueError("%s: %d elements, expected %d" % (name, t.numel(), int(numel)))
     if not t.is_contiguous():
-        raise ValueError("contiguous tensor required")
+        raise ValueError("%s: contiguous tensor required" % name)
+    if not t.is_cuda:
+        raise ValueError("%s: device tensor required" % name)
+    if device is not None and t.device.index != device:
+        raise ValueError("%s: on device %s, the context is on device %d" % (name, t.device, device))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _psd_struct(psd, n, f_lo, f_hi, device=None):
+    """lt_psd for a device FP64 tensor [3][n/2+1] (one row per channel A, E, T)."""
+    _ptr(psd, "psd", torch.float64, shape=(3, n // 2 + 1), device=device)
+    return Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
+
+
+def _params_ptr(params, device=None):
+    return _ptr(params, "params", torch.float64, shape=(None, 16), device=device)
 
 
 def _stream(stream=None):
@@ -209,39 +236,78 @@ class Context:
 
     # -- entry points ---------------------------------------------------------
     def phenomt_modes(self, params, g, cfg, out, stream=None):
-        _check(_lib.lt_phenomt_modes(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
-                                     ctypes.byref(self.grid(g)), _ptr(out), _stream(stream)))
+        """out: device FP64 [B][n_modes][n] complex, e.g. a float64 tensor [B, n_modes, n, 2]."""
+        B, n = params.shape[0], int(g["n"])
+        nm = bin(int(cfg.mode_mask) & 31).count("1")
+        pp = _params_ptr(params, self.device)
+        po = _ptr(out, "modes", torch.float64, numel=B * nm * n * 2, device=self.device)
+        _check(_lib.lt_phenomt_modes(self.h, pp, B, ctypes.byref(cfg), ctypes.byref(self.grid(g)), po,
+                                     _stream(stream)))
         return out
 
     def phenomt_polarizations(self, params, g, cfg, out, stream=None):
-        _check(_lib.lt_phenomt_polarizations(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
-                                             ctypes.byref(self.grid(g)), _ptr(out), _stream(stream)))
+        """out: device FP64 [B][2][n] (h+, hx)."""
+        B, n = params.shape[0], int(g["n"])
+        pp = _params_ptr(params, self.device)
+        po = _ptr(out, "hpc", torch.float64, numel=B * 2 * n, device=self.device)
+        _check(_lib.lt_phenomt_polarizations(self.h, pp, B, ctypes.byref(cfg), ctypes.byref(self.grid(g)), po,
+                                             _stream(stream)))
         return out
 
     def lisa_tdi_response(self, params, g, cfg, orbit, tdi, out, status=None, stream=None):
-        _check(_lib.lt_lisa_tdi_response(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
-                                         ctypes.byref(self.grid(g)), ctypes.byref(orbit), ctypes.byref(tdi),
-                                         _ptr(out), _ptr(status), _stream(stream)))
+        """out: device [B][3][n] in real_dtype(cfg.precision); status: device int32 [B] or None."""
+        B, n = params.shape[0], int(g["n"])
+        pp = _params_ptr(params, self.device)
+        po = _ptr(out, "out", real_dtype(cfg.precision), numel=B * 3 * n, device=self.device)
+        ps = _ptr(status, "status", torch.int32, numel=B, device=self.device)
+        _check(_lib.lt_lisa_tdi_response(self.h, pp, B, ctypes.byref(cfg), ctypes.byref(self.grid(g)),
+                                         ctypes.byref(orbit), ctypes.byref(tdi), po, ps, _stream(stream)))
         return out
 
     def tdi_loglike(self, params, g, cfg, orbit, tdi, psd, data_aet, dd, logl, logl_full=None, status=None,
-                    f_lo=3e-4, f_hi=0.02, stream=None):
-        P = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
-        D = Data(_ptr(data_aet), float(dd))
-        _check(_lib.lt_tdi_loglike(self.h, _ptr(params), params.shape[0], ctypes.byref(cfg),
-                                   ctypes.byref(self.grid(g)), ctypes.byref(orbit), ctypes.byref(tdi),
-                                   ctypes.byref(P), ctypes.byref(D), _ptr(logl), _ptr(logl_full), _ptr(status),
-                                   _stream(stream)))
+                    f_lo=3e-4, f_hi=0.02, stream=None, workspace=None):
+        """psd: device FP64 [3][n/2+1]; data_aet: device [3][n] in real_dtype(cfg.precision); logl,
+        logl_full: device FP64 [B] (logl may be None when logl_full is given); status: int32 [B];
+        workspace: None (the context's scratch) or a device uint8 tensor (see workspace_size)."""
+        B, n = params.shape[0], int(g["n"])
+        pp = _params_ptr(params, self.device)
+        P = _psd_struct(psd, n, f_lo, f_hi, self.device)
+        D = Data(_ptr(data_aet, "data", real_dtype(cfg.precision), numel=3 * n, device=self.device), float(dd))
+        pl = _ptr(logl, "logl", torch.float64, numel=B, device=self.device)
+        pf = _ptr(logl_full, "logl_full", torch.float64, numel=B, device=self.device)
+        ps = _ptr(status, "status", torch.int32, numel=B, device=self.device)
+        pw = _ptr(workspace, "workspace", torch.uint8, shape=(None,), device=self.device)
+        wb = workspace.numel() if workspace is not None else 0
+        _check(_lib.lt_tdi_loglike(self.h, pp, B, ctypes.byref(cfg), ctypes.byref(self.grid(g)),
+                                   ctypes.byref(orbit), ctypes.byref(tdi), ctypes.byref(P), ctypes.byref(D),
+                                   pl, pf, ps, pw, wb, _stream(stream)))
         return logl
 
+    def workspace_size(self, batch, g, cfg, tdi):
+        """(bytes for full chunks, bytes for chunks of one template) of tdi_loglike's workspace."""
+        full, one = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.lt_workspace_size(self.h, int(batch), ctypes.byref(cfg), ctypes.byref(self.grid(g)),
+                                      ctypes.byref(tdi), ctypes.byref(full), ctypes.byref(one)))
+        return int(full.value), int(one.value)
+
     def noise_inner(self, x, g, psd, out, channels=7, precision=LT_FP64, f_lo=3e-4, f_hi=0.02, stream=None):
-        P = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
-        _check(_lib.lt_noise_inner(self.h, _ptr(x), x.shape[0], ctypes.byref(self.grid(g)), ctypes.byref(P),
-                                   channels, precision, _ptr(out), _stream(stream)))
+        """x: device [B][3][n] in real_dtype(precision); out: device FP64 [B]."""
+        B, n = x.shape[0], int(g["n"])
+        px = _ptr(x, "x", real_dtype(precision), numel=B * 3 * n, device=self.device)
+        P = _psd_struct(psd, n, f_lo, f_hi, self.device)
+        po = _ptr(out, "out", torch.float64, numel=B, device=self.device)
+        _check(_lib.lt_noise_inner(self.h, px, B, ctypes.byref(self.grid(g)), ctypes.byref(P), channels, precision,
+                                   po, _stream(stream)))
         return out
 
     def rfft(self, x, dt, out, precision=LT_FP64, stream=None):
-        _check(_lib.lt_rfft(self.h, _ptr(x), x.shape[0], x.shape[1], dt, precision, _ptr(out), _stream(stream)))
+        """x: device [rows][n] in real_dtype(precision); out: [rows][n/2+1] complex of the same real type
+        (e.g. a tensor [rows, n/2+1, 2])."""
+        rdt = real_dtype(precision)
+        px = _ptr(x, "x", rdt, shape=(None, None), device=self.device)
+        rows, n = x.shape
+        po = _ptr(out, "spec", rdt, numel=rows * (n // 2 + 1) * 2, device=self.device)
+        _check(_lib.lt_rfft(self.h, px, rows, n, dt, precision, po, _stream(stream)))
         return out
 
     def profile_enable(self, on=True):
@@ -256,8 +322,8 @@ class Context:
 
 def psd_sangria(g, generation, out, arm=ARM_M, stream=None):
     """Fills out [3][n/2+1] (device FP64) with the PSD of Eqs. (2.14)-(2.15)."""
-    _check(_lib.lt_psd_sangria(ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), generation, arm, _ptr(out),
-                               _stream(stream)))
+    po = _ptr(out, "S", torch.float64, numel=3 * (int(g["n"]) // 2 + 1))
+    _check(_lib.lt_psd_sangria(ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), generation, arm, po, _stream(stream)))
     return out
 
 
@@ -290,8 +356,9 @@ class Sampler:
             self._ic, pic = _host(icov)
             c.n_gauss, c.gauss_mean, c.gauss_icov = self._m.shape[0], pm, pic
         else:
-            self._psd = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
-            self._data = Data(_ptr(data_aet), float(dd))
+            self._psd = _psd_struct(psd, int(g["n"]), f_lo, f_hi, device)
+            self._data = Data(_ptr(data_aet, "data", real_dtype(cfg.precision), numel=3 * int(g["n"]),
+                                   device=device), float(dd))
             self._keep = (psd, data_aet)
             args = [ctypes.byref(cfg), ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), ctypes.byref(orbit),
                     ctypes.byref(tdi), ctypes.byref(self._psd), ctypes.byref(self._data)]
@@ -357,7 +424,7 @@ def fisher(ctx, x0, param_kind, t_c, steps, g, cfg, orbit, tdi, psd, f_lo=3e-4, 
     st, ps = _host(steps)
     d = x.size
     G = np.zeros((d, d))
-    P = Psd((ctypes.c_void_p * 3)(*[psd[i].data_ptr() for i in range(3)]), f_lo, f_hi)
+    P = _psd_struct(psd, int(g["n"]), f_lo, f_hi, ctx.device)
     _check(_lib.lt_fisher(ctx.h, px, kinds[param_kind], float(t_c), ps, ctypes.byref(cfg),
                           ctypes.byref(Grid(g["t0"], g["dt"], g["n"])), ctypes.byref(orbit), ctypes.byref(tdi),
                           ctypes.byref(P), G.ctypes.data))
@@ -383,6 +450,7 @@ class Flow:
         h = ctypes.c_void_p()
         _check(_lib.lt_flow_create(device, dim, n_layers, hidden, max_batch, ctypes.byref(h)))
         self.h, self.d, self.L, self.H, self.max_batch = h, dim, n_layers, hidden, max_batch
+        self.device = device
 
     @property
     def num_params(self):
@@ -410,26 +478,35 @@ class Flow:
         _check(_lib.lt_flow_get_params(self.h, w.ctypes.data))
         return w
 
+    def _rows(self, x, name="x"):
+        """Pointer of device FP64 rows [n][dim] on the flow's device."""
+        return _ptr(x, name, torch.float64, shape=(None, self.d), device=self.device)
+
     def log_prob(self, x, out=None, stream=None):
+        px = self._rows(x)
         out = out if out is not None else torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
-        _check(_lib.lt_flow_log_prob(self.h, _ptr(x), x.shape[0], _ptr(out), _stream(stream)))
+        po = _ptr(out, "logq", torch.float64, numel=x.shape[0], device=self.device)
+        _check(_lib.lt_flow_log_prob(self.h, px, x.shape[0], po, _stream(stream)))
         return out
 
     def sample(self, z, stream=None):
+        pz = self._rows(z, "z")
         x = torch.empty_like(z)
         logq = torch.empty(z.shape[0], dtype=torch.float64, device=z.device)
-        _check(_lib.lt_flow_sample(self.h, _ptr(z), z.shape[0], _ptr(x), _ptr(logq), _stream(stream)))
+        _check(_lib.lt_flow_sample(self.h, pz, z.shape[0], _ptr(x), _ptr(logq), _stream(stream)))
         return x, logq
 
     def loss_grad(self, x):
         import numpy as np
+        px = self._rows(x)
         logq = np.zeros(x.shape[0])
         g = np.zeros(self.num_params, dtype=np.float32)
-        _check(_lib.lt_flow_loss_grad(self.h, _ptr(x), x.shape[0], logq.ctypes.data, g.ctypes.data))
+        _check(_lib.lt_flow_loss_grad(self.h, px, x.shape[0], logq.ctypes.data, g.ctypes.data))
         return logq, g
 
     def train(self, x, steps, batch, lr, stream=None):
-        _check(_lib.lt_flow_train(self.h, _ptr(x), x.shape[0], int(steps), int(batch), float(lr), _stream(stream)))
+        px = self._rows(x)
+        _check(_lib.lt_flow_train(self.h, px, x.shape[0], int(steps), int(batch), float(lr), _stream(stream)))
 
     def close(self):
         if self.h:
