@@ -173,6 +173,22 @@ lt_status lt_tdi_loglike(lt_ctx* ctx, const double* params, int64_t batch, const
                          const lt_psd* psd, const lt_data* data, double* logl, double* logl_full,
                          int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
 
+/* lt_tdi_loglike for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation and
+ * results, with every per-call array in a fixed scratch of 128 MiB that the library holds on
+ * each GPU it runs on until the process ends.  The call allocates, frees and synchronises
+ * nothing and records no events; the FFT plan and orbit node table for (grid, orbit) must
+ * already be in the context (any lt_tdi_loglike call with them builds both), else
+ * LT_ERR_CONFIG.  Templates run in chunks that fit the scratch (at 2^20 samples four in mixed
+ * precision, two in FP64); a grid whose single template does not fit returns
+ * LT_ERR_WORKSPACE before any launch.  Every call on a GPU uses that GPU's one scratch, so
+ * calls that overlap on one GPU (different streams or contexts, unsynchronised) race and give
+ * wrong results: order them. */
+lt_status lt_tdi_loglike_noalloc(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                                 const lt_grid* grid, const lt_orbit* orbit, const lt_tdi_cfg* tdi,
+                                 const lt_psd* psd, const lt_data* data, double* logl, double* logl_full,
+                                 int32_t* status, void* stream);
+
 /* Workspace of lt_tdi_loglike for `batch` templates with this configuration:
  * bytes (nullable) for full-size chunks (min(batch, 256) templates per chunk),
  * min_bytes (nullable) for chunks of one template.  Host only; no device work. */

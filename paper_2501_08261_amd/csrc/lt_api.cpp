@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -76,12 +77,38 @@ struct lt_ctx {
       orbits;
   DevBuf tpl, work, partial, wperm, wave, nodes, refs;
   DevBuf ws;              // lt_tdi_loglike's scratch when the caller passes no workspace
+  void* scratch = nullptr;   // this device's copy of the fixed scratch (lt_tdi_loglike_noalloc)
   bool profiling = false;
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
   double prof_ms[8] = {0};
   int64_t prof_n[8] = {0};
 };
+
+// ------------------------------------------------------------------ fixed scratch
+// Device memory of lt_tdi_loglike_noalloc, for callers that cannot allocate: one copy per GPU,
+// loaded with the library and held until the process ends.  In host code the array's name is
+// not a device address: every host use goes through the address hipGetSymbolAddress returns for
+// the current device (kept per device by lt_ctx_create).  Calls on one GPU share it.
+constexpr size_t kFixedScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[kMaxDevices];
+
+// the fixed scratch's device address on `device` (current): looked up once per device
+static hipError_t fixed_scratch(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 // Events bracket a launch on its stream when profiling is on.
 struct Prof {
@@ -562,8 +589,11 @@ lt_status lt_ctx_create(int hip_device, lt_ctx** out) {
   LT_HIP(hipGetDeviceCount(&n));
   if (hip_device < 0 || hip_device >= n) return fail(LT_ERR_CONFIG, "no such HIP device");
   LT_HIP(hipSetDevice(hip_device));
+  void* fixed = nullptr;
+  LT_HIP(fixed_scratch(hip_device, &fixed));
   lt_ctx* c = new lt_ctx();
   c->device = hip_device;
+  c->scratch = fixed;
   *out = c;
   return LT_OK;
 }
@@ -890,6 +920,30 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
     base = (unsigned char*)c->ws.p;
   }
   return loglike_run(c, params, batch, cfg, g, o, t, psd, data, logl, logl_full, status, nfold, chunk, base, true, s);
+}
+
+lt_status lt_tdi_loglike_noalloc(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg,
+                                 const lt_grid* g, const lt_orbit* o, const lt_tdi_cfg* t, const lt_psd* psd,
+                                 const lt_data* data, double* logl, double* logl_full, int32_t* status,
+                                 void* stream) {
+  int nfold;
+  lt_status st = check_loglike(c, params, batch, cfg, g, o, t, psd, data, logl, logl_full, &nfold);
+  if (st) return st;
+  if (!c->scratch) return fail(LT_ERR_DEVICE, "no fixed scratch on this device");
+  const int64_t chunk = loglike_chunk_for(kFixedScratchBytes, batch, cfg, g, t, nfold);
+  if (chunk < 1) {
+    const size_t need = loglike_layout(1, cfg, g, t, nfold, nullptr, nullptr);
+    return fail(LT_ERR_WORKSPACE, "one template of this grid needs " + std::to_string(need) +
+                                      " bytes of scratch, more than the fixed " +
+                                      std::to_string(kFixedScratchBytes) + " (use lt_tdi_loglike)");
+  }
+  // no profiling events either: this path creates nothing
+  const bool prof = c->profiling;
+  c->profiling = false;
+  st = loglike_run(c, params, batch, cfg, g, o, t, psd, data, logl, logl_full, status, nfold, chunk,
+                   (unsigned char*)c->scratch, false, (hipStream_t)stream);
+  c->profiling = prof;
+  return st;
 }
 
 lt_status lt_noise_inner(lt_ctx* c, const void* x, int64_t batch, const lt_grid* g, const lt_psd* psd, int channels,

@@ -81,6 +81,9 @@ _sig = {
     "lt_tdi_loglike": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
                         ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data), _P, _P, _P, _P,
                         ctypes.c_size_t, _P], ctypes.c_int),
+    "lt_tdi_loglike_noalloc": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
+                                ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data), _P, _P, _P, _P],
+                               ctypes.c_int),
     "lt_workspace_size": ([_P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(TdiCfg),
                            ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "lt_noise_inner": ([_P, _P, _I64, ctypes.POINTER(Grid), ctypes.POINTER(Psd), ctypes.c_int, ctypes.c_int, _P, _P],
@@ -281,6 +284,22 @@ class Context:
         _check(_lib.lt_tdi_loglike(self.h, pp, B, ctypes.byref(cfg), ctypes.byref(self.grid(g)),
                                    ctypes.byref(orbit), ctypes.byref(tdi), ctypes.byref(P), ctypes.byref(D),
                                    pl, pf, ps, pw, wb, _stream(stream)))
+        return logl
+
+    def tdi_loglike_noalloc(self, params, g, cfg, orbit, tdi, psd, data_aet, dd, logl, logl_full=None, status=None,
+                            f_lo=3e-4, f_hi=0.02, stream=None):
+        """tdi_loglike with the library's fixed scratch: allocates nothing (the grid's FFT plan and
+        the orbit's node table must already be in the context)."""
+        B, n = params.shape[0], int(g["n"])
+        pp = _params_ptr(params, self.device)
+        P = _psd_struct(psd, n, f_lo, f_hi, self.device)
+        D = Data(_ptr(data_aet, "data", real_dtype(cfg.precision), numel=3 * n, device=self.device), float(dd))
+        pl = _ptr(logl, "logl", torch.float64, numel=B, device=self.device)
+        pf = _ptr(logl_full, "logl_full", torch.float64, numel=B, device=self.device)
+        ps = _ptr(status, "status", torch.int32, numel=B, device=self.device)
+        _check(_lib.lt_tdi_loglike_noalloc(self.h, pp, B, ctypes.byref(cfg), ctypes.byref(self.grid(g)),
+                                           ctypes.byref(orbit), ctypes.byref(tdi), ctypes.byref(P), ctypes.byref(D),
+                                           pl, pf, ps, _stream(stream)))
         return logl
 
     def workspace_size(self, batch, g, cfg, tdi):
