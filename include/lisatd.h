@@ -382,6 +382,14 @@ lt_status lt_sampler_set_flow_fold(lt_sampler* s, int index, double period, doub
  * log q(x) and log q(y) - log N(z') in place of log q(y) (the ratio of the flow's
  * Jacobians); the fold applies as before.  Rebuilds the captured step. */
 lt_status lt_sampler_set_flow_walk(lt_sampler* s, double step);
+/* Mixes the flow move with the plain stretch move (the learned proposal's rate p_flow): each
+ * sampler step runs the flow move with probability p_flow in [0, 1], decided on the device by
+ * u < p_flow with u from Philox counter (step, 0x800, 0, 0); a step without it proposes
+ * nothing for it (its likelihood rows are unphysical and skipped).  The choice does not depend
+ * on the state, and every move is an exact Metropolis-Hastings step, so the mixture keeps the
+ * target.  1 (the default) runs the flow move every step; 0 is the plain sampler (the
+ * fallback), even with a flow attached.  Rebuilds the captured step. */
+lt_status lt_flow_set_mix(lt_sampler* s, double p_flow);
 /* Flow moves accepted and proposed since lt_sampler_set_state (host int64 [2]). */
 lt_status lt_sampler_flow_counts(lt_sampler* s, int64_t* counts);
 

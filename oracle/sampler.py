@@ -29,6 +29,11 @@ of the GPU sampler:
   (step, 0x600, walker, 0), and both ln q carry - ln n (the proposal density
   of a copy is q_flow(y_f) / n), so the ratio stays exact; a y_f outside the
   window is outside the proposal's range and is rejected;
+* mixture with the plain move (the learned proposal mixed with the stretch move at rate
+  p_flow): each step runs the flow move only when u < p_flow, u from counter
+  (step, 0x800, 0, 0); a step without it proposes nothing for it.  Every step's kernel
+  (stretch move, flow move, swaps) keeps the target, and the choice does not depend on the
+  state, so the mixture keeps it too; p_flow = 1 runs the flow move every step;
 * optional latent random walk in place of the independence proposal:
   z = f(x) (the flow's forward map of the folded position), z' = z + w eps,
   eps standard normal from counter (step, 0x700, walker, q) like the base
@@ -49,6 +54,7 @@ W0, W1 = 0x9E3779B9, 0xBB67AE85
 MASK = 0xFFFFFFFF
 TAG_MOVE, TAG_SHIFT, TAG_SWAP, TAG_FLOWZ, TAG_FLOWU, TAG_FLOWC, TAG_FLOWW = (0x100, 0x200, 0x300, 0x400, 0x500,
                                                                      0x600, 0x700)
+TAG_FLOWG = 0x800
 
 
 def philox4x32_10(ctr, key):
@@ -117,7 +123,9 @@ class PTSampler:
         self.flow = None
         self.fold = None
         self.walk = 0.0
+        self.p_flow = 1.0
         self.facc = self.fprop = 0
+        self.flow_steps = 0
 
     def set_flow(self, P, mu, sigma):
         """Attach a flow (oracle.flow parameters; None detaches)."""
@@ -126,6 +134,15 @@ class PTSampler:
     def set_flow_fold(self, index, period=math.pi, start=0.0):
         """Fold coordinate `index` into [start, start + period) for the flow move (index < 0: none)."""
         self.fold = None if index < 0 else (int(index), float(period), float(start))
+
+    def set_flow_mix(self, p_flow):
+        """Probability that a step runs the flow move (0: the plain sampler)."""
+        self.p_flow = float(p_flow)
+
+    def flow_gate(self, s):
+        """Whether step s runs the flow move: u < p_flow, u from counter (s, 0x800, 0, 0)."""
+        r = philox4x32_10(_ctr(s, TAG_FLOWG, np.array([0])), self.key)
+        return bool(u01(r[0, 0]) < self.p_flow)
 
     def set_flow_walk(self, step):
         """Latent random walk of this step as the flow move (0: independence proposals)."""
@@ -219,6 +236,7 @@ class PTSampler:
         self.step_count = 0
         self.acc = self.prop = self.sacc = self.sprop = 0
         self.facc = self.fprop = 0
+        self.flow_steps = 0
 
     def step(self):
         T, W, d, half = self.T, self.W, self.d, self.W // 2
@@ -242,8 +260,9 @@ class PTSampler:
             self.logp[t[ok], k[ok]] = lpy[ok]
             self.acc += int(ok.sum())
             self.prop += ok.size
-        if self.flow is not None:
+        if self.flow is not None and self.p_flow > 0.0 and self.flow_gate(s):
             self.flow_move(s)
+            self.flow_steps += 1
         for i in range(T - 2, -1, -1):
             rr = philox4x32_10(_ctr(s, TAG_SHIFT + i, np.array([0])), self.key)
             shift = int(rr[0, 0] % np.uint64(W))

@@ -728,13 +728,15 @@ static lt_status band_bins(const lt_grid* g, const lt_psd* psd, int* k_lo, int* 
 // FFT both passes over rows of [rows][n] (in place), band power into `partial`
 // (band weights in wperm)
 static lt_status fft_band(lt_ctx* c, Plan* p, void* series, int64_t rows, int precision, int k_lo, int k_hi,
-                          const lt_grid* g, double* partial, const double* wperm, hipStream_t s) {
+                          const lt_grid* g, double* partial, const double* wperm, const int32_t* skip,
+                          hipStream_t s) {
   {
     Prof pr(c, 2, s);
-    LT_HIP(launch_fft_pass1(p->dev, series, rows, precision, s));
+    LT_HIP(launch_fft_pass1(p->dev, series, rows, precision, skip, s));
   }
   Prof pr(c, 3, s);
-  LT_HIP(launch_fft_pass2(p->dev, series, rows, precision, 1, g->dt, nullptr, wperm, 3, partial, k_lo, k_hi, s));
+  LT_HIP(launch_fft_pass2(p->dev, series, rows, precision, 1, g->dt, nullptr, wperm, 3, partial, k_lo, k_hi, skip,
+                          s));
   return LT_OK;
 }
 
@@ -753,12 +755,12 @@ static lt_status band_power(lt_ctx* c, Plan* p, void* series, int64_t rows, int 
   }
   {
     Prof pr(c, 2, s);
-    LT_HIP(launch_fft_pass1(p->dev, series, rows, precision, s));
+    LT_HIP(launch_fft_pass1(p->dev, series, rows, precision, nullptr, s));
   }
   {
     Prof pr(c, 3, s);
     LT_HIP(launch_fft_pass2(p->dev, series, rows, precision, 1, g->dt, nullptr, (const double*)c->wperm.p, 3,
-                            (double*)c->partial.p, k_lo, k_hi, s));
+                            (double*)c->partial.p, k_lo, k_hi, nullptr, s));
   }
   return LT_OK;
 }
@@ -874,7 +876,7 @@ static lt_status loglike_run(lt_ctx* c, const double* params, int64_t batch, con
     }
     st = run_tdi_core(c, w.tpl, b, cfg, g, od, t, 2, data->aet, w.work, stat, w.wave, w.nodes, w.refs, s);
     if (st) return st;
-    st = fft_band(c, p, w.work, b * 3, cfg->precision, k_lo, k_hi, g, w.partial, w.wperm, s);
+    st = fft_band(c, p, w.work, b * 3, cfg->precision, k_lo, k_hi, g, w.partial, w.wperm, stat, s);
     if (st) return st;
     Prof pr(c, 4, s);
     LT_HIP(launch_finalize(w.partial, b, nfold, scale, data->dd, stat, logl ? logl + off : nullptr,
@@ -987,10 +989,11 @@ lt_status lt_rfft(lt_ctx* c, const void* x, int64_t rows, int64_t n, double dt, 
   LT_HIP(hipMemcpyAsync(c->work.p, x, bytes, hipMemcpyDeviceToDevice, s));
   {
     Prof pr(c, 2, s);
-    LT_HIP(launch_fft_pass1(p->dev, c->work.p, rows, precision, s));
+    LT_HIP(launch_fft_pass1(p->dev, c->work.p, rows, precision, nullptr, s));
   }
   Prof pr(c, 3, s);
-  LT_HIP(launch_fft_pass2(p->dev, c->work.p, rows, precision, 0, dt, spec, nullptr, 3, nullptr, 0, p->dev.n, s));
+  LT_HIP(launch_fft_pass2(p->dev, c->work.p, rows, precision, 0, dt, spec, nullptr, 3, nullptr, 0, p->dev.n, nullptr,
+                          s));
   return LT_OK;
 }
 

@@ -129,12 +129,13 @@ __device__ inline C2<R> wN(const C2<R>* lo, const C2<R>* hi, int64_t k) {
 constexpr int kCB = 8;   // columns per pass-1 workgroup
 
 template <typename R>
-__global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data) {
+__global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data, const int32_t* skip) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int n1 = p.n1, n2 = p.n2;
   C2<R>* a = (C2<R>*)smem;
   C2<R>* b = a + kCB * n1;
   const int64_t row = blockIdx.y;
+  if (skip && skip[row / 3] != 0) return;   // a faulted template's rows are not needed
   const int j2_0 = blockIdx.x * kCB;
   C2<R>* z = data + row * p.n;
   for (int i = threadIdx.x; i < kCB * n1; i += kFT) {
@@ -162,7 +163,9 @@ __global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data) {
 template <typename R>
 __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, int mode, double dt,
                                                C2<R>* spec, const double* wperm, int64_t ch_rows,
-                                               double* partial, int64_t kb_lo, int64_t kb_hi) {
+                                               double* partial, int64_t kb_lo, int64_t kb_hi,
+                                               const int32_t* skip) {
+  if (skip && skip[blockIdx.y / 3] != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kFT / 64];
   const int n1 = p.n1, n2 = p.n2;
@@ -308,11 +311,12 @@ __device__ inline void ct_fft_strided(C2<R>* buf, const C2<R>* tw) {
 constexpr int kP1Pad = 512 / 8 + 1;
 constexpr int kP1Threads = 512;   // 2 workgroups of 65.7 KB fit a CU: 16 waves
 template <typename R>
-__global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* data) {
+__global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* data, const int32_t* skip) {
   constexpr int N1 = 512, N2 = 1024, CB = 128 / (int)sizeof(C2<R>), LP = N1 + kP1Pad;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<R>* buf = (C2<R>*)smem;      // [CB][LP]
   const int64_t row = blockIdx.y;
+  if (skip && skip[row / 3] != 0) return;   // a faulted template's rows are not needed
   const int j2_0 = blockIdx.x * CB;
   C2<R>* z = data + row * ((int64_t)N1 * N2);
   constexpr int PT = CB * N1 / kP1Threads;   // elements per thread
@@ -357,7 +361,8 @@ __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* d
 template <typename R>
 __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* data, int mode, double dt,
                                                     C2<R>* spec, const double* wperm, double* partial,
-                                                    int64_t kb_lo, int64_t kb_hi) {
+                                                    int64_t kb_lo, int64_t kb_hi, const int32_t* skip) {
+  if (skip && skip[blockIdx.y / 3] != 0) return;
   constexpr int N1 = 512, N2 = 1024, NR = 4;
   constexpr bool PAD = sizeof(R) == 4;
   constexpr int LS = PAD ? N2 + N2 / 8 + 1 : N2;
@@ -496,36 +501,37 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
 static bool hot_plan(const FftPlanDev& p) { return p.n1 == 512 && p.n2 == 1024; }
 
 template <typename R>
-static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, hipStream_t s) {
+static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, const int32_t* skip, hipStream_t s) {
   if (hot_plan(p)) {
     constexpr int CB = 128 / (int)sizeof(C2<R>);
     const int bytes = CB * (512 + kP1Pad) * (int)sizeof(C2<R>);
     hipError_t e = hipFuncSetAttribute((const void*)k_pass1_512<R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
     dim3 grid((unsigned)(p.n2 / CB), (unsigned)rows);
-    hipLaunchKernelGGL(k_pass1_512<R>, grid, dim3(kP1Threads), bytes, s, p, (C2<R>*)data);
+    hipLaunchKernelGGL(k_pass1_512<R>, grid, dim3(kP1Threads), bytes, s, p, (C2<R>*)data, skip);
     return hipGetLastError();
   }
   size_t bytes = 2 * (size_t)kCB * p.n1 * sizeof(C2<R>);
   hipError_t e = hipFuncSetAttribute((const void*)k_pass1<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)((p.n2 + kCB - 1) / kCB), (unsigned)rows);
-  hipLaunchKernelGGL(k_pass1<R>, grid, dim3(kFT), bytes, s, p, (C2<R>*)data);
+  hipLaunchKernelGGL(k_pass1<R>, grid, dim3(kFT), bytes, s, p, (C2<R>*)data, skip);
   return hipGetLastError();
 }
 
-hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int precision, hipStream_t s) {
-  return precision == 0 ? p1<double>(p, data, rows, s) : p1<float>(p, data, rows, s);
+hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int precision, const int32_t* skip,
+                            hipStream_t s) {
+  return precision == 0 ? p1<double>(p, data, rows, skip, s) : p1<float>(p, data, rows, skip, s);
 }
 
 template <typename R>
 static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mode, double dt, void* spec,
                      const double* wperm, int64_t ch_rows, double* partial, int64_t kb_lo, int64_t kb_hi,
-                     hipStream_t s) {
+                     const int32_t* skip, hipStream_t s) {
   if (hot_plan(p)) {
     dim3 grid((unsigned)((p.n1 / 2 + 2) / 2), (unsigned)rows);
     hipLaunchKernelGGL(k_pass2_1024<R>, grid, dim3(kFT), 0, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
-                       partial, kb_lo, kb_hi);
+                       partial, kb_lo, kb_hi, skip);
     return hipGetLastError();
   }
   size_t bytes = 4 * (size_t)p.n2 * sizeof(C2<R>);
@@ -533,15 +539,15 @@ static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mo
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)(p.n1 / 2 + 1), (unsigned)rows);
   hipLaunchKernelGGL(k_pass2<R>, grid, dim3(kFT), bytes, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
-                     ch_rows, partial, kb_lo, kb_hi);
+                     ch_rows, partial, kb_lo, kb_hi, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_pass2(const FftPlanDev& p, const void* data, int64_t rows, int precision, int mode, double dt,
                             void* spec, const double* wperm, int64_t ch_rows, double* partial, int64_t kb_lo,
-                            int64_t kb_hi, hipStream_t s) {
-  return precision == 0 ? p2<double>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, kb_lo, kb_hi, s)
-                        : p2<float>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, kb_lo, kb_hi, s);
+                            int64_t kb_hi, const int32_t* skip, hipStream_t s) {
+  return precision == 0 ? p2<double>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, kb_lo, kb_hi, skip, s)
+                        : p2<float>(p, data, rows, mode, dt, spec, wperm, ch_rows, partial, kb_lo, kb_hi, skip, s);
 }
 
 // weights in pass-2 order: w[c][k1 * n2 + k2] = 1/S_c(k) inside the band of an

@@ -78,12 +78,15 @@ struct FftPlanDev {
   const double* whid; const float* whif;    // exp(-2 pi i 1024 k / N), k <= N/1024
 };
 
-hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int precision, hipStream_t s);
+// skip (nullable): per-template status; rows 3b .. 3b + 2 of a template with nonzero status are
+// not transformed (pass 2 writes no partial sums for them)
+hipError_t launch_fft_pass1(const FftPlanDev& p, void* data, int64_t rows, int precision, const int32_t* skip,
+                            hipStream_t s);
 // mode 0: spectrum out[row][k] = R_k * dt (k = 0..n); mode 1: band power partial sums
 // mode 1 (band power) reads weights and accumulates only for bins kb_lo..kb_hi
 hipError_t launch_fft_pass2(const FftPlanDev& p, const void* data, int64_t rows, int precision, int mode,
                             double dt, void* spec_out, const double* wperm, int64_t ch_stride_rows,
-                            double* partial, int64_t kb_lo, int64_t kb_hi, hipStream_t s);
+                            double* partial, int64_t kb_lo, int64_t kb_hi, const int32_t* skip, hipStream_t s);
 hipError_t launch_weights(const FftPlanDev& p, const double* const* S, int k_lo, int k_hi, int channels,
                           double* wperm, hipStream_t s);
 // out[b] = scale * sum_{c, pairs} partial; logl variant adds dd/2 and handles status

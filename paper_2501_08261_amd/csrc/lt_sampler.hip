@@ -47,6 +47,8 @@ struct Dev {
   double fold_p, fold_c0;
   double *fxf, *flkx;       // folded cold positions [W][d]; log(number of copies) of each
   double walk;              // > 0: the flow move is a random walk of this step in the flow's latent space
+  double p_flow;            // probability that a step runs the flow move (1: every step)
+  int* fgate;               // this step's draw: 1 = the flow move runs
 };
 
 __device__ inline void to_params(const Dev& D, const double* x, double* p) {
@@ -179,13 +181,27 @@ __global__ void k_flow_fold(Dev D) {
   D.flkx[k] = lk;
 }
 
+// whether this step runs the flow move: u < p_flow, u from counter (step, 0x800, 0, 0)
+__global__ void k_flow_gate(Dev D) {
+  uint32_t c[4] = {(uint32_t)*D.step, kTagFlowG, 0u, 0u};
+  philox4x32_10(c, D.k0, D.k1);
+  *D.fgate = u01(c[0]) < D.p_flow ? 1 : 0;
+}
+
 // proposals: unfolded into a uniformly drawn copy (log q(y) less log(number of copies)), prior,
-// likelihood parameters
+// likelihood parameters.  A step without the flow move gets unphysical parameter rows (zero
+// masses), which the likelihood skips after its per-template setup.
 __global__ void k_flow_prep(Dev D) {
 #pragma clang fp contract(off)
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= D.W) return;
   double* y = D.fy + (int64_t)k * D.d;
+  if (!*D.fgate) {
+    D.fylogp[k] = -INFINITY;
+    if (D.target == LT_TARGET_TDI)
+      for (int i = 0; i < 16; ++i) D.params[(int64_t)k * 16 + i] = 0.0;
+    return;
+  }
   bool out = false;
   if (D.fold_i >= 0) {
     const int i = D.fold_i;
@@ -211,7 +227,7 @@ __global__ void k_flow_prep(Dev D) {
 // log alpha = beta_0 (logL_y - logL_x) + (logP_y - logP_x) + log q(x) - log q(y)
 __global__ void k_flow_accept(Dev D) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= D.W) return;
+  if (k >= D.W || !*D.fgate) return;
   uint32_t c[4] = {(uint32_t)*D.step, kTagFlowU, (uint32_t)k, 0u};
   philox4x32_10(c, D.k0, D.k1);
   const double lly = D.fylogl[k], lpy = D.fylogp[k];
@@ -344,8 +360,10 @@ static lt_status record_step(lt_sampler* s, hipStream_t st) {
     hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h);
     S_HIP(hipGetLastError());
   }
-  if (s->flow) {
+  if (s->flow && s->D.p_flow > 0.0) {
     const int W = s->cfg.n_walkers;
+    hipLaunchKernelGGL(k_flow_gate, dim3(1), dim3(1), 0, st, s->D);
+    S_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_flow_fold, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());
     if (s->D.walk > 0.0) {
@@ -413,6 +431,7 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
   D.a = cfg->stretch_a; D.t_c = cfg->t_c;
   D.fold_i = -1;
   D.walk = 0.0;
+  D.p_flow = 1.0;
   D.fold_p = 1.0;
   D.fold_c0 = 0.0;
   D.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
@@ -428,7 +447,7 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
       (r = salloc(s, &D.sprop, TW)) || (r = salloc(s, &D.fy, (size_t)W * d)) || (r = salloc(s, &D.fqy, W)) ||
       (r = salloc(s, &D.fqx, W)) || (r = salloc(s, &D.fylogl, W)) || (r = salloc(s, &D.fylogp, W)) ||
       (r = salloc(s, &D.facc, W)) || (r = salloc(s, &D.fprop, W)) || (r = salloc(s, &D.fxf, (size_t)W * d)) ||
-      (r = salloc(s, &D.flkx, W))) {
+      (r = salloc(s, &D.flkx, W)) || (r = salloc(s, &D.fgate, 1))) {
     lt_sampler_destroy(s);
     return r;
   }
@@ -580,6 +599,19 @@ lt_status lt_sampler_set_flow_walk(lt_sampler* s, double step) {
   s->exec = nullptr;
   s->graph = nullptr;
   s->D.walk = step;
+  return LT_OK;
+}
+
+lt_status lt_flow_set_mix(lt_sampler* s, double p_flow) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  if (!(p_flow >= 0.0 && p_flow <= 1.0)) return sfail(LT_ERR_CONFIG, "p_flow must lie in [0, 1]");
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->exec = nullptr;
+  s->graph = nullptr;
+  s->D.p_flow = p_flow;
   return LT_OK;
 }
 

@@ -550,6 +550,8 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   const int64_t N = P.g.n;
   const int64_t n0 = tile * kTile;
   const TplConst& c = P.tc[b];
+  // the likelihood discards a faulted template's residual: nothing to write
+  if (P.out_mode == 2 && c.valid == 0.0) return;
   // y is needed on [n0 - HY, n0 + kTile + K/2]: the centred stencils of the
   // shortest TDI delays reach K/2 - 1 samples past the last output sample
   const int MY = kTile + HY + K / 2 + 1;

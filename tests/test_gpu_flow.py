@@ -268,6 +268,47 @@ def test_sampler_flow_move_parity(lib, T, full):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("p_flow", [0.0, 0.35])
+def test_sampler_flow_mix_parity(lib, p_flow):
+    """P31: the flow move mixed with the stretch move at rate p_flow (a Philox draw per step on
+    the device) against the oracle chain, step by step; p_flow = 0 is the plain sampler."""
+    d, W, T, seed = 4, 16, 2, 4242
+    rng = np.random.default_rng(9)
+    A = rng.normal(size=(d, d))
+    icov = np.linalg.inv(A @ A.T + d * np.eye(d))
+    means = rng.normal(size=(1, d))
+    lo, hi = -30 * np.ones(d), 30 * np.ones(d)
+    P = fl.init_params(d, 4, 32, 2)
+    mu, sig = means[0] - 0.4, np.linspace(1.5, 2.5, d)
+    start = means[0] + rng.normal(size=(T, W, d))
+    fg = lib.Flow(d, 4, 32, W)
+    fg.set_params(lib.flow_pack(P), mu, sig)
+    g = lib.Sampler(W, T, d, lo, hi, seed, target="gauss", param_kind="raw", t_max=5.0, means=means, icov=icov)
+    g.set_flow(fg)
+    g.set_flow_mix(p_flow)
+    g.set_state(start)
+    o = PTSampler(gaussian_logl(means, icov), lo, hi, W, T, d, seed, t_max=5.0)
+    o.set_flow(P, mu, sig)
+    o.set_flow_mix(p_flow)
+    o.set_state(start)
+    for s in range(40):
+        g.step(1)
+        o.step()
+        pos, logl, _, step, cnt = g.state()
+        assert np.max(np.abs(pos - o.X)) < 1e-12 * (1 + np.max(np.abs(o.X))), s
+        assert cnt[0] == o.acc and cnt[2] == o.sacc
+        assert g.flow_counts() == (o.facc, o.fprop), s
+    if p_flow > 0:
+        assert 0 < o.flow_steps < 40 and 0 < o.facc
+    else:
+        assert o.fprop == 0
+    with pytest.raises(lib.LisaTDError):
+        g.set_flow_mix(1.5)
+    g.close()
+    fg.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("T", [1, 3])
 def test_sampler_flow_fold_parity(lib, T):
     """P29: flow move with the symmetry fold (copies drawn from Philox, -ln n corrections,

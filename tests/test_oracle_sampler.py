@@ -1,4 +1,5 @@
 """Pins of the oracle sampler: Philox known answers, Gaussian moments, tempering, ESS."""
+import math
 import os
 
 import numpy as np
@@ -258,3 +259,43 @@ def test_flow_walk_keeps_the_target():
     assert np.all(np.abs(flat.mean(0) - m) < 5 * err)
     assert np.allclose(np.cov(flat.T), C, atol=0.12)
     assert 0.2 < s.facc / s.fprop < 0.95
+
+
+def test_flow_mix_keeps_the_target():
+    """P31: the flow move mixed with the stretch move at rate p_flow (a Philox draw per step
+    decides): the chain still samples the target with a mismatched flow, the flow move runs on
+    the expected fraction of steps, and p_flow = 0 is the plain sampler, draw for draw."""
+    rng = np.random.default_rng(5)
+    d = 2
+    C = np.array([[1.0, -0.4], [-0.4, 0.5]])
+    m = np.array([-0.3, 0.8])
+    start = m + rng.multivariate_normal(np.zeros(d), C, size=(1, 32))
+    s = PTSampler(gaussian_logl(m, np.linalg.inv(C)), [-40] * d, [40] * d, 32, 1, d, seed=21)
+    s.set_state(start)
+    s.set_flow(_identity_flow(d), m + np.array([-0.8, 0.6]), np.array([1.5, 1.2]))
+    s.set_flow_mix(0.3)
+    chain = []
+    n = 3000
+    for i in range(n):
+        s.step()
+        if i >= 200:
+            chain.append(s.X[0].copy())
+    chain = np.array(chain)
+    flat = chain.reshape(-1, d)
+    tau = integrated_time(chain).max()
+    err = np.sqrt(np.diag(C) / (flat.shape[0] / tau))
+    assert np.all(np.abs(flat.mean(0) - m) < 5 * err)
+    assert np.allclose(np.cov(flat.T), C, atol=0.1)
+    assert abs(s.flow_steps / n - 0.3) < 4 * math.sqrt(0.3 * 0.7 / n)
+    assert s.fprop == 32 * s.flow_steps and 0 < s.facc < s.fprop
+    # p_flow = 0: identical to the sampler without a flow
+    a = PTSampler(gaussian_logl(m, np.linalg.inv(C)), [-40] * d, [40] * d, 32, 1, d, seed=22)
+    b = PTSampler(gaussian_logl(m, np.linalg.inv(C)), [-40] * d, [40] * d, 32, 1, d, seed=22)
+    a.set_state(start)
+    b.set_state(start)
+    b.set_flow(_identity_flow(d), m, np.ones(d))
+    b.set_flow_mix(0.0)
+    for _ in range(50):
+        a.step()
+        b.step()
+    assert np.array_equal(a.X, b.X) and b.fprop == 0
