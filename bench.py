@@ -21,13 +21,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE runs of this script (scaled by the same process's 1 GiB copy
-# calibration), keyed by (kernel, batch, samples, taps, precision).  Any other
-# configuration, or a changed kernel, reports null.
-PMC_TRAFFIC = {
-    # profiles/k_tdi_precessing_k8_2p20_b256.md: FETCH 2.412 GiB + WRITE 3.000 GiB per 256-template launch
-    ("tdi_response", 256, 2 ** 20, 8, "mixed"): int((2.412 + 3.000) * 2 ** 30),
+# Per-launch device counters of the bench configuration, from rocprofv3 --pmc runs of this
+# script (summaries in profiles/): HBM bytes (FETCH_SIZE, WRITE_SIZE scaled by the same process's
+# 1 GiB copy calibration) and issued VALU wave-instructions (all, FP32 and FP64 multiply-adds),
+# keyed by (kernel class, templates per launch, samples, taps, precision).  Any other
+# configuration, or a kernel changed since the counters were taken, reports null.
+PMC = {
+    # profiles/k_tdi_precessing_k8_2p20_b256.md
+    ("tdi_response", 256, 2 ** 20, 8, "mixed"): {"fetch": 2771580000, "write": 3221230000, "valu": 5.139e9,
+                                                 "fma_f32": 1.566e9, "fma_f64": 9.94e8},
+    ("waveform", 256, 2 ** 20, 8, "mixed"): {"fetch": 1958000, "write": 2147480000, "valu": 1.577e9,
+                                             "fma_f32": 3.735e8, "fma_f64": 7.308e7},
 }
 
 N_SAMPLES = 2 ** 20
@@ -55,38 +59,55 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(g, params, taps):
-    """Times the oracle (as it stands) on a bounded sample of the same workload:
-    the full chain (polarisations, six links, TDI 2.0 X, Y, Z, A, E, T) for one
-    template on a contiguous slice of the 2^20 grid, plus the rfft and band
-    inner products of one full-length 3-channel series; scaled to logL/s."""
+SLICE = 1 << 17
+
+
+def _oracle_time(args):
+    """Seconds per template of the oracle (as it stands), on one core: the full chain
+    (polarisations, six links, TDI 2.0 X, Y, Z, A, E, T) for one template on a contiguous
+    slice of the grid, scaled to the whole grid, plus the rfft and band inner products of one
+    full-length 3-channel series."""
+    p, g, taps = args
     import numpy as np
+    from threadpoolctl import threadpool_limits
     from oracle import likelihood as olk
     from oracle.orbits import Orbit
     from oracle.response import Response
     from oracle.waveform import Template
-    from threadpoolctl import threadpool_limits
-    limiter = threadpool_limits(1)      # numpy's thread pools pinned: the oracle runs on one core
-    n = g["n"]
-    slice_len = 1 << 17
-    r = Response(Template(params[0]), g["t0"], g["dt"], n, Orbit("kepler"), taps=taps, precessing=True,
-                 generation=20)
-    idx = np.arange(n - slice_len - 4096, n - 4096)
+    with threadpool_limits(1):          # numpy's thread pools pinned: one core per process
+        n = g["n"]
+        r = Response(Template(p), g["t0"], g["dt"], n, Orbit("kepler"), taps=taps, precessing=True, generation=20)
+        idx = np.arange(n - SLICE - 4096, n - 4096)
+        t0 = time.perf_counter()
+        r.aet(idx)
+        t_resp = time.perf_counter() - t0
+        x = np.random.default_rng(0).standard_normal((3, n))
+        S = olk.channel_psds(n, g["dt"], 20)
+        t0 = time.perf_counter()
+        olk.loglike(x, 0.5 * x, S, g["dt"])
+        t_fft = time.perf_counter() - t0
+    return t_resp * (n / SLICE) + t_fft, t_resp + t_fft
+
+
+def cpu_baseline(g, params, taps):
+    """The oracle timed on the host's cores: one process per core (at most 16, the host share of
+    one GPU), each running the bounded sample of _oracle_time on its own template, all at once;
+    throughput = sum over processes of 1 / (seconds per template).  Also the same sample on
+    one core alone."""
+    import multiprocessing as mp
+    single, work1 = _oracle_time((params[0], g, taps))
+    P = max(1, min(os.cpu_count() or 1, 16))
+    ctx = mp.get_context("spawn")       # fresh interpreters: nothing of this process's GPU state
     t0 = time.perf_counter()
-    r.aet(idx)
-    t_resp = (time.perf_counter() - t0) * (n / slice_len)
-    x = np.random.default_rng(0).standard_normal((3, n))
-    S = olk.channel_psds(n, g["dt"], 20)
-    t0 = time.perf_counter()
-    olk.loglike(x, 0.5 * x, S, g["dt"])
-    t_fft = time.perf_counter() - t0
-    per = t_resp + t_fft
-    limiter.restore_original_limits()
-    return {"value": 1.0 / per, "unit": "logL evals/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "oracle on template 0: response+TDI on %d of %d samples (scaled x%.0f) + full-length "
-                      "rfft/inner products; %.1f s measured" % (slice_len, n, n / slice_len,
-                                                              per * slice_len / n + t_fft)}
+    with ctx.Pool(P) as pool:
+        res = pool.map(_oracle_time, [(params[i % len(params)], g, taps) for i in range(P)])
+    wall = time.perf_counter() - t0
+    value = sum(1.0 / per for per, _ in res)
+    return {"value": value, "unit": "logL evals/s", "cores": P, "kind": "oracle",
+            "sample": "oracle, one process per core on %d of the bench templates: response+TDI on %d of %d "
+                      "samples (scaled x%.0f) + full-length rfft/inner products; %.1f s of work per process, "
+                      "%.1f s wall" % (P, SLICE, g["n"], g["n"] / SLICE, max(w for _, w in res), wall),
+            "single_core": {"value": 1.0 / single, "cores": 1, "seconds_measured": work1}}
 
 
 # eigenvalue floor of the Fisher draws, relative to the largest eigenvalue of the unit-diagonal
@@ -131,10 +152,11 @@ def _sampler(lib, inputs, ctx, su, W, T, seed):
     return smp
 
 
-def sampler_bench(lib, inputs, prec, steps=3, W=512, T=8):
+def sampler_bench(lib, inputs, prec, steps=200, W=512, T=8, ref_steps=10):
     """One full sampler step on the device (propose, waveform, response, FFT,
     logL, accept, swaps) replayed as a HIP graph: 512 walkers x 8 temperatures,
-    precessing 14-D, 2^20 samples, TDI-2 AET, Fisher-initialised."""
+    precessing 14-D, 2^20 samples, TDI-2 AET, Fisher-initialised; `steps` steps timed,
+    and the likelihood alone (two calls of half the ensemble) over `ref_steps`."""
     import torch
     ctx = lib.Context(0)
     su = _tdi_setup(lib, inputs, ctx, N_SAMPLES, prec)
@@ -163,10 +185,10 @@ def sampler_bench(lib, inputs, prec, steps=3, W=512, T=8):
     half()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(2 * steps):
+    for _ in range(2 * ref_steps):
         half()
     torch.cuda.synchronize()
-    dl = (time.perf_counter() - t0) / steps
+    dl = (time.perf_counter() - t0) / ref_steps
     ctx.close()
     return {"walkers": W, "temps": T, "steps": steps, "ms_per_step": 1e3 * dt, "steps_per_s": 1.0 / dt,
             "logl_per_s": T * W / dt, "stretch_accept": cnt[0] / max(cnt[1], 1),
@@ -328,6 +350,16 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
             res[label]["flow_accept"] = acc / max(prop, 1)
         else:
             res[label]["stretch_accept"] = smp.state()[4][0] / max(smp.state()[4][1], 1)
+    # with the flow's training counted: the learned sampler's wall time includes the Adam steps;
+    # break-even = the number of measured steps after which the learned sampler with its
+    # training has produced as many effective samples per second as the plain one
+    for v in res.values():
+        v["ess_per_step"] = W / v["tau_max"]
+    rl, rp = res["learned"]["ess_per_step"], res["plain"]["ess_per_step"]
+    tl, tp = 1e-3 * res["learned"]["ms_per_step"], 1e-3 * res["plain"]["ms_per_step"]
+    res["learned"]["ess_per_s_with_training"] = m * rl / (m * tl + t_train)
+    gain = rl * tp - rp * tl
+    breakeven = rp * t_train / gain if gain > 0 else None
     sd = res["plain"]["std"]
     shift = float(np.max(np.abs(res["learned"]["mean"] - res["plain"]["mean"]) / sd))
     std_ratio = (res["learned"]["std"] / sd).tolist()
@@ -357,8 +389,55 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
             "flow_train_tflops": flow_gemm_flops(dim) * 2048 * rounds * train_steps / t_train / 1e12,
             "plain": res["plain"], "learned": res["learned"],
             "ratio": res["learned"]["ess_per_s"] / res["plain"]["ess_per_s"],
+            "ratio_with_training": res["learned"]["ess_per_s_with_training"] / res["plain"]["ess_per_s"],
+            "breakeven_steps": breakeven,
             "posterior_mean_shift_sigma": shift, "posterior_std_ratio": [round(x, 3) for x in std_ratio],
             "fisher_vs_mcmc": fisher}
+
+
+def mixed_vs_fp64(lib, inputs, ctx, g, P, modes, orb, tdi, S, coarse):
+    """Per-result error of the mixed-precision likelihood against the FP64 path (which matches
+    the oracle to 1e-6 + 1e-11 (d|d)), both on the same data: the FP64 zero-noise injection,
+    rounded to FP32 for the mixed path, with (d|d) of the rounded series in FP64.  Templates:
+    the bench batch, the injection itself and 15 templates next to it (relative offsets of
+    1e-5 in the masses and 1e-4 in the angles)."""
+    import numpy as np
+    import torch
+    dev = "cuda:0"
+    n = g["n"]
+    inj = inputs.tab1_injection(True, g)
+    rng = np.random.default_rng(17)
+    near = np.repeat(inj[None], 15, axis=0)
+    near[:, 0:2] *= 1.0 + 1e-5 * rng.standard_normal((15, 2))
+    near[:, 9:11] += 1e-4 * rng.standard_normal((15, 2))
+    near[:, 12:15] += 1e-4 * rng.standard_normal((15, 3))
+    Q = np.concatenate([P, inj[None], near])
+    cfg64 = ctx.wf_cfg(modes, True, precision=lib.LT_FP64, coarse=coarse)
+    cfg32 = ctx.wf_cfg(modes, True, precision=lib.LT_MIXED, coarse=coarse)
+    d64 = torch.zeros((1, 3, n), dtype=torch.float64, device=dev)
+    ctx.lisa_tdi_response(torch.tensor(inj[None], device=dev), g, cfg64, orb, tdi, d64)
+    d32 = d64.float()
+    dd = torch.zeros(1, dtype=torch.float64, device=dev)
+    ctx.noise_inner(d32.double(), g, S, dd)
+    torch.cuda.synchronize()
+    ddv = float(dd.item())
+    params = torch.tensor(Q, device=dev)
+    l64 = torch.zeros(len(Q), dtype=torch.float64, device=dev)
+    l32 = torch.zeros(len(Q), dtype=torch.float64, device=dev)
+    ctx.tdi_loglike(params, g, cfg64, orb, tdi, S, d32.double()[0].contiguous(), ddv, l64)
+    ctx.tdi_loglike(params, g, cfg32, orb, tdi, S, d32[0].contiguous(), ddv, l32)
+    torch.cuda.synchronize()
+    a64, a32 = l64.cpu().numpy(), l32.cpu().numpy()
+    ok = np.isfinite(a64) & np.isfinite(a32)
+    err = np.abs(a32 - a64)[ok]
+    rel = (err / np.maximum(np.abs(a64[ok]), 1e-300))
+    nb = len(P)
+    return {"templates": int(len(Q)), "compared": int(ok.sum()), "max_abs": float(err.max()),
+            "median_abs": float(np.median(err)), "max_rel": float(rel.max()),
+            "injection_abs": float(abs(a32[nb] - a64[nb])),
+            "near_injection_max_abs": float(np.max(np.abs(a32[nb + 1:] - a64[nb + 1:]))),
+            "near_injection_logl_full_range": [float(np.min(a64[nb + 1:] - 0.5 * ddv)),
+                                               float(np.max(a64[nb + 1:] - 0.5 * ddv))]}
 
 
 def main():
@@ -427,10 +506,10 @@ def main():
     for _ in range(a.profile_steps):
         step()
     torch.cuda.synchronize()
-    ms, cnt = ctx.profile_read(5)
+    ms, cnt = ctx.profile_read(6)
     ctx.profile_enable(False)
-    names = ["setup", "tdi_response", "fft_pass1", "fft_pass2_band", "finalize"]
-    kern = {names[i]: {"avg_ms": ms[i] / max(cnt[i], 1), "launches": cnt[i]} for i in range(5)}
+    names = ["setup", "tdi_response", "fft_pass1", "fft_pass2_band", "finalize", "waveform"]
+    kern = {names[i]: {"avg_ms": ms[i] / max(cnt[i], 1), "launches": cnt[i]} for i in range(6)}
     n_ok = int((status == 0).sum().item())
     # roofline of the dominant kernel (algorithmic work per template-sample, design notes)
     rsz = 4 if prec == lib.LT_MIXED else 8
@@ -438,20 +517,43 @@ def main():
     # the dominant kernel: largest time per step; the templates one launch processes follow
     # from its launch count (the likelihood runs in chunks)
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
-    per_launch = a.batch * a.profile_steps / max(kern[dom]["launches"], 1)     # templates per launch
-    kern[dom]["templates_per_launch"] = per_launch
+    for k in kern:
+        kern[k]["templates_per_launch"] = a.batch * a.profile_steps / max(kern[k]["launches"], 1) \
+            if k != "setup" else None
+    per_launch = kern[dom]["templates_per_launch"]
     units = a.n * per_launch * (active_frac if dom == "tdi_response" else 1.0)   # template-samples of work
+    pmc = PMC.get((dom, per_launch, a.n, TAPS, a.precision)) or {}
+    traffic = pmc["fetch"] + pmc["write"] if "fetch" in pmc else None
+    t_dom = kern[dom]["avg_ms"] * 1e-3
     if dom in fft_bytes:
-        achieved = fft_bytes[dom] * units / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+        achieved = fft_bytes[dom] * units / t_dom / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-                "traffic": PMC_TRAFFIC.get((dom, per_launch, a.n, TAPS, a.precision)), "kernel": dom}
+                "traffic": traffic, "kernel": dom}
     else:
         from paper_2501_08261_amd import workcount
         flops = workcount.tdi_flops_per_sample(TAPS, 20)
-        achieved = flops * units / (kern[dom]["avg_ms"] * 1e-3) / 1e12
-        peak = 78.6 if prec == lib.LT_FP64 else 157.3
+        achieved = flops * units / t_dom / 1e12
+        # one multiply-add per lane per clock: 256 CUs x 64 lanes x 2 flops x 2.4 GHz (the build
+        # emits no packed FP32 instructions, so the FP32 ceiling is the FP64 one)
+        peak = workcount.VALU_PEAK_TFLOPS
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": PMC_TRAFFIC.get((dom, per_launch, a.n, TAPS, a.precision)), "kernel": dom}
+                "traffic": traffic, "kernel": dom,
+                "achieved_is": "algorithmic-equivalent: the direct method's %d flops per active template-sample "
+                               "(combined filters execute fewer)" % flops}
+        if "fma_f32" in pmc:
+            ex = workcount.executed_flops(pmc["fma_f32"], pmc["fma_f64"])
+            roof["executed"] = {"tflops": ex / t_dom / 1e12, "frac": ex / t_dom / 1e12 / peak,
+                                "valu_insts_per_cycle_per_cu": workcount.issue_rate(pmc["valu"], t_dom),
+                                "source": "SQ_INSTS_VALU_FMA_F32/F64, SQ_INSTS_VALU per launch (profiles/)"}
+    wpmc = PMC.get(("waveform", kern["waveform"]["templates_per_launch"], a.n, TAPS, a.precision)) or {}
+    if "fma_f64" in wpmc:
+        tw = kern["waveform"]["avg_ms"] * 1e-3
+        kern["waveform"]["fp64_tflops"] = workcount.executed_flops(0, wpmc["fma_f64"]) / tw / 1e12
+        kern["waveform"]["fp64_frac"] = kern["waveform"]["fp64_tflops"] / workcount.VALU_PEAK_TFLOPS
+        kern["waveform"]["fp32_tflops"] = workcount.executed_flops(wpmc["fma_f32"], 0) / tw / 1e12
+        kern["waveform"]["valu_insts_per_cycle_per_cu"] = workcount.issue_rate(wpmc["valu"], tw)
+    mixed_err = mixed_vs_fp64(lib, inputs, ctx, g, P, modes, orb, tdi, S, a.coarse) \
+        if prec == lib.LT_MIXED else None
     out = {
         "metric": "logL evals/s (1M-sample precessing AET); ESS/s learned vs plain proposal",
         "value": value, "unit": "logL evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -465,6 +567,7 @@ def main():
                    "every second sample, linear in between", "templates_valid": n_ok},
         "kernels_ms": kern,
         "roofline": roof,
+        "mixed_vs_fp64": mixed_err,
     }
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)

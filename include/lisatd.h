@@ -214,9 +214,10 @@ lt_status lt_psd_sangria(const lt_grid* grid, int generation, double arm_m, doub
 
 /* Per-kernel timing for benchmarks: when enabled, the library records HIP
  * events around each launch on the launch stream.  lt_profile_read returns,
- * for kernel class k (0 waveform, setup and the per-call tables, 1 response
- * kernel, 2 fft pass 1, 3 fft pass 2 + band reduction, 4 finalize), the summed milliseconds and
- * launch counts since the last reset (it synchronises the recorded events). */
+ * for kernel class k (0 per-template setup and the per-call tables, 1 response
+ * kernel, 2 fft pass 1, 3 fft pass 2 + band reduction, 4 finalize, 5 waveform),
+ * the summed milliseconds and launch counts since the last reset (it
+ * synchronises the recorded events); n_classes <= 8. */
 lt_status lt_profile_enable(lt_ctx* ctx, int on);
 lt_status lt_profile_read(lt_ctx* ctx, double* ms, int64_t* launches, int n_classes);
 

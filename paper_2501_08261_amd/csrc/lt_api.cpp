@@ -641,7 +641,7 @@ static lt_status run_tdi_core(lt_ctx* c, const TplConst* tc, int64_t batch, cons
                               const OrbitDev& od, const lt_tdi_cfg* t, int out_mode, const void* data, void* out,
                               int32_t* status, void* wave, double* nodes, void* refs, hipStream_t s) {
   {
-    Prof pr(c, 0, s);
+    Prof pr(c, 5, s);
     LT_HIP(launch_wave(tc, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, cfg->precision, gdev(g), wave, s));
   }
   TdiLaunch L;

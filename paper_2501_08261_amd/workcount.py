@@ -23,3 +23,23 @@ def tdi_flops_per_sample(taps, generation):
     if generation == 20:
         return 60 * 3 * K + 72 * 2 * K
     return 36 * 3 * K + 48 * 2 * K
+
+
+# One multiply-add per lane per clock on every SIMD: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# x 2.4 GHz = 78.6 TFLOP/s, the vector FP64 peak and the FP32 peak without packed (two-wide)
+# FP32 instructions, which this build does not emit.
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+CLOCK_HZ = 2.4e9
+N_CU = 256
+
+
+def executed_flops(fma_f32_insts, fma_f64_insts):
+    """Flops of issued multiply-add wave-instructions (64 lanes, 2 flops each), from the
+    SQ_INSTS_VALU_FMA_F32 / _F64 counters of one launch."""
+    return 128.0 * (fma_f32_insts + fma_f64_insts)
+
+
+def issue_rate(valu_insts, seconds):
+    """VALU wave-instructions issued per clock per CU over a launch of `seconds`."""
+    return valu_insts / (seconds * CLOCK_HZ * N_CU)
+
