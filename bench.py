@@ -21,22 +21,29 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Per-launch device counters of the bench configuration, from rocprofv3 --pmc runs of this
-# script (summaries in profiles/): HBM bytes (FETCH_SIZE, WRITE_SIZE scaled by the same process's
-# 1 GiB copy calibration) and issued VALU wave-instructions (all, FP32 and FP64 multiply-adds),
-# keyed by (kernel class, templates per launch, samples, taps, precision).  Any other
-# configuration, or a kernel changed since the counters were taken, reports null.
+# Device counters of the bench configuration per template of a launch (a launch's counters
+# scale with its templates), from rocprofv3 --pmc runs of this script (summaries in profiles/):
+# HBM bytes (FETCH_SIZE, WRITE_SIZE scaled by the same process's 1 GiB copy calibration) and
+# issued VALU wave-instructions (all, FP32 and FP64 multiply-adds), keyed by (kernel class,
+# samples, taps, precision).  Any other configuration, or a kernel changed since the counters
+# were taken, reports null.
 PMC = {
-    # profiles/k_tdi_precessing_k8_2p20_b256.md
-    ("tdi_response", 256, 2 ** 20, 8, "mixed"): {"fetch": 2771580000, "write": 3221230000, "valu": 5.139e9,
-                                                 "fma_f32": 1.566e9, "fma_f64": 9.94e8},
-    ("waveform", 256, 2 ** 20, 8, "mixed"): {"fetch": 1958000, "write": 2147480000, "valu": 1.577e9,
-                                             "fma_f32": 3.735e8, "fma_f64": 7.308e7},
+    # profiles/k_tdi_precessing_k8_2p20_b256.md (a launch of 256 templates, divided by 256)
+    ("tdi_response", 2 ** 20, 8, "mixed"): {"fetch": 2771580000 / 256, "write": 3221230000 / 256,
+                                            "valu": 5.139e9 / 256, "fma_f32": 1.566e9 / 256, "fma_f64": 9.94e8 / 256},
+    ("waveform", 2 ** 20, 8, "mixed"): {"fetch": 1958000 / 256, "write": 2147480000 / 256, "valu": 1.577e9 / 256,
+                                        "fma_f32": 3.735e8 / 256, "fma_f64": 7.308e7 / 256},
 }
+
+
+def pmc_per_launch(kernel, n, taps, precision, templates):
+    """The counters of one launch of `templates` templates (None when not profiled)."""
+    v = PMC.get((kernel, n, taps, precision))
+    return {k: x * templates for k, x in v.items()} if v and templates else {}
 
 N_SAMPLES = 2 ** 20
 BATCH = 256
-TAPS = 8
+TAPS = 8      # the smallest order whose interpolation error is below the FP32 floor (tests/test_oracle_taps.py)
 
 
 def parse():
@@ -484,6 +491,13 @@ def main():
     del hbuf
     active_frac = float(np.mean(active)) / a.n
 
+    # launch shape (templates per launch, work order, persistent grid): chosen by the library's
+    # autotuner on this workload, cached per workload in the temporary directory
+    import tempfile
+    tuning, tune_ms = ctx.autotune(params, g, cfg, orb, tdi, S, d[0], ddv,
+                                   cache_path=os.path.join(tempfile.gettempdir(), "lisatd_tuning.txt"), reps=3)
+    print("tuning %s (%.3f ms per call)" % (tuning, tune_ms), file=sys.stderr, flush=True)
+
     def step():
         ctx.tdi_loglike(params, g, cfg, orb, tdi, S, d[0], ddv, logl, status=status)
 
@@ -522,7 +536,7 @@ def main():
             if k != "setup" else None
     per_launch = kern[dom]["templates_per_launch"]
     units = a.n * per_launch * (active_frac if dom == "tdi_response" else 1.0)   # template-samples of work
-    pmc = PMC.get((dom, per_launch, a.n, TAPS, a.precision)) or {}
+    pmc = pmc_per_launch(dom, a.n, TAPS, a.precision, per_launch)
     traffic = pmc["fetch"] + pmc["write"] if "fetch" in pmc else None
     t_dom = kern[dom]["avg_ms"] * 1e-3
     if dom in fft_bytes:
@@ -545,7 +559,7 @@ def main():
             roof["executed"] = {"tflops": ex / t_dom / 1e12, "frac": ex / t_dom / 1e12 / peak,
                                 "valu_insts_per_cycle_per_cu": workcount.issue_rate(pmc["valu"], t_dom),
                                 "source": "SQ_INSTS_VALU_FMA_F32/F64, SQ_INSTS_VALU per launch (profiles/)"}
-    wpmc = PMC.get(("waveform", kern["waveform"]["templates_per_launch"], a.n, TAPS, a.precision)) or {}
+    wpmc = pmc_per_launch("waveform", a.n, TAPS, a.precision, kern["waveform"]["templates_per_launch"])
     if "fma_f64" in wpmc:
         tw = kern["waveform"]["avg_ms"] * 1e-3
         kern["waveform"]["fp64_tflops"] = workcount.executed_flops(0, wpmc["fma_f64"]) / tw / 1e12
@@ -564,7 +578,8 @@ def main():
                    "global_batch": a.batch, "seq_len": a.n, "parallelism": "single GPU",
                    "active_sample_fraction": active_frac,
                    "precision": a.precision, "waveform_grid": "every sample" if a.coarse == 1 else
-                   "every second sample, linear in between", "templates_valid": n_ok},
+                   "every second sample, linear in between", "templates_valid": n_ok,
+                   "launch_shape": tuning},
         "kernels_ms": kern,
         "roofline": roof,
         "mixed_vs_fp64": mixed_err,

@@ -121,6 +121,36 @@ const char* lt_last_error(void);
 lt_status lt_ctx_create(int hip_device, lt_ctx** out);
 lt_status lt_ctx_destroy(lt_ctx* ctx);
 
+/* Launch shape of the likelihood (lt_tdi_loglike and its variants, lt_lisa_tdi_response).
+ * None of it changes a result: every variant computes every output with the same operations
+ * in the same order, which the GPU tests check bit for bit.
+ *  chunk:      templates per launch of lt_tdi_loglike, 1..4096 (256; bounded by the workspace)
+ *  rotate:     1 rotates the template order with the tile in the response kernel's work order
+ *              (each of the 8 XCDs then sees every template), 0 keeps it (1)
+ *  persistent: 1 runs the response kernel as a persistent grid of wg_per_cu workgroups per
+ *              compute unit taking (template, tile) items from a counter, 0 as one
+ *              workgroup per item (0)
+ *  wg_per_cu:  1..16 (4) */
+typedef struct { int chunk; int rotate; int persistent; int wg_per_cu; } lt_tuning;
+/* tune = null restores the defaults. */
+lt_status lt_ctx_set_tuning(lt_ctx* ctx, const lt_tuning* tune);
+lt_status lt_ctx_get_tuning(lt_ctx* ctx, lt_tuning* tune);
+/* Autotuner of the launch shape for one workload: when cache_path (nullable) names a file
+ * holding an entry for this workload's key (device architecture and compute units, grid
+ * length, precision, taps, generation, modes, precessing, coarse, batch), that entry is used;
+ * otherwise every candidate shape (chunk 64, 128, 256, 512 up to the batch; rotate 0 / 1;
+ * one workgroup per item, or persistent with 4 or 8 workgroups per compute unit) runs
+ * lt_tdi_loglike on the given templates and data, once to warm up, then in three rounds of
+ * `reps` calls under HIP events on `stream` (candidates interleaved; a candidate's time is its
+ * best round); a shape whose logL differs in any bit from the default shape's makes
+ * the call fail with LT_ERR_DEVICE (a broken invariance, never expected), else the fastest
+ * is chosen and appended to the file.  The choice is set on the context and returned in *best (nullable); *best_ms
+ * (nullable) is its time per call (-1 when read from the file).  Synchronous; allocates the
+ * candidates' scratch and one logL buffer. */
+lt_status lt_autotune(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* grid,
+                      const lt_orbit* orbit, const lt_tdi_cfg* tdi, const lt_psd* psd, const lt_data* data,
+                      const char* cache_path, int reps, lt_tuning* best, double* best_ms, void* stream);
+
 /* Co-precessing modes h_lm(t_k) for the modes in cfg->mode_mask (ascending bit
  * order: 22, 21, 33, 32, 44), m > 0, zero before the f_low start (Sec. II.A).
  * modes: device complex FP64 [batch][n_modes][n] interleaved (re, im).

@@ -4,10 +4,13 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -77,6 +80,9 @@ struct lt_ctx {
       orbits;
   DevBuf tpl, work, partial, wperm, wave, nodes, refs;
   DevBuf ws;              // lt_tdi_loglike's scratch when the caller passes no workspace
+  DevBuf tune_out;        // lt_autotune's logL outputs
+  lt_tuning tune{256, 1, 0, 4};   // launch shape of the likelihood (lt_ctx_set_tuning, lt_autotune)
+  int tune_discarded = 0;         // shapes lt_autotune found to change a result (none expected)
   void* scratch = nullptr;   // this device's copy of the fixed scratch (lt_tdi_loglike_noalloc)
   bool profiling = false;
   struct Rec { int cls; hipEvent_t a, b; };
@@ -522,9 +528,9 @@ static TermTable make_terms(int gen) {
 }
 
 // ------------------------------------------------------------------ checks
-// templates per launch of lt_tdi_loglike: bounds the workspace (2 waveform + 3 TDI series
-// of n samples per template) and amortises the per-launch tables and the launch tails
-constexpr int64_t kLoglikeChunk = 256;
+// templates per launch of lt_tdi_loglike (lt_tuning.chunk, 256 by default): bounds the
+// workspace (2 waveform + 3 TDI series of n samples per template) and amortises the
+// per-launch tables and the launch tails
 
 static lt_status check_common(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g) {
   if (!c) return fail(LT_ERR_NULL, "null context");
@@ -658,6 +664,9 @@ static lt_status run_tdi_core(lt_ctx* c, const TplConst* tc, int64_t batch, cons
   L.data = data;
   L.out = out;
   L.status = status;
+  L.rotate = c->tune.rotate;
+  L.persistent = c->tune.persistent;
+  L.wg_per_cu = c->tune.wg_per_cu;
   L.nodes = nodes;
   L.refs = refs;
   {
@@ -808,10 +817,10 @@ static size_t loglike_layout(int64_t chunk, const lt_wf_cfg* cfg, const lt_grid*
   return total;
 }
 
-// largest chunk (at most kLoglikeChunk and the batch) whose scratch fits `bytes`; 0 if none does
+// largest chunk (at most `cap` and the batch) whose scratch fits `bytes`; 0 if none does
 static int64_t loglike_chunk_for(size_t bytes, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
-                                 const lt_tdi_cfg* t, int nfold) {
-  int64_t hi = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+                                 const lt_tdi_cfg* t, int nfold, int64_t cap) {
+  int64_t hi = batch < cap ? batch : cap;
   if (loglike_layout(hi, cfg, g, t, nfold, nullptr, nullptr) <= bytes) return hi;
   int64_t lo = 0;   // invariant: layout(lo) fits (or lo = 0), layout(hi) does not
   while (hi - lo > 1) {
@@ -897,7 +906,7 @@ lt_status lt_workspace_size(lt_ctx* c, int64_t batch, const lt_wf_cfg* cfg, cons
   size_t nb = 0, rb = 0;
   tdi_table_bytes(1, cfg, g, t, &nb, &rb);
   if (rb == 0) return fail(LT_ERR_UNSUPPORTED, "taps must be one of 2,4,6,8,12,16,24,32");
-  const int64_t full = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+  const int64_t full = batch < c->tune.chunk ? batch : c->tune.chunk;
   if (bytes) *bytes = loglike_layout(full, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
   if (min_bytes) *min_bytes = loglike_layout(1, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
   return LT_OK;
@@ -913,11 +922,11 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
   int64_t chunk;
   unsigned char* base;
   if (workspace) {
-    chunk = loglike_chunk_for(workspace_bytes, batch, cfg, g, t, nfold);
+    chunk = loglike_chunk_for(workspace_bytes, batch, cfg, g, t, nfold, c->tune.chunk);
     if (chunk < 1) return fail(LT_ERR_WORKSPACE, "workspace smaller than one template needs (lt_workspace_size)");
     base = (unsigned char*)workspace;
   } else {
-    chunk = batch < kLoglikeChunk ? batch : kLoglikeChunk;
+    chunk = batch < c->tune.chunk ? batch : c->tune.chunk;
     LT_HIP(c->ws.ensure(loglike_layout(chunk, cfg, g, t, nfold, nullptr, nullptr)));
     base = (unsigned char*)c->ws.p;
   }
@@ -932,7 +941,7 @@ lt_status lt_tdi_loglike_noalloc(lt_ctx* c, const double* params, int64_t batch,
   lt_status st = check_loglike(c, params, batch, cfg, g, o, t, psd, data, logl, logl_full, &nfold);
   if (st) return st;
   if (!c->scratch) return fail(LT_ERR_DEVICE, "no fixed scratch on this device");
-  const int64_t chunk = loglike_chunk_for(kFixedScratchBytes, batch, cfg, g, t, nfold);
+  const int64_t chunk = loglike_chunk_for(kFixedScratchBytes, batch, cfg, g, t, nfold, c->tune.chunk);
   if (chunk < 1) {
     const size_t need = loglike_layout(1, cfg, g, t, nfold, nullptr, nullptr);
     return fail(LT_ERR_WORKSPACE, "one template of this grid needs " + std::to_string(need) +
@@ -946,6 +955,146 @@ lt_status lt_tdi_loglike_noalloc(lt_ctx* c, const double* params, int64_t batch,
                    (unsigned char*)c->scratch, false, (hipStream_t)stream);
   c->profiling = prof;
   return st;
+}
+
+lt_status lt_ctx_set_tuning(lt_ctx* c, const lt_tuning* t) {
+  if (!c) return fail(LT_ERR_NULL, "null context");
+  if (!t) {
+    c->tune = lt_tuning{256, 1, 0, 4};
+    return LT_OK;
+  }
+  if (t->chunk < 1 || t->chunk > 4096) return fail(LT_ERR_CONFIG, "chunk must be in [1, 4096]");
+  if ((t->rotate != 0 && t->rotate != 1) || (t->persistent != 0 && t->persistent != 1))
+    return fail(LT_ERR_CONFIG, "rotate and persistent must be 0 or 1");
+  if (t->wg_per_cu < 1 || t->wg_per_cu > 16) return fail(LT_ERR_CONFIG, "wg_per_cu must be in [1, 16]");
+  c->tune = *t;
+  return LT_OK;
+}
+
+lt_status lt_ctx_get_tuning(lt_ctx* c, lt_tuning* t) {
+  if (!c || !t) return fail(LT_ERR_NULL, "null argument");
+  *t = c->tune;
+  return LT_OK;
+}
+
+// the workload key of a cached tuning
+static std::string tune_key(lt_ctx* c, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g, const lt_tdi_cfg* t) {
+  hipDeviceProp_t prop;
+  std::ostringstream k;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+    k << prop.gcnArchName << ":" << prop.multiProcessorCount << "cu";
+  else
+    k << "unknown";
+  k << "|n=" << g->n << "|prec=" << cfg->precision << "|taps=" << t->taps << "|gen=" << t->generation
+    << "|modes=" << cfg->mode_mask << "|prec_spin=" << cfg->precessing << "|coarse=" << cfg->coarse
+    << "|batch=" << batch;
+  std::string s = k.str();
+  for (char& ch : s)
+    if (ch == ' ' || ch == '\t') ch = '_';
+  return s;
+}
+
+lt_status lt_autotune(lt_ctx* c, const double* params, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                      const lt_orbit* o, const lt_tdi_cfg* t, const lt_psd* psd, const lt_data* data,
+                      const char* cache_path, int reps, lt_tuning* best, double* best_ms, void* stream) {
+  int nfold;
+  double unused = 0.0;   // the outputs are the tuner's own
+  lt_status st = check_loglike(c, params, batch, cfg, g, o, t, psd, data, &unused, nullptr, &nfold);
+  if (st) return st;
+  if (reps < 1 || reps > 1000) return fail(LT_ERR_CONFIG, "reps must be in [1, 1000]");
+  const std::string key = tune_key(c, batch, cfg, g, t);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    lt_tuning found{0, 0, 0, 0};
+    bool have = false;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string k;
+      lt_tuning v{0, 0, 0, 0};
+      if (ls >> k >> v.chunk >> v.rotate >> v.persistent >> v.wg_per_cu && k == key) {
+        found = v;
+        have = true;      // the last entry for the key wins
+      }
+    }
+    if (have && lt_ctx_set_tuning(c, &found) == LT_OK) {
+      if (best) *best = found;
+      if (best_ms) *best_ms = -1.0;
+      return LT_OK;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<lt_tuning> cand;
+  for (int chunk : {256, 64, 128, 512}) {
+    if (chunk > 256 && chunk / 2 >= batch) continue;   // no larger chunk than the batch needs
+    if (chunk < 256 && chunk >= batch) continue;
+    for (int rot : {1, 0}) {
+      cand.push_back({chunk, rot, 0, 4});
+      cand.push_back({chunk, rot, 1, 4});
+      cand.push_back({chunk, rot, 1, 8});
+    }
+  }
+  LT_HIP(c->tune_out.ensure((size_t)batch * sizeof(double)));
+  double* out = (double*)c->tune_out.p;
+  std::vector<double> ref((size_t)batch), got((size_t)batch);
+  hipEvent_t e0, e1;
+  LT_HIP(hipEventCreate(&e0));
+  LT_HIP(hipEventCreate(&e1));
+  const lt_tuning saved = c->tune;
+  c->tune_discarded = 0;
+  double bms = 1e300;
+  lt_tuning bt = saved;
+  // every candidate once (warm-up, sizes its scratch, checks its results against the default
+  // shape's), then three rounds of `reps` timed calls each, candidates interleaved so that a
+  // drift of the clocks hits all of them; a candidate's time is its best round
+  std::vector<double> tbest(cand.size(), 1e300);
+  for (int round = -1; round < 3 && st == LT_OK; ++round) {
+    for (size_t i = 0; i < cand.size() && st == LT_OK; ++i) {
+      c->tune = cand[i];
+      const int calls = round < 0 ? 1 : reps;
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(LT_ERR_DEVICE, "event record"); break; }
+      for (int r = 0; r < calls && st == LT_OK; ++r)
+        st = lt_tdi_loglike(c, params, batch, cfg, g, o, t, psd, data, out, nullptr, nullptr, nullptr, 0, stream);
+      if (st) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(LT_ERR_DEVICE, "autotune timing");
+        break;
+      }
+      if (round < 0) {
+        if (hipMemcpy(got.data(), out, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+          st = fail(LT_ERR_DEVICE, "autotune copy");
+          break;
+        }
+        if (i == 0) ref = got;
+        if (std::memcmp(ref.data(), got.data(), ref.size() * sizeof(double)) != 0) ++c->tune_discarded;
+      } else {
+        tbest[i] = std::min(tbest[i], (double)ms / reps);
+      }
+    }
+  }
+  for (size_t i = 0; i < cand.size(); ++i)
+    if (tbest[i] < bms) {
+      bms = tbest[i];
+      bt = cand[i];
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) {
+    c->tune = saved;
+    return st;
+  }
+  c->tune = bt;
+  if (c->tune_discarded) return fail(LT_ERR_DEVICE, "autotune: a launch shape changed the results");
+  if (best) *best = bt;
+  if (best_ms) *best_ms = bms;
+  if (cache_path) {
+    std::ofstream outf(cache_path, std::ios::app);
+    if (outf) outf << key << " " << bt.chunk << " " << bt.rotate << " " << bt.persistent << " " << bt.wg_per_cu << " "
+                   << bms << "\n";
+  }
+  return LT_OK;
 }
 
 lt_status lt_noise_inner(lt_ctx* c, const void* x, int64_t batch, const lt_grid* g, const lt_psd* psd, int channels,

@@ -59,6 +59,13 @@ struct TdiLaunch {
   double* nodes;      // scratch: response geometry per (template, orbit node), then the window bounds
   void* refs;         // scratch: TDI term references and combined filters per tile
   int* win;           // set by launch_tdi: window bounds per (template, tile), after the node records
+  // launch shape (results do not depend on it): rotate the template order with the tile; one
+  // persistent grid of wg_per_cu workgroups per CU taking (template, tile) items from a counter
+  // instead of one workgroup per item
+  int rotate = 1;
+  int persistent = 0;
+  int wg_per_cu = 4;
+  unsigned long long* counter;   // set by launch_tdi: the persistent grid's item counter, after the records
 };
 // stage 0: the per-launch tables (node geometry, term references, combined filters);
 // stage 1: the response kernel itself

@@ -375,6 +375,7 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
   __shared__ double fgd[TAY ? kGroups * kNV * JMAX : 1];     // F summed in FP64
   __shared__ int s_comb, s_span_bad;
   const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) *P.counter = 0ull;   // the persistent response kernel's item counter
   const int64_t n0 = (int64_t)blockIdx.x * kTile;
   const int64_t m_lo = n0 - HY;
   constexpr int S = kTile / kNV;
@@ -536,17 +537,11 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
 //  D: X, Y, Z from y at the TDI delays (the tile's combined filters, read as scalars from
 //     its record, or per term), then A, E, T (global)
 template <typename R, int K, bool TAY>
-__global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
+__device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, int NNMAX, int64_t ntile,
+                                         int64_t tile, int b, unsigned char* smem) {
   using Lay = RefLayout<R, K>;
-  extern __shared__ __align__(16) unsigned char smem[];
   constexpr int JMAX = Lay::JMAX;
   const int tid = threadIdx.x;
-  // workgroups in dispatch order take the templates of one tile back to back, so that its record
-  // stays in L2; the template order rotates with the tile, so that the round-robin placement of
-  // workgroups on the XCDs gives each XCD every template (lengths differ) over the tiles
-  const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-  const int64_t tile = wg / P.batch;
-  const int b = (int)((wg % P.batch + tile) % P.batch);
   const int64_t N = P.g.n;
   const int64_t n0 = tile * kTile;
   const TplConst& c = P.tc[b];
@@ -578,7 +573,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
 
   // the tile's window bounds (k_windows): largest and smallest delay over its nodes, in samples
   typedef const __attribute__((address_space(4))) int cwin_t;
-  cwin_t* wp = (cwin_t*)(P.win + 4 * ((int64_t)b * gridDim.x + tile));
+  cwin_t* wp = (cwin_t*)(P.win + 4 * ((int64_t)b * ntile + tile));
   const int smooth = wp[2];
   const long long w0 = (long long)m_lo - wp[0] - K / 2 - 2;
   const long long w1 = (long long)m_hi - wp[1] + K / 2 + 2;
@@ -872,6 +867,48 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
   }
 }
 
+// Work item i of a launch (tile-major): template (i mod batch + tile) mod batch of tile
+// i / batch when `rotate`, else template i mod batch.  Consecutive items share a tile, so that
+// its record stays in L2; with the rotation, the round-robin placement of workgroups on the
+// XCDs gives each XCD every template (lengths differ) over the tiles.
+__device__ inline void tdi_item_index(const TdiLaunch& P, int64_t i, int64_t* tile, int* b) {
+  *tile = i / P.batch;
+  const int64_t r = i - *tile * P.batch;
+  *b = (int)(P.rotate ? (r + *tile) % P.batch : r);
+}
+
+// one workgroup per item
+template <typename R, int K, bool TAY>
+__global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int NNMAX) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int64_t tile;
+  int b;
+  tdi_item_index(P, (int64_t)blockIdx.y * gridDim.x + blockIdx.x, &tile, &b);
+  tdi_item<R, K, TAY>(P, HY, WMAX, NNMAX, gridDim.x, tile, b, smem);
+}
+
+// persistent: a fixed grid whose workgroups take items from a counter until none is left (the
+// counter is zeroed by k_tdi_refs, which runs before on the same stream).  Every thread of a
+// workgroup runs the same items and meets the same barriers; the loop ends for all of them
+// when the counter passes the last item.
+template <typename R, int K, bool TAY>
+__global__ __launch_bounds__(kNT) void k_tdi_persistent(TdiLaunch P, int HY, int WMAX, int NNMAX, int ntile) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int64_t s_item;
+  const int64_t total = (int64_t)ntile * P.batch;
+  for (;;) {
+    __syncthreads();                   // the previous item is done with the LDS and s_item
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd((unsigned long long*)P.counter, 1ull);
+    __syncthreads();
+    const int64_t i = s_item;
+    if (i >= total) break;
+    int64_t tile;
+    int b;
+    tdi_item_index(P, i, &tile, &b);
+    tdi_item<R, K, TAY>(P, HY, WMAX, NNMAX, ntile, tile, b, smem);
+  }
+}
+
 // launch geometry of the response kernel (host)
 template <typename R, int K>
 struct TdiGeom {
@@ -909,6 +946,7 @@ static hipError_t launch_tdi_t(const TdiLaunch& P0, int stage, hipStream_t s) {
   TdiGeom<R, K> G;
   hipError_t e = G.make(P);
   if (e != hipSuccess) return e;
+  P.counter = (unsigned long long*)((unsigned char*)P.refs + (size_t)G.ntile * RefLayout<R, K>::stride);
   if (stage == 0) {
     hipLaunchKernelGGL(k_nodes, dim3((unsigned)((P.orb.n_nodes + kNT - 1) / kNT), (unsigned)P.batch), dim3(kNT), 0,
                        s, P.tc, P.orb, P.g.inv_dt, P.nodes);
@@ -920,6 +958,21 @@ static hipError_t launch_tdi_t(const TdiLaunch& P0, int stage, hipStream_t s) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_tdi_refs<R, K, TAY>), dim3(G.ntile), dim3(kNT), 0, s, P, G.HY, G.MYP, G.comb);
+    return hipGetLastError();
+  }
+  if (P.persistent) {
+    e = hipFuncSetAttribute((const void*)k_tdi_persistent<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)G.bytes);
+    if (e != hipSuccess) return e;
+    int dev = 0, ncu = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t items = (int64_t)G.ntile * P.batch;
+    int64_t wgs = (int64_t)ncu * (P.wg_per_cu > 0 ? P.wg_per_cu : 1);
+    if (wgs > items) wgs = items;
+    hipLaunchKernelGGL((k_tdi_persistent<R, K, TAY>), dim3((unsigned)wgs), dim3(kNT), G.bytes, s, P, G.HY, G.WMAX,
+                       G.NNMAX, (int)G.ntile);
     return hipGetLastError();
   }
   e = hipFuncSetAttribute((const void*)k_tdi<R, K, TAY>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)G.bytes);
@@ -949,7 +1002,8 @@ void tdi_scratch_bytes(const TdiLaunch& P, size_t* nodes, size_t* refs) {
   *nodes = (size_t)P.batch * (size_t)P.orb.n_nodes * kNodeRec * sizeof(double) +
            (size_t)P.batch * (size_t)((P.g.n + kTile - 1) / kTile) * 4 * sizeof(int);
   const size_t stride = P.precision == 0 ? refs_stride_k<double>(P.taps) : refs_stride_k<float>(P.taps);
-  *refs = (size_t)((P.g.n + kTile - 1) / kTile) * stride;
+  // the records, then the persistent kernel's item counter
+  *refs = stride ? (size_t)((P.g.n + kTile - 1) / kTile) * stride + 256 : 0;
 }
 
 template <typename R>

@@ -57,6 +57,14 @@ class Data(ctypes.Structure):
     _fields_ = [("aet", ctypes.c_void_p), ("dd", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int), ("rotate", ctypes.c_int), ("persistent", ctypes.c_int),
+                ("wg_per_cu", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"chunk": self.chunk, "rotate": self.rotate, "persistent": self.persistent, "wg_per_cu": self.wg_per_cu}
+
+
 class SamplerCfg(ctypes.Structure):
     _fields_ = [("n_walkers", ctypes.c_int), ("n_temps", ctypes.c_int), ("dim", ctypes.c_int),
                 ("param_kind", ctypes.c_int), ("target", ctypes.c_int), ("stretch_a", ctypes.c_double),
@@ -84,6 +92,11 @@ _sig = {
     "lt_tdi_loglike_noalloc": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
                                 ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data), _P, _P, _P, _P],
                                ctypes.c_int),
+    "lt_ctx_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int),
+    "lt_ctx_get_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int),
+    "lt_autotune": ([_P, _P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(Orbit),
+                     ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), ctypes.POINTER(Data), ctypes.c_char_p, ctypes.c_int,
+                     ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "lt_workspace_size": ([_P, _I64, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid), ctypes.POINTER(TdiCfg),
                            ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "lt_noise_inner": ([_P, _P, _I64, ctypes.POINTER(Grid), ctypes.POINTER(Psd), ctypes.c_int, ctypes.c_int, _P, _P],
@@ -302,6 +315,31 @@ class Context:
                                            ctypes.byref(orbit), ctypes.byref(tdi), ctypes.byref(P), ctypes.byref(D),
                                            pl, pf, ps, _stream(stream)))
         return logl
+
+    def set_tuning(self, chunk=256, rotate=1, persistent=0, wg_per_cu=4):
+        """Launch shape of the likelihood (lt_tuning); results do not depend on it."""
+        t = Tuning(int(chunk), int(rotate), int(persistent), int(wg_per_cu))
+        _check(_lib.lt_ctx_set_tuning(self.h, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(_lib.lt_ctx_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, params, g, cfg, orbit, tdi, psd, data_aet, dd, cache_path=None, reps=3, f_lo=3e-4, f_hi=0.02,
+                 stream=None):
+        """lt_autotune: the fastest launch shape for this workload (cached in cache_path); returns
+        (tuning dict, ms per call or -1 when read from the cache)."""
+        B, n = params.shape[0], int(g["n"])
+        pp = _params_ptr(params, self.device)
+        P = _psd_struct(psd, n, f_lo, f_hi, self.device)
+        D = Data(_ptr(data_aet, "data", real_dtype(cfg.precision), numel=3 * n, device=self.device), float(dd))
+        t, ms = Tuning(), ctypes.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(_lib.lt_autotune(self.h, pp, B, ctypes.byref(cfg), ctypes.byref(self.grid(g)), ctypes.byref(orbit),
+                                ctypes.byref(tdi), ctypes.byref(P), ctypes.byref(D), path, int(reps), ctypes.byref(t),
+                                ctypes.byref(ms), _stream(stream)))
+        return t.as_dict(), ms.value
 
     def workspace_size(self, batch, g, cfg, tdi):
         """(bytes for full chunks, bytes for chunks of one template) of tdi_loglike's workspace."""
