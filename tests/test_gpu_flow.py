@@ -270,7 +270,7 @@ def test_sampler_flow_move_parity(lib, T, full):
 @pytest.mark.gpu
 @pytest.mark.parametrize("p_flow", [0.0, 0.35])
 def test_sampler_flow_mix_parity(lib, p_flow):
-    """P31: the flow move mixed with the stretch move at rate p_flow (a Philox draw per step on
+    """P36: the flow move mixed with the stretch move at rate p_flow (a Philox draw per step on
     the device) against the oracle chain, step by step; p_flow = 0 is the plain sampler."""
     d, W, T, seed = 4, 16, 2, 4242
     rng = np.random.default_rng(9)

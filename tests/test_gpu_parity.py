@@ -259,7 +259,7 @@ def test_tdi_full_size_sampled(lt, precision):
                      precessing=True, generation=20)
         want = np.array(r.aet(idx))
         if precision == 0:
-            # R26: both sides round the absolute sample time (up to n dt) to u64 n samples;
+            # both sides round the absolute sample time (up to n dt) to u64 n samples;
             # heavy templates' TDI 2.0 channels are (2 pi f L)^2 below h, so that floor
             # is measured against max|h| (the highest mode frequency is below 2 omega_ring)
             tpl = Template(P[b])

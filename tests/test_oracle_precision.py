@@ -85,7 +85,7 @@ def test_extended_reference_phase_accuracy():
 
 
 def test_loglike_fp64_floor_one_day():
-    """R21 on the oracle alone: at the one-day (2,2) case (K = 2 and 8) the FP64 oracle's logL
+    """The logL tolerance on the oracle alone: at the one-day (2,2) case (K = 2 and 8) the FP64 oracle's logL
     differs from the extended reference by more than the 1e-6 absolute target for the
     mismatched template, and by less than 1e-11 (d|d), the bound the GPU tests apply."""
     g, inj, tmpl = inputs.single_template_case()
@@ -99,12 +99,12 @@ def test_loglike_fp64_floor_one_day():
         gaps = [abs(a - b) for a, b in zip(olk.loglike(d64, h64, S, g["dt"]), olk.loglike(dld, hld, S, g["dt"]))]
         gap_inj = abs(olk.loglike(d64, d64, S, g["dt"])[0] - olk.loglike(dld, dld, S, g["dt"])[0])
         assert max(gaps) > 1e-6                       # FP64 itself cannot meet 1e-6 absolute here
-        assert max(gaps + [gap_inj]) < 1e-11 * dd     # the R21 reading covers it
+        assert max(gaps + [gap_inj]) < 1e-11 * dd     # the 1e-6 + 1e-11 (d|d) tolerance covers it
         assert max(gaps) > 1e-12 * dd                 # and is not loose by orders of magnitude
 
 
 def test_tdi2_fp64_floor_heavy_template():
-    """R26 on the oracle alone: the bench batch's heaviest template (1e7 Msun, precessing,
+    """The long-grid TDI tolerance on the oracle alone: the bench batch's heaviest template (1e7 Msun, precessing,
     Kepler arms, TDI 2.0, K = 8, 2^20 samples): the FP64 oracle's own error on the last
     samples exceeds 1e-9 of the channel, and stays below the time-rounding floor term."""
     n = 2 ** 20

@@ -262,7 +262,7 @@ def test_flow_walk_keeps_the_target():
 
 
 def test_flow_mix_keeps_the_target():
-    """P31: the flow move mixed with the stretch move at rate p_flow (a Philox draw per step
+    """P36: the flow move mixed with the stretch move at rate p_flow (a Philox draw per step
     decides): the chain still samples the target with a mismatched flow, the flow move runs on
     the expected fraction of steps, and p_flow = 0 is the plain sampler, draw for draw."""
     rng = np.random.default_rng(5)
