@@ -17,6 +17,7 @@
 // identity and its log q the exact standardised normal density.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -51,16 +52,29 @@ __device__ __host__ inline bf16 to_bf16(float f) {
 // layout of the instruction (wave64): lane l supplies A[l % 32][4 (l / 32) + j]
 // and B[4 (l / 32) + j][l % 32], j = 0..3, and receives
 // D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32], r = 0..15.
+// One 4-element fragment of a k-contiguous operand row: four consecutive BF16 values (8 bytes,
+// aligned when the caller picks this path: row stride and row start multiples of 4 elements).
+__device__ inline short4v frag_vec(const bf16* row, int k) {
+  return *reinterpret_cast<const short4v*>(row + k);
+}
+
+// AV / BV: the A (B) operand is read as 8-byte fragments along k (sAk = 1, sAm % 4 == 0,
+// aligned base; sBk = 1, sBn % 4 == 0), else element by element.  Same products in the same
+// order either way.  mask (nullable): the epilogue multiplies by (mask[row][col] > 0) (the
+// backward pass through a ReLU) instead of adding the bias.
+template <bool AV, bool BV>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A, int64_t sAm,
                                               int64_t sAk, const bf16* __restrict__ B, int64_t sBk, int64_t sBn,
                                               float* __restrict__ C, int64_t ldc, bf16* __restrict__ Cb,
-                                              const float* __restrict__ bias, int relu) {
+                                              const float* __restrict__ bias, int relu,
+                                              const float* __restrict__ mask) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
   if (m0 >= M || n0 >= N) return;   // whole wavefront leaves together
   const int lm = lane & 31, lk = (lane >> 5) * 4;
   const int m = m0 + lm, n = n0 + lm;
+  const int mr = m < M ? m : M - 1, nr = n < N ? n : N - 1;   // clamped rows for the vector reads
   float16v acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
@@ -71,13 +85,23 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
   for (; k0 + 8 * KU <= K; k0 += 8 * KU) {
     short4v a[KU], b[KU];
 #pragma unroll
-    for (int u = 0; u < KU; ++u)
+    for (int u = 0; u < KU; ++u) {
+      const int kk = k0 + 8 * u + lk;
+      if constexpr (AV) {
+        a[u] = frag_vec(A + (int64_t)mr * sAm, kk);
+        if (m >= M) a[u] = short4v{0, 0, 0, 0};
+      } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = k0 + 8 * u + lk + j;
-        a[u][j] = m < M ? (short)A[(int64_t)m * sAm + (int64_t)k * sAk] : (short)0;
-        b[u][j] = n < N ? (short)B[(int64_t)k * sBk + (int64_t)n * sBn] : (short)0;
+        for (int j = 0; j < 4; ++j) a[u][j] = m < M ? (short)A[(int64_t)m * sAm + (int64_t)(kk + j) * sAk] : (short)0;
       }
+      if constexpr (BV) {
+        b[u] = frag_vec(B + (int64_t)nr * sBn, kk);
+        if (n >= N) b[u] = short4v{0, 0, 0, 0};
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[u][j] = n < N ? (short)B[(int64_t)(kk + j) * sBk + (int64_t)n * sBn] : (short)0;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < KU; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[u], b[u], acc, 0, 0, 0);
   }
@@ -97,12 +121,75 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
     const int col = n0 + lm;
     if (row < M && col < N) {
       float v = acc[r];
-      if (bias) v += bias[col];
-      if (relu) v = v > 0.0f ? v : 0.0f;
+      if (mask) {
+        v = mask[(int64_t)row * ldc + col] > 0.0f ? v : 0.0f;
+      } else {
+        if (bias) v += bias[col];
+        if (relu) v = v > 0.0f ? v : 0.0f;
+      }
       C[(int64_t)row * ldc + col] = v;
       if (Cb) Cb[(int64_t)row * ldc + col] = to_bf16(v);
     }
   }
+}
+
+// Split-K partial products of the weight gradients (M, N <= a few hundred, K = the batch):
+// the z-th slice of the grid sums k in [z kc, min(K, (z + 1) kc)) into part[z][M][N] with the
+// instruction and operand layout of k_gemm; k_split_sum then adds the slices in order.
+__global__ __launch_bounds__(256) void k_gemm_part(int M, int N, int K, int kc, const bf16* __restrict__ A,
+                                                   int64_t sAm, int64_t sAk, const bf16* __restrict__ B,
+                                                   int64_t sBk, int64_t sBn, float* __restrict__ part) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  if (m0 >= M || n0 >= N) return;   // whole wavefront leaves together
+  const int lm = lane & 31, lk = (lane >> 5) * 4;
+  const int m = m0 + lm, n = n0 + lm;
+  const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+  float16v acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  constexpr int KU = 8;
+  int k0 = kb;
+  for (; k0 + 8 * KU <= ke; k0 += 8 * KU) {
+    short4v a[KU], b[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + 8 * u + lk + j;
+        a[u][j] = m < M ? (short)A[(int64_t)m * sAm + (int64_t)k * sAk] : (short)0;
+        b[u][j] = n < N ? (short)B[(int64_t)k * sBk + (int64_t)n * sBn] : (short)0;
+      }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[u], b[u], acc, 0, 0, 0);
+  }
+  for (; k0 < ke; k0 += 8) {
+    short4v a, b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + lk + j;
+      a[j] = (k < ke && m < M) ? (short)A[(int64_t)m * sAm + (int64_t)k * sAk] : (short)0;
+      b[j] = (k < ke && n < N) ? (short)B[(int64_t)k * sBk + (int64_t)n * sBn] : (short)0;
+    }
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+  float* P = part + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = m0 + 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3);
+    const int col = n0 + lm;
+    if (row < M && col < N) P[(int64_t)row * N + col] = acc[r];
+  }
+}
+
+// C[i] = sum over the slices z = 0, 1, ... of part[z][i], in that order
+__global__ void k_split_sum(const float* part, int splits, int64_t mn, float* C) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= mn) return;
+  float acc = part[i];
+  for (int z = 1; z < splits; ++z) acc += part[(int64_t)z * mn + i];
+  C[i] = acc;
 }
 
 // u (FP64 [n][d]) columns [c0, c0+w) -> BF16 [n][w]
@@ -269,13 +356,29 @@ __global__ void k_relu_bwd(float* g, const float* h, int64_t count, bf16* gb) {
   gb[i] = to_bf16(v);
 }
 
-// out[c] = sum_r g[r][c]; one 64-lane wavefront per column, fixed order
-__global__ __launch_bounds__(64) void k_colsum(const float* g, int n, int w, float* out) {
-  const int c = blockIdx.x;
-  float acc = 0.0f;
-  for (int r = threadIdx.x; r < n; r += 64) acc += g[(int64_t)r * w + c];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-  if (threadIdx.x == 0) out[c] = acc;
+// out[c] = sum_r g[r][c]: a workgroup of 16 wavefronts takes 64 columns (each read is 64
+// consecutive floats); wavefront q sums rows r = 16 i + q into eight running sums (i mod 8, so
+// that eight loads are in flight), which it adds in order; the 16 wavefront sums are then added
+// in order
+__global__ __launch_bounds__(1024) void k_colsum(const float* g, int n, int w, float* out) {
+  __shared__ float red[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (c < w) {
+    int r = wave;
+    for (; r + 16 * 7 < n; r += 16 * 8)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j] += g[(int64_t)(r + 16 * j) * w + c];
+    for (int j = 0; r < n; r += 16, ++j) a[j] += g[(int64_t)r * w + c];
+  }
+  red[wave][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  __syncthreads();
+  if (wave == 0 && c < w) {
+    float t = 0.0f;
+    for (int q = 0; q < 16; ++q) t += red[q][lane];
+    out[c] = t;
+  }
 }
 
 // gu[r][c0 + c] += g[r][c]
@@ -454,6 +557,8 @@ struct lt_flow {
   double* lnz = nullptr;   // log N of the walked latent rows
   float *a1 = nullptr, *a2 = nullptr, *o = nullptr, *tmpH = nullptr, *go = nullptr, *tmpA = nullptr;
   bf16 *uA = nullptr, *h1 = nullptr, *h2 = nullptr, *gob = nullptr, *gH = nullptr;
+  float* part = nullptr;   // split-K partial products of the weight gradients
+  int64_t part_count = 0;
   std::vector<void*> allocs;
 };
 
@@ -483,10 +588,47 @@ hipError_t falloc(lt_flow* f, T** p, size_t count) {
 
 inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// an operand can be read as 8-byte fragments along k: unit k stride, rows 4-element aligned
+inline bool k_contiguous(const bf16* p, int64_t s_row, int64_t s_k) {
+  return s_k == 1 && s_row % 4 == 0 && ((uintptr_t)p & 7) == 0;
+}
+
 void gemm(hipStream_t st, int M, int N, int K, const bf16* A, int64_t sAm, int64_t sAk, const bf16* B, int64_t sBk,
-          int64_t sBn, float* C, int64_t ldc, bf16* Cb, const float* bias, int relu) {
+          int64_t sBn, float* C, int64_t ldc, bf16* Cb, const float* bias, int relu, const float* mask = nullptr) {
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb, bias, relu);
+  const bool av = k_contiguous(A, sAm, sAk), bv = k_contiguous(B, sBn, sBk);
+  if (av && bv)
+    hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
+                       bias, relu, mask);
+  else if (av)
+    hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
+                       bias, relu, mask);
+  else if (bv)
+    hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
+                       bias, relu, mask);
+  else
+    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
+                       bias, relu, mask);
+}
+
+// weight gradient C[M][N] (row stride N) = sum_k A(m, k) B(k, n) over the batch K: split-K
+// over slices of 128 rows of the batch (as many as the partial buffer holds), then the slices
+// summed in order
+void gemm_wgrad(lt_flow* f, hipStream_t st, int M, int N, int K, const bf16* A, int64_t sAm, int64_t sAk,
+                const bf16* B, int64_t sBk, int64_t sBn, float* C) {
+  const int64_t mn = (int64_t)M * N;
+  int splits = (K + 127) / 128;
+  const int64_t cap = f->part_count / mn;
+  if (splits > cap) splits = (int)cap;
+  if (splits < 2) {
+    gemm(st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, N, nullptr, nullptr, 0);
+    return;
+  }
+  const int kc = ((K + splits - 1) / splits + 63) & ~63;
+  splits = (K + kc - 1) / kc;
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)splits);
+  hipLaunchKernelGGL(k_gemm_part, grid, dim3(256), 0, st, M, N, K, kc, A, sAm, sAk, B, sBk, sBn, f->part);
+  hipLaunchKernelGGL(k_split_sum, dim3(blocks(mn)), dim3(256), 0, st, f->part, splits, mn, C);
 }
 
 struct Slots {
@@ -569,20 +711,16 @@ void backward(lt_flow* f, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_couple_bwd, dim3(blocks(n)), dim3(256), 0, s, f->gu, n, d, Lo.b0, Lo.nb, S.o, S.s, S.ub,
                        1.0 / n, f->go, f->gob);
     // dW3 = g_o^T h2, db3 = column sums of g_o
-    gemm(s, no, H, n, f->gob, 1, no, S.h2, H, 1, f->g + Lo.W3, H, nullptr, nullptr, 0);
-    hipLaunchKernelGGL(k_colsum, dim3(no), dim3(64), 0, s, f->go, n, no, f->g + Lo.b3);
+    gemm_wgrad(f, s, no, H, n, f->gob, 1, no, S.h2, H, 1, f->g + Lo.W3);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(no, 64)), dim3(1024), 0, s, f->go, n, no, f->g + Lo.b3);
     // g_a2 = (g_o W3) * (h2 > 0); dW2 = g_a2^T h1
-    gemm(s, n, H, no, f->gob, no, 1, f->wb + Lo.W3, H, 1, f->tmpH, H, nullptr, nullptr, 0);
-    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks((int64_t)n * H)), dim3(256), 0, s, f->tmpH, S.a2, (int64_t)n * H,
-                       f->gH);
-    gemm(s, H, H, n, f->gH, 1, H, S.h1, H, 1, f->g + Lo.W2, H, nullptr, nullptr, 0);
-    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(64), 0, s, f->tmpH, n, H, f->g + Lo.b2);
+    gemm(s, n, H, no, f->gob, no, 1, f->wb + Lo.W3, H, 1, f->tmpH, H, f->gH, nullptr, 0, S.a2);
+    gemm_wgrad(f, s, H, H, n, f->gH, 1, H, S.h1, H, 1, f->g + Lo.W2);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(H, 64)), dim3(1024), 0, s, f->tmpH, n, H, f->g + Lo.b2);
     // g_a1 = (g_a2 W2) * (h1 > 0); dW1 = g_a1^T u_A
-    gemm(s, n, H, H, f->gH, H, 1, f->wb + Lo.W2, H, 1, f->tmpH, H, nullptr, nullptr, 0);
-    hipLaunchKernelGGL(k_relu_bwd, dim3(blocks((int64_t)n * H)), dim3(256), 0, s, f->tmpH, S.a1, (int64_t)n * H,
-                       f->gH);
-    gemm(s, H, Lo.na, n, f->gH, 1, H, S.uA, Lo.na, 1, f->g + Lo.W1, Lo.na, nullptr, nullptr, 0);
-    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(64), 0, s, f->tmpH, n, H, f->g + Lo.b1);
+    gemm(s, n, H, H, f->gH, H, 1, f->wb + Lo.W2, H, 1, f->tmpH, H, f->gH, nullptr, 0, S.a1);
+    gemm_wgrad(f, s, H, Lo.na, n, f->gH, 1, H, S.uA, Lo.na, 1, f->g + Lo.W1);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(H, 64)), dim3(1024), 0, s, f->tmpH, n, H, f->g + Lo.b1);
     // dL/du_A += g_a1 W1
     gemm(s, n, Lo.na, H, f->gH, H, 1, f->wb + Lo.W1, Lo.na, 1, f->tmpA, Lo.na, nullptr, nullptr, 0);
     hipLaunchKernelGGL(k_scatter_add, dim3(blocks((int64_t)n * Lo.na)), dim3(256), 0, s, f->gu, n, d, Lo.a0, Lo.na,
@@ -677,6 +815,14 @@ lt_status lt_flow_create(int hip_device, int dim, int n_layers, int hidden, int 
   FA(a1, L * B * H); FA(a2, L * B * H); FA(o, L * B * 2 * dim); FA(s, L * B * dim); FA(ub, L * B * dim);
   FA(uA, L * B * dim); FA(h1, L * B * H); FA(h2, L * B * H);
   FA(tmpH, B * H); FA(go, B * 2 * dim); FA(gob, B * 2 * dim); FA(gH, B * H); FA(tmpA, B * dim);
+  // split-K partials: up to 16 slices of the largest weight matrix, at most 64 MiB
+  {
+    const int64_t mx = H * std::max<int64_t>(H, 2 * dim);
+    int64_t sl = std::min<int64_t>(16, ((B + 127) / 128));
+    while (sl > 1 && sl * mx * 4 > ((int64_t)64 << 20)) --sl;
+    f->part_count = sl > 1 ? sl * mx : 0;
+    if (f->part_count) FA(part, f->part_count);
+  }
 #undef FA
   if (e != hipSuccess) {
     lt_flow_destroy(f);
