@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-sampler", action="store_true", help="skip the sampler-step and ESS measurements")
     ap.add_argument("--ess-precessing", action="store_true",
                     help="also measure ESS/s on the precessing 14-D posterior (slow to equilibrate)")
+    ap.add_argument("--p-flow", type=float, default=1.0,
+                    help="fraction of sampler steps that run the flow move in the ESS measurements")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known traffic) to calibrate HBM counters")
     return ap.parse_args()
@@ -256,16 +258,63 @@ def dominant_mode(s, min_sep=8.0, min_frac=0.02, axes=4):
     return s[keep], float(keep.mean())
 
 
+def quantile_gap(a, b, n_batches=20):
+    """Largest difference between the 5 / 50 / 95 % marginal quantiles of two chains
+    [steps][walkers][d], in units of its Monte-Carlo standard error (batch quantiles)."""
+    import numpy as np
+    from paper_2501_08261_amd.diagnostics import batch_quantile_se
+    qa, sa = batch_quantile_se(a, n_batches=n_batches)
+    qb, sb = batch_quantile_se(b, n_batches=n_batches)
+    return float(np.max(np.abs(qa - qb) / np.sqrt(sa ** 2 + sb ** 2)))
+
+
+def train_early_stop(flow, s, mu, L, val_frac=0.25, chunk=250, max_steps=3000, patience=2, lr=3e-4, seed=0):
+    """Fit the flow to a window of chain samples s [n][d] in time order, holding out its last
+    val_frac of rows: Adam in chunks of `chunk` steps (batch 2048) on the shuffled earlier
+    samples, the held-out mean log q after each chunk, stop after `patience` chunks without
+    improvement and keep the best parameters.  The chain is correlated in time, so a later
+    stretch of it is the fair check of what the flow will meet as a proposal; training on
+    without it overfits the window (the held-out log q falls while the training one rises).
+    Returns (Adam steps run, best held-out mean log q)."""
+    import numpy as np
+    import torch
+    nv = max(1, int(round(val_frac * s.shape[0])))
+    tr = s[:-nv]
+    va = torch.tensor(s[-nv:], device="cuda:0")
+    flow.set_whitening(mu, L)
+    xs = torch.tensor(tr[np.random.default_rng(seed).permutation(len(tr))], device="cuda:0")
+
+    def val_logq():
+        tot = 0.0
+        for i in range(0, va.shape[0], flow.max_batch):
+            tot += float(flow.log_prob(va[i:i + flow.max_batch]).sum().item())
+        return tot / va.shape[0]
+    best, best_p, bad, done = val_logq(), flow.get_params(), 0, 0
+    while done < max_steps and bad < patience:
+        # each chunk starts where the previous one stopped in the shuffled samples
+        flow.train(torch.roll(xs, -((done * 2048) % xs.shape[0]), 0), chunk, 2048, lr)
+        done += chunk
+        v = val_logq()
+        if v > best:
+            best, best_p, bad = v, flow.get_params(), 0
+        else:
+            bad += 1
+    flow.set_params(best_p, np.zeros(s.shape[-1]), np.ones(s.shape[-1]))
+    flow.set_whitening(mu, L)
+    return done, best
+
+
 def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=500, rounds=4, window=400,
-              train_steps=1500, m=1000, walk=0.0, split_modes=True):
+              train_steps=1500, m=1000, walk=0.0, split_modes=True, p_flow=1.0, early_stop=True, pool=1, exclusive=True, control=True):
     """Effective samples per second of the cold chain, stretch moves alone against
     stretch + learned-flow moves, on one injection and one GPU (TDI-2 AET, 512
     walkers x 8 temperatures, n samples around the merger, Fisher-initialised).
 
     The flow (8 couplings, width 256) learns from the sampler's own chain: after
-    `burn` plain steps, `rounds` times: whiten by the last `window` steps' cold
-    samples (Cholesky of their covariance), train `train_steps` Adam steps on them,
-    attach, run `window` more steps.  The flow is then frozen and both samplers
+    `burn` plain steps, `rounds` times: take the cold samples of the last `pool` windows
+    of `window` steps, whiten by the Cholesky factor of their covariance, train on them
+    (train_early_stop: at most `train_steps` Adam steps, stopped by the latest quarter of
+    the samples; early_stop=False: exactly `train_steps`), attach, run `window` more steps.  The flow is then frozen and both samplers
     restart from the same state for `m` recorded steps; ESS = m W / max_q tau_q
     (worst coordinate), ESS/s uses the time of 200 unrecorded steps.
 
@@ -277,10 +326,14 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     chains, since only psi mod pi is identified.
 
     walk > 0 replaces the flow's independence proposals by a random walk of that step in
-    its latent space (lt_sampler_set_flow_walk)."""
+    its latent space (lt_sampler_set_flow_walk).  p_flow < 1 runs the flow move on that
+    fraction of the steps once the flow is attached (lt_flow_set_mix); the others run the
+    stretch moves and swaps alone.  exclusive: the flow's steps skip the cold rung's stretch
+    moves (lt_sampler_set_flow_exclusive).  control: also compare two plain chains.  Posterior accuracy: the largest gap between the two
+    chains' 5 / 50 / 95 % quantiles in units of its Monte-Carlo error (quantile_gap)."""
     import numpy as np
     import torch
-    from paper_2501_08261_amd.diagnostics import autocorr_time
+    from paper_2501_08261_amd.diagnostics import autocorr_time, batch_ess
     kind = "precessing14" if precessing else "aligned10"
     modes = ((2, 2), (2, 1), (3, 3), (3, 2), (4, 4))
     ctx = lib.Context(0)
@@ -314,9 +367,10 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         return X
 
     t_train = 0.0
-    mode_frac = []
+    mode_frac, steps_run, recent = [], [], []
     for r in range(rounds):
-        s = _record(smp, window).reshape(-1, dim)
+        recent.append(_record(smp, window).reshape(-1, dim))
+        s = np.concatenate(recent[-pool:])
         two = 2.0 * s[:, ipsi]
         start = 0.5 * np.arctan2(np.sin(two).mean(), np.cos(two).mean()) - 0.5 * np.pi
         s = fold(s, start)
@@ -325,18 +379,33 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
             mode_frac.append(kept)
         smp.set_flow_fold(ipsi, np.pi, start)
         smp.set_flow_walk(walk)
-        flow.set_whitening(s.mean(0), np.linalg.cholesky(np.cov(s.T)))
-        xs = torch.tensor(s[np.random.default_rng(r).permutation(len(s))], device="cuda:0")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        flow.train(xs, train_steps, 2048, 3e-4)
-        torch.cuda.synchronize()
-        t_train += time.perf_counter() - t1
+        if early_stop:
+            # whitened by the earlier 3/4 of the window (rows in time order), which it trains on;
+            # the latest quarter decides when to stop
+            fit = s[:len(s) - max(1, int(round(0.25 * len(s))))]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            done, best = train_early_stop(flow, s, fit.mean(0), np.linalg.cholesky(np.cov(fit.T)),
+                                          max_steps=train_steps, seed=r)
+            torch.cuda.synchronize()
+            t_train += time.perf_counter() - t1
+            steps_run.append(done)
+        else:
+            flow.set_whitening(s.mean(0), np.linalg.cholesky(np.cov(s.T)))
+            xs = torch.tensor(s[np.random.default_rng(r).permutation(len(s))], device="cuda:0")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            flow.train(xs, train_steps, 2048, 3e-4)
+            torch.cuda.synchronize()
+            t_train += time.perf_counter() - t1
+            steps_run.append(train_steps)
         smp.set_flow(flow)
+        smp.set_flow_mix(p_flow)
+        smp.set_flow_exclusive(exclusive)
     _record(smp, window)
     t_adapt = time.perf_counter() - t0
     state = smp.state()[0]
-    res = {}
+    res, chains = {}, {}
     for label, fl in (("learned", flow), ("plain", None)):
         smp.set_state(state)
         smp.set_flow(fl)
@@ -349,14 +418,28 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         chain = fold(_record(smp, m), start)
         acc, prop = smp.flow_counts()
         tau = autocorr_time(chain)
+        chains[label] = chain
+        eb = batch_ess(chain)
         flat = chain.reshape(-1, dim)
         res[label] = {"ess_per_s": m * W / float(tau.max()) / (m * t_step), "tau_max": float(tau.max()),
                       "tau_median": float(np.median(tau)), "ms_per_step": 1e3 * t_step,
+                      "ess_batch": float(eb.min()), "ess_batch_per_s": float(eb.min()) / (m * t_step),
+                      "ess_batch_coord": [round(float(v)) for v in eb],
                       "mean": flat.mean(0), "std": flat.std(0)}
         if fl is not None:
             res[label]["flow_accept"] = acc / max(prop, 1)
         else:
             res[label]["stretch_accept"] = smp.state()[4][0] / max(smp.state()[4][1], 1)
+    qgap_control = None
+    if control:
+        # a second plain chain from the same state with another seed: the gap two plain chains
+        # show is the floor of the check
+        smp2 = lib.Sampler(W, T, dim, lo, hi, 6, target="tdi", param_kind=kind, t_c=inj[11], g=g, cfg=cfg,
+                           orbit=orb, tdi=tdi, psd=S, data_aet=d[0], dd=float(dd.item()))
+        smp2.set_state(state)
+        smp2.step(220)
+        qgap_control = quantile_gap(fold(_record(smp2, m), start), chains["plain"])
+        smp2.close()
     # with the flow's training counted: the learned sampler's wall time includes the Adam steps;
     # break-even = the number of measured steps after which the learned sampler with its
     # training has produced as many effective samples per second as the plain one
@@ -389,13 +472,17 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     smp.close()
     flow.close()
     ctx.close()
+    qgap = quantile_gap(chains["learned"], chains["plain"])
     return {"target": kind, "flow_move": "latent walk, step %g" % walk if walk > 0 else "independence",
+            "p_flow": p_flow, "flow_exclusive": bool(exclusive), "quantile_gap_mc_sigma": qgap,
+            "quantile_gap_plain_vs_plain": qgap_control,
             "n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
             "flow_training_share": mode_frac,
-            "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": rounds * train_steps,
-            "flow_train_tflops": flow_gemm_flops(dim) * 2048 * rounds * train_steps / t_train / 1e12,
+            "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": steps_run,
+            "flow_train_tflops": flow_gemm_flops(dim) * 2048 * sum(steps_run) / t_train / 1e12,
             "plain": res["plain"], "learned": res["learned"],
             "ratio": res["learned"]["ess_per_s"] / res["plain"]["ess_per_s"],
+            "ratio_batch": res["learned"]["ess_batch_per_s"] / res["plain"]["ess_batch_per_s"],
             "ratio_with_training": res["learned"]["ess_per_s_with_training"] / res["plain"]["ess_per_s"],
             "breakeven_steps": breakeven,
             "posterior_mean_shift_sigma": shift, "posterior_std_ratio": [round(x, 3) for x in std_ratio],
@@ -594,9 +681,9 @@ def main():
         out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4, "launches": 3}
     ctx.close()
     if not a.no_sampler:
-        runs = [("sampler", sampler_bench, {}), ("ess", ess_bench, {})]
+        runs = [("sampler", sampler_bench, {}), ("ess", ess_bench, {"p_flow": a.p_flow})]
         if a.ess_precessing:
-            runs.append(("ess_precessing", ess_bench, {"precessing": True}))
+            runs.append(("ess_precessing", ess_bench, {"precessing": True, "p_flow": a.p_flow}))
         for key, fn, kw in runs:
             try:
                 out[key] = fn(lib, inputs, prec, **kw)

@@ -421,6 +421,13 @@ lt_status lt_sampler_set_flow_walk(lt_sampler* s, double step);
  * target.  1 (the default) runs the flow move every step; 0 is the plain sampler (the
  * fallback), even with a flow attached.  Rebuilds the captured step. */
 lt_status lt_flow_set_mix(lt_sampler* s, double p_flow);
+/* on = 1: a step that runs the flow move (above) skips the stretch moves of the cold rung,
+ * whose walkers then move by the flow move alone on that step (their stretch rows are neither
+ * evaluated nor counted); the hotter rungs keep theirs.  The choice is the step's gate, not the
+ * state, so the target is kept.  It saves the cold rung's likelihood rows on the flow's steps.
+ * 0 (the default): both moves run.  Rebuilds the captured step.  Status LT_ERR_CONFIG unless
+ * on is 0 or 1. */
+lt_status lt_sampler_set_flow_exclusive(lt_sampler* s, int on);
 /* Flow moves accepted and proposed since lt_sampler_set_state (host int64 [2]). */
 lt_status lt_sampler_flow_counts(lt_sampler* s, int64_t* counts);
 

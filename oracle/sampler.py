@@ -34,6 +34,10 @@ of the GPU sampler:
   (step, 0x800, 0, 0); a step without it proposes nothing for it.  Every step's kernel
   (stretch move, flow move, swaps) keeps the target, and the choice does not depend on the
   state, so the mixture keeps it too; p_flow = 1 runs the flow move every step;
+  optionally (exclusive) a step that runs the flow move skips the stretch move on the
+  cold rung (its rows are neither proposed nor counted): the cold rung's kernel on that
+  step is then the flow move alone, again a state-independent choice between kernels
+  that keep the target;
 * optional latent random walk in place of the independence proposal:
   z = f(x) (the flow's forward map of the folded position), z' = z + w eps,
   eps standard normal from counter (step, 0x700, walker, q) like the base
@@ -124,6 +128,7 @@ class PTSampler:
         self.fold = None
         self.walk = 0.0
         self.p_flow = 1.0
+        self.flow_exclusive = False
         self.facc = self.fprop = 0
         self.flow_steps = 0
 
@@ -138,6 +143,10 @@ class PTSampler:
     def set_flow_mix(self, p_flow):
         """Probability that a step runs the flow move (0: the plain sampler)."""
         self.p_flow = float(p_flow)
+
+    def set_flow_exclusive(self, on):
+        """On steps that run the flow move, skip the cold rung's stretch moves."""
+        self.flow_exclusive = bool(on)
 
     def flow_gate(self, s):
         """Whether step s runs the flow move: u < p_flow, u from counter (s, 0x800, 0, 0)."""
@@ -241,9 +250,13 @@ class PTSampler:
     def step(self):
         T, W, d, half = self.T, self.W, self.d, self.W // 2
         s = self.step_count
+        gate = self.flow is not None and self.p_flow > 0.0 and self.flow_gate(s)
+        t_first = 1 if gate and self.flow_exclusive else 0
         for h in (0, 1):
-            t = np.repeat(np.arange(T), half)
-            k = h * half + np.tile(np.arange(half), T)
+            t = np.repeat(np.arange(t_first, T), half)
+            k = h * half + np.tile(np.arange(half), T - t_first)
+            if t.size == 0:
+                continue
             r = philox4x32_10(_ctr(s, TAG_MOVE + h, t * W + k), self.key)
             jj = np.minimum((u01(r[:, 0]) * half).astype(np.int64), half - 1)
             j = (1 - h) * half + jj
@@ -260,7 +273,7 @@ class PTSampler:
             self.logp[t[ok], k[ok]] = lpy[ok]
             self.acc += int(ok.sum())
             self.prop += ok.size
-        if self.flow is not None and self.p_flow > 0.0 and self.flow_gate(s):
+        if gate:
             self.flow_move(s)
             self.flow_steps += 1
         for i in range(T - 2, -1, -1):

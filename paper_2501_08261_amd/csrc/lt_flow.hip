@@ -67,7 +67,9 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
                                               int64_t sAk, const bf16* __restrict__ B, int64_t sBk, int64_t sBn,
                                               float* __restrict__ C, int64_t ldc, bf16* __restrict__ Cb,
                                               const float* __restrict__ bias, int relu,
-                                              const float* __restrict__ mask) {
+                                              const float* __restrict__ mask,
+                                              const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
@@ -193,7 +195,8 @@ __global__ void k_split_sum(const float* part, int splits, int64_t mn, float* C)
 }
 
 // u (FP64 [n][d]) columns [c0, c0+w) -> BF16 [n][w]
-__global__ void k_gather(const double* u, int n, int d, int c0, int w, bf16* out) {
+__global__ void k_gather(const double* u, int n, int d, int c0, int w, bf16* out, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * w) return;
   const int r = i / w, c = i - r * w;
@@ -218,7 +221,8 @@ __device__ inline void couple_row(double* u, int r, int d, int b0, int nb, const
 }
 
 __global__ void k_couple(double* u, int n, int d, int b0, int nb, const float* o, double* s_out, double* ub_in,
-                         double* logdet, int inverse) {
+                         double* logdet, int inverse, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   couple_row(u, r, d, b0, nb, o + (int64_t)r * 2 * nb, s_out, ub_in, logdet, inverse);
@@ -275,7 +279,8 @@ constexpr int kFusedThreads = 512;   // eight wavefronts: one 32-column tile of 
 __global__ __launch_bounds__(kFusedThreads) void k_couple_fused(double* u, int n, int d, int a0, int na, int b0, int nb,
                                                       int H, const bf16* W1, const float* bias1, const bf16* W2,
                                                       const float* bias2, const bf16* W3, const float* bias3,
-                                                      double* logdet, int inverse) {
+                                                      double* logdet, int inverse, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   extern __shared__ __align__(16) unsigned char sm[];
   const int KA = (na + 7) & ~7;
   bf16* uA = (bf16*)sm;
@@ -392,7 +397,8 @@ __global__ void k_scatter_add(double* gu, int n, int d, int c0, int w, const flo
 // u = Lw^-1 (x[src] - mu), src = (start + r) mod n_src, by forward substitution
 // (one thread per row); logdet = 0.  A diagonal Lw gives (x - mu) / sigma exactly.
 __global__ void k_standardise(const double* x, int64_t n_src, int64_t start, int n, int d, const double* mu,
-                              const double* Lw, double* u, double* logdet) {
+                              const double* Lw, double* u, double* logdet, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   const int64_t src = (start + r) % n_src;
@@ -407,7 +413,8 @@ __global__ void k_standardise(const double* x, int64_t n_src, int64_t start, int
 
 // log q = -|u|^2/2 - d/2 log 2pi + logdet - lsig; optionally dL/dz = u / n for the mean NLL
 __global__ void k_logq(const double* u, int n, int d, const double* logdet, double lsig, double* logq, double* gu,
-                       double inv_n) {
+                       double inv_n, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   double q = 0.0;
@@ -420,7 +427,8 @@ __global__ void k_logq(const double* u, int n, int d, const double* logdet, doub
 }
 
 // logq += logdet - lsig (inverse pass: base density computed before it)
-__global__ void k_logq_add(int n, const double* logdet, double lsig, double* logq) {
+__global__ void k_logq_add(int n, const double* logdet, double lsig, double* logq, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   logq[r] = logq[r] + logdet[r] - lsig;
@@ -428,8 +436,10 @@ __global__ void k_logq_add(int n, const double* logdet, double lsig, double* log
 
 // x = Lw u + mu, the diagonal product and the additions rounded separately (no
 // fused multiply-add), so that a diagonal Lw gives u sigma + mu exactly
-__global__ void k_destandardise(const double* u, int n, int d, const double* mu, const double* Lw, double* x) {
+__global__ void k_destandardise(const double* u, int n, int d, const double* mu, const double* Lw, double* x,
+                                const int* __restrict__ gate) {
 #pragma clang fp contract(off)
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * d) return;
   const int r = i / d, c = i - r * d;
@@ -446,19 +456,23 @@ __global__ void k_load(const double* z, int64_t count, double* u) {
   if (i < count) u[i] = z[i];
 }
 
-__global__ void k_zero(double* p, int64_t count) {
+__global__ void k_zero(double* p, int64_t count, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0.0;
 }
 
-__global__ void k_copy(const double* src, int64_t count, double* dst) {
+__global__ void k_copy(const double* src, int64_t count, double* dst, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) dst[i] = src[i];
 }
 
 // standard normal base samples for the proposal of walker k: Philox counter
 // (step, kTagFlowZ, k, q) gives two Box-Muller pairs for coordinates 4q..4q+3
-__global__ void k_base_normal(const uint64_t* step, uint32_t k0, uint32_t k1, int n, int d, double* u) {
+__global__ void k_base_normal(const uint64_t* step, uint32_t k0, uint32_t k1, int n, int d, double* u,
+                              const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const uint32_t st = (uint32_t)*step;
@@ -480,7 +494,8 @@ __global__ void k_base_normal(const uint64_t* step, uint32_t k0, uint32_t k1, in
 // log N(z) = -|z|^2 / 2 - (d / 2) log(2 pi) (squares summed in coordinate order):
 // lq_x = logq - log N(u), lnz2 = log N(u + sigma eps)
 __global__ void k_walk(const uint64_t* step, uint32_t k0, uint32_t k1, int n, int d, double sigma, double* u,
-                       const double* logq, double* lq_x, double* lnz2) {
+                       const double* logq, double* lq_x, double* lnz2, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const uint32_t st = (uint32_t)*step;
@@ -508,7 +523,8 @@ __global__ void k_walk(const uint64_t* step, uint32_t k0, uint32_t k1, int n, in
   lnz2[k] = -0.5 * w2 - c0;
 }
 
-__global__ void k_sub(double* a, const double* b, int n) {
+__global__ void k_sub(double* a, const double* b, int n, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) a[k] -= b[k];
 }
@@ -545,6 +561,8 @@ struct LayerOff {
 
 struct lt_flow {
   int device = 0, d = 0, L = 0, H = 0, maxB = 0;
+  // device flag read by the kernels of the sampler's flow move (nullable): 0 skips them
+  const int* gate = nullptr;
   int64_t nparam = 0;
   std::vector<LayerOff> lay;
   float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
@@ -594,21 +612,22 @@ inline bool k_contiguous(const bf16* p, int64_t s_row, int64_t s_k) {
 }
 
 void gemm(hipStream_t st, int M, int N, int K, const bf16* A, int64_t sAm, int64_t sAk, const bf16* B, int64_t sBk,
-          int64_t sBn, float* C, int64_t ldc, bf16* Cb, const float* bias, int relu, const float* mask = nullptr) {
+          int64_t sBn, float* C, int64_t ldc, bf16* Cb, const float* bias, int relu, const float* mask = nullptr,
+          const int* gate = nullptr) {
   dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
   const bool av = k_contiguous(A, sAm, sAk), bv = k_contiguous(B, sBn, sBk);
   if (av && bv)
     hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
-                       bias, relu, mask);
+                       bias, relu, mask, gate);
   else if (av)
     hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
-                       bias, relu, mask);
+                       bias, relu, mask, gate);
   else if (bv)
     hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
-                       bias, relu, mask);
+                       bias, relu, mask, gate);
   else
     hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, M, N, K, A, sAm, sAk, B, sBk, sBn, C, ldc, Cb,
-                       bias, relu, mask);
+                       bias, relu, mask, gate);
 }
 
 // weight gradient C[M][N] (row stride N) = sum_k A(m, k) B(k, n) over the batch K: split-K
@@ -666,39 +685,41 @@ void pass(lt_flow* f, int n, int inverse, hipStream_t st, bool keep) {
     const LayerOff& Lo = f->lay[l];
     const size_t fb = keep ? 0 : fused_bytes(f, Lo);
     if (fb > 0) {
-      hipLaunchKernelGGL(k_couple_fused, dim3(blocks(n, 32)), dim3(kFusedThreads), fb, st, f->u, n, d, Lo.a0, Lo.na, Lo.b0,
-                         Lo.nb, H, f->wb + Lo.W1, f->w + Lo.b1, f->wb + Lo.W2, f->w + Lo.b2, f->wb + Lo.W3,
-                         f->w + Lo.b3, f->logdet, inverse);
+      hipLaunchKernelGGL(k_couple_fused, dim3(blocks(n, 32)), dim3(kFusedThreads), fb, st, f->u, n, d, Lo.a0, Lo.na,
+                         Lo.b0, Lo.nb, H, f->wb + Lo.W1, f->w + Lo.b1, f->wb + Lo.W2, f->w + Lo.b2, f->wb + Lo.W3,
+                         f->w + Lo.b3, f->logdet, inverse, f->gate);
       continue;
     }
     Slots S = slots(f, l, n);
-    hipLaunchKernelGGL(k_gather, dim3(blocks((int64_t)n * Lo.na)), dim3(256), 0, st, f->u, n, d, Lo.a0, Lo.na, S.uA);
-    gemm(st, n, H, Lo.na, S.uA, Lo.na, 1, f->wb + Lo.W1, 1, Lo.na, S.a1, H, S.h1, f->w + Lo.b1, 1);
-    gemm(st, n, H, H, S.h1, H, 1, f->wb + Lo.W2, 1, H, S.a2, H, S.h2, f->w + Lo.b2, 1);
-    gemm(st, n, 2 * Lo.nb, H, S.h2, H, 1, f->wb + Lo.W3, 1, H, S.o, 2 * Lo.nb, nullptr, f->w + Lo.b3, 0);
+    hipLaunchKernelGGL(k_gather, dim3(blocks((int64_t)n * Lo.na)), dim3(256), 0, st, f->u, n, d, Lo.a0, Lo.na, S.uA,
+                       f->gate);
+    gemm(st, n, H, Lo.na, S.uA, Lo.na, 1, f->wb + Lo.W1, 1, Lo.na, S.a1, H, S.h1, f->w + Lo.b1, 1, nullptr, f->gate);
+    gemm(st, n, H, H, S.h1, H, 1, f->wb + Lo.W2, 1, H, S.a2, H, S.h2, f->w + Lo.b2, 1, nullptr, f->gate);
+    gemm(st, n, 2 * Lo.nb, H, S.h2, H, 1, f->wb + Lo.W3, 1, H, S.o, 2 * Lo.nb, nullptr, f->w + Lo.b3, 0, nullptr,
+         f->gate);
     hipLaunchKernelGGL(k_couple, dim3(blocks(n)), dim3(256), 0, st, f->u, n, d, Lo.b0, Lo.nb, S.o, S.s, S.ub,
-                       f->logdet, inverse);
+                       f->logdet, inverse, f->gate);
   }
 }
 
 // log q of n rows x[(start + r) mod n_src] into f->logq (and dL/dz into f->gu when grad)
 void logq_rows(lt_flow* f, const double* x, int64_t n_src, int64_t start, int n, bool grad, hipStream_t st) {
   hipLaunchKernelGGL(k_standardise, dim3(blocks(n, 64)), dim3(64), 0, st, x, n_src, start, n, f->d, f->mu, f->Lw,
-                     f->u, f->logdet);
+                     f->u, f->logdet, f->gate);
   pass(f, n, 0, st, grad);
   hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, f->d, f->logdet, f->lsig, f->logq,
-                     grad ? f->gu : (double*)nullptr, 1.0 / n);
+                     grad ? f->gu : (double*)nullptr, 1.0 / n, f->gate);
 }
 
 // inverse pass from base samples already in f->u: x (FP64 [n][d]) and log q(x)
 void sample_rows(lt_flow* f, int n, double* x, double* logq, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero, dim3(blocks(n)), dim3(256), 0, st, f->logdet, (int64_t)n);
+  hipLaunchKernelGGL(k_zero, dim3(blocks(n)), dim3(256), 0, st, f->logdet, (int64_t)n, f->gate);
   hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, f->d, f->logdet, 0.0, logq,
-                     (double*)nullptr, 0.0);
+                     (double*)nullptr, 0.0, f->gate);
   pass(f, n, 1, st, false);
-  hipLaunchKernelGGL(k_logq_add, dim3(blocks(n)), dim3(256), 0, st, n, f->logdet, f->lsig, logq);
+  hipLaunchKernelGGL(k_logq_add, dim3(blocks(n)), dim3(256), 0, st, n, f->logdet, f->lsig, logq, f->gate);
   hipLaunchKernelGGL(k_destandardise, dim3(blocks((int64_t)n * f->d)), dim3(256), 0, st, f->u, n, f->d, f->mu,
-                     f->Lw, x);
+                     f->Lw, x, f->gate);
 }
 
 // backward pass of the mean NLL after logq_rows(grad = true); gradients into f->g
@@ -748,27 +769,34 @@ int flow_dim(const lt_flow* f) { return f->d; }
 int flow_max_batch(const lt_flow* f) { return f->maxB; }
 int flow_device(const lt_flow* f) { return f->device; }
 // proposals y ~ q for n walkers from Philox base samples keyed by (k0, k1) at the device step counter
+// gate (nullable): device flag; where it reads 0 at run time, every kernel of the call returns at once
 hipError_t flow_propose(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y, double* logq_y,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_base_normal, dim3(blocks(n, 64)), dim3(64), 0, st, step, k0, k1, n, f->d, f->u);
+                        hipStream_t st, const int* gate) {
+  f->gate = gate;
+  hipLaunchKernelGGL(k_base_normal, dim3(blocks(n, 64)), dim3(64), 0, st, step, k0, k1, n, f->d, f->u, f->gate);
   sample_rows(f, n, y, logq_y, st);
+  f->gate = nullptr;
   return hipGetLastError();
 }
 // log q of the n rows of x (FP64 [n][d]) into logq
-hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st) {
+hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st, const int* gate) {
+  f->gate = gate;
   logq_rows(f, x, n, 0, n, false, st);
-  hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, st, f->logq, (int64_t)n, logq);
+  hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, st, f->logq, (int64_t)n, logq, f->gate);
+  f->gate = nullptr;
   return hipGetLastError();
 }
 // latent random walk from the rows of x: z = f(x), y = f^-1(z + sigma eps);
 // lq_x = log q(x) - log N(z), lq_y = log q(y) - log N(z + sigma eps)
 hipError_t flow_walk(lt_flow* f, const double* x, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double sigma,
-                     double* y, double* lq_y, double* lq_x, hipStream_t st) {
+                     double* y, double* lq_y, double* lq_x, hipStream_t st, const int* gate) {
+  f->gate = gate;
   logq_rows(f, x, n, 0, n, false, st);
   hipLaunchKernelGGL(k_walk, dim3(blocks(n, 64)), dim3(64), 0, st, step, k0, k1, n, f->d, sigma, f->u, f->logq, lq_x,
-                     f->lnz);
+                     f->lnz, f->gate);
   sample_rows(f, n, y, lq_y, st);
-  hipLaunchKernelGGL(k_sub, dim3(blocks(n)), dim3(256), 0, st, lq_y, f->lnz, n);
+  hipLaunchKernelGGL(k_sub, dim3(blocks(n)), dim3(256), 0, st, lq_y, f->lnz, n, f->gate);
+  f->gate = nullptr;
   return hipGetLastError();
 }
 }  // namespace lt
@@ -919,7 +947,7 @@ lt_status lt_flow_log_prob(lt_flow* f, const double* x, int64_t n, double* logq,
   FL_HIP(hipSetDevice(f->device));
   hipStream_t s = (hipStream_t)stream;
   logq_rows(f, x, n, 0, (int)n, false, s);
-  hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, s, f->logq, n, logq);
+  hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, s, f->logq, n, logq, f->gate);
   FL_HIP(hipGetLastError());
   return LT_OK;
 }

@@ -49,6 +49,7 @@ struct Dev {
   double walk;              // > 0: the flow move is a random walk of this step in the flow's latent space
   double p_flow;            // probability that a step runs the flow move (1: every step)
   int* fgate;               // this step's draw: 1 = the flow move runs
+  int fexcl;                // 1: a step that runs the flow move skips the cold rung's stretch moves
 };
 
 __device__ inline void to_params(const Dev& D, const double* x, double* p) {
@@ -77,12 +78,20 @@ __device__ inline double log_prior(const Dev& D, const double* x) {
   return 0.0;
 }
 
-// proposals for half h: one thread per (temperature, walker of the half)
-__global__ void k_propose(Dev D, int h) {
+// proposals for half h: one thread per (temperature, walker of the half).  excl: on a step
+// whose gate runs the flow move, the cold rung proposes nothing (unphysical parameter rows,
+// which the likelihood skips after its per-template setup)
+__global__ void k_propose(Dev D, int h, int excl) {
   const int half = D.W / 2;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= D.T * half) return;
   const int t = idx / half, kk = idx - t * half;
+  if (excl && t == 0 && *D.fgate) {
+    D.ylogp[idx] = -INFINITY;
+    if (D.target == LT_TARGET_TDI)
+      for (int i = 0; i < 16; ++i) D.params[(int64_t)idx * 16 + i] = 0.0;
+    return;
+  }
   const int k = h * half + kk;
   uint32_t c[4] = {(uint32_t)*D.step, kTagMove + (uint32_t)h, (uint32_t)(t * D.W + k), 0u};
   philox4x32_10(c, D.k0, D.k1);
@@ -133,11 +142,12 @@ __global__ void k_gauss(Dev D, const double* xs, int64_t count, double* out) {
   out[idx] = best + log(acc / D.n_gauss);
 }
 
-__global__ void k_accept(Dev D, int h) {
+__global__ void k_accept(Dev D, int h, int excl) {
   const int half = D.W / 2;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= D.T * half) return;
   const int t = idx / half, kk = idx - t * half;
+  if (excl && t == 0 && *D.fgate) return;   // no cold stretch move on this step: nothing counted
   const int64_t w = (int64_t)t * D.W + h * half + kk;
   const double lly = D.ylogl[idx], lpy = D.ylogp[idx];
   const double la = (D.d - 1) * D.ylogz[idx] + D.beta[t] * (lly - D.logl[w]) + (lpy - D.logp[w]);
@@ -286,10 +296,10 @@ int flow_dim(const lt_flow* f);
 int flow_max_batch(const lt_flow* f);
 int flow_device(const lt_flow* f);
 hipError_t flow_propose(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y, double* logq_y,
-                        hipStream_t st);
-hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st);
+                        hipStream_t st, const int* gate);
+hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st, const int* gate);
 hipError_t flow_walk(lt_flow* f, const double* x, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double sigma,
-                     double* y, double* lq_y, double* lq_x, hipStream_t st);
+                     double* y, double* lq_y, double* lq_x, hipStream_t st, const int* gate);
 }
 
 struct lt_sampler {
@@ -352,27 +362,33 @@ static lt_status eval_logl(lt_sampler* s, const double* xs, int64_t count, doubl
 static lt_status record_step(lt_sampler* s, hipStream_t st) {
   const int half = s->cfg.n_walkers / 2;
   const int n = s->cfg.n_temps * half;
+  const bool flow = s->flow && s->D.p_flow > 0.0;
+  const int excl = flow && s->D.fexcl ? 1 : 0;
+  if (flow) {
+    // the step's draw of the flow move, read by the stretch half-steps when excl is set
+    hipLaunchKernelGGL(k_flow_gate, dim3(1), dim3(1), 0, st, s->D);
+    S_HIP(hipGetLastError());
+  }
   for (int h = 0; h < 2; ++h) {
-    hipLaunchKernelGGL(k_propose, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h);
+    hipLaunchKernelGGL(k_propose, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h, excl);
     S_HIP(hipGetLastError());
     lt_status r = eval_logl(s, s->D.Y, n, s->D.ylogl, st);
     if (r != LT_OK) return r;
-    hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h);
+    hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, st, s->D, h, excl);
     S_HIP(hipGetLastError());
   }
-  if (s->flow && s->D.p_flow > 0.0) {
+  if (flow) {
     const int W = s->cfg.n_walkers;
-    hipLaunchKernelGGL(k_flow_gate, dim3(1), dim3(1), 0, st, s->D);
-    S_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_flow_fold, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());
     if (s->D.walk > 0.0) {
       // y = f^-1(f(x) + walk eps): fqx, fqy carry log q - log N of the two latent points
       S_HIP(lt::flow_walk(s->flow, s->D.fxf, W, s->D.step, s->D.k0, s->D.k1, s->D.walk, s->D.fy, s->D.fqy, s->D.fqx,
-                          st));
+                          st, s->D.fgate));
     } else {
-      S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st));
-      S_HIP(lt::flow_logq(s->flow, s->D.fxf, W, s->D.fqx, st));
+      // the flow's kernels return at once in a step that the gate leaves without the move
+      S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st, s->D.fgate));
+      S_HIP(lt::flow_logq(s->flow, s->D.fxf, W, s->D.fqx, st, s->D.fgate));
     }
     hipLaunchKernelGGL(k_flow_prep, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());
@@ -432,6 +448,7 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
   D.fold_i = -1;
   D.walk = 0.0;
   D.p_flow = 1.0;
+  D.fexcl = 0;
   D.fold_p = 1.0;
   D.fold_c0 = 0.0;
   D.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
@@ -612,6 +629,19 @@ lt_status lt_flow_set_mix(lt_sampler* s, double p_flow) {
   s->exec = nullptr;
   s->graph = nullptr;
   s->D.p_flow = p_flow;
+  return LT_OK;
+}
+
+lt_status lt_sampler_set_flow_exclusive(lt_sampler* s, int on) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  if (on != 0 && on != 1) return sfail(LT_ERR_CONFIG, "exclusive must be 0 or 1");
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->exec = nullptr;
+  s->graph = nullptr;
+  s->D.fexcl = on;
   return LT_OK;
 }
 

@@ -29,3 +29,36 @@ def ess(chain, window=5.0):
     """Effective samples of the worst coordinate: steps x walkers / max tau."""
     x = np.asarray(chain)
     return x.shape[0] * x.shape[1] / float(np.max(autocorr_time(x, window)))
+
+
+def _batches(chain, n_batches):
+    x = np.asarray(chain, dtype=np.float64)
+    L = x.shape[0] // n_batches
+    if L < 1:
+        raise ValueError("fewer steps than batches")
+    return x[:L * n_batches].reshape(n_batches, L, *x.shape[1:])
+
+
+def batch_ess(chain, n_batches=20):
+    """Effective samples per coordinate from batch means of the whole ensemble: the chain
+    [steps][walkers][dim] is cut into n_batches runs of consecutive steps, each run's mean over
+    all its steps and walkers is one batch mean, and ESS = n_batches var(x) / var(batch means).
+    Unlike autocorr_time, which removes each walker's own mean, this sees correlation between
+    walkers (a coupled ensemble, or one that drifts as a whole) as well as along the chain.
+    Capped at the number of samples."""
+    b = _batches(chain, n_batches)
+    bm = b.mean(axis=(1, 2))
+    var_x = b.reshape(-1, b.shape[-1]).var(axis=0)
+    var_bm = bm.var(axis=0, ddof=1)
+    n = b.shape[0] * b.shape[1] * b.shape[2]
+    return np.minimum(n_batches * var_x / np.maximum(var_bm, 1e-300), n)
+
+
+def batch_quantile_se(chain, qs=(0.05, 0.5, 0.95), n_batches=20):
+    """Quantiles of each coordinate's marginal [len(qs)][dim] and their Monte-Carlo standard
+    errors from the spread of the same quantiles over n_batches runs of consecutive steps."""
+    x = np.asarray(chain, dtype=np.float64)
+    b = _batches(x, n_batches)
+    q = np.quantile(x.reshape(-1, x.shape[-1]), qs, axis=0)
+    qb = np.stack([np.quantile(bb.reshape(-1, bb.shape[-1]), qs, axis=0) for bb in b])
+    return q, qb.std(axis=0, ddof=1) / np.sqrt(n_batches)

@@ -310,6 +310,46 @@ def test_sampler_flow_mix_parity(lib, p_flow):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("T", [1, 2])
+def test_sampler_flow_exclusive_parity(lib, T):
+    """P37: on the flow move's steps the cold rung skips its stretch moves; the GPU chain, the
+    stretch, swap and flow counts match the oracle's step by step."""
+    d, W, seed = 4, 16, 4243
+    rng = np.random.default_rng(11)
+    A = rng.normal(size=(d, d))
+    icov = np.linalg.inv(A @ A.T + d * np.eye(d))
+    means = rng.normal(size=(1, d))
+    lo, hi = -30 * np.ones(d), 30 * np.ones(d)
+    P = fl.init_params(d, 4, 32, 3)
+    mu, sig = means[0] + 0.3, np.linspace(1.2, 2.2, d)
+    start = means[0] + rng.normal(size=(T, W, d))
+    fg = lib.Flow(d, 4, 32, W)
+    fg.set_params(lib.flow_pack(P), mu, sig)
+    g = lib.Sampler(W, T, d, lo, hi, seed, target="gauss", param_kind="raw", t_max=5.0, means=means, icov=icov)
+    g.set_flow(fg)
+    g.set_flow_mix(0.5)
+    g.set_flow_exclusive(True)
+    g.set_state(start)
+    o = PTSampler(gaussian_logl(means, icov), lo, hi, W, T, d, seed, t_max=5.0)
+    o.set_flow(P, mu, sig)
+    o.set_flow_mix(0.5)
+    o.set_flow_exclusive(True)
+    o.set_state(start)
+    for s in range(40):
+        g.step(1)
+        o.step()
+        pos, logl, _, step, cnt = g.state()
+        assert np.max(np.abs(pos - o.X)) < 1e-12 * (1 + np.max(np.abs(o.X))), s
+        assert (cnt[0], cnt[1], cnt[2]) == (o.acc, o.prop, o.sacc), s
+        assert g.flow_counts() == (o.facc, o.fprop), s
+    assert 0 < o.flow_steps < 40 and o.prop == 40 * T * W - o.flow_steps * W
+    with pytest.raises(lib.LisaTDError):
+        lib._check(lib._lib.lt_sampler_set_flow_exclusive(g.h, 2))
+    g.close()
+    fg.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("T", [1, 3])
 def test_sampler_flow_fold_parity(lib, T):
     """P29: flow move with the symmetry fold (copies drawn from Philox, -ln n corrections,

@@ -299,3 +299,34 @@ def test_flow_mix_keeps_the_target():
         a.step()
         b.step()
     assert np.array_equal(a.X, b.X) and b.fprop == 0
+
+
+def test_flow_exclusive_keeps_the_target():
+    """P37: on the steps that run the flow move, the flow move replaces the cold rung's stretch
+    moves (the hotter rungs keep theirs): the cold chain still samples the target with a
+    mismatched flow, and exactly the cold rows of the flow steps go unproposed."""
+    rng = np.random.default_rng(6)
+    d, W, T = 2, 32, 2
+    C = np.array([[1.0, 0.5], [0.5, 0.8]])
+    m = np.array([0.4, -0.6])
+    start = m + rng.multivariate_normal(np.zeros(d), C, size=(T, W))
+    s = PTSampler(gaussian_logl(m, np.linalg.inv(C)), [-40] * d, [40] * d, W, T, d, seed=23, t_max=4.0)
+    s.set_state(start)
+    s.set_flow(_identity_flow(d), m + np.array([0.7, -0.5]), np.array([1.4, 1.3]))
+    s.set_flow_mix(0.5)
+    s.set_flow_exclusive(True)
+    chain = []
+    n = 3000
+    for i in range(n):
+        s.step()
+        if i >= 200:
+            chain.append(s.X[0].copy())
+    chain = np.array(chain)
+    flat = chain.reshape(-1, d)
+    tau = integrated_time(chain).max()
+    err = np.sqrt(np.diag(C) / (flat.shape[0] / tau))
+    assert np.all(np.abs(flat.mean(0) - m) < 5 * err)
+    assert np.allclose(np.cov(flat.T), C, atol=0.1)
+    assert abs(s.flow_steps / n - 0.5) < 4 * math.sqrt(0.25 / n)
+    assert s.prop == n * T * W - s.flow_steps * W
+    assert s.fprop == W * s.flow_steps and 0 < s.facc < s.fprop
