@@ -73,6 +73,33 @@ template <typename R, int RAD> __device__ inline void dft(C2<R>* v) {
     v[1] = e[1] + t1; v[5] = e[1] - t1;
     v[2] = e[2] + t2; v[6] = e[2] - t2;
     v[3] = e[3] + t3; v[7] = e[3] - t3;
+  } else if constexpr (RAD == 16) {
+    // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.  A DFT-4 over n1 for each n2, the products
+    // with exp(-2 pi i n2 k1 / 16), a DFT-4 over n2 for each k1
+    const R c1 = (R)0.92387953251128675613, s1 = (R)0.38268343236508977173, h = (R)0.70710678118654752440;
+    C2<R> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = v[4 * n1 + n2];
+      dft<R, 4>(y[n2]);
+    }
+    y[1][1] = cm(y[1][1], C2<R>{c1, -s1});
+    y[1][2] = cm(y[1][2], C2<R>{h, -h});
+    y[1][3] = cm(y[1][3], C2<R>{s1, -c1});
+    y[2][1] = cm(y[2][1], C2<R>{h, -h});
+    y[2][2] = mi(y[2][2]);
+    y[2][3] = cm(y[2][3], C2<R>{-h, -h});
+    y[3][1] = cm(y[3][1], C2<R>{s1, -c1});
+    y[3][2] = cm(y[3][2], C2<R>{-h, -h});
+    y[3][3] = cm(y[3][3], C2<R>{-c1, s1});
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C2<R> z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+      dft<R, 4>(z);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+    }
   }
 }
 
@@ -248,15 +275,16 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
 // writes the outputs in Stockham order into the same LDS buffer, synchronises.
 // LS: distance between consecutive transforms in buf (>= L; padding avoids LDS bank conflicts);
 // NT: threads of the workgroup
-// PAD8: element i of a series sits at i + i / 8 (one spare slot per eight elements).  A
-// stage with NS < 32 writes each lane's RAD outputs NS elements apart; without the slots,
-// 8-byte elements 8 apart fall on two bank groups of the 32 LDS banks.
-template <bool PAD8>
+// PSH: element i of a series sits at i + (i >> PSH) (one spare slot per 2^PSH elements; 0: no
+// slots).  A stage with NS < 32 writes each lane's RAD outputs NS elements apart, the lanes
+// RAD NS elements apart; without the slots, 8-byte elements 8 (or 16) apart fall on a few
+// bank groups of the 32 LDS banks.
+template <int PSH>
 __device__ inline int lix(int i) {
-  return PAD8 ? i + (i >> 3) : i;
+  return PSH ? i + (i >> PSH) : i;
 }
 
-template <typename R, int L, int NFFT, int RAD, int NS, int LS = L, int NT = kFT, bool PAD8 = false>
+template <typename R, int L, int NFFT, int RAD, int NS, int LS = L, int NT = kFT, int PSH = 0>
 __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
   constexpr int M = L / RAD;
   constexpr int JOBS = NFFT * M;
@@ -271,7 +299,7 @@ __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
       const C2<R>* src = buf + f * LS;
 #pragma unroll
       for (int r = 0; r < RAD; ++r) {
-        v[p][r] = src[lix<PAD8>(j + r * M)];
+        v[p][r] = src[lix<PSH>(j + r * M)];
         if (NS > 1 && r > 0) v[p][r] = cm(v[p][r], tw[r * k * STEP]);
       }
       dft<R, RAD>(v[p]);
@@ -286,7 +314,7 @@ __device__ inline void ct_stage(C2<R>* buf, const C2<R>* tw) {
       C2<R>* dst = buf + f * LS;
       const int d0 = (j / NS) * NS * RAD + k;
 #pragma unroll
-      for (int r = 0; r < RAD; ++r) dst[lix<PAD8>(d0 + r * NS)] = v[p][r];
+      for (int r = 0; r < RAD; ++r) dst[lix<PSH>(d0 + r * NS)] = v[p][r];
     }
   }
   __syncthreads();
@@ -298,10 +326,10 @@ __device__ inline void ct_fft(C2<R>* buf, const C2<R>* tw) {
   if constexpr (sizeof...(REST) > 0) ct_fft<R, L, NFFT, NS * RAD, REST...>(buf, tw);
 }
 
-template <typename R, int L, int LS, int NT, bool PAD8, int NFFT, int NS, int RAD, int... REST>
+template <typename R, int L, int LS, int NT, int PSH, int NFFT, int NS, int RAD, int... REST>
 __device__ inline void ct_fft_strided(C2<R>* buf, const C2<R>* tw) {
-  ct_stage<R, L, NFFT, RAD, NS, LS, NT, PAD8>(buf, tw);
-  if constexpr (sizeof...(REST) > 0) ct_fft_strided<R, L, LS, NT, PAD8, NFFT, NS * RAD, REST...>(buf, tw);
+  ct_stage<R, L, NFFT, RAD, NS, LS, NT, PSH>(buf, tw);
+  if constexpr (sizeof...(REST) > 0) ct_fft_strided<R, L, LS, NT, PSH, NFFT, NS * RAD, REST...>(buf, tw);
 }
 
 // pass 1 for n1 = 512: CB columns (128 bytes of each row) per workgroup.  Column c
@@ -331,12 +359,12 @@ __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* d
 #pragma unroll
     for (int t = 0; t < PT; ++t) {
       const int i = threadIdx.x + t * kP1Threads, j1 = i / CB, jj = i % CB;
-      buf[jj * LP + lix<true>(j1)] = v[t];
+      buf[jj * LP + lix<3>(j1)] = v[t];
     }
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
-  ct_fft_strided<R, N1, LP, kP1Threads, true, CB, 1, 8, 8, 8>(buf, tw);
+  ct_fft_strided<R, N1, LP, kP1Threads, 3, CB, 1, 8, 8, 8>(buf, tw);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   // twiddle tables read for all of this thread's elements before the first product
@@ -351,35 +379,37 @@ __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* d
 #pragma unroll
   for (int t = 0; t < PT; ++t) {
     const int i = threadIdx.x + t * kP1Threads, k1 = i / CB, jj = i % CB;
-    z[(int64_t)k1 * N2 + j2_0 + jj] = cm(buf[jj * LP + lix<true>(k1)], cm(tl[t], th[t]));
+    z[(int64_t)k1 * N2 + j2_0 + jj] = cm(buf[jj * LP + lix<3>(k1)], cm(tl[t], th[t]));
   }
 }
 
-// pass 2 for n2 = 1024: two row pairs (up to four rows) per workgroup.  In FP32 a row keeps a
-// spare LDS slot per eight elements (row stride LS = N2 + N2 / 8 + 1), as in pass 1: the
-// Stockham stages' strided writes then spread over the banks.
-template <typename R>
+// pass 2 for n2 = 1024: NP row pairs (up to 2 NP rows) per workgroup, each row in LDS with
+// spare slots (below) so that the Stockham stages' strided writes spread over the banks.
+template <typename R, int NP>
 __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* data, int mode, double dt,
                                                     C2<R>* spec, const double* wperm, double* partial,
                                                     int64_t kb_lo, int64_t kb_hi, const int32_t* skip) {
-  if (skip && skip[blockIdx.y / 3] != 0) return;
-  constexpr int N1 = 512, N2 = 1024, NR = 4;
-  constexpr bool PAD = sizeof(R) == 4;
-  constexpr int LS = PAD ? N2 + N2 / 8 + 1 : N2;
+  const int64_t row = blockIdx.y;
+  if (skip && skip[row / 3] != 0) return;
+  constexpr int N1 = 512, N2 = 1024, NR = 2 * NP;
+  // FP32: stages of radix 16, 8, 8 (three LDS round trips instead of four; a radix-16 butterfly
+  // holds 16 complex values per lane), rows with a spare slot per 16 elements, so that the
+  // first stage's writes (lanes 16 elements apart) and every other access of a 16-lane group
+  // meet distinct bank pairs; FP64 (twice the registers per value): radix 4, 4, 8, 8, no slots
+  constexpr bool R16 = sizeof(R) == 4;
+  constexpr int PSH = R16 ? 4 : (sizeof(R) == 4 ? 3 : 0);
+  constexpr int LS = R16 ? N2 + N2 / 16 : (sizeof(R) == 4 ? N2 + N2 / 8 + 1 : N2);
   constexpr int64_t n = (int64_t)N1 * N2;
   __shared__ C2<R> buf[NR * LS];
   __shared__ int rowk1[NR];
   __shared__ double red[kFT / 64];
-  const int64_t row = blockIdx.y;
-  const int pa = 2 * blockIdx.x;       // pairs pa, pa + 1 (pair index <= N1/2)
+  const int pa = NP * blockIdx.x;      // pairs pa .. pa + NP - 1 (pair index <= N1/2)
   const C2<R>* z = data + row * n;
-  // row slots: 0: pa, 1: N1 - pa, 2: pa + 1, 3: N1 - pa - 1 (-1 where absent / duplicate)
-  if (threadIdx.x == 0) {
-    int r0 = pa, r1 = (N1 - pa) % N1, r2 = pa + 1, r3 = N1 - pa - 1;
-    rowk1[0] = r0;
-    rowk1[1] = (r1 != r0) ? r1 : -1;
-    rowk1[2] = (r2 <= N1 / 2) ? r2 : -1;
-    rowk1[3] = (r2 <= N1 / 2 && r3 != r2) ? r3 : -1;
+  // row slots 2q: pa + q, 2q + 1: N1 - pa - q (-1 where absent or a duplicate)
+  if (threadIdx.x < NP) {
+    const int q = threadIdx.x, a = pa + q, b = (N1 - a) % N1;
+    rowk1[2 * q] = a <= N1 / 2 ? a : -1;
+    rowk1[2 * q + 1] = (a <= N1 / 2 && b != a) ? b : -1;
   }
   __syncthreads();
   {
@@ -395,12 +425,15 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
 #pragma unroll
     for (int m = 0; m < PT; ++m) {
       const int i = threadIdx.x + m * kFT;
-      buf[(i / N2) * LS + lix<PAD>(i % N2)] = v[m];
+      buf[(i / N2) * LS + lix<PSH>(i % N2)] = v[m];
     }
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw2d, p.tw2f);
-  ct_fft_strided<R, N2, LS, kFT, PAD, NR, 1, 4, 4, 8, 8>(buf, tw);
+  if constexpr (R16)
+    ct_fft_strided<R, N2, LS, kFT, PSH, NR, 1, 16, 8, 8>(buf, tw);
+  else
+    ct_fft_strided<R, N2, LS, kFT, PSH, NR, 1, 4, 4, 8, 8>(buf, tw);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   double acc = 0.0;
@@ -429,13 +462,13 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       for (int r = 0; r < NR; ++r) {
         if (!on[r]) continue;
         const int k1 = rowk1[r];
-        const C2<R> Zk = buf[r * LS + lix<PAD>(k2)];
+        const C2<R> Zk = buf[r * LS + lix<PSH>(k2)];
         C2<R> Zm;
         if (k1 == 0) {
-          Zm = buf[r * LS + lix<PAD>((N2 - k2) % N2)];
+          Zm = buf[r * LS + lix<PSH>((N2 - k2) % N2)];
         } else {
           const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
-          Zm = buf[rm * LS + lix<PAD>(N2 - 1 - k2)];
+          Zm = buf[rm * LS + lix<PSH>(N2 - 1 - k2)];
         }
         const C2<R> zc = {Zm.x, -Zm.y};
         const C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
@@ -464,12 +497,12 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       k1 = rowk1[r];
       if (k1 < 0) continue;
       k = k1 + (int64_t)N1 * k2;
-      Zk = buf[r * LS + lix<PAD>(k2)];
+      Zk = buf[r * LS + lix<PSH>(k2)];
       if (k1 == 0) {
-        Zm = buf[r * LS + lix<PAD>((N2 - k2) % N2)];
+        Zm = buf[r * LS + lix<PSH>((N2 - k2) % N2)];
       } else {
         const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
-        Zm = buf[rm * LS + lix<PAD>(N2 - 1 - k2)];
+        Zm = buf[rm * LS + lix<PSH>(N2 - 1 - k2)];
       }
     } else {
       if (pa != 0) continue;
@@ -493,12 +526,17 @@ __global__ __launch_bounds__(kFT) void k_pass2_1024(FftPlanDev p, const C2<R>* d
       double t = 0.0;
       for (int i = 0; i < kFT / 64; ++i) t += red[i];
       partial[row * (N1 / 2 + 1) + pa] = t;
-      if (pa + 1 <= N1 / 2) partial[row * (N1 / 2 + 1) + pa + 1] = 0.0;
+      for (int q = 1; q < NP; ++q)
+        if (pa + q <= N1 / 2) partial[row * (N1 / 2 + 1) + pa + q] = 0.0;
     }
   }
 }
 
 static bool hot_plan(const FftPlanDev& p) { return p.n1 == 512 && p.n2 == 1024; }
+// row pairs per pass-2 workgroup (one pair, or four, ran 15 % and 30 % slower on the bench
+// workload; ordering the rows channel by channel, so that concurrent workgroups share one
+// channel's weights, changed nothing)
+constexpr int kP2Pairs = 2;
 
 template <typename R>
 static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, const int32_t* skip, hipStream_t s) {
@@ -529,9 +567,10 @@ static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mo
                      const double* wperm, int64_t ch_rows, double* partial, int64_t kb_lo, int64_t kb_hi,
                      const int32_t* skip, hipStream_t s) {
   if (hot_plan(p)) {
-    dim3 grid((unsigned)((p.n1 / 2 + 2) / 2), (unsigned)rows);
-    hipLaunchKernelGGL(k_pass2_1024<R>, grid, dim3(kFT), 0, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
-                       partial, kb_lo, kb_hi, skip);
+    constexpr int NP = kP2Pairs;
+    dim3 grid((unsigned)((p.n1 / 2 + NP) / NP), (unsigned)rows);
+    hipLaunchKernelGGL((k_pass2_1024<R, NP>), grid, dim3(kFT), 0, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec,
+                       wperm, partial, kb_lo, kb_hi, skip);
     return hipGetLastError();
   }
   size_t bytes = 4 * (size_t)p.n2 * sizeof(C2<R>);

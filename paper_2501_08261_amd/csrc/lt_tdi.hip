@@ -248,7 +248,11 @@ constexpr int kNodeRec = kNodeVals + 2;
 // degrees from the arms over the tile) the quotients P = N / (1 - k.n) are smooth enough to be
 // interpolated themselves.
 constexpr double kSmoothKn = 0.02;
-__constant__ int kRecv[6] = {1, 2, 0, 2, 0, 1};     // receiver spacecraft (0-based) of links 1,2,3,-1,-2,-3
+// receiver spacecraft (0-based) of links 1, 2, 3, -1, -2, -3; a compile-time function, so that in
+// the unrolled link loops the receiver's interpolated h is picked by register, not by a select
+__host__ __device__ constexpr int recv_sc(int li) {
+  return li == 0 ? 1 : li == 1 ? 2 : li == 2 ? 0 : li == 3 ? 2 : li == 4 ? 0 : 1;
+}
 __constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacecraft 1, 2, 3
 
 // ------------------------------------------------------- response geometry per (template, orbit node)
@@ -667,7 +671,7 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
           }
           R hps, hxs;
           lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
-          const int rc = kRecv[li];
+          const int rc = recv_sc(li);
           yb[li * MYP + mi] = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
         }
       } else {
@@ -692,7 +696,7 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
           }
           R hps, hxs;
           lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
-          const int rc = kRecv[li];
+          const int rc = recv_sc(li);
           const R num = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
           if constexpr (sizeof(R) == 4)
             yb[li * MYP + mi] = num * __builtin_amdgcn_rcpf(v3);
