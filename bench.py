@@ -63,6 +63,10 @@ def parse():
                     help="also measure ESS/s on the precessing 14-D posterior (slow to equilibrate)")
     ap.add_argument("--p-flow", type=float, default=1.0,
                     help="fraction of sampler steps that run the flow move in the ESS measurements")
+    ap.add_argument("--ess-only", choices=["aligned", "precessing"], default=None,
+                    help="only run the ESS/s measurement of learned against plain proposals on that posterior")
+    ap.add_argument("--flow-train", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS Adam steps of the flow (14-D, 8 couplings, width 256, batch 2048)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known traffic) to calibrate HBM counters")
     return ap.parse_args()
@@ -534,12 +538,41 @@ def mixed_vs_fp64(lib, inputs, ctx, g, P, modes, orb, tdi, S, coarse):
                                                float(np.max(a64[nb + 1:] - 0.5 * ddv))]}
 
 
+def flow_train_bench(lib, steps, d=14, layers=8, hidden=256, batch=2048):
+    """Adam steps of the flow on 20,000 standard-normal rows: ms per step and the matrix-core
+    rate of its GEMMs (flow_gemm_flops per row)."""
+    import numpy as np
+    import torch
+    f = lib.Flow(d, layers, hidden, batch)
+    f.set_params(lib.flow_init_params(d, layers, hidden, 3), np.zeros(d), np.ones(d))
+    x = torch.tensor(np.random.default_rng(0).standard_normal((20000, d)), device="cuda:0")
+    f.train(x, 20, batch, 3e-4)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    f.train(x, steps, batch, 3e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    f.close()
+    return {"flow_train_ms_per_step": 1e3 * dt, "steps": steps, "batch": batch, "dim": d, "layers": layers,
+            "hidden": hidden, "tflops": flow_gemm_flops(d, layers, hidden) * batch / dt / 1e12}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if a.flow_train > 0:
+        from paper_2501_08261_amd import lib
+        print(json.dumps(flow_train_bench(lib, a.flow_train)))
+        return
+    if a.ess_only:
+        from paper_2501_08261_amd import inputs, lib
+        prec = lib.LT_MIXED if a.precision == "mixed" else lib.LT_FP64
+        r = ess_bench(lib, inputs, prec, precessing=a.ess_only == "precessing", p_flow=a.p_flow)
+        print(json.dumps(r, default=float))
+        return
     import numpy as np
     import torch
     from paper_2501_08261_amd import inputs, lib
