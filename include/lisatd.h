@@ -239,7 +239,9 @@ lt_status lt_rfft(lt_ctx* ctx, const void* x, int64_t rows, int64_t n, double dt
 
 /* Analytic PSD of Eqs. (2.14)-(2.15) (readings: x = 2 pi f L / c,
  * acceleration noise 2.4e-15 m s^-2 / sqrt(Hz), TDI 2.0 factor 4 sin^2(2x)) on
- * the rfft grid of `grid`; bin 0 is set to +inf.  S: device FP64 [3][n/2+1]. */
+ * the rfft grid of `grid`; bin 0 is set to +inf.  S: device FP64 [3][n/2+1].  A set-up
+ * call: the spectra are computed on the host and copied on `stream`, and the call returns
+ * after the copy (it synchronises the stream). */
 lt_status lt_psd_sangria(const lt_grid* grid, int generation, double arm_m, double* S, void* stream);
 
 /* Per-kernel timing for benchmarks: when enabled, the library records HIP
