@@ -194,7 +194,9 @@ lt_status lt_lisa_tdi_response(lt_ctx* ctx, const double* params, int64_t batch,
  * smaller than a single template's needs is LT_ERR_WORKSPACE.  With
  * workspace = null the context keeps its own scratch, grown on demand (growth
  * synchronises the device before the old block is freed) to chunks of 256:
- * 5 series of n samples per template plus the tables.  The workspace, like the
+ * 5 series of n samples per template of a chunk plus the tables, and the set-up
+ * constants of every template of the call (624 bytes and a status word each; they are
+ * computed for the whole batch in one launch).  The workspace, like the
  * context's scratch, is in use until the stream reaches the end of the call:
  * calls sharing a workspace or a context must be ordered (same stream, or
  * synchronised by the caller). */
@@ -210,8 +212,8 @@ lt_status lt_tdi_loglike(lt_ctx* ctx, const double* params, int64_t batch, const
  * nothing and records no events; the FFT plan and orbit node table for (grid, orbit) must
  * already be in the context (any lt_tdi_loglike call with them builds both), else
  * LT_ERR_CONFIG.  Templates run in chunks that fit the scratch (at 2^20 samples four in mixed
- * precision, two in FP64); a grid whose single template does not fit returns
- * LT_ERR_WORKSPACE before any launch.  Every call on a GPU uses that GPU's one scratch, so
+ * precision, two in FP64, beside the set-up constants of the whole batch); a batch and grid
+ * for which chunks of one template do not fit return LT_ERR_WORKSPACE before any launch.  Every call on a GPU uses that GPU's one scratch, so
  * calls that overlap on one GPU (different streams or contexts, unsynchronised) race and give
  * wrong results: order them. */
 lt_status lt_tdi_loglike_noalloc(lt_ctx* ctx, const double* params, int64_t batch, const lt_wf_cfg* cfg,
@@ -221,7 +223,8 @@ lt_status lt_tdi_loglike_noalloc(lt_ctx* ctx, const double* params, int64_t batc
 
 /* Workspace of lt_tdi_loglike for `batch` templates with this configuration:
  * bytes (nullable) for full-size chunks (min(batch, 256) templates per chunk),
- * min_bytes (nullable) for chunks of one template.  Host only; no device work. */
+ * min_bytes (nullable) for chunks of one template (both include the set-up constants of all
+ * `batch` templates).  Host only; no device work. */
 lt_status lt_workspace_size(lt_ctx* ctx, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* grid,
                             const lt_tdi_cfg* tdi, size_t* bytes, size_t* min_bytes);
 

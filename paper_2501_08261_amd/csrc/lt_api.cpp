@@ -778,8 +778,8 @@ static lt_status band_power(lt_ctx* c, Plan* p, void* series, int64_t rows, int 
 // One block of device memory per lt_tdi_loglike call, carved into the arrays one chunk of
 // templates needs; each array starts on a 256-byte boundary.
 struct LoglikeScratch {
-  TplConst* tpl;      // [chunk] template constants
-  int32_t* status;    // [chunk] when the caller passes no status array
+  TplConst* tpl;      // [batch] template constants (set up for the whole call in one launch)
+  int32_t* status;    // [batch] when the caller passes no status array
   double* wperm;      // [3][n + 1] band weights in pass-2 order
   void* work;         // [chunk][3][n] residual, transformed in place
   double* partial;    // [chunk][3][n1/2 + 1] band partial sums
@@ -790,13 +790,14 @@ struct LoglikeScratch {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// bytes of the scratch for chunks of `chunk` templates, and (base != null) the arrays within it
-static size_t loglike_layout(int64_t chunk, const lt_wf_cfg* cfg, const lt_grid* g, const lt_tdi_cfg* t, int nfold,
-                             unsigned char* base, LoglikeScratch* out) {
+// bytes of the scratch of a call over `batch` templates in chunks of `chunk`, and (base != null)
+// the arrays within it
+static size_t loglike_layout(int64_t chunk, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
+                             const lt_tdi_cfg* t, int nfold, unsigned char* base, LoglikeScratch* out) {
   const size_t rsz = cfg->precision == LT_FP64 ? sizeof(double) : sizeof(float);
   size_t nb = 0, rb = 0;
   tdi_table_bytes(chunk, cfg, g, t, &nb, &rb);
-  const size_t parts[8] = {(size_t)chunk * sizeof(TplConst), (size_t)chunk * sizeof(int32_t),
+  const size_t parts[8] = {(size_t)batch * sizeof(TplConst), (size_t)batch * sizeof(int32_t),
                            (size_t)3 * (g->n + 1) * sizeof(double), (size_t)chunk * 3 * g->n * rsz,
                            (size_t)chunk * 3 * nfold * sizeof(double), (size_t)chunk * 2 * g->n * rsz, nb, rb};
   size_t off[8], total = 0;
@@ -821,11 +822,11 @@ static size_t loglike_layout(int64_t chunk, const lt_wf_cfg* cfg, const lt_grid*
 static int64_t loglike_chunk_for(size_t bytes, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
                                  const lt_tdi_cfg* t, int nfold, int64_t cap) {
   int64_t hi = batch < cap ? batch : cap;
-  if (loglike_layout(hi, cfg, g, t, nfold, nullptr, nullptr) <= bytes) return hi;
+  if (loglike_layout(hi, batch, cfg, g, t, nfold, nullptr, nullptr) <= bytes) return hi;
   int64_t lo = 0;   // invariant: layout(lo) fits (or lo = 0), layout(hi) does not
   while (hi - lo > 1) {
     const int64_t mid = (lo + hi) / 2;
-    if (loglike_layout(mid, cfg, g, t, nfold, nullptr, nullptr) <= bytes) lo = mid;
+    if (loglike_layout(mid, batch, cfg, g, t, nfold, nullptr, nullptr) <= bytes) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -868,22 +869,22 @@ static lt_status loglike_run(lt_ctx* c, const double* params, int64_t batch, con
   st = band_bins(g, psd, &k_lo, &k_hi);
   if (st) return st;
   LoglikeScratch w;
-  loglike_layout(chunk, cfg, g, t, nfold, base, &w);
+  loglike_layout(chunk, batch, cfg, g, t, nfold, base, &w);
   const double scale = 4.0 * g->dt / (double)g->n;
+  int32_t* stat_all = status ? status : w.status;
   {
-    Prof pr(c, 0, s);   // per-call table, timed with the setup
+    Prof pr(c, 0, s);   // per-call table and set-up
     LT_HIP(launch_weights(p->dev, psd->S, k_lo, k_hi, t->channels, w.wperm, s));
+    // every template's constants in one launch: a thread's set-up is a long serial FP64 chain,
+    // so one launch per chunk would pay that latency once per chunk
+    LT_HIP(launch_setup(params, batch, cfg->f_low, cfg->f_ref, gdev(g), w.tpl, stat_all, s));
   }
   // one stream, chunks of templates: the response kernel already fills the GPU, and running a
   // chunk's FFT beside the next chunk's response on a second stream measured no faster than this
   for (int64_t off = 0; off < batch; off += chunk) {
     const int64_t b = batch - off < chunk ? batch - off : chunk;
-    int32_t* stat = status ? status + off : w.status;
-    {
-      Prof pr(c, 0, s);
-      LT_HIP(launch_setup(params + off * 16, b, cfg->f_low, cfg->f_ref, gdev(g), w.tpl, stat, s));
-    }
-    st = run_tdi_core(c, w.tpl, b, cfg, g, od, t, 2, data->aet, w.work, stat, w.wave, w.nodes, w.refs, s);
+    int32_t* stat = stat_all + off;
+    st = run_tdi_core(c, w.tpl + off, b, cfg, g, od, t, 2, data->aet, w.work, stat, w.wave, w.nodes, w.refs, s);
     if (st) return st;
     st = fft_band(c, p, w.work, b * 3, cfg->precision, k_lo, k_hi, g, w.partial, w.wperm, stat, s);
     if (st) return st;
@@ -907,8 +908,8 @@ lt_status lt_workspace_size(lt_ctx* c, int64_t batch, const lt_wf_cfg* cfg, cons
   tdi_table_bytes(1, cfg, g, t, &nb, &rb);
   if (rb == 0) return fail(LT_ERR_UNSUPPORTED, "taps must be one of 2,4,6,8,12,16,24,32");
   const int64_t full = batch < c->tune.chunk ? batch : c->tune.chunk;
-  if (bytes) *bytes = loglike_layout(full, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
-  if (min_bytes) *min_bytes = loglike_layout(1, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
+  if (bytes) *bytes = loglike_layout(full, batch, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
+  if (min_bytes) *min_bytes = loglike_layout(1, batch, cfg, g, t, n1 / 2 + 1, nullptr, nullptr);
   return LT_OK;
 }
 
@@ -927,7 +928,7 @@ lt_status lt_tdi_loglike(lt_ctx* c, const double* params, int64_t batch, const l
     base = (unsigned char*)workspace;
   } else {
     chunk = batch < c->tune.chunk ? batch : c->tune.chunk;
-    LT_HIP(c->ws.ensure(loglike_layout(chunk, cfg, g, t, nfold, nullptr, nullptr)));
+    LT_HIP(c->ws.ensure(loglike_layout(chunk, batch, cfg, g, t, nfold, nullptr, nullptr)));
     base = (unsigned char*)c->ws.p;
   }
   return loglike_run(c, params, batch, cfg, g, o, t, psd, data, logl, logl_full, status, nfold, chunk, base, true, s);
@@ -943,8 +944,8 @@ lt_status lt_tdi_loglike_noalloc(lt_ctx* c, const double* params, int64_t batch,
   if (!c->scratch) return fail(LT_ERR_DEVICE, "no fixed scratch on this device");
   const int64_t chunk = loglike_chunk_for(kFixedScratchBytes, batch, cfg, g, t, nfold, c->tune.chunk);
   if (chunk < 1) {
-    const size_t need = loglike_layout(1, cfg, g, t, nfold, nullptr, nullptr);
-    return fail(LT_ERR_WORKSPACE, "one template of this grid needs " + std::to_string(need) +
+    const size_t need = loglike_layout(1, batch, cfg, g, t, nfold, nullptr, nullptr);
+    return fail(LT_ERR_WORKSPACE, "chunks of one template of this batch and grid need " + std::to_string(need) +
                                       " bytes of scratch, more than the fixed " +
                                       std::to_string(kFixedScratchBytes) + " (use lt_tdi_loglike)");
   }

@@ -36,6 +36,8 @@ struct TplConst {
   double n_start;        // first grid index at or after the f_low start (may be < 0 or > n)
   double pad4[5];
 };
+// include/lisatd.h states this size (per-template scratch of the likelihood)
+static_assert(sizeof(TplConst) == 624, "set-up constants: 78 doubles per template");
 
 struct cplx { double re, im; };
 __device__ __host__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }

@@ -352,15 +352,6 @@ __global__ void k_couple_bwd(double* gu, int n, int d, int b0, int nb, const flo
   }
 }
 
-// g (FP32 [count]) *= (h > 0), BF16 copy
-__global__ void k_relu_bwd(float* g, const float* h, int64_t count, bf16* gb) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const float v = h[i] > 0.0f ? g[i] : 0.0f;
-  g[i] = v;
-  gb[i] = to_bf16(v);
-}
-
 // out[c] = sum_r g[r][c]: a workgroup of 16 wavefronts takes 64 columns (each read is 64
 // consecutive floats); wavefront q sums rows r = 16 i + q into eight running sums (i mod 8, so
 // that eight loads are in flight), which it adds in order; the 16 wavefront sums are then added
