@@ -309,7 +309,7 @@ def train_early_stop(flow, s, mu, L, val_frac=0.25, chunk=250, max_steps=3000, p
 
 
 def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=500, rounds=4, window=400,
-              train_steps=1500, m=1000, walk=0.0, split_modes=True, p_flow=1.0, early_stop=True, pool=1, exclusive=True, control=True):
+              train_steps=1500, m=1000, walk=0.0, split_modes=True, p_flow=1.0, early_stop=True, pool=1, exclusive=True, control=True, reinit=False):
     """Effective samples per second of the cold chain, stretch moves alone against
     stretch + learned-flow moves, on one injection and one GPU (TDI-2 AET, 512
     walkers x 8 temperatures, n samples around the merger, Fisher-initialised).
@@ -333,7 +333,8 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     its latent space (lt_sampler_set_flow_walk).  p_flow < 1 runs the flow move on that
     fraction of the steps once the flow is attached (lt_flow_set_mix); the others run the
     stretch moves and swaps alone.  exclusive: the flow's steps skip the cold rung's stretch
-    moves (lt_sampler_set_flow_exclusive).  control: also compare two plain chains.  Posterior accuracy: the largest gap between the two
+    moves (lt_sampler_set_flow_exclusive).  control: also compare two plain chains.  reinit:
+    each round trains a freshly initialised flow instead of continuing the last one.  Posterior accuracy: the largest gap between the two
     chains' 5 / 50 / 95 % quantiles in units of its Monte-Carlo error (quantile_gap)."""
     import numpy as np
     import torch
@@ -383,6 +384,8 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
             mode_frac.append(kept)
         smp.set_flow_fold(ipsi, np.pi, start)
         smp.set_flow_walk(walk)
+        if reinit:
+            flow.set_params(lib.flow_init_params(dim, 8, 256, 3 + r), np.zeros(dim), np.ones(dim))
         if early_stop:
             # whitened by the earlier 3/4 of the window (rows in time order), which it trains on;
             # the latest quarter decides when to stop
