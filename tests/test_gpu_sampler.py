@@ -89,9 +89,13 @@ def test_gpu_gaussian_moments(lib):
     s.close()
 
 
-def test_chain_parity_tdi(lib):
+@pytest.mark.parametrize("flow", [False, True])
+def test_chain_parity_tdi(lib, flow):
     """Two sampler steps on the real likelihood (aligned, static arms, TDI 1.5,
-    K = 2, FP64, 4096 samples) agree with the oracle sampler using the oracle logL."""
+    K = 2, FP64, 4096 samples) agree with the oracle sampler using the oracle logL.
+    flow: with a flow move on every step that takes the place of the cold rung's stretch moves
+    (P37): the cold rung's skipped rows go through the likelihood as unphysical rows."""
+    from oracle import flow as fl
     from paper_2501_08261_amd.lib import Context
     n = 4096
     gr = inputs.grid(n, 5.0)
@@ -131,6 +135,19 @@ def test_chain_parity_tdi(lib):
         return np.array(out)
     o = PTSampler(ologl, lo, hi, W, T, 10, 2024)
     o.set_state(start)
+    fg = None
+    if flow:
+        # identity flow over a Gaussian around the injection a few start widths wide
+        P = fl.init_params(10, 2, 16, 5)
+        sig = 3e-4 * (hi - lo)
+        fg = lib.Flow(10, 2, 16, W)
+        fg.set_params(lib.flow_pack(P), x0, sig)
+        smp.set_flow(fg)
+        smp.set_flow_mix(1.0)
+        smp.set_flow_exclusive(True)
+        o.set_flow(P, x0, sig)
+        o.set_flow_mix(1.0)
+        o.set_flow_exclusive(True)
     _, gl, _, _, _ = smp.state()
     tol = 1e-6 + 1e-11 * dd.item()
     assert np.max(np.abs(gl - o.logl)) < tol
@@ -140,7 +157,10 @@ def test_chain_parity_tdi(lib):
         pos, gl, _, _, cnt = smp.state()
         assert np.max(np.abs(pos - o.X) / (hi - lo)) < 1e-12
         assert np.max(np.abs(gl - o.logl)) < tol
-        assert cnt[0] == o.acc
+        assert (cnt[0], cnt[1]) == (o.acc, o.prop)
+    if flow:
+        assert smp.flow_counts() == (o.facc, o.fprop) and o.fprop == 2 * W and o.prop == 2 * (T - 1) * W
+        fg.close()
     smp.close()
     ctx.close()
 
