@@ -179,11 +179,32 @@ __device__ inline int stencil_start(double fl, int len) {
 // FP32: explicit weights first.  Its partial sums start at c_0 y_0, and with
 // c_0 = 1/(K-1)! ~ 1e-34 at K = 32 and strain-sized y ~ 1e-21 that product
 // is below the FP32 range; the weights themselves are O(1).
-template <typename R, int K>
+// ysh > 0: element i of the series sits at a[i + (i >> ysh)] (the padded link series of the
+// FP64 response kernel)
+template <int YSH>
+__device__ inline int ypos(int i) {
+  return YSH ? i + (i >> YSH) : i;
+}
+
+template <typename R, int K, int YSH = 0>
 __device__ inline R lag1(const R* a, int len, double s) {
   double fl = floor(s);
   const R f = (R)(s - fl);
-  const R* p = a + stencil_start<K>(fl, len);
+  const int j0 = stencil_start<K>(fl, len);
+  if constexpr (YSH > 0) {
+    // FP64 product form (see below) over the padded series
+    constexpr LagDen<K> den;
+    R P = f - (R)(-K / 2 + 1);
+    R S = (R)den.inv[0] * a[ypos<YSH>(j0)];
+#pragma unroll
+    for (int i = 1; i < K; ++i) {
+      const R d = f - (R)(i - K / 2 + 1);
+      S = S * d + (R)den.inv[i] * a[ypos<YSH>(j0 + i)] * P;
+      P *= d;
+    }
+    return S;
+  }
+  const R* p = a + j0;
   if (sizeof(R) == 4) {
     R w[K];
     lag_weights<R, K>(f, w);
@@ -555,10 +576,15 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
   // shortest TDI delays reach K/2 - 1 samples past the last output sample
   const int MY = kTile + HY + K / 2 + 1;
   const int MYP = (MY + kYPad + 3) & ~3;   // multiple of 4: aligned vector reads in phase D
+  // FP64: a spare slot after every 16 samples of a link series.  Phase D's per-term reads have
+  // lanes four samples (32 bytes) apart, which without the slots put four lanes of a 16-lane
+  // group on each bank pair; with them the 16 lanes meet 16 different pairs
+  constexpr int YSH = sizeof(R) == 8 ? 4 : 0;
+  const int MYR = MYP + (YSH ? MYP >> YSH : 0);   // row stride of the link series in LDS
   R* yb = (R*)smem;
-  R* hpb = yb + 6 * MYP;
+  R* hpb = yb + 6 * MYR;
   R* hxb = hpb + WMAX;
-  double* nd = (double*)(smem + (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15));
+  double* nd = (double*)(smem + (((size_t)(6 * MYR + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15));
   // FP32 copies of the node geometry (mixed precision: it scales an FP32 product): P+, Px per
   // link (12 per node) where the tile is smooth, else N+, Nx, 1 - k.n (18 per node)
   float* ndp = (float*)(nd + NNMAX * kNodeVals);
@@ -644,7 +670,7 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
       int64_t m = m_lo + mi;
       if (m < 0 || m >= N) {
 #pragma unroll
-        for (int li = 0; li < 6; ++li) yb[li * MYP + mi] = (R)0;
+        for (int li = 0; li < 6; ++li) yb[li * MYR + ypos<YSH>(mi)] = (R)0;
         continue;
       }
       const double* o0 = nd + (jl0 + it - 1) * kNodeVals;
@@ -672,7 +698,7 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
           R hps, hxs;
           lag2<R, K>(hpb, hxb, W, mloc - v2 * inv_dt, hps, hxs);
           const int rc = recv_sc(li);
-          yb[li * MYP + mi] = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
+          yb[li * MYR + ypos<YSH>(mi)] = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
         }
       } else {
 #pragma unroll
@@ -699,14 +725,15 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
           const int rc = recv_sc(li);
           const R num = v0 * (hps - hpr[rc]) + v1 * (hxs - hxr[rc]);
           if constexpr (sizeof(R) == 4)
-            yb[li * MYP + mi] = num * __builtin_amdgcn_rcpf(v3);
+            yb[li * MYR + ypos<YSH>(mi)] = num * __builtin_amdgcn_rcpf(v3);
           else
-            yb[li * MYP + mi] = num / v3;
+            yb[li * MYR + ypos<YSH>(mi)] = num / v3;
         }
       }
     }
     // zero the tail of each y series up to its padded length: filter taps beyond the data read it
-    for (int i = tid; i < 6 * (MYP - MY); i += kNT) yb[(i / (MYP - MY)) * MYP + MY + (i % (MYP - MY))] = (R)0;
+    for (int i = tid; i < 6 * (MYP - MY); i += kNT)
+      yb[(i / (MYP - MY)) * MYR + ypos<YSH>(MY + (i % (MYP - MY)))] = (R)0;
     __syncthreads();
   }
 
@@ -750,7 +777,8 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
         for (int g = 0; g < P.terms.n_groups[cc]; ++g) {
           const int gi = (cc * 4 + g) * kNV + vw;
           const int J = gjs[kGroups * kNV + gi];
-          const R* yl = yb + P.terms.g_link[cc][g] * MYP + gjs[gi] + dn0;
+          static_assert(!TAY || YSH == 0, "combined filters read unpadded series");
+          const R* yl = yb + P.terms.g_link[cc][g] * MYR + gjs[gi] + dn0;
           typedef double v4d __attribute__((ext_vector_type(4)));
           typedef const __attribute__((address_space(4))) v4d cd4_t;
           cd4_t* F = (cd4_t*)(crec + Lay::fd + (size_t)gi * JMAX * sizeof(double));
@@ -812,12 +840,12 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
       for (int t = 0; t < P.terms.n_terms[cc]; ++t) {
         const Term& tm = P.terms.t[cc][t];
         const int e = (cc * 16 + t) * kNV + v;
-        const R* yl = yb + tm.link * MYP;
+        const R* yl = yb + tm.link * MYR;
         const int flag = tflag[e];
         R val[4];
         if (flag == 2) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) val[k] = yl[nb + k - m_lo];
+          for (int k = 0; k < 4; ++k) val[k] = yl[ypos<YSH>((int)(nb + k - m_lo))];
         } else {
           R dl[4];
           if (TAY) {
@@ -832,7 +860,7 @@ __device__ __forceinline__ void tdi_item(const TdiLaunch& P, int HY, int WMAX, i
           const int jb = tjr[e] + (int)(nb - nref);
           const double f0 = tf0[e];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) val[k] = lag1<R, K>(yl, MY, (double)(jb + k) + (f0 - (double)dl[k]));
+          for (int k = 0; k < 4; ++k) val[k] = lag1<R, K, YSH>(yl, MY, (double)(jb + k) + (f0 - (double)dl[k]));
         }
         if (tm.sign > 0) {
 #pragma unroll
@@ -931,7 +959,8 @@ struct TdiGeom {
     if (P.orb.spacing * kNV != kTile) return hipErrorInvalidValue;
     if (!P.nodes || !P.refs) return hipErrorInvalidValue;
     constexpr int JMAX = CombLen<K>::value;
-    bytes = (((size_t)(6 * MYP + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) + (size_t)NNMAX * kNodeVals * sizeof(double) +
+    const int MYR = MYP + (sizeof(R) == 8 ? MYP / 16 : 0);   // padded link series (FP64)
+    bytes = (((size_t)(6 * MYR + 2 * WMAX) * sizeof(R) + 15) & ~(size_t)15) + (size_t)NNMAX * kNodeVals * sizeof(double) +
             (sizeof(R) == 4 ? (size_t)NNMAX * 18 * sizeof(float) : 0);
     if (bytes > 160 * 1024) return hipErrorInvalidValue;
     // combined filters: a group spans its delay range plus one stencil plus up to 3 alignment taps
