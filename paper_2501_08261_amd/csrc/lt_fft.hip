@@ -337,10 +337,13 @@ __device__ inline void ct_fft_strided(C2<R>* buf, const C2<R>* tw) {
 // elements, plus one): the 16 lanes that move one 128-byte row segment then touch 16
 // different bank pairs instead of one.
 constexpr int kP1Pad = 512 / 8 + 1;
+// bytes of each row per workgroup (64 and 256 ran 2.21 and 1.89 ms against 1.59 on the bench
+// workload: narrower segments waste the memory bursts, wider ones leave one workgroup per CU)
+constexpr int kP1Bytes = 128;
 constexpr int kP1Threads = 512;   // 2 workgroups of 65.7 KB fit a CU: 16 waves
 template <typename R>
 __global__ __launch_bounds__(kP1Threads) void k_pass1_512(FftPlanDev p, C2<R>* data, const int32_t* skip) {
-  constexpr int N1 = 512, N2 = 1024, CB = 128 / (int)sizeof(C2<R>), LP = N1 + kP1Pad;
+  constexpr int N1 = 512, N2 = 1024, CB = kP1Bytes / (int)sizeof(C2<R>), LP = N1 + kP1Pad;
   extern __shared__ __align__(16) unsigned char smem[];
   C2<R>* buf = (C2<R>*)smem;      // [CB][LP]
   const int64_t row = blockIdx.y;
@@ -541,7 +544,7 @@ constexpr int kP2Pairs = 2;
 template <typename R>
 static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, const int32_t* skip, hipStream_t s) {
   if (hot_plan(p)) {
-    constexpr int CB = 128 / (int)sizeof(C2<R>);
+    constexpr int CB = kP1Bytes / (int)sizeof(C2<R>);
     const int bytes = CB * (512 + kP1Pad) * (int)sizeof(C2<R>);
     hipError_t e = hipFuncSetAttribute((const void*)k_pass1_512<R>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
