@@ -59,8 +59,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--no-sampler", action="store_true", help="skip the sampler-step and ESS measurements")
-    ap.add_argument("--ess-precessing", action="store_true",
-                    help="also measure ESS/s on the precessing 14-D posterior (slow to equilibrate)")
+    ap.add_argument("--no-ess-precessing", action="store_true",
+                    help="skip the ESS/s measurement on the precessing 14-D posterior (the C4 injection)")
     ap.add_argument("--p-flow", type=float, default=1.0,
                     help="fraction of sampler steps that run the flow move in the ESS measurements")
     ap.add_argument("--ess-only", choices=["aligned", "precessing"], default=None,
@@ -718,7 +718,7 @@ def main():
     ctx.close()
     if not a.no_sampler:
         runs = [("sampler", sampler_bench, {}), ("ess", ess_bench, {"p_flow": a.p_flow})]
-        if a.ess_precessing:
+        if not a.no_ess_precessing:
             runs.append(("ess_precessing", ess_bench, {"precessing": True, "p_flow": a.p_flow}))
         for key, fn, kw in runs:
             try:
