@@ -38,6 +38,12 @@ of the GPU sampler:
   cold rung (its rows are neither proposed nor counted): the cold rung's kernel on that
   step is then the flow move alone, again a state-independent choice between kernels
   that keep the target;
+* optional mixture of two flows (one per mode of a two-mode posterior): the proposal
+  density is q = w1 q1 + (1 - w1) q2.  Each walker draws its component, flow 1 when
+  u < w1 with u from counter (step, 0x900, walker, 0); both flows map the same base
+  normals, and the walker takes its component's point.  log q of the proposal and of
+  the current (folded) position is the mixture's, log(w1 q1 + w2 q2) from both flows'
+  forward passes, so the independence acceptance above is the exact one for q;
 * optional latent random walk in place of the independence proposal:
   z = f(x) (the flow's forward map of the folded position), z' = z + w eps,
   eps standard normal from counter (step, 0x700, walker, q) like the base
@@ -59,6 +65,7 @@ MASK = 0xFFFFFFFF
 TAG_MOVE, TAG_SHIFT, TAG_SWAP, TAG_FLOWZ, TAG_FLOWU, TAG_FLOWC, TAG_FLOWW = (0x100, 0x200, 0x300, 0x400, 0x500,
                                                                      0x600, 0x700)
 TAG_FLOWG = 0x800
+TAG_FLOWM = 0x900
 
 
 def philox4x32_10(ctr, key):
@@ -129,6 +136,7 @@ class PTSampler:
         self.walk = 0.0
         self.p_flow = 1.0
         self.flow_exclusive = False
+        self.flow2 = None
         self.facc = self.fprop = 0
         self.flow_steps = 0
 
@@ -143,6 +151,23 @@ class PTSampler:
     def set_flow_mix(self, p_flow):
         """Probability that a step runs the flow move (0: the plain sampler)."""
         self.p_flow = float(p_flow)
+
+    def set_flow_mixture(self, P2, mu2, sigma2, w1):
+        """Second flow of a two-component proposal q = w1 q1 + (1 - w1) q2 (None: one flow)."""
+        if P2 is None:
+            self.flow2 = None
+            return
+        if not 0.0 < w1 < 1.0:
+            raise ValueError("w1 must lie in (0, 1)")
+        self.flow2 = (P2, np.asarray(mu2, float), np.asarray(sigma2, float), float(w1))
+
+    def _mix_logq(self, x):
+        """log(w1 q1(x) + w2 q2(x)) of folded points x."""
+        P, mu, sigma = self.flow
+        P2, mu2, sigma2, w1 = self.flow2
+        _, l1 = _flow.forward(P, x, mu, sigma)
+        _, l2 = _flow.forward(P2, x, mu2, sigma2)
+        return np.logaddexp(math.log(w1) + l1, math.log(1.0 - w1) + l2)
 
     def set_flow_exclusive(self, on):
         """On steps that run the flow move, skip the cold rung's stretch moves."""
@@ -199,7 +224,18 @@ class PTSampler:
             xf[:, i] = c0 + ((x - c0) - Pf * np.floor((x - c0) / Pf))
             _, nx = self._copies(xf[:, i], i, Pf)
             lkx = np.where(nx > 0, np.log(np.maximum(nx, 1).astype(np.float64)), 0.0)
-        if self.walk > 0.0:
+        if self.flow2 is not None:
+            if self.walk > 0.0:
+                raise ValueError("the latent walk takes one flow")
+            P2, mu2, sigma2, w1 = self.flow2
+            z = self.flow_normals(s)
+            y1, _ = _flow.inverse(P, z, mu, sigma)
+            y2, _ = _flow.inverse(P2, z, mu2, sigma2)
+            rc = philox4x32_10(_ctr(s, TAG_FLOWM, np.arange(W)), self.key)
+            y = np.where((u01(rc[:, 0]) < w1)[:, None], y1, y2)
+            lqy = self._mix_logq(y)
+            lqx = self._mix_logq(xf)
+        elif self.walk > 0.0:
             z, lqx = _flow.forward(P, xf, mu, sigma)
             zn = z + self.walk * self.flow_normals(s, TAG_FLOWW)
             lqx = lqx - self._log_normal(z)

@@ -330,3 +330,51 @@ def test_flow_exclusive_keeps_the_target():
     assert abs(s.flow_steps / n - 0.5) < 4 * math.sqrt(0.25 / n)
     assert s.prop == n * T * W - s.flow_steps * W
     assert s.fprop == W * s.flow_steps and 0 < s.facc < s.fprop
+
+
+def _two_mode_run(monkeypatch=None, plant=False, mixture=True, n=2500, seed=31):
+    d, W = 2, 32
+    m = np.array([[-6.0, 0.5], [6.0, -0.5]])
+    icov = np.eye(d)
+    rng = np.random.default_rng(seed)
+    start = m[0] + rng.normal(size=(1, W, d))          # every walker starts in mode 1
+    s = PTSampler(gaussian_logl(m, icov), [-40] * d, [40] * d, W, 1, d, seed=seed)
+    s.set_state(start)
+    s.set_flow(_identity_flow(d), m[0] + 0.2, np.array([1.3, 1.2]))
+    if mixture:
+        s.set_flow_mixture(_identity_flow(d), m[1] - 0.1, np.array([1.2, 1.4]), 0.4)
+    if plant:
+        # a plausible mistake: the proposal density of the component that was drawn only
+        monkeypatch.setattr(PTSampler, "_mix_logq", lambda self, x: flow_forward(self.flow, x))
+    chain = []
+    for i in range(n):
+        s.step()
+        if i >= 300:
+            chain.append(s.X[0].copy())
+    return np.array(chain), m, s
+
+
+def flow_forward(fl_tuple, x):
+    from oracle import flow as fl
+    P, mu, sigma = fl_tuple
+    return fl.forward(P, x, mu, sigma)[1]
+
+
+def test_flow_mixture_keeps_the_target(monkeypatch):
+    """P38: a mixture of two flows, one on each mode of a two-mode Gaussian, as the independence
+    proposal (q = w1 q1 + w2 q2, the component drawn per walker): from a start in one mode the
+    chain holds both modes with their equal weights and the target's moments; one flow alone
+    does not reach the second mode; using the drawn component's density instead of the mixture's
+    biases the weights."""
+    chain, m, s = _two_mode_run()
+    flat = chain.reshape(-1, 2)
+    frac2 = np.mean(flat[:, 0] > 0)
+    assert abs(frac2 - 0.5) < 0.05
+    for k, sel in ((0, flat[:, 0] < 0), (1, flat[:, 0] > 0)):
+        assert np.all(np.abs(flat[sel].mean(0) - m[k]) < 0.08)
+        assert np.allclose(np.cov(flat[sel].T), np.eye(2), atol=0.12)
+    assert 0.3 < s.facc / s.fprop < 0.95
+    one, _, _ = _two_mode_run(mixture=False, n=800)
+    assert np.mean(one.reshape(-1, 2)[:, 0] > 0) < 0.02
+    bad, _, _ = _two_mode_run(monkeypatch, plant=True)
+    assert abs(np.mean(bad.reshape(-1, 2)[:, 0] > 0) - 0.5) > 0.1
