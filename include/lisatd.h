@@ -433,6 +433,16 @@ lt_status lt_flow_set_mix(lt_sampler* s, double p_flow);
  * 0 (the default): both moves run.  Rebuilds the captured step.  Status LT_ERR_CONFIG unless
  * on is 0 or 1. */
 lt_status lt_sampler_set_flow_exclusive(lt_sampler* s, int on);
+/* A second flow for the flow move (second = NULL: one flow again): the independence proposal
+ * becomes the mixture q = w_first q1 + (1 - w_first) q2, for posteriors with two modes (one
+ * flow trained on each).  Each cold walker draws its component, the first flow when u < w_first
+ * with u from Philox counter (step, 0x900, walker, 0); both flows map the step's base normals
+ * and the walker takes its component's point; log q of the proposal and of the current (folded)
+ * position is log(w_first q1 + (1 - w_first) q2), from both flows' forward passes, so the
+ * acceptance above stays exact for q.  Same dimension, device and max_batch >= n_walkers as the
+ * first flow; w_first in (0, 1); not with the latent walk (LT_ERR_CONFIG).  Like the first flow,
+ * the second must outlive the sampler or be detached first.  Rebuilds the captured step. */
+lt_status lt_sampler_set_flow_mixture(lt_sampler* s, lt_flow* second, double w_first);
 /* Flow moves accepted and proposed since lt_sampler_set_state (host int64 [2]). */
 lt_status lt_sampler_flow_counts(lt_sampler* s, int64_t* counts);
 

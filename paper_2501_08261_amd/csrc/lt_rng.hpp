@@ -28,6 +28,6 @@ __host__ __device__ inline double u01(uint32_t u) { return ((double)u + 0.5) * 2
 
 // purposes (second counter word)
 constexpr uint32_t kTagMove = 0x100, kTagShift = 0x200, kTagSwap = 0x300, kTagFlowZ = 0x400, kTagFlowU = 0x500,
-                   kTagFlowC = 0x600, kTagFlowW = 0x700, kTagFlowG = 0x800;
+                   kTagFlowC = 0x600, kTagFlowW = 0x700, kTagFlowG = 0x800, kTagFlowM = 0x900;
 
 }  // namespace lt_rng

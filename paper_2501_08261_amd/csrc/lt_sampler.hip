@@ -50,6 +50,10 @@ struct Dev {
   double p_flow;            // probability that a step runs the flow move (1: every step)
   int* fgate;               // this step's draw: 1 = the flow move runs
   int fexcl;                // 1: a step that runs the flow move skips the cold rung's stretch moves
+  // mixture of two flows (second flow attached): component weights w1, 1 - w1; the second
+  // flow's proposals and log densities
+  double mw1;
+  double *fy2, *fqy2, *fqx2;
 };
 
 __device__ inline void to_params(const Dev& D, const double* x, double* p) {
@@ -191,6 +195,32 @@ __global__ void k_flow_fold(Dev D) {
   D.flkx[k] = lk;
 }
 
+// mixture proposal: walker k takes the second flow's point when u >= w1, u from counter
+// (step, 0x900, k, 0) (both flows mapped the same base normals)
+__global__ void k_flow_pick(Dev D) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.W || !*D.fgate) return;
+  uint32_t c[4] = {(uint32_t)*D.step, kTagFlowM, (uint32_t)k, 0u};
+  philox4x32_10(c, D.k0, D.k1);
+  if (!(u01(c[0]) < D.mw1))
+    for (int i = 0; i < D.d; ++i) D.fy[(int64_t)k * D.d + i] = D.fy2[(int64_t)k * D.d + i];
+}
+
+// log(w1 q1 + w2 q2) into a, from the two flows' log densities a (first) and b (second)
+__device__ inline double log_mix(double a, double b, double lw1, double lw2) {
+  const double x = lw1 + a, y = lw2 + b;
+  if (x == y) return x + 0.69314718055994530942;
+  return x > y ? x + log1p(exp(y - x)) : y + log1p(exp(x - y));
+}
+
+__global__ void k_flow_mixq(Dev D) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.W || !*D.fgate) return;
+  const double lw1 = log(D.mw1), lw2 = log1p(-D.mw1);
+  D.fqy[k] = log_mix(D.fqy[k], D.fqy2[k], lw1, lw2);
+  D.fqx[k] = log_mix(D.fqx[k], D.fqx2[k], lw1, lw2);
+}
+
 // whether this step runs the flow move: u < p_flow, u from counter (step, 0x800, 0, 0)
 __global__ void k_flow_gate(Dev D) {
   uint32_t c[4] = {(uint32_t)*D.step, kTagFlowG, 0u, 0u};
@@ -319,6 +349,7 @@ struct lt_sampler {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   lt_flow* flow = nullptr;
+  lt_flow* flow2 = nullptr;    // second component of a mixture proposal (nullable)
   void* ws = nullptr;          // likelihood workspace (TDI target), sized for the whole ensemble
   size_t ws_bytes = 0;
 };
@@ -385,6 +416,20 @@ static lt_status record_step(lt_sampler* s, hipStream_t st) {
       // y = f^-1(f(x) + walk eps): fqx, fqy carry log q - log N of the two latent points
       S_HIP(lt::flow_walk(s->flow, s->D.fxf, W, s->D.step, s->D.k0, s->D.k1, s->D.walk, s->D.fy, s->D.fqy, s->D.fqx,
                           st, s->D.fgate));
+    } else if (s->flow2) {
+      // mixture: both flows map the step's base normals, each walker keeps its component's
+      // point, and the mixture density is taken at the proposals and the current positions
+      const unsigned gw = (unsigned)((W + 127) / 128);
+      S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st, s->D.fgate));
+      S_HIP(lt::flow_propose(s->flow2, W, s->D.step, s->D.k0, s->D.k1, s->D.fy2, s->D.fqy2, st, s->D.fgate));
+      hipLaunchKernelGGL(k_flow_pick, dim3(gw), dim3(128), 0, st, s->D);
+      S_HIP(hipGetLastError());
+      S_HIP(lt::flow_logq(s->flow, s->D.fy, W, s->D.fqy, st, s->D.fgate));
+      S_HIP(lt::flow_logq(s->flow2, s->D.fy, W, s->D.fqy2, st, s->D.fgate));
+      S_HIP(lt::flow_logq(s->flow, s->D.fxf, W, s->D.fqx, st, s->D.fgate));
+      S_HIP(lt::flow_logq(s->flow2, s->D.fxf, W, s->D.fqx2, st, s->D.fgate));
+      hipLaunchKernelGGL(k_flow_mixq, dim3(gw), dim3(128), 0, st, s->D);
+      S_HIP(hipGetLastError());
     } else {
       // the flow's kernels return at once in a step that the gate leaves without the move
       S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st, s->D.fgate));
@@ -449,6 +494,7 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
   D.walk = 0.0;
   D.p_flow = 1.0;
   D.fexcl = 0;
+  D.mw1 = 1.0;
   D.fold_p = 1.0;
   D.fold_c0 = 0.0;
   D.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
@@ -464,7 +510,8 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
       (r = salloc(s, &D.sprop, TW)) || (r = salloc(s, &D.fy, (size_t)W * d)) || (r = salloc(s, &D.fqy, W)) ||
       (r = salloc(s, &D.fqx, W)) || (r = salloc(s, &D.fylogl, W)) || (r = salloc(s, &D.fylogp, W)) ||
       (r = salloc(s, &D.facc, W)) || (r = salloc(s, &D.fprop, W)) || (r = salloc(s, &D.fxf, (size_t)W * d)) ||
-      (r = salloc(s, &D.flkx, W)) || (r = salloc(s, &D.fgate, 1))) {
+      (r = salloc(s, &D.flkx, W)) || (r = salloc(s, &D.fgate, 1)) || (r = salloc(s, &D.fy2, (size_t)W * d)) ||
+      (r = salloc(s, &D.fqy2, W)) || (r = salloc(s, &D.fqx2, W))) {
     lt_sampler_destroy(s);
     return r;
   }
@@ -589,6 +636,26 @@ lt_status lt_sampler_set_flow(lt_sampler* s, lt_flow* flow) {
   return LT_OK;
 }
 
+lt_status lt_sampler_set_flow_mixture(lt_sampler* s, lt_flow* second, double w_first) {
+  if (!s) return sfail(LT_ERR_NULL, "null sampler");
+  if (second) {
+    if (!(w_first > 0.0 && w_first < 1.0)) return sfail(LT_ERR_CONFIG, "w_first must lie in (0, 1)");
+    if (lt::flow_dim(second) != s->cfg.dim) return sfail(LT_ERR_CONFIG, "flow dimension differs from the sampler's");
+    if (lt::flow_max_batch(second) < s->cfg.n_walkers) return sfail(LT_ERR_SHAPE, "flow max_batch < n_walkers");
+    if (lt::flow_device(second) != s->device) return sfail(LT_ERR_CONFIG, "flow lives on another device");
+    if (s->D.walk > 0.0) return sfail(LT_ERR_CONFIG, "the latent walk takes one flow");
+  }
+  S_HIP(hipSetDevice(s->device));
+  S_HIP(hipDeviceSynchronize());
+  if (s->exec) (void)hipGraphExecDestroy(s->exec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  s->exec = nullptr;
+  s->graph = nullptr;
+  s->flow2 = second;
+  s->D.mw1 = second ? w_first : 1.0;
+  return LT_OK;
+}
+
 lt_status lt_sampler_set_flow_fold(lt_sampler* s, int index, double period, double start) {
   if (!s) return sfail(LT_ERR_NULL, "null sampler");
   if (index < -1 || index >= s->cfg.dim) return sfail(LT_ERR_CONFIG, "fold index");
@@ -609,6 +676,7 @@ lt_status lt_sampler_set_flow_fold(lt_sampler* s, int index, double period, doub
 lt_status lt_sampler_set_flow_walk(lt_sampler* s, double step) {
   if (!s) return sfail(LT_ERR_NULL, "null sampler");
   if (!(step >= 0.0 && std::isfinite(step))) return sfail(LT_ERR_CONFIG, "walk step must be finite and >= 0");
+  if (step > 0.0 && s->flow2) return sfail(LT_ERR_CONFIG, "the latent walk takes one flow (a mixture is attached)");
   S_HIP(hipSetDevice(s->device));
   S_HIP(hipDeviceSynchronize());
   if (s->exec) (void)hipGraphExecDestroy(s->exec);

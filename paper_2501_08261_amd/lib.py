@@ -116,6 +116,7 @@ _sig = {
     "lt_sampler_flow_counts": ([_P, _P], ctypes.c_int),
     "lt_flow_set_mix": ([_P, ctypes.c_double], ctypes.c_int),
     "lt_sampler_set_flow_exclusive": ([_P, ctypes.c_int], ctypes.c_int),
+    "lt_sampler_set_flow_mixture": ([_P, _P, ctypes.c_double], ctypes.c_int),
     "lt_fisher": ([_P, _P, ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(WfCfg), ctypes.POINTER(Grid),
                    ctypes.POINTER(Orbit), ctypes.POINTER(TdiCfg), ctypes.POINTER(Psd), _P], ctypes.c_int),
     "lt_fisher_draw": ([_P, _P, ctypes.c_int, _P, _P, _I64, ctypes.c_uint64, ctypes.c_double, _P], ctypes.c_int),
@@ -460,6 +461,11 @@ class Sampler:
     def set_flow_mix(self, p_flow):
         """Probability that a step runs the flow move (1: every step; 0: the plain sampler)."""
         _check(_lib.lt_flow_set_mix(self.h, float(p_flow)))
+
+    def set_flow_mixture(self, flow2, w_first):
+        """Second flow of a two-component proposal w_first q1 + (1 - w_first) q2 (None: one flow)."""
+        _check(_lib.lt_sampler_set_flow_mixture(self.h, flow2.h if flow2 is not None else None, float(w_first)))
+        self._flow2 = flow2
 
     def set_flow_exclusive(self, on):
         """On steps that run the flow move, skip the cold rung's stretch moves (lt_sampler_set_flow_exclusive)."""

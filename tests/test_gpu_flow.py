@@ -350,6 +350,51 @@ def test_sampler_flow_exclusive_parity(lib, T):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("T,excl", [(1, False), (2, True)])
+def test_sampler_flow_mixture_parity(lib, T, excl):
+    """P38: a mixture of two flows as the proposal (component per walker from Philox, mixture
+    density at both ends) against the oracle chain, step by step, on a two-mode Gaussian whose
+    walkers start in one mode; the chain reaches the other through the second flow."""
+    d, W, seed = 3, 16, 4244
+    means = np.array([[-6.0, 0.5, 0.0], [6.0, -0.5, 1.0]])
+    icov = np.eye(d)
+    lo, hi = -40 * np.ones(d), 40 * np.ones(d)
+    rng = np.random.default_rng(12)
+    start = means[0] + rng.normal(size=(T, W, d))
+    P1, P2 = fl.init_params(d, 2, 32, 4), fl.init_params(d, 2, 32, 5)
+    mu1, s1 = means[0] + 0.2, np.array([1.3, 1.2, 1.1])
+    mu2, s2 = means[1] - 0.1, np.array([1.2, 1.4, 1.0])
+    f1, f2 = lib.Flow(d, 2, 32, W), lib.Flow(d, 2, 32, W)
+    f1.set_params(lib.flow_pack(P1), mu1, s1)
+    f2.set_params(lib.flow_pack(P2), mu2, s2)
+    g = lib.Sampler(W, T, d, lo, hi, seed, target="gauss", param_kind="raw", t_max=5.0, means=means, icov=icov)
+    g.set_flow(f1)
+    g.set_flow_mixture(f2, 0.4)
+    g.set_flow_exclusive(excl)
+    g.set_state(start)
+    o = PTSampler(gaussian_logl(means, icov), lo, hi, W, T, d, seed, t_max=5.0)
+    o.set_flow(P1, mu1, s1)
+    o.set_flow_mixture(P2, mu2, s2, 0.4)
+    o.set_flow_exclusive(excl)
+    o.set_state(start)
+    for st in range(40):
+        g.step(1)
+        o.step()
+        pos, logl, _, step, cnt = g.state()
+        assert np.max(np.abs(pos - o.X)) < 1e-12 * (1 + np.max(np.abs(o.X))), st
+        assert (cnt[0], cnt[1], cnt[2]) == (o.acc, o.prop, o.sacc), st
+        assert g.flow_counts() == (o.facc, o.fprop), st
+    assert np.mean(o.X[0, :, 0] > 0) > 0.2    # the second mode is reached
+    with pytest.raises(lib.LisaTDError):
+        g.set_flow_mixture(f2, 1.0)
+    with pytest.raises(lib.LisaTDError):
+        g.set_flow_walk(0.1)
+    g.close()
+    f1.close()
+    f2.close()
+
+
+@pytest.mark.gpu
 @pytest.mark.parametrize("T", [1, 3])
 def test_sampler_flow_fold_parity(lib, T):
     """P29: flow move with the symmetry fold (copies drawn from Philox, -ln n corrections,
