@@ -229,13 +229,13 @@ def flow_gemm_flops(d, layers=8, hidden=256):
     return 3 * layers * 2 * (hidden * a + hidden * hidden + 2 * (d - a) * hidden)
 
 
-def dominant_mode(s, min_sep=8.0, min_frac=0.02, axes=4):
-    """The samples of the more populated of two clusters when s holds two well separated modes,
-    else all of s; and the fraction kept.  Two-means on coordinates scaled by their standard
-    deviations, started from a split at the median along each of the first `axes` principal
-    axes; the best separated split counts when the Mahalanobis distance between its means
-    under the pooled within-cluster covariance is at least min_sep (a median split of one
-    Gaussian gives about 2.7) and its smaller part holds at least min_frac of the samples."""
+def split_modes(s, min_sep=8.0, min_frac=0.02, axes=4):
+    """The larger of two clusters of s when s holds two well separated modes (a boolean mask of
+    its rows), else None.  Two-means on coordinates scaled by their standard deviations,
+    started from a split at the median along each of the first `axes` principal axes; the best
+    separated split counts when the Mahalanobis distance between its means under the pooled
+    within-cluster covariance is at least min_sep (a median split of one Gaussian gives about
+    2.7) and its smaller part holds at least min_frac of the samples."""
     import numpy as np
     z = (s - s.mean(0)) / s.std(0)
     vt = np.linalg.svd(z, full_matrices=False)[2]
@@ -257,8 +257,16 @@ def dominant_mode(s, min_sep=8.0, min_frac=0.02, axes=4):
         if sep > best_sep:
             best, best_sep = lab, sep
     if best is None or best_sep < min_sep or min(best.mean(), 1.0 - best.mean()) < min_frac:
+        return None
+    return best if best.mean() >= 0.5 else ~best
+
+
+def dominant_mode(s, min_sep=8.0, min_frac=0.02, axes=4):
+    """The samples of the more populated of two clusters when s holds two well separated modes,
+    else all of s; and the fraction kept (split_modes)."""
+    keep = split_modes(s, min_sep, min_frac, axes)
+    if keep is None:
         return s, 1.0
-    keep = best if best.mean() >= 0.5 else ~best
     return s[keep], float(keep.mean())
 
 
@@ -309,7 +317,8 @@ def train_early_stop(flow, s, mu, L, val_frac=0.25, chunk=250, max_steps=3000, p
 
 
 def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=500, rounds=4, window=400,
-              train_steps=1500, m=1000, walk=0.0, split_modes=True, p_flow=1.0, early_stop=True, pool=1, exclusive=True, control=True, reinit=False):
+              train_steps=1500, m=1000, walk=0.0, modes="mixture", p_flow=1.0, early_stop=True, pool=1,
+              exclusive=True, control=True, reinit=False, fisher_reg=None):
     """Effective samples per second of the cold chain, stretch moves alone against
     stretch + learned-flow moves, on one injection and one GPU (TDI-2 AET, 512
     walkers x 8 temperatures, n samples around the merger, Fisher-initialised).
@@ -318,7 +327,11 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     `burn` plain steps, `rounds` times: take the cold samples of the last `pool` windows
     of `window` steps, whiten by the Cholesky factor of their covariance, train on them
     (train_early_stop: at most `train_steps` Adam steps, stopped by the latest quarter of
-    the samples; early_stop=False: exactly `train_steps`), attach, run `window` more steps.  The flow is then frozen and both samplers
+    the samples; early_stop=False: exactly `train_steps`), attach, run `window` more steps.
+    When the samples hold two separated modes (split_modes), modes="mixture" trains one flow
+    on each and proposes from their mixture, weighted by the modes' shares
+    (lt_sampler_set_flow_mixture); modes="dominant" trains on the larger mode only; "off"
+    trains on everything.  The flows are then frozen and both samplers
     restart from the same state for `m` recorded steps; ESS = m W / max_q tau_q
     (worst coordinate), ESS/s uses the time of 200 unrecorded steps.
 
@@ -334,8 +347,10 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
     fraction of the steps once the flow is attached (lt_flow_set_mix); the others run the
     stretch moves and swaps alone.  exclusive: the flow's steps skip the cold rung's stretch
     moves (lt_sampler_set_flow_exclusive).  control: also compare two plain chains.  reinit:
-    each round trains a freshly initialised flow instead of continuing the last one.  Posterior accuracy: the largest gap between the two
-    chains' 5 / 50 / 95 % quantiles in units of its Monte-Carlo error (quantile_gap)."""
+    each round trains a freshly initialised flow instead of continuing the last one.
+    fisher_reg: the eigenvalue floor of the Fisher start (None: FISHER_REG).  Posterior
+    accuracy: the largest gap between the two chains' 5 / 50 / 95 % quantiles in units of its
+    Monte-Carlo error (quantile_gap)."""
     import numpy as np
     import torch
     from paper_2501_08261_amd.diagnostics import autocorr_time, batch_ess
@@ -359,7 +374,8 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
                    tdi, S)
     smp = lib.Sampler(W, T, dim, lo, hi, 5, target="tdi", param_kind=kind, t_c=inj[11], g=g, cfg=cfg, orbit=orb,
                       tdi=tdi, psd=S, data_aet=d[0], dd=float(dd.item()))
-    smp.set_state(lib.fisher_draw(x0, G, lo, hi, T * W, 5, FISHER_REG))
+    reg = FISHER_REG if fisher_reg is None else fisher_reg
+    smp.set_state(lib.fisher_draw(x0, G, lo, hi, T * W, 5, reg))
     t0 = time.perf_counter()
     smp.step(burn)
     flow = lib.Flow(dim, 8, 256, max(2048, W))
@@ -371,42 +387,53 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         X[..., ipsi] = start + np.mod(X[..., ipsi] - start, np.pi)
         return X
 
+    flow2 = None
     t_train = 0.0
     mode_frac, steps_run, recent = [], [], []
+
+    def fit_flow(f, rows, r):
+        """train f on rows (time order); seconds and Adam steps"""
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if early_stop:
+            # whitened by the earlier 3/4 of the rows, which it trains on; the latest quarter
+            # decides when to stop
+            fit = rows[:len(rows) - max(1, int(round(0.25 * len(rows))))]
+            done, _ = train_early_stop(f, rows, fit.mean(0), np.linalg.cholesky(np.cov(fit.T)),
+                                       max_steps=train_steps, seed=r)
+        else:
+            f.set_whitening(rows.mean(0), np.linalg.cholesky(np.cov(rows.T)))
+            xs = torch.tensor(rows[np.random.default_rng(r).permutation(len(rows))], device="cuda:0")
+            f.train(xs, train_steps, 2048, 3e-4)
+            done = train_steps
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1, done
+
     for r in range(rounds):
         recent.append(_record(smp, window).reshape(-1, dim))
         s = np.concatenate(recent[-pool:])
         two = 2.0 * s[:, ipsi]
         start = 0.5 * np.arctan2(np.sin(two).mean(), np.cos(two).mean()) - 0.5 * np.pi
         s = fold(s, start)
-        if split_modes:
-            s, kept = dominant_mode(s)
-            mode_frac.append(kept)
+        keep = split_modes(s) if modes != "off" else None
+        mode_frac.append(1.0 if keep is None else float(keep.mean()))
         smp.set_flow_fold(ipsi, np.pi, start)
         smp.set_flow_walk(walk)
         if reinit:
             flow.set_params(lib.flow_init_params(dim, 8, 256, 3 + r), np.zeros(dim), np.ones(dim))
-        if early_stop:
-            # whitened by the earlier 3/4 of the window (rows in time order), which it trains on;
-            # the latest quarter decides when to stop
-            fit = s[:len(s) - max(1, int(round(0.25 * len(s))))]
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            done, best = train_early_stop(flow, s, fit.mean(0), np.linalg.cholesky(np.cov(fit.T)),
-                                          max_steps=train_steps, seed=r)
-            torch.cuda.synchronize()
-            t_train += time.perf_counter() - t1
+        dt, done = fit_flow(flow, s if keep is None else s[keep], r)
+        t_train += dt
+        steps_run.append(done)
+        if keep is not None and modes == "mixture":
+            if flow2 is None:
+                flow2 = lib.Flow(dim, 8, 256, max(2048, W))
+                flow2.set_params(lib.flow_init_params(dim, 8, 256, 4), np.zeros(dim), np.ones(dim))
+            dt, done = fit_flow(flow2, s[~keep], r)
+            t_train += dt
             steps_run.append(done)
-        else:
-            flow.set_whitening(s.mean(0), np.linalg.cholesky(np.cov(s.T)))
-            xs = torch.tensor(s[np.random.default_rng(r).permutation(len(s))], device="cuda:0")
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            flow.train(xs, train_steps, 2048, 3e-4)
-            torch.cuda.synchronize()
-            t_train += time.perf_counter() - t1
-            steps_run.append(train_steps)
         smp.set_flow(flow)
+        smp.set_flow_mixture(flow2 if (keep is not None and modes == "mixture") else None,
+                             float(keep.mean()) if keep is not None else 0.5)
         smp.set_flow_mix(p_flow)
         smp.set_flow_exclusive(exclusive)
     _record(smp, window)
@@ -478,13 +505,15 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         del v["mean"], v["std"]
     smp.close()
     flow.close()
+    if flow2 is not None:
+        flow2.close()
     ctx.close()
     qgap = quantile_gap(chains["learned"], chains["plain"])
     return {"target": kind, "flow_move": "latent walk, step %g" % walk if walk > 0 else "independence",
             "p_flow": p_flow, "flow_exclusive": bool(exclusive), "quantile_gap_mc_sigma": qgap,
             "quantile_gap_plain_vs_plain": qgap_control,
             "n_samples": n, "walkers": W, "temps": T, "steps_measured": m,
-            "flow_training_share": mode_frac,
+            "flow_training_share": mode_frac, "modes": modes,
             "adaptive_burn_in_s": t_adapt, "flow_train_s": t_train, "train_steps": steps_run,
             "flow_train_tflops": flow_gemm_flops(dim) * 2048 * sum(steps_run) / t_train / 1e12,
             "plain": res["plain"], "learned": res["learned"],

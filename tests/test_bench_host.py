@@ -46,3 +46,15 @@ def test_flow_gemm_flops_counts_every_weight_three_times():
         a, b = d // 2, d - d // 2
         weights = layers * (hidden * a + hidden * hidden + 2 * b * hidden)
         assert bench.flow_gemm_flops(d, layers, hidden) == 3 * 2 * weights
+
+
+def test_split_modes_marks_the_larger_cluster():
+    """The mask of the larger of two separated clusters (each flow of a mixture proposal trains on
+    one side of it), None for one Gaussian."""
+    rng = np.random.default_rng(4)
+    a = rng.normal(size=(3000, 5))
+    b = rng.normal(size=(1200, 5)) + np.array([0.0, 14.0, 0.0, 0.0, 0.0])
+    s = np.vstack([a, b])
+    keep = bench.split_modes(s)
+    assert keep is not None and keep.sum() == 3000 and keep[:3000].all() and not keep[3000:].any()
+    assert bench.split_modes(a) is None
