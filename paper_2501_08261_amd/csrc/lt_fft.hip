@@ -106,14 +106,14 @@ template <typename R, int RAD> __device__ inline void dft(C2<R>* v) {
 // One Stockham stage of radix RAD over `nfft` transforms of length L held in
 // src (row-major [nfft][L]); writes dst.  tw: exp(-2 pi i k / L), k < L.
 template <typename R, int RAD>
-__device__ inline void stage(const C2<R>* src, C2<R>* dst, int L, int Ns, int nfft, const C2<R>* tw) {
+__device__ inline void stage(const C2<R>* src, C2<R>* dst, int L, int Ns, int nfft, const C2<R>* tw, int ls) {
   const int m = L / RAD;
   const int jobs = nfft * m;
   const int step = L / (Ns * RAD);
   for (int job = threadIdx.x; job < jobs; job += kFT) {
     int f = job / m, j = job - f * m;
-    const C2<R>* s = src + f * L;
-    C2<R>* d = dst + f * L;
+    const C2<R>* s = src + f * ls;
+    C2<R>* d = dst + f * ls;
     int k = j % Ns;
     C2<R> v[RAD];
 #pragma unroll
@@ -128,17 +128,18 @@ __device__ inline void stage(const C2<R>* src, C2<R>* dst, int L, int Ns, int nf
   }
 }
 
-// Full mixed-radix Stockham FFT in LDS; returns the buffer holding the result.
+// Full mixed-radix Stockham FFT in LDS over nfft transforms ls elements apart; returns the
+// buffer holding the result.
 template <typename R>
-__device__ C2<R>* lds_fft(C2<R>* a, C2<R>* b, int L, const int* rad, int nr, int nfft, const C2<R>* tw) {
+__device__ C2<R>* lds_fft(C2<R>* a, C2<R>* b, int L, const int* rad, int nr, int nfft, const C2<R>* tw, int ls) {
   int Ns = 1;
   for (int s = 0; s < nr; ++s) {
     switch (rad[s]) {
-      case 2: stage<R, 2>(a, b, L, Ns, nfft, tw); break;
-      case 3: stage<R, 3>(a, b, L, Ns, nfft, tw); break;
-      case 4: stage<R, 4>(a, b, L, Ns, nfft, tw); break;
-      case 5: stage<R, 5>(a, b, L, Ns, nfft, tw); break;
-      default: stage<R, 8>(a, b, L, Ns, nfft, tw); break;
+      case 2: stage<R, 2>(a, b, L, Ns, nfft, tw, ls); break;
+      case 3: stage<R, 3>(a, b, L, Ns, nfft, tw, ls); break;
+      case 4: stage<R, 4>(a, b, L, Ns, nfft, tw, ls); break;
+      case 5: stage<R, 5>(a, b, L, Ns, nfft, tw, ls); break;
+      default: stage<R, 8>(a, b, L, Ns, nfft, tw, ls); break;
     }
     Ns *= rad[s];
     __syncthreads();
@@ -153,93 +154,100 @@ __device__ inline C2<R> wN(const C2<R>* lo, const C2<R>* hi, int64_t k) {
   return cm(lo[k & 1023], hi[k >> 10]);
 }
 
-constexpr int kCB = 8;   // columns per pass-1 workgroup
+constexpr int kCB = 16;        // columns per pass-1 workgroup (fewer for long columns)
+constexpr int kP2MaxPairs = 16;   // row pairs per pass-2 workgroup, at most
 
 template <typename R>
-__global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data, const int32_t* skip) {
+// cb columns per workgroup (cb lanes move one row segment), each column n1 + 1 elements apart
+// in LDS: an odd stride puts the cb lanes of a segment on different bank pairs
+__global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data, const int32_t* skip, int cb) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int n1 = p.n1, n2 = p.n2;
+  const int n1 = p.n1, n2 = p.n2, ls = n1 + 1;
   C2<R>* a = (C2<R>*)smem;
-  C2<R>* b = a + kCB * n1;
+  C2<R>* b = a + cb * ls;
   const int64_t row = blockIdx.y;
   if (skip && skip[row / 3] != 0) return;   // a faulted template's rows are not needed
-  const int j2_0 = blockIdx.x * kCB;
+  const int j2_0 = blockIdx.x * cb;
   C2<R>* z = data + row * p.n;
-  for (int i = threadIdx.x; i < kCB * n1; i += kFT) {
-    int j1 = i / kCB, jj = i - j1 * kCB;
+  for (int i = threadIdx.x; i < cb * n1; i += kFT) {
+    int j1 = i / cb, jj = i - j1 * cb;
     int j2 = j2_0 + jj;
-    a[jj * n1 + j1] = j2 < n2 ? z[(int64_t)j1 * n2 + j2] : C2<R>{(R)0, (R)0};
+    a[jj * ls + j1] = j2 < n2 ? z[(int64_t)j1 * n2 + j2] : C2<R>{(R)0, (R)0};
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
-  C2<R>* res = lds_fft<R>(a, b, n1, p.rad1, p.nr1, kCB, tw);
+  C2<R>* res = lds_fft<R>(a, b, n1, p.rad1, p.nr1, cb, tw, ls);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
-  for (int i = threadIdx.x; i < kCB * n1; i += kFT) {
-    int k1 = i / kCB, jj = i - k1 * kCB;
+  for (int i = threadIdx.x; i < cb * n1; i += kFT) {
+    int k1 = i / cb, jj = i - k1 * cb;
     int j2 = j2_0 + jj;
     if (j2 < n2) {
-      C2<R> v = res[jj * n1 + k1];
+      C2<R> v = res[jj * ls + k1];
       int64_t m = (int64_t)j2 * k1;                     // < n
       z[(int64_t)k1 * n2 + j2] = cm(v, wN<R>(lo, hi, 2 * m));
     }
   }
 }
 
-// pass 2: rows k1 = pair and k1' = (n1 - pair) mod n1
+// pass 2: np row pairs per workgroup, pairs p = np * blockIdx.x + q, q < np; pair p holds rows
+// k1 = p and k1' = (n1 - p) mod n1 (slots 2q and 2q + 1; -1 where absent or a duplicate, the
+// slot then transformed as zeros), which hold every mirror bin of each other
 template <typename R>
 __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, int mode, double dt,
                                                C2<R>* spec, const double* wperm, int64_t ch_rows,
                                                double* partial, int64_t kb_lo, int64_t kb_hi,
-                                               const int32_t* skip) {
+                                               const int32_t* skip, int np) {
   if (skip && skip[blockIdx.y / 3] != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[kFT / 64];
-  const int n1 = p.n1, n2 = p.n2;
+  __shared__ int rowk1[2 * kP2MaxPairs];
+  const int n1 = p.n1, n2 = p.n2, nr = 2 * np;
   const int64_t n = p.n;
-  const int pair = blockIdx.x;
+  const int pa = np * blockIdx.x;
   const int64_t row = blockIdx.y;
-  const int k1a = pair, k1b = (n1 - pair) % n1;
-  const int nrows = (k1a == k1b) ? 1 : 2;
+  if (threadIdx.x < np) {
+    const int q = threadIdx.x, x = pa + q, y = (n1 - x) % n1;
+    rowk1[2 * q] = x <= n1 / 2 ? x : -1;
+    rowk1[2 * q + 1] = (x <= n1 / 2 && y != x) ? y : -1;
+  }
+  __syncthreads();
   C2<R>* a = (C2<R>*)smem;
-  C2<R>* b = a + 2 * n2;
+  C2<R>* b = a + nr * n2;
   const C2<R>* z = data + row * n;
-  for (int i = threadIdx.x; i < nrows * n2; i += kFT) {
-    int r = i / n2, j2 = i - r * n2;
-    int k1 = r == 0 ? k1a : k1b;
-    a[r * n2 + j2] = z[(int64_t)k1 * n2 + j2];
+  for (int i = threadIdx.x; i < nr * n2; i += kFT) {
+    const int r = i / n2, j2 = i - r * n2;
+    const int k1 = rowk1[r];
+    a[r * n2 + j2] = k1 >= 0 ? z[(int64_t)k1 * n2 + j2] : C2<R>{(R)0, (R)0};
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw2d, p.tw2f);
-  C2<R>* Z = lds_fft<R>(a, b, n2, p.rad2, p.nr2, nrows, tw);
+  C2<R>* Z = lds_fft<R>(a, b, n2, p.rad2, p.nr2, nr, tw, n2);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   const double* w = wperm;
   double acc = 0.0;
   // outputs: every k in the rows of this block, plus the Nyquist bin for pair 0
-  const int nout = nrows * n2 + (pair == 0 ? 1 : 0);
+  const int nout = nr * n2 + (pa == 0 ? 1 : 0);
   for (int i = threadIdx.x; i < nout; i += kFT) {
-    int r, k2;
     int64_t k;
     C2<R> Zk, Zm;
-    if (i < nrows * n2) {
-      r = i / n2;
-      k2 = i - r * n2;
-      int k1 = r == 0 ? k1a : k1b;
+    if (i < nr * n2) {
+      const int r = i / n2, k2 = i - r * n2;
+      const int k1 = rowk1[r];
+      if (k1 < 0) continue;
       k = k1 + (int64_t)n1 * k2;
       Zk = Z[r * n2 + k2];
       if (k1 == 0) {
         Zm = Z[r * n2 + (n2 - k2) % n2];
       } else {
-        int rm = (nrows == 1) ? 0 : 1 - r;
+        const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
         Zm = Z[rm * n2 + (n2 - 1 - k2)];
       }
     } else {
       k = n;          // Nyquist: Z_n = Z_0
       Zk = Z[0];
       Zm = Z[0];
-      r = 0;
-      k2 = 0;
     }
     if (mode != 0 && (k < kb_lo || k > kb_hi)) continue;   // outside the band: weight 0, not read
     C2<R> zc = {Zm.x, -Zm.y};
@@ -264,7 +272,9 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int i = 0; i < kFT / 64; ++i) t += red[i];
-      partial[row * (n1 / 2 + 1) + pair] = t;
+      partial[row * (n1 / 2 + 1) + pa] = t;
+      for (int q = 1; q < np; ++q)
+        if (pa + q <= n1 / 2) partial[row * (n1 / 2 + 1) + pa + q] = 0.0;
     }
   }
 }
@@ -552,11 +562,15 @@ static hipError_t p1(const FftPlanDev& p, void* data, int64_t rows, const int32_
     hipLaunchKernelGGL(k_pass1_512<R>, grid, dim3(kP1Threads), bytes, s, p, (C2<R>*)data, skip);
     return hipGetLastError();
   }
-  size_t bytes = 2 * (size_t)kCB * p.n1 * sizeof(C2<R>);
+  // kCB columns where that fits 64 KiB of LDS, else as many as fit 160 KiB
+  int cb = kCB;
+  if (2 * (size_t)cb * (p.n1 + 1) * sizeof(C2<R>) > 65536)
+    while (cb > 1 && 2 * (size_t)cb * (p.n1 + 1) * sizeof(C2<R>) > 160 * 1024) cb /= 2;
+  size_t bytes = 2 * (size_t)cb * (p.n1 + 1) * sizeof(C2<R>);
   hipError_t e = hipFuncSetAttribute((const void*)k_pass1<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)((p.n2 + kCB - 1) / kCB), (unsigned)rows);
-  hipLaunchKernelGGL(k_pass1<R>, grid, dim3(kFT), bytes, s, p, (C2<R>*)data, skip);
+  dim3 grid((unsigned)((p.n2 + cb - 1) / cb), (unsigned)rows);
+  hipLaunchKernelGGL(k_pass1<R>, grid, dim3(kFT), bytes, s, p, (C2<R>*)data, skip, cb);
   return hipGetLastError();
 }
 
@@ -576,12 +590,15 @@ static hipError_t p2(const FftPlanDev& p, const void* data, int64_t rows, int mo
                        wperm, partial, kb_lo, kb_hi, skip);
     return hipGetLastError();
   }
-  size_t bytes = 4 * (size_t)p.n2 * sizeof(C2<R>);
+  // pairs per workgroup: about 2048 elements of rows (two buffers), at most kP2MaxPairs
+  int np = 1024 / p.n2;
+  np = np < 1 ? 1 : (np > kP2MaxPairs ? kP2MaxPairs : np);
+  size_t bytes = 2 * (size_t)(2 * np) * p.n2 * sizeof(C2<R>);
   hipError_t e = hipFuncSetAttribute((const void*)k_pass2<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)(p.n1 / 2 + 1), (unsigned)rows);
+  dim3 grid((unsigned)((p.n1 / 2 + np) / np), (unsigned)rows);
   hipLaunchKernelGGL(k_pass2<R>, grid, dim3(kFT), bytes, s, p, (const C2<R>*)data, mode, dt, (C2<R>*)spec, wperm,
-                     ch_rows, partial, kb_lo, kb_hi, skip);
+                     ch_rows, partial, kb_lo, kb_hi, skip, np);
   return hipGetLastError();
 }
 
