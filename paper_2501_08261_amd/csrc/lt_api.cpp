@@ -643,9 +643,12 @@ lt_status lt_phenomt_polarizations(lt_ctx* c, const double* params, int64_t batc
 // Response kernels for `batch` templates whose constants tc are set up: waveform into `wave`
 // ([batch][2][n] in the precision's real type), the per-launch tables into `nodes` and `refs`
 // (sizes from tdi_scratch_bytes), the fused response into `out`.
+// refs_ready: refs already hold the term references of this configuration (an earlier chunk of
+// the same call computed them)
 static lt_status run_tdi_core(lt_ctx* c, const TplConst* tc, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* g,
                               const OrbitDev& od, const lt_tdi_cfg* t, int out_mode, const void* data, void* out,
-                              int32_t* status, void* wave, double* nodes, void* refs, hipStream_t s) {
+                              int32_t* status, void* wave, double* nodes, void* refs, hipStream_t s,
+                              bool refs_ready = false) {
   {
     Prof pr(c, 5, s);
     LT_HIP(launch_wave(tc, batch, cfg->mode_mask, cfg->precessing, cfg->coarse, cfg->precision, gdev(g), wave, s));
@@ -669,6 +672,7 @@ static lt_status run_tdi_core(lt_ctx* c, const TplConst* tc, int64_t batch, cons
   L.wg_per_cu = c->tune.wg_per_cu;
   L.nodes = nodes;
   L.refs = refs;
+  L.refs_ready = refs_ready ? 1 : 0;
   {
     Prof pr(c, 0, s);
     LT_HIP(launch_tdi(L, 0, s));
@@ -884,7 +888,8 @@ static lt_status loglike_run(lt_ctx* c, const double* params, int64_t batch, con
   for (int64_t off = 0; off < batch; off += chunk) {
     const int64_t b = batch - off < chunk ? batch - off : chunk;
     int32_t* stat = stat_all + off;
-    st = run_tdi_core(c, w.tpl + off, b, cfg, g, od, t, 2, data->aet, w.work, stat, w.wave, w.nodes, w.refs, s);
+    st = run_tdi_core(c, w.tpl + off, b, cfg, g, od, t, 2, data->aet, w.work, stat, w.wave, w.nodes, w.refs, s,
+                      off > 0);
     if (st) return st;
     st = fft_band(c, p, w.work, b * 3, cfg->precision, k_lo, k_hi, g, w.partial, w.wperm, stat, s);
     if (st) return st;

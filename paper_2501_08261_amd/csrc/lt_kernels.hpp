@@ -66,6 +66,9 @@ struct TdiLaunch {
   int persistent = 0;
   int wg_per_cu = 4;
   unsigned long long* counter;   // set by launch_tdi: the persistent grid's item counter, after the records
+  // 1: refs already hold this configuration's term references and filters (they depend on the
+  // grid, orbit and TDI configuration, not on the templates): the tables stage skips them
+  int refs_ready = 0;
 };
 // stage 0: the per-launch tables (node geometry, term references, combined filters);
 // stage 1: the response kernel itself

@@ -323,8 +323,9 @@ __global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb,
 // the orbit nodes the tile interpolates (nodes jn_lo .. jn_hi, as in k_tdi), and whether the
 // projection quotients are smooth over them (1 - k.n >= kSmoothKn on every link), four int32
 __global__ __launch_bounds__(kNT) void k_windows(const double* nodes, OrbitDev orb, int64_t batch, int ntile,
-                                                 int HY, int MY, int* win) {
+                                                 int HY, int MY, int* win, unsigned long long* counter) {
   const int64_t idx = (int64_t)blockIdx.x * kNT + threadIdx.x;
+  if (idx == 0) *counter = 0ull;   // the persistent response kernel's item counter
   if (idx >= batch * ntile) return;
   const int64_t b = idx / ntile, tile = idx - b * ntile;
   constexpr int S = kTile / (kTile / 256);
@@ -400,7 +401,6 @@ __global__ __launch_bounds__(kNT) void k_tdi_refs(TdiLaunch P, int HY, int MYP, 
   __shared__ double fgd[TAY ? kGroups * kNV * JMAX : 1];     // F summed in FP64
   __shared__ int s_comb, s_span_bad;
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) *P.counter = 0ull;   // the persistent response kernel's item counter
   const int64_t n0 = (int64_t)blockIdx.x * kTile;
   const int64_t m_lo = n0 - HY;
   constexpr int S = kTile / kNV;
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(kNT) void k_tdi(TdiLaunch P, int HY, int WMAX, int 
 }
 
 // persistent: a fixed grid whose workgroups take items from a counter until none is left (the
-// counter is zeroed by k_tdi_refs, which runs before on the same stream).  Every thread of a
+// counter is zeroed by k_windows, which runs before on the same stream).  Every thread of a
 // workgroup runs the same items and meets the same barriers; the loop ends for all of them
 // when the counter passes the last item.
 template <typename R, int K, bool TAY>
@@ -987,9 +987,9 @@ static hipError_t launch_tdi_t(const TdiLaunch& P0, int stage, hipStream_t s) {
     if (e != hipSuccess) return e;
     const int64_t nw = P.batch * (int64_t)G.ntile;
     hipLaunchKernelGGL(k_windows, dim3((unsigned)((nw + kNT - 1) / kNT)), dim3(kNT), 0, s, P.nodes, P.orb, P.batch,
-                       (int)G.ntile, G.HY, kTile + G.HY + K / 2 + 1, P.win);
+                       (int)G.ntile, G.HY, kTile + G.HY + K / 2 + 1, P.win, P.counter);
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || P.refs_ready) return e;
     hipLaunchKernelGGL((k_tdi_refs<R, K, TAY>), dim3(G.ntile), dim3(kNT), 0, s, P, G.HY, G.MYP, G.comb);
     return hipGetLastError();
   }
