@@ -524,10 +524,24 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
     S_HIP(hipMemcpy(D.gmean, cfg->gauss_mean, (size_t)cfg->n_gauss * d * sizeof(double), hipMemcpyHostToDevice));
     S_HIP(hipMemcpy(D.gicov, cfg->gauss_icov, (size_t)d * d * sizeof(double), hipMemcpyHostToDevice));
   } else {
+    // chunks of templates: as large as a workspace of 4 GiB allows (whole half-steps on short
+    // grids, where per-chunk launches would dominate; 256 templates at 2^20 samples)
+    lt_tuning tu;
+    lt_status r2 = lt_ctx_get_tuning(s->ctx, &tu);
+    for (int ch = tu.chunk * 2; r2 == LT_OK && ch <= 4096 && ch / 2 < (int)TW; ch *= 2) {
+      size_t b = 0;
+      lt_tuning t2 = tu;
+      t2.chunk = ch;
+      if ((r2 = lt_ctx_set_tuning(s->ctx, &t2)) != LT_OK) break;
+      if ((r2 = lt_workspace_size(s->ctx, TW, &s->wf, &s->grid, &s->tdi, &b, nullptr)) != LT_OK) break;
+      if (b > ((size_t)4 << 30)) break;
+      tu.chunk = ch;
+    }
+    if (r2 == LT_OK) r2 = lt_ctx_set_tuning(s->ctx, &tu);
     // one workspace for every likelihood call of the sampler (at most the whole ensemble per
     // call), so that a captured step allocates nothing
     size_t wsb = 0;
-    lt_status r2 = lt_workspace_size(s->ctx, TW, &s->wf, &s->grid, &s->tdi, &wsb, nullptr);
+    if (r2 == LT_OK) r2 = lt_workspace_size(s->ctx, TW, &s->wf, &s->grid, &s->tdi, &wsb, nullptr);
     if (r2 == LT_OK) r2 = salloc(s, (unsigned char**)&s->ws, wsb);
     if (r2 != LT_OK) {
       lt_sampler_destroy(s);
