@@ -31,8 +31,8 @@ PMC = {
     # profiles/k_tdi_precessing_k8_2p20_b256.md (a launch of 256 templates, divided by 256)
     ("tdi_response", 2 ** 20, 8, "mixed"): {"fetch": 2771580000 / 256, "write": 3221230000 / 256,
                                             "valu": 5.100e9 / 256, "fma_f32": 1.566e9 / 256, "fma_f64": 9.94e8 / 256},
-    ("waveform", 2 ** 20, 8, "mixed"): {"fetch": 1958000 / 256, "write": 2147480000 / 256, "valu": 1.577e9 / 256,
-                                        "fma_f32": 3.735e8 / 256, "fma_f64": 7.308e7 / 256},
+    ("waveform", 2 ** 20, 8, "mixed"): {"fetch": 2473600 / 256, "write": 2147480000 / 256, "valu": 1.3455e9 / 256,
+                                        "fma_f32": 3.4925e8 / 256, "fma_f64": 7.308e7 / 256},
 }
 
 

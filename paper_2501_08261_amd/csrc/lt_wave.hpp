@@ -290,13 +290,6 @@ __device__ inline bool phase_state(const TplConst& c, double t, double& phi, dou
   return true;
 }
 
-// phase reduced to [-pi, pi] in FP64 (two-part 2 pi), for FP32 trigonometry
-__device__ inline double reduce2pi(double x) {
-  double k = rint(x * 0.15915494309189533577);
-  double r = fma(-k, 6.283185307179586232, x);
-  return fma(-k, 2.4492935982947064e-16, r);
-}
-
 template <typename A> struct cx { A re, im; };
 template <typename A> __device__ inline cx<A> xmul(cx<A> a, cx<A> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -311,9 +304,33 @@ template <typename A> __device__ inline cx<A> pair_sum(cx<A> a, cx<A> b, cx<A> c
 
 // sin / cos of an FP64 phase in arithmetic type A
 __device__ inline void sincos_a(double x, double& s, double& c) { sincos(x, &s, &c); }
-__device__ inline void sincos_a(double x, float& s, float& c) { sincosf((float)reduce2pi(x), &s, &c); }
+// FP32 sin / cos of an FP64 phase: x = q pi/2 + r with q = rint(2x / pi), r taken in FP64
+// (two-part pi/2) and rounded to FP32, |r| <= pi/4; sin r and cos r from their Taylor series
+// through r^9 and r^10 (the first omitted terms are below 3e-9 there), then the quadrant
+// q mod 4 maps them onto sin x and cos x.  Valid for |x| < 2^31 pi/2.
+__device__ inline void sincos_a(double x, float& s, float& c) {
+  const double q = rint(x * 0.63661977236758134308);
+  const float r = (float)fma(-q, 6.1232339957367660360e-17, fma(-q, 1.5707963267948966192, x));
+  const int k = (int)q;
+  const float r2 = r * r;
+  float sp = fmaf(r2, (float)(1.0 / 362880.0), (float)(-1.0 / 5040.0));
+  sp = fmaf(r2, sp, (float)(1.0 / 120.0));
+  sp = fmaf(r2, sp, (float)(-1.0 / 6.0));
+  const float sr = fmaf(r * r2, sp, r);
+  float cr = fmaf(r2, (float)(-1.0 / 3628800.0), (float)(1.0 / 40320.0));
+  cr = fmaf(r2, cr, (float)(-1.0 / 720.0));
+  cr = fmaf(r2, cr, (float)(1.0 / 24.0));
+  cr = fmaf(r2, cr, -0.5f);
+  cr = fmaf(r2, cr, 1.0f);
+  // quadrants 1, 2, 3: (cos r, -sin r), (-sin r, -cos r), (-cos r, sin r)
+  float ss = (k & 1) ? cr : sr, cc = (k & 1) ? sr : cr;
+  s = (k & 2) ? -ss : ss;
+  c = ((k + 1) & 2) ? -cc : cc;
+}
 __device__ inline double rsqrt_a(double x) { return 1.0 / sqrt(x); }
 __device__ inline float rsqrt_a(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double sqrt_a(double x) { return sqrt(x); }
+__device__ inline float sqrt_a(float x) { return __builtin_amdgcn_sqrtf(x); }   // 1 ulp
 
 template <typename A> struct NewtonSteps;
 template <> struct NewtonSteps<double> { static constexpr int n = 2; };
@@ -328,7 +345,7 @@ template <> struct NewtonSteps<float> { static constexpr int n = 1; };
 //   W3,3 = -sqrt6 a^5 conj(b), W3,2 = a^4 (A2 - 5 B2), W3,-2 = b^4 (5 A2 - B2),
 //   W3,-3 = sqrt6 conj(a) b^5, W4,4 = 2 sqrt7 a^6 conj(b)^2, W4,-4 = 2 sqrt7 conj(a)^2 b^6.
 template <typename A, bool PREC>
-__device__ inline cx<A> polarization_t(const TplConst& c, int mode_mask, double t) {
+__device__ __attribute__((always_inline)) inline cx<A> polarization_t(const TplConst& c, int mode_mask, double t) {
   double phi, msw, vd, ampd;
   bool insp;
   if (!phase_state<NewtonSteps<A>::n>(c, t, phi, msw, vd, ampd, insp)) return {(A)0, (A)0};
@@ -367,9 +384,9 @@ __device__ inline cx<A> polarization_t(const TplConst& c, int mode_mask, double 
   const double gamma = -c.kappa + 2.0 * c.Cp * ((1.0 / 3.0) * iu3 + 0.5 * c.sig * iu2 - 0.5 * c.vsig2 * vd) - c.g_ref;
   const A a1 = (A)1 + (A)c.sig * u;
   const A cb = a1 * rsqrt_a(a1 * a1 + (A)c.vsig2 * x);
-  const A chb = sqrt((A)0.5 * ((A)1 + cb));
+  const A chb = sqrt_a((A)0.5 * ((A)1 + cb));
   const A omc = (A)0.5 * ((A)1 - cb);
-  const A shb = sqrt(omc > (A)0 ? omc : (A)0);
+  const A shb = sqrt_a(omc > (A)0 ? omc : (A)0);
   A ss, cs, sd, cd;
   sincos_a(0.5 * (alpha + gamma), ss, cs);
   sincos_a(0.5 * (alpha - gamma), sd, cd);
