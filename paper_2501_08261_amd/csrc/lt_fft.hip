@@ -103,18 +103,38 @@ template <typename R, int RAD> __device__ inline void dft(C2<R>* v) {
   }
 }
 
+// Division of a non-negative value by a divisor that is the same for the whole workgroup: a
+// shift when the divisor is a power of two (a uniform branch), else the integer division.
+struct UDiv {
+  int d, sh;
+  __device__ explicit UDiv(int d_) : d(d_), sh((d_ & (d_ - 1)) == 0 ? __builtin_ctz((unsigned)d_) : -1) {}
+  __device__ int div(int a) const { return sh >= 0 ? a >> sh : a / d; }
+};
+
 // One Stockham stage of radix RAD over `nfft` transforms of length L held in
 // src (row-major [nfft][L]); writes dst.  tw: exp(-2 pi i k / L), k < L.
-template <typename R, int RAD>
+// P2: L is a power of two (then so are L / RAD and Ns): indices by shifts and masks.
+template <typename R, int RAD, bool P2>
 __device__ inline void stage(const C2<R>* src, C2<R>* dst, int L, int Ns, int nfft, const C2<R>* tw, int ls) {
   const int m = L / RAD;
   const int jobs = nfft * m;
   const int step = L / (Ns * RAD);
+  const int lm = P2 ? __builtin_ctz((unsigned)m) : 0, lns = P2 ? __builtin_ctz((unsigned)Ns) : 0;
   for (int job = threadIdx.x; job < jobs; job += kFT) {
-    int f = job / m, j = job - f * m;
+    int f, j, k, q;
+    if constexpr (P2) {
+      f = job >> lm;
+      j = job & (m - 1);
+      k = j & (Ns - 1);
+      q = j >> lns;
+    } else {
+      f = job / m;
+      j = job - f * m;
+      q = j / Ns;
+      k = j - q * Ns;
+    }
     const C2<R>* s = src + f * ls;
     C2<R>* d = dst + f * ls;
-    int k = j % Ns;
     C2<R> v[RAD];
 #pragma unroll
     for (int r = 0; r < RAD; ++r) {
@@ -122,7 +142,7 @@ __device__ inline void stage(const C2<R>* src, C2<R>* dst, int L, int Ns, int nf
       if (r > 0 && k > 0) v[r] = cm(v[r], tw[r * k * step]);
     }
     dft<R, RAD>(v);
-    int base = (j / Ns) * Ns * RAD + k;
+    int base = q * Ns * RAD + k;
 #pragma unroll
     for (int r = 0; r < RAD; ++r) d[base + r * Ns] = v[r];
   }
@@ -133,13 +153,23 @@ __device__ inline void stage(const C2<R>* src, C2<R>* dst, int L, int Ns, int nf
 template <typename R>
 __device__ C2<R>* lds_fft(C2<R>* a, C2<R>* b, int L, const int* rad, int nr, int nfft, const C2<R>* tw, int ls) {
   int Ns = 1;
+  const bool p2 = (L & (L - 1)) == 0;
   for (int s = 0; s < nr; ++s) {
     switch (rad[s]) {
-      case 2: stage<R, 2>(a, b, L, Ns, nfft, tw, ls); break;
-      case 3: stage<R, 3>(a, b, L, Ns, nfft, tw, ls); break;
-      case 4: stage<R, 4>(a, b, L, Ns, nfft, tw, ls); break;
-      case 5: stage<R, 5>(a, b, L, Ns, nfft, tw, ls); break;
-      default: stage<R, 8>(a, b, L, Ns, nfft, tw, ls); break;
+      case 2:
+        if (p2) stage<R, 2, true>(a, b, L, Ns, nfft, tw, ls);
+        else stage<R, 2, false>(a, b, L, Ns, nfft, tw, ls);
+        break;
+      case 3: stage<R, 3, false>(a, b, L, Ns, nfft, tw, ls); break;
+      case 4:
+        if (p2) stage<R, 4, true>(a, b, L, Ns, nfft, tw, ls);
+        else stage<R, 4, false>(a, b, L, Ns, nfft, tw, ls);
+        break;
+      case 5: stage<R, 5, false>(a, b, L, Ns, nfft, tw, ls); break;
+      default:
+        if (p2) stage<R, 8, true>(a, b, L, Ns, nfft, tw, ls);
+        else stage<R, 8, false>(a, b, L, Ns, nfft, tw, ls);
+        break;
     }
     Ns *= rad[s];
     __syncthreads();
@@ -169,8 +199,9 @@ __global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data, const 
   if (skip && skip[row / 3] != 0) return;   // a faulted template's rows are not needed
   const int j2_0 = blockIdx.x * cb;
   C2<R>* z = data + row * p.n;
+  const UDiv cbd(cb);
   for (int i = threadIdx.x; i < cb * n1; i += kFT) {
-    int j1 = i / cb, jj = i - j1 * cb;
+    int j1 = cbd.div(i), jj = i - j1 * cb;
     int j2 = j2_0 + jj;
     a[jj * ls + j1] = j2 < n2 ? z[(int64_t)j1 * n2 + j2] : C2<R>{(R)0, (R)0};
   }
@@ -180,7 +211,7 @@ __global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data, const 
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   for (int i = threadIdx.x; i < cb * n1; i += kFT) {
-    int k1 = i / cb, jj = i - k1 * cb;
+    int k1 = cbd.div(i), jj = i - k1 * cb;
     int j2 = j2_0 + jj;
     if (j2 < n2) {
       C2<R> v = res[jj * ls + k1];
@@ -215,8 +246,9 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
   C2<R>* a = (C2<R>*)smem;
   C2<R>* b = a + nr * n2;
   const C2<R>* z = data + row * n;
+  const UDiv n2d(n2);
   for (int i = threadIdx.x; i < nr * n2; i += kFT) {
-    const int r = i / n2, j2 = i - r * n2;
+    const int r = n2d.div(i), j2 = i - r * n2;
     const int k1 = rowk1[r];
     a[r * n2 + j2] = k1 >= 0 ? z[(int64_t)k1 * n2 + j2] : C2<R>{(R)0, (R)0};
   }
@@ -227,25 +259,28 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
   const double* w = wperm;
   double acc = 0.0;
+  const int ch = (int)(row % 3);
   // outputs: every k in the rows of this block, plus the Nyquist bin for pair 0
   const int nout = nr * n2 + (pa == 0 ? 1 : 0);
   for (int i = threadIdx.x; i < nout; i += kFT) {
-    int64_t k;
+    int64_t k, widx;   // bin, and its index in pass-2 order (k1 * n2 + k2; Nyquist at n)
     C2<R> Zk, Zm;
     if (i < nr * n2) {
-      const int r = i / n2, k2 = i - r * n2;
+      const int r = n2d.div(i), k2 = i - r * n2;
       const int k1 = rowk1[r];
       if (k1 < 0) continue;
       k = k1 + (int64_t)n1 * k2;
+      widx = (int64_t)k1 * n2 + k2;
       Zk = Z[r * n2 + k2];
       if (k1 == 0) {
-        Zm = Z[r * n2 + (n2 - k2) % n2];
+        Zm = Z[r * n2 + (k2 == 0 ? 0 : n2 - k2)];
       } else {
         const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
         Zm = Z[rm * n2 + (n2 - 1 - k2)];
       }
     } else {
       k = n;          // Nyquist: Z_n = Z_0
+      widx = n;
       Zk = Z[0];
       Zm = Z[0];
     }
@@ -257,9 +292,7 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
     if (mode == 0) {
       spec[row * (n + 1) + k] = sc(X, (R)dt);
     } else {
-      // weights are stored in pass-2 order: index k1 * n2 + k2 (Nyquist at n)
-      int64_t ch = (row % 3);
-      int64_t widx = (k == n) ? n : (int64_t)(k % n1) * n2 + k / n1;
+      // weights are stored in pass-2 order
       double wv = w[ch * (n + 1) + widx];
       double xr = (double)X.x, xi = (double)X.y;
       acc += wv * (xr * xr + xi * xi);
