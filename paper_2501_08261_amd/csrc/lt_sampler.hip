@@ -524,11 +524,16 @@ lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_
     S_HIP(hipMemcpy(D.gmean, cfg->gauss_mean, (size_t)cfg->n_gauss * d * sizeof(double), hipMemcpyHostToDevice));
     S_HIP(hipMemcpy(D.gicov, cfg->gauss_icov, (size_t)d * d * sizeof(double), hipMemcpyHostToDevice));
   } else {
-    // chunks of templates: as large as a workspace of 4 GiB allows (whole half-steps on short
-    // grids, where per-chunk launches would dominate; 256 templates at 2^20 samples)
+    // chunks of templates: on short grids larger than the default 256, which cuts the fixed
+    // costs of each chunk, while a chunk's residual (3 n samples per template) stays within
+    // 128 MiB, so that the FFT passes find it in the last-level cache after the response kernel
+    // wrote it (2^14 samples: 512 templates; 256 from 2^16 samples up), and its workspace
+    // within 4 GiB
     lt_tuning tu;
     lt_status r2 = lt_ctx_get_tuning(s->ctx, &tu);
+    const size_t rsz = s->wf.precision == LT_FP64 ? 8 : 4;
     for (int ch = tu.chunk * 2; r2 == LT_OK && ch <= 4096 && ch / 2 < (int)TW; ch *= 2) {
+      if ((size_t)ch * 3 * (size_t)s->grid.n * rsz > ((size_t)128 << 20)) break;
       size_t b = 0;
       lt_tuning t2 = tu;
       t2.chunk = ch;
