@@ -63,6 +63,8 @@ def parse():
                     help="skip the ESS/s measurement on the precessing 14-D posterior (the C4 injection)")
     ap.add_argument("--p-flow", type=float, default=1.0,
                     help="fraction of sampler steps that run the flow move in the ESS measurements")
+    ap.add_argument("--ess-reference", type=int, default=0,
+                    help="with --ess-only: also run a plain chain of this many steps as the accuracy reference")
     ap.add_argument("--ess-only", choices=["aligned", "precessing"], default=None,
                     help="only run the ESS/s measurement of learned against plain proposals on that posterior")
     ap.add_argument("--flow-train", type=int, default=0, metavar="STEPS",
@@ -318,7 +320,7 @@ def train_early_stop(flow, s, mu, L, val_frac=0.25, chunk=250, max_steps=3000, p
 
 def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=500, rounds=4, window=400,
               train_steps=1500, m=1000, walk=0.0, modes="mixture", p_flow=1.0, early_stop=True, pool=1,
-              exclusive=True, control=True, reinit=False, fisher_reg=None):
+              exclusive=True, control=True, reinit=False, fisher_reg=None, ref_steps=0):
     """Effective samples per second of the cold chain, stretch moves alone against
     stretch + learned-flow moves, on one injection and one GPU (TDI-2 AET, 512
     walkers x 8 temperatures, n samples around the merger, Fisher-initialised).
@@ -465,6 +467,7 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
         else:
             res[label]["stretch_accept"] = smp.state()[4][0] / max(smp.state()[4][1], 1)
     qgap_control = None
+    ctrl_shift = ctrl_std = None
     if control:
         # a second plain chain from the same state with another seed: the gap two plain chains
         # show is the floor of the check
@@ -472,8 +475,36 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
                            orbit=orb, tdi=tdi, psd=S, data_aet=d[0], dd=float(dd.item()))
         smp2.set_state(state)
         smp2.step(220)
-        qgap_control = quantile_gap(fold(_record(smp2, m), start), chains["plain"])
+        c2 = fold(_record(smp2, m), start)
+        qgap_control = quantile_gap(c2, chains["plain"])
+        f2 = c2.reshape(-1, c2.shape[-1])
+        ctrl_shift = float(np.max(np.abs(f2.mean(0) - res["plain"]["mean"]) / res["plain"]["std"]))
+        ctrl_std = (f2.std(0) / res["plain"]["std"]).tolist()
         smp2.close()
+    reference = None
+    if ref_steps > 0:
+        # a long plain chain (another seed, every 10th step kept) as the reference that both
+        # measured chains are held against: their means in its standard deviations, their
+        # standard deviations over its own
+        smp3 = lib.Sampler(W, T, dim, lo, hi, 7, target="tdi", param_kind=kind, t_c=inj[11], g=g, cfg=cfg,
+                           orbit=orb, tdi=tdi, psd=S, data_aet=d[0], dd=float(dd.item()))
+        smp3.set_state(state)
+        smp3.step(220)
+        rows = []
+        for i in range(ref_steps // 10):
+            smp3.step(10)
+            rows.append(smp3.state()[0][0].copy())
+            if (i + 1) % 200 == 0:
+                print("reference chain: %d steps" % (10 * (i + 1)), file=sys.stderr, flush=True)
+        smp3.close()
+        fr = fold(np.array(rows), start).reshape(-1, dim)
+        mr, sr = fr.mean(0), fr.std(0)
+        reference = {"steps": ref_steps}
+        for label, ch in (("learned", chains["learned"]), ("plain", chains["plain"])) + \
+                ((("plain2", c2),) if control else ()):
+            f = ch.reshape(-1, dim)
+            reference[label] = {"mean_shift_sigma": float(np.max(np.abs(f.mean(0) - mr) / sr)),
+                                "std_ratio": [round(float(x), 3) for x in f.std(0) / sr]}
     # with the flow's training counted: the learned sampler's wall time includes the Adam steps;
     # break-even = the number of measured steps after which the learned sampler with its
     # training has produced as many effective samples per second as the plain one
@@ -522,6 +553,9 @@ def ess_bench(lib, inputs, prec, precessing=False, n=1 << 14, W=512, T=8, burn=5
             "ratio_with_training": res["learned"]["ess_per_s_with_training"] / res["plain"]["ess_per_s"],
             "breakeven_steps": breakeven,
             "posterior_mean_shift_sigma": shift, "posterior_std_ratio": [round(x, 3) for x in std_ratio],
+            "plain_vs_plain": None if ctrl_std is None else
+            {"mean_shift_sigma": ctrl_shift, "std_ratio": [round(x, 3) for x in ctrl_std]},
+            "against_long_plain_chain": reference,
             "fisher_vs_mcmc": fisher}
 
 
@@ -602,7 +636,8 @@ def main():
     if a.ess_only:
         from paper_2501_08261_amd import inputs, lib
         prec = lib.LT_MIXED if a.precision == "mixed" else lib.LT_FP64
-        r = ess_bench(lib, inputs, prec, precessing=a.ess_only == "precessing", p_flow=a.p_flow)
+        r = ess_bench(lib, inputs, prec, precessing=a.ess_only == "precessing", p_flow=a.p_flow,
+                      ref_steps=a.ess_reference)
         print(json.dumps(r, default=float))
         return
     import numpy as np

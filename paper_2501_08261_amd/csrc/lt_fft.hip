@@ -247,10 +247,27 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
   C2<R>* b = a + nr * n2;
   const C2<R>* z = data + row * n;
   const UDiv n2d(n2);
-  for (int i = threadIdx.x; i < nr * n2; i += kFT) {
-    const int r = n2d.div(i), j2 = i - r * n2;
-    const int k1 = rowk1[r];
-    a[r * n2 + j2] = k1 >= 0 ? z[(int64_t)k1 * n2 + j2] : C2<R>{(R)0, (R)0};
+  {
+    // kU loads per thread issued before their LDS stores (one memory latency per kU * kFT)
+    constexpr int kU = 8;
+    for (int i0 = threadIdx.x; i0 < nr * n2; i0 += kU * kFT) {
+      C2<R> v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kFT;
+        v[u] = C2<R>{(R)0, (R)0};
+        if (i < nr * n2) {
+          const int r = n2d.div(i), j2 = i - r * n2;
+          const int k1 = rowk1[r];
+          if (k1 >= 0) v[u] = z[(int64_t)k1 * n2 + j2];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kFT;
+        if (i < nr * n2) a[i] = v[u];
+      }
+    }
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw2d, p.tw2f);
@@ -260,17 +277,71 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
   const double* w = wperm;
   double acc = 0.0;
   const int ch = (int)(row % 3);
-  // outputs: every k in the rows of this block, plus the Nyquist bin for pair 0
+  if (mode != 0) {
+    // band power.  Bin k = k1 + n1 k2 lies in [kb_lo, kb_hi] only for k2 <= kb_hi / n1: the
+    // items are (row slot r, k2) for k2 < K2, kU per thread with their weights and twiddles
+    // loaded before they are used.  Weights are stored in pass-2 order (k1 n2 + k2; Nyquist n).
+    const int64_t k2top = kb_hi / n1 < n2 - 1 ? kb_hi / n1 : n2 - 1;
+    const int K2 = k2top > 0 ? (int)k2top + 1 : 1;
+    const UDiv K2d(K2);
+    const int nitem = nr * K2;
+    constexpr int kU = 4;
+    for (int i0 = threadIdx.x; i0 < nitem; i0 += kU * kFT) {
+      bool on[kU];
+      int rs[kU], k2s[kU];
+      double wv[kU];
+      C2<R> lk[kU], hk[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int i = i0 + u * kFT;
+        const int r = K2d.div(i), k2 = i - r * K2;
+        const int k1 = i < nitem ? rowk1[r] : -1;
+        const int64_t k = k1 + (int64_t)n1 * k2;
+        on[u] = k1 >= 0 && k >= kb_lo && k <= kb_hi;
+        rs[u] = r;
+        k2s[u] = k2;
+        wv[u] = on[u] ? w[ch * (n + 1) + (int64_t)k1 * n2 + k2] : 0.0;
+        lk[u] = on[u] ? lo[k & 1023] : C2<R>{(R)0, (R)0};
+        hk[u] = on[u] ? hi[k >> 10] : C2<R>{(R)0, (R)0};
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (!on[u]) continue;
+        const int r = rs[u], k2 = k2s[u], k1 = rowk1[r];
+        const C2<R> Zk = Z[r * n2 + k2];
+        C2<R> Zm;
+        if (k1 == 0) {
+          Zm = Z[r * n2 + (k2 == 0 ? 0 : n2 - k2)];
+        } else {
+          const int rm = (rowk1[r ^ 1] >= 0) ? (r ^ 1) : r;   // the mirror row sits in the paired slot
+          Zm = Z[rm * n2 + (n2 - 1 - k2)];
+        }
+        const C2<R> zc = {Zm.x, -Zm.y};
+        const C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
+        const C2<R> X = sm + mi(cm(cm(lk[u], hk[u]), df));
+        const double xr = (double)X.x, xi = (double)X.y;
+        acc += wv[u] * (xr * xr + xi * xi);
+      }
+    }
+    if (pa == 0 && threadIdx.x == 0 && n >= kb_lo && n <= kb_hi) {
+      // Nyquist: Z_n = Z_0, twiddle -1
+      const C2<R> Zk = Z[0], zc = {Z[0].x, -Z[0].y};
+      const C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
+      const C2<R> X = sm + mi(cm(C2<R>{(R)-1, (R)0}, df));
+      const double xr = (double)X.x, xi = (double)X.y;
+      acc += w[ch * (n + 1) + n] * (xr * xr + xi * xi);
+    }
+  }
+  // full spectrum (mode 0): every k in the rows of this block, plus the Nyquist bin for pair 0
   const int nout = nr * n2 + (pa == 0 ? 1 : 0);
-  for (int i = threadIdx.x; i < nout; i += kFT) {
-    int64_t k, widx;   // bin, and its index in pass-2 order (k1 * n2 + k2; Nyquist at n)
+  for (int i = threadIdx.x; mode == 0 && i < nout; i += kFT) {
+    int64_t k;
     C2<R> Zk, Zm;
     if (i < nr * n2) {
       const int r = n2d.div(i), k2 = i - r * n2;
       const int k1 = rowk1[r];
       if (k1 < 0) continue;
       k = k1 + (int64_t)n1 * k2;
-      widx = (int64_t)k1 * n2 + k2;
       Zk = Z[r * n2 + k2];
       if (k1 == 0) {
         Zm = Z[r * n2 + (k2 == 0 ? 0 : n2 - k2)];
@@ -280,23 +351,14 @@ __global__ __launch_bounds__(kFT) void k_pass2(FftPlanDev p, const C2<R>* data, 
       }
     } else {
       k = n;          // Nyquist: Z_n = Z_0
-      widx = n;
       Zk = Z[0];
       Zm = Z[0];
     }
-    if (mode != 0 && (k < kb_lo || k > kb_hi)) continue;   // outside the band: weight 0, not read
     C2<R> zc = {Zm.x, -Zm.y};
-    C2<R> s = sc(Zk + zc, (R)0.5), d = sc(Zk - zc, (R)0.5);
+    C2<R> sm = sc(Zk + zc, (R)0.5), df = sc(Zk - zc, (R)0.5);
     C2<R> wk = (k == n) ? C2<R>{(R)-1, (R)0} : wN<R>(lo, hi, k);
-    C2<R> X = s + mi(cm(wk, d));
-    if (mode == 0) {
-      spec[row * (n + 1) + k] = sc(X, (R)dt);
-    } else {
-      // weights are stored in pass-2 order
-      double wv = w[ch * (n + 1) + widx];
-      double xr = (double)X.x, xi = (double)X.y;
-      acc += wv * (xr * xr + xi * xi);
-    }
+    C2<R> X = sm + mi(cm(wk, df));
+    spec[row * (n + 1) + k] = sc(X, (R)dt);
   }
   if (mode != 0) {
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
