@@ -200,23 +200,41 @@ __global__ __launch_bounds__(kFT) void k_pass1(FftPlanDev p, C2<R>* data, const 
   const int j2_0 = blockIdx.x * cb;
   C2<R>* z = data + row * p.n;
   const UDiv cbd(cb);
-  for (int i = threadIdx.x; i < cb * n1; i += kFT) {
-    int j1 = cbd.div(i), jj = i - j1 * cb;
-    int j2 = j2_0 + jj;
-    a[jj * ls + j1] = j2 < n2 ? z[(int64_t)j1 * n2 + j2] : C2<R>{(R)0, (R)0};
+  // kU loads per thread in flight before their LDS stores, and kU twiddle pairs before the
+  // multiplies and stores of the output loop
+  constexpr int kU = 8;
+  for (int i0 = threadIdx.x; i0 < cb * n1; i0 += kU * kFT) {
+    C2<R> v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kFT, j1 = cbd.div(i), j2 = j2_0 + (i - j1 * cb);
+      v[u] = (i < cb * n1 && j2 < n2) ? z[(int64_t)j1 * n2 + j2] : C2<R>{(R)0, (R)0};
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kFT, j1 = cbd.div(i), jj = i - j1 * cb;
+      if (i < cb * n1) a[jj * ls + j1] = v[u];
+    }
   }
   __syncthreads();
   const C2<R>* tw = (const C2<R>*)tw_ptr<R>(p.tw1d, p.tw1f);
   C2<R>* res = lds_fft<R>(a, b, n1, p.rad1, p.nr1, cb, tw, ls);
   const C2<R>* lo = (const C2<R>*)tw_ptr<R>(p.wlod, p.wlof);
   const C2<R>* hi = (const C2<R>*)tw_ptr<R>(p.whid, p.whif);
-  for (int i = threadIdx.x; i < cb * n1; i += kFT) {
-    int k1 = cbd.div(i), jj = i - k1 * cb;
-    int j2 = j2_0 + jj;
-    if (j2 < n2) {
-      C2<R> v = res[jj * ls + k1];
-      int64_t m = (int64_t)j2 * k1;                     // < n
-      z[(int64_t)k1 * n2 + j2] = cm(v, wN<R>(lo, hi, 2 * m));
+  for (int i0 = threadIdx.x; i0 < cb * n1; i0 += kU * kFT) {
+    C2<R> lk[kU], hk[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kFT, k1 = cbd.div(i), j2 = j2_0 + (i - k1 * cb);
+      const bool on = i < cb * n1 && j2 < n2;
+      const int64_t k = 2 * (int64_t)j2 * k1;           // 2 j2 k1 < 2n
+      lk[u] = on ? lo[k & 1023] : C2<R>{(R)0, (R)0};
+      hk[u] = on ? hi[k >> 10] : C2<R>{(R)0, (R)0};
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = i0 + u * kFT, k1 = cbd.div(i), jj = i - k1 * cb, j2 = j2_0 + jj;
+      if (i < cb * n1 && j2 < n2) z[(int64_t)k1 * n2 + j2] = cm(res[jj * ls + k1], cm(lk[u], hk[u]));
     }
   }
 }

@@ -328,8 +328,27 @@ __global__ __launch_bounds__(kFusedThreads) void k_couple_fused(double* u, int n
     }
   }
   __syncthreads();
-  if (threadIdx.x < 32 && r0 + (int)threadIdx.x < n)
-    couple_row(u, r0 + threadIdx.x, d, b0, nb, o + threadIdx.x * no, nullptr, nullptr, logdet, inverse);
+  // the coupling of couple_row, one (row, j) per thread (the serial loop per row waited on a
+  // load of u and an FP64 tanh and exp for each j in turn); each row's log-determinant then
+  // sums its s in the order j = 0 .. nb - 1, as couple_row does
+  double* sd = (double*)(o + 32 * no);   // 8-byte aligned: every block before it is
+  for (int i = threadIdx.x; i < 32 * nb; i += kFusedThreads) {
+    const int rr = i / nb, j = i - rr * nb, r = r0 + rr;
+    if (r < n) {
+      const float* orow = o + rr * no;
+      const double s = kSMax * tanh((double)orow[j] / kSMax);
+      const double t = (double)orow[nb + j];
+      double& x = u[(int64_t)r * d + b0 + j];
+      x = inverse ? (x - t) * exp(-s) : x * exp(s) + t;
+      sd[i] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && r0 + (int)threadIdx.x < n) {
+    double ld = 0.0;
+    for (int j = 0; j < nb; ++j) ld += sd[threadIdx.x * nb + j];
+    logdet[r0 + threadIdx.x] += ld;
+  }
 }
 
 // coupling backward: gu holds dL/dy on entry and dL/du_B on exit; writes g_o (FP32 + BF16)
@@ -664,7 +683,8 @@ Slots slots(const lt_flow* f, int l, int n) {
 // LDS of k_couple_fused for one layer (0: the layer runs unfused)
 size_t fused_bytes(const lt_flow* f, const LayerOff& Lo) {
   if (f->H % 32 != 0 || f->H > 256) return 0;
-  return (size_t)32 * ((Lo.na + 7) & ~7) * 2 + (size_t)2 * 32 * f->H * 2 + (size_t)32 * 2 * Lo.nb * 4;
+  return (size_t)32 * ((Lo.na + 7) & ~7) * 2 + (size_t)2 * 32 * f->H * 2 + (size_t)32 * 2 * Lo.nb * 4 +
+         (size_t)32 * Lo.nb * 8;
 }
 
 // forward (inverse = 0) or inverse pass over the n rows of f->u; logdet accumulates sum s.
