@@ -271,23 +271,34 @@ __device__ inline float16v tile_mma(const bf16* A, int lda, const bf16* W, int K
   return acc;
 }
 
-// A whole coupling layer for 32 rows, when its activations need not be kept (sampling and
-// log q without gradients): gather u_A, h1 = relu(u_A W1^T + b1), h2 = relu(h1 W2^T + b2) (BF16
-// in LDS, rounded where the unfused layer writes its BF16 copies), o = h2 W3^T + b3, coupling.
-// LDS: u_A [32][KA], h1 and h2 [32][H] BF16, o [32][2 nb] FP32.
+// One coupling layer applied to n rows of u (FP64 [n][d]): the rows, the layer's weights and
+// the direction
+struct FusedLayer {
+  double* u;
+  double* logdet;
+  int n, a0, na, b0, nb, inverse;
+  const bf16 *W1, *W2, *W3;
+  const float *bias1, *bias2, *bias3;
+};
+
+// A whole coupling layer for the 32 rows of workgroup blk, when its activations need not be
+// kept (sampling and log q without gradients): gather u_A, h1 = relu(u_A W1^T + b1),
+// h2 = relu(h1 W2^T + b2) (BF16 in LDS, rounded where the unfused layer writes its BF16
+// copies), o = h2 W3^T + b3, coupling.  LDS: u_A [32][KA], h1 and h2 [32][H] BF16,
+// o [32][2 nb] FP32, s [32][nb] FP64.
 constexpr int kFusedThreads = 512;   // eight wavefronts: one 32-column tile of h each at H = 256
-__global__ __launch_bounds__(kFusedThreads) void k_couple_fused(double* u, int n, int d, int a0, int na, int b0, int nb,
-                                                      int H, const bf16* W1, const float* bias1, const bf16* W2,
-                                                      const float* bias2, const bf16* W3, const float* bias3,
-                                                      double* logdet, int inverse, const int* __restrict__ gate) {
-  if (gate && *gate == 0) return;   // a sampler step without the flow move
-  extern __shared__ __align__(16) unsigned char sm[];
+__device__ inline void fused_layer(const FusedLayer& Ly, int blk, int d, int H, unsigned char* sm) {
+  double* u = Ly.u;
+  double* logdet = Ly.logdet;
+  const int n = Ly.n, a0 = Ly.a0, na = Ly.na, b0 = Ly.b0, nb = Ly.nb, inverse = Ly.inverse;
+  const bf16 *W1 = Ly.W1, *W2 = Ly.W2, *W3 = Ly.W3;
+  const float *bias1 = Ly.bias1, *bias2 = Ly.bias2, *bias3 = Ly.bias3;
   const int KA = (na + 7) & ~7;
   bf16* uA = (bf16*)sm;
   bf16* h1 = uA + 32 * KA;
   bf16* h2 = h1 + 32 * H;
   float* o = (float*)(h2 + 32 * H);
-  const int r0 = blockIdx.x * 32;
+  const int r0 = blk * 32;
   constexpr int NW = kFusedThreads / 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < 32 * KA; i += kFusedThreads) {
@@ -349,6 +360,26 @@ __global__ __launch_bounds__(kFusedThreads) void k_couple_fused(double* u, int n
     for (int j = 0; j < nb; ++j) ld += sd[threadIdx.x * nb + j];
     logdet[r0 + threadIdx.x] += ld;
   }
+}
+
+__global__ __launch_bounds__(kFusedThreads) void k_couple_fused(FusedLayer Ly, int d, int H,
+                                                                const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // a sampler step without the flow move
+  extern __shared__ __align__(16) unsigned char sm[];
+  fused_layer(Ly, blockIdx.x, d, H, sm);
+}
+
+// two independent groups of rows in one launch: workgroups [0, nblk_a) run layer A on theirs,
+// the others layer B (the flow move's proposals and its log q of the current positions, which
+// alone fill few compute units)
+__global__ __launch_bounds__(kFusedThreads) void k_couple_fused2(FusedLayer A, FusedLayer B, int nblk_a, int d, int H,
+                                                                 const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  extern __shared__ __align__(16) unsigned char sm[];
+  if ((int)blockIdx.x < nblk_a)
+    fused_layer(A, blockIdx.x, d, H, sm);
+  else
+    fused_layer(B, blockIdx.x - nblk_a, d, H, sm);
 }
 
 // coupling backward: gu holds dL/dy on entry and dL/du_B on exit; writes g_o (FP32 + BF16)
@@ -687,6 +718,26 @@ size_t fused_bytes(const lt_flow* f, const LayerOff& Lo) {
          (size_t)32 * Lo.nb * 8;
 }
 
+FusedLayer fused_args(const lt_flow* f, int l, double* u, double* logdet, int n, int inverse) {
+  const LayerOff& Lo = f->lay[l];
+  FusedLayer a;
+  a.u = u;
+  a.logdet = logdet;
+  a.n = n;
+  a.a0 = Lo.a0;
+  a.na = Lo.na;
+  a.b0 = Lo.b0;
+  a.nb = Lo.nb;
+  a.inverse = inverse;
+  a.W1 = f->wb + Lo.W1;
+  a.W2 = f->wb + Lo.W2;
+  a.W3 = f->wb + Lo.W3;
+  a.bias1 = f->w + Lo.b1;
+  a.bias2 = f->w + Lo.b2;
+  a.bias3 = f->w + Lo.b3;
+  return a;
+}
+
 // forward (inverse = 0) or inverse pass over the n rows of f->u; logdet accumulates sum s.
 // keep = false (no backward pass follows): each layer is one fused launch where it fits.
 void pass(lt_flow* f, int n, int inverse, hipStream_t st, bool keep) {
@@ -696,9 +747,8 @@ void pass(lt_flow* f, int n, int inverse, hipStream_t st, bool keep) {
     const LayerOff& Lo = f->lay[l];
     const size_t fb = keep ? 0 : fused_bytes(f, Lo);
     if (fb > 0) {
-      hipLaunchKernelGGL(k_couple_fused, dim3(blocks(n, 32)), dim3(kFusedThreads), fb, st, f->u, n, d, Lo.a0, Lo.na,
-                         Lo.b0, Lo.nb, H, f->wb + Lo.W1, f->w + Lo.b1, f->wb + Lo.W2, f->w + Lo.b2, f->wb + Lo.W3,
-                         f->w + Lo.b3, f->logdet, inverse, f->gate);
+      hipLaunchKernelGGL(k_couple_fused, dim3(blocks(n, 32)), dim3(kFusedThreads), fb, st,
+                         fused_args(f, l, f->u, f->logdet, n, inverse), d, H, f->gate);
       continue;
     }
     Slots S = slots(f, l, n);
@@ -795,6 +845,38 @@ hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream
   logq_rows(f, x, n, 0, n, false, st);
   hipLaunchKernelGGL(k_copy, dim3(blocks(n)), dim3(256), 0, st, f->logq, (int64_t)n, logq, f->gate);
   f->gate = nullptr;
+  return hipGetLastError();
+}
+// flow_propose and flow_logq of the same n in one pass when the flow holds 2n rows and its
+// layers run fused: the proposals in rows [0, n) of f->u, the rows of x in [n, 2n), and layer
+// L-1-q of the inverse pass with layer q of the forward pass in one launch; each row sees the
+// same operations as in the separate calls, so the results are the same
+hipError_t flow_propose_logq(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y,
+                             double* logq_y, const double* x, double* logq_x, hipStream_t st, const int* gate) {
+  const size_t fb = fused_bytes(f, f->lay[0]);
+  if (2 * n > f->maxB || fb == 0) {
+    hipError_t e = flow_propose(f, n, step, k0, k1, y, logq_y, st, gate);
+    return e != hipSuccess ? e : flow_logq(f, x, n, logq_x, st, gate);
+  }
+  const int d = f->d;
+  double* ux = f->u + (int64_t)n * d;
+  double* ldx = f->logdet + n;
+  hipLaunchKernelGGL(k_base_normal, dim3(blocks(n, 64)), dim3(64), 0, st, step, k0, k1, n, d, f->u, gate);
+  hipLaunchKernelGGL(k_zero, dim3(blocks(n)), dim3(256), 0, st, f->logdet, (int64_t)n, gate);
+  hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, f->u, n, d, f->logdet, 0.0, logq_y,
+                     (double*)nullptr, 0.0, gate);
+  hipLaunchKernelGGL(k_standardise, dim3(blocks(n, 64)), dim3(64), 0, st, x, (int64_t)n, (int64_t)0, n, d, f->mu,
+                     f->Lw, ux, ldx, gate);
+  const unsigned nblk = blocks(n, 32);
+  for (int q = 0; q < f->L; ++q)
+    hipLaunchKernelGGL(k_couple_fused2, dim3(2 * nblk), dim3(kFusedThreads), fb, st,
+                       fused_args(f, f->L - 1 - q, f->u, f->logdet, n, 1), fused_args(f, q, ux, ldx, n, 0),
+                       (int)nblk, d, f->H, gate);
+  hipLaunchKernelGGL(k_logq_add, dim3(blocks(n)), dim3(256), 0, st, n, f->logdet, f->lsig, logq_y, gate);
+  hipLaunchKernelGGL(k_destandardise, dim3(blocks((int64_t)n * d)), dim3(256), 0, st, f->u, n, d, f->mu, f->Lw, y,
+                     gate);
+  hipLaunchKernelGGL(k_logq, dim3(blocks(n)), dim3(256), 0, st, ux, n, d, ldx, f->lsig, logq_x, (double*)nullptr,
+                     1.0 / n, gate);
   return hipGetLastError();
 }
 // latent random walk from the rows of x: z = f(x), y = f^-1(z + sigma eps);

@@ -328,6 +328,8 @@ int flow_device(const lt_flow* f);
 hipError_t flow_propose(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y, double* logq_y,
                         hipStream_t st, const int* gate);
 hipError_t flow_logq(lt_flow* f, const double* x, int n, double* logq, hipStream_t st, const int* gate);
+hipError_t flow_propose_logq(lt_flow* f, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double* y,
+                             double* logq_y, const double* x, double* logq_x, hipStream_t st, const int* gate);
 hipError_t flow_walk(lt_flow* f, const double* x, int n, const uint64_t* step, uint32_t k0, uint32_t k1, double sigma,
                      double* y, double* lq_y, double* lq_x, hipStream_t st, const int* gate);
 }
@@ -432,8 +434,8 @@ static lt_status record_step(lt_sampler* s, hipStream_t st) {
       S_HIP(hipGetLastError());
     } else {
       // the flow's kernels return at once in a step that the gate leaves without the move
-      S_HIP(lt::flow_propose(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, st, s->D.fgate));
-      S_HIP(lt::flow_logq(s->flow, s->D.fxf, W, s->D.fqx, st, s->D.fgate));
+      S_HIP(lt::flow_propose_logq(s->flow, W, s->D.step, s->D.k0, s->D.k1, s->D.fy, s->D.fqy, s->D.fxf, s->D.fqx, st,
+                                  s->D.fgate));
     }
     hipLaunchKernelGGL(k_flow_prep, dim3((unsigned)((W + 127) / 128)), dim3(128), 0, st, s->D);
     S_HIP(hipGetLastError());

@@ -233,9 +233,11 @@ def test_trained_flow_matches_gaussian(lib):
     f.close()
 
 
-@pytest.mark.parametrize("T,full", [(1, False), (2, False), (2, True)])
-def test_sampler_flow_move_parity(lib, T, full):
-    """P28: GPU chain with an (exact, identity) flow move against the oracle chain, step by step."""
+@pytest.mark.parametrize("T,full,mb", [(1, False, 1), (2, False, 1), (2, True, 1), (2, False, 2), (2, True, 2)])
+def test_sampler_flow_move_parity(lib, T, full, mb):
+    """P28: GPU chain with an (exact, identity) flow move against the oracle chain, step by step.
+    mb = 2: the flow holds twice the walkers, so the proposals and the log q of the current
+    positions go through its passes together (one launch per layer for both)."""
     d, W, seed = 5, 16, 777
     rng = np.random.default_rng(T)
     A = rng.normal(size=(d, d))
@@ -245,7 +247,7 @@ def test_sampler_flow_move_parity(lib, T, full):
     P = fl.init_params(d, 4, 32, 1)
     mu, sig = means[0] + 0.5, np.linspace(1.0, 3.0, d)
     start = means[0] + rng.normal(size=(T, W, d))
-    fg = lib.Flow(d, 4, 32, W)
+    fg = lib.Flow(d, 4, 32, mb * W)
     fg.set_params(lib.flow_pack(P), mu, sig)
     if full:                 # whitening by the target's own Cholesky factor (scaled up by 1.2)
         sig = 1.2 * np.linalg.cholesky(np.linalg.inv(icov))

@@ -140,7 +140,7 @@ def test_chain_parity_tdi(lib, flow):
         # identity flow over a Gaussian around the injection a few start widths wide
         P = fl.init_params(10, 2, 16, 5)
         sig = 3e-4 * (hi - lo)
-        fg = lib.Flow(10, 2, 16, W)
+        fg = lib.Flow(10, 2, 16, 2 * W)   # room for the proposals and the current positions in one pass
         fg.set_params(lib.flow_pack(P), x0, sig)
         smp.set_flow(fg)
         smp.set_flow_mix(1.0)
