@@ -190,10 +190,11 @@ lt_status lt_lisa_tdi_response(lt_ctx* ctx, const double* params, int64_t batch,
  * call then allocates and synchronises nothing, except that the first call
  * with a new grid length or orbit builds that grid's FFT plan and orbit node
  * table in the context (host work, an upload, kept for later calls).  The
- * chunk is the largest (up to 256 templates) that fits the workspace; one
- * smaller than a single template's needs is LT_ERR_WORKSPACE.  With
- * workspace = null the context keeps its own scratch, grown on demand (growth
- * synchronises the device before the old block is freed) to chunks of 256:
+ * chunk is the largest (up to the context's launch-shape chunk, 256 templates
+ * unless lt_ctx_set_tuning or lt_autotune set another) that fits the
+ * workspace; one smaller than a single template's needs is LT_ERR_WORKSPACE.
+ * With workspace = null the context keeps its own scratch, grown on demand
+ * (growth synchronises the device before the old block is freed) to full chunks:
  * 5 series of n samples per template of a chunk plus the tables, and the set-up
  * constants of every template of the call (624 bytes and a status word each; they are
  * computed for the whole batch in one launch).  The workspace, like the
@@ -222,7 +223,7 @@ lt_status lt_tdi_loglike_noalloc(lt_ctx* ctx, const double* params, int64_t batc
                                  int32_t* status, void* stream);
 
 /* Workspace of lt_tdi_loglike for `batch` templates with this configuration:
- * bytes (nullable) for full-size chunks (min(batch, 256) templates per chunk),
+ * bytes (nullable) for full-size chunks (min(batch, the context's chunk) templates per chunk),
  * min_bytes (nullable) for chunks of one template (both include the set-up constants of all
  * `batch` templates).  Host only; no device work. */
 lt_status lt_workspace_size(lt_ctx* ctx, int64_t batch, const lt_wf_cfg* cfg, const lt_grid* grid,
@@ -297,7 +298,10 @@ typedef struct {
 
 /* Creates a sampler with its own context (so that the captured graph owns its
  * scratch).  For LT_TARGET_TDI the likelihood configuration is copied; the
- * device arrays psd->S[] and data->aet must stay valid for the sampler's life. */
+ * device arrays psd->S[] and data->aet must stay valid for the sampler's life.
+ * That context's chunk is 256 templates, doubled while a chunk's residual
+ * (3 n samples per template) stays within 128 MiB and the workspace for half
+ * the ensemble within 4 GiB (512 at 2^14 samples); results do not depend on it. */
 lt_status lt_sampler_create(int hip_device, const lt_sampler_cfg* cfg, const lt_wf_cfg* wf, const lt_grid* grid,
                             const lt_orbit* orbit, const lt_tdi_cfg* tdi, const lt_psd* psd, const lt_data* data,
                             lt_sampler** out);
