@@ -283,12 +283,7 @@ __constant__ int kRecvLink[3] = {2, 0, 1};          // a link received by spacec
 // The three geometric factors are smooth in time and can be interpolated separately between
 // the nodes; their quotient is not, where the wave travels almost along an arm (k.n -> 1: the
 // quotient then turns through its range within a node interval, while y itself vanishes).
-__global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb, double inv_dt, double* nodes) {
-  const int j = blockIdx.x * kNT + threadIdx.x;
-  const int b = blockIdx.y;
-  if (j >= orb.n_nodes) return;
-  const TplConst& c = tc[b];
-  double* o = nodes + ((int64_t)b * orb.n_nodes + j) * kNodeRec;
+__device__ inline void node_record(const TplConst& c, const OrbitDev& orb, int j, double inv_dt, double* o) {
   int dhi = -(1 << 30), dlo = 1 << 30;
   double dmin = 2.0;
   for (int q = 0; q < 6; ++q) {
@@ -317,6 +312,22 @@ __global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb,
   wb.y = dlo;
   *reinterpret_cast<int2*>(o + kNodeVals) = wb;
   o[kNodeVals + 1] = dmin;
+}
+
+// One record per (template, node).  The workgroup builds its kNT records in LDS and writes them
+// as one contiguous block: stored by each thread directly, a store instruction touched 64
+// records kNodeRec * 8 bytes apart, and the partial lines cost 2.7 times the record bytes in
+// HBM writes.
+__global__ __launch_bounds__(kNT) void k_nodes(const TplConst* tc, OrbitDev orb, double inv_dt, double* nodes) {
+  __shared__ double rec[kNT * kNodeRec];
+  const int j0 = blockIdx.x * kNT;
+  const int j = j0 + threadIdx.x;
+  const int b = blockIdx.y;
+  if (j < orb.n_nodes) node_record(tc[b], orb, j, inv_dt, rec + threadIdx.x * kNodeRec);
+  __syncthreads();
+  const int nj = orb.n_nodes - j0 < kNT ? orb.n_nodes - j0 : kNT;
+  double* dst = nodes + ((int64_t)b * orb.n_nodes + j0) * kNodeRec;
+  for (int i = threadIdx.x; i < nj * kNodeRec; i += kNT) dst[i] = rec[i];
 }
 
 // window bounds of every (template, tile): the largest and smallest delay in samples over
