@@ -282,7 +282,7 @@ def quantile_gap(a, b, n_batches=20):
     return float(np.max(np.abs(qa - qb) / np.sqrt(sa ** 2 + sb ** 2)))
 
 
-def train_early_stop(flow, s, mu, L, val_frac=0.25, chunk=250, max_steps=3000, patience=2, lr=3e-4, seed=0):
+def train_early_stop(flow, s, mu, L, val_frac=0.25, chunk=250, max_steps=3000, patience=1, lr=3e-4, seed=0):
     """Fit the flow to a window of chain samples s [n][d] in time order, holding out its last
     val_frac of rows: Adam in chunks of `chunk` steps (batch 2048) on the shuffled earlier
     samples, the held-out mean log q after each chunk, stop after `patience` chunks without
